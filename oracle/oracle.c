@@ -1,0 +1,946 @@
+/*
+ * CPU oracle — TEST INFRASTRUCTURE ONLY (see oracle.h).
+ *
+ * Plain C99, built with -O2 -ffp-contract=off -fno-fast-math on x86-64 (SSE2
+ * binary64, round to nearest even, no FMA).  Every arithmetic expression is
+ * written in the order that defines the method; the GPU kernels follow the same
+ * definition from their own source.
+ *
+ * What the paper fixes and where:
+ *  - particle histories driven by pseudorandom numbers, material data and
+ *    geometry, tallied with a statistical error: Sec. "Monte Carlo Neutron
+ *    Transport and MC/DC";
+ *  - the fixed-source loop that transports each particle until a physical
+ *    event (capture, time or space boundary), a simulation event (time census)
+ *    or a variance-reduction event (implicit capture) ends it: Sec. "MC/DC on
+ *    CPUs", transport-loop paragraph;
+ *  - the move kernel (position += direction * distance, time += distance /
+ *    speed): Fig. 2;
+ *  - tally accumulation by a plain add on the CPU, an atomic add on the GPU:
+ *    Fig. 3;
+ *  - hash-based (counter-based) random numbers for replicable testing: Sec.
+ *    "Monte Carlo Neutron Transport and MC/DC", list of novel developments.
+ * Everything else (RNG algorithm, sampling formulas, estimator, tie rules,
+ * weight windows) is a reading recorded in the design notes and restated in
+ * the comments below.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define O_INF HUGE_VAL
+
+/* ------------------------------------------------------------------------ */
+/* Counter-based RNG: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).     */
+/* Ten rounds; each round multiplies words 0 and 2 by the two Philox         */
+/* multipliers, and the key is bumped by the two Weyl constants between      */
+/* rounds.                                                                   */
+/* ------------------------------------------------------------------------ */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* One random stream per particle: key = seed, counter = (k, tag, history low
+ * word, history high 16 bits | problem << 16).  Each draw uses one Philox
+ * block and advances k. */
+typedef struct {
+    uint32_t key[2];
+    uint32_t tag, c2, c3;
+    uint32_t k;
+} o_stream;
+
+static o_stream o_stream_make(uint64_t seed, uint64_t hist, uint32_t problem, uint32_t tag)
+{
+    o_stream s;
+    s.key[0] = (uint32_t)seed;
+    s.key[1] = (uint32_t)(seed >> 32);
+    s.tag = tag;
+    s.c2 = (uint32_t)hist;
+    s.c3 = (uint32_t)((hist >> 32) & 0xFFFFu) | (problem << 16);
+    s.k = 0;
+    return s;
+}
+
+static void o_block(o_stream *s, uint32_t out[4])
+{
+    uint32_t ctr[4] = {s->k, s->tag, s->c2, s->c3};
+    orc_philox4x32_10(ctr, s->key, out);
+    s->k += 1u;
+}
+
+/* xi = ((u >> 12) + 0.5) * 2^-52 with u = (r1 << 32) | r0: exact, in (0,1). */
+static double o_draw(o_stream *s)
+{
+    uint32_t r[4];
+    o_block(s, r);
+    uint64_t u = ((uint64_t)r[1] << 32) | (uint64_t)r[0];
+    return ((double)(u >> 12) + 0.5) * 0x1p-52;
+}
+
+double orc_uniform(uint64_t seed, uint64_t hist, uint32_t problem, uint32_t tag, uint32_t k)
+{
+    o_stream s = o_stream_make(seed, hist, problem, tag);
+    s.k = k;
+    return o_draw(&s);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Own natural log and exp, so that both implementations round identically. */
+/* log: Cody-Waite style reduction x = 2^e * m with m in [sqrt(1/2),sqrt(2)), */
+/* log m = 2 atanh(f), f = (m-1)/(m+1), odd series through f^21 (|f|<0.1716).*/
+/* exp: n = floor(x/ln2 + 1/2), r = (x - n ln2_hi) - n ln2_lo, Taylor        */
+/* polynomial of degree 13 in Horner form, times 2^n built from exponent bits.*/
+/* ln2_hi = ln 2 rounded to 32 significant bits, ln2_lo = the remainder.     */
+/* ------------------------------------------------------------------------ */
+static const double O_LN2_HI = 0x1.62e42feep-1;          /* 6.93147180369123816490e-01 */
+static const double O_LN2_LO = 0x1.a39ef35793c76p-33;    /* 1.90821492927058770002e-10 */
+static const double O_INV_LN2 = 1.4426950408889634;
+static const double O_SQRT2 = 1.4142135623730951;
+
+static uint64_t o_bits(double x) { uint64_t b; memcpy(&b, &x, 8); return b; }
+static double o_from_bits(uint64_t b) { double x; memcpy(&x, &b, 8); return x; }
+
+double orc_log(double x)
+{
+    /* domain: positive normal numbers (the transport loop only takes logs of
+     * numbers in (0,1) that are multiples of 2^-53) */
+    uint64_t b = o_bits(x);
+    int e = (int)((b >> 52) & 0x7FFu) - 1023;
+    double m = o_from_bits((b & 0x000FFFFFFFFFFFFFull) | 0x3FF0000000000000ull);
+    if (m > O_SQRT2) {
+        m = m * 0.5;
+        e = e + 1;
+    }
+    double f = (m - 1.0) / (m + 1.0);
+    double s = f * f;
+    double p = 1.0 / 21.0;
+    p = p * s + 1.0 / 19.0;
+    p = p * s + 1.0 / 17.0;
+    p = p * s + 1.0 / 15.0;
+    p = p * s + 1.0 / 13.0;
+    p = p * s + 1.0 / 11.0;
+    p = p * s + 1.0 / 9.0;
+    p = p * s + 1.0 / 7.0;
+    p = p * s + 1.0 / 5.0;
+    p = p * s + 1.0 / 3.0;
+    double lm = 2.0 * f + (2.0 * f) * (s * p);
+    double de = (double)e;
+    return de * O_LN2_HI + (de * O_LN2_LO + lm);
+}
+
+double orc_exp(double x)
+{
+    if (x > 700.0) x = 700.0;
+    if (x < -700.0) x = -700.0;
+    double n = floor(x * O_INV_LN2 + 0.5);
+    double r = (x - n * O_LN2_HI) - n * O_LN2_LO;
+    double p = 1.0 / 6227020800.0;        /* 1/13! */
+    p = p * r + 1.0 / 479001600.0;        /* 1/12! */
+    p = p * r + 1.0 / 39916800.0;         /* 1/11! */
+    p = p * r + 1.0 / 3628800.0;          /* 1/10! */
+    p = p * r + 1.0 / 362880.0;           /* 1/9!  */
+    p = p * r + 1.0 / 40320.0;            /* 1/8!  */
+    p = p * r + 1.0 / 5040.0;             /* 1/7!  */
+    p = p * r + 1.0 / 720.0;              /* 1/6!  */
+    p = p * r + 1.0 / 120.0;              /* 1/5!  */
+    p = p * r + 1.0 / 24.0;               /* 1/4!  */
+    p = p * r + 1.0 / 6.0;                /* 1/3!  */
+    p = p * r + 0.5;                      /* 1/2!  */
+    p = p * r + 1.0;                      /* 1/1!  */
+    p = p * r + 1.0;                      /* 1/0!  */
+    int64_t ni = (int64_t)n;
+    double scale = o_from_bits((uint64_t)(ni + 1023) << 52);
+    return p * scale;
+}
+
+/* Isotropic direction, Marsaglia (1972): draw a = 2 xi1 - 1, b = 2 xi2 - 1
+ * until 0 < s = a^2 + b^2 < 1; then u = (2a sqrt(1-s), 2b sqrt(1-s), 1 - 2s). */
+static void o_direction(o_stream *st, double u[3])
+{
+    double a, b, s;
+    for (;;) {
+        a = 2.0 * o_draw(st) - 1.0;
+        b = 2.0 * o_draw(st) - 1.0;
+        s = a * a + b * b;
+        if (s < 1.0 && s > 0.0) break;
+    }
+    double r = sqrt(1.0 - s);
+    u[0] = (2.0 * a) * r;
+    u[1] = (2.0 * b) * r;
+    u[2] = 1.0 - 2.0 * s;
+}
+
+uint32_t orc_directions(uint64_t seed, uint64_t hist, uint32_t n, double *u)
+{
+    o_stream s = o_stream_make(seed, hist, 0, 0);
+    for (uint32_t i = 0; i < n; ++i) o_direction(&s, u + 3 * i);
+    return s.k;
+}
+
+/* ------------------------------------------------------------------------ */
+/* FP32 MLP forward (log-importance): inputs -> H -> H -> 1 with ReLU.       */
+/* Parameter layout: W1[H][in], b1[H], W2[H][H], b2[H], W3[H], b3.           */
+/* Each neuron: acc = bias, then acc = acc + w_i * x_i for i ascending, as   */
+/* separate float multiply and add.                                          */
+/* ------------------------------------------------------------------------ */
+float orc_mlp_f32(const float *prm, int32_t in_dim, int32_t H, const float *in)
+{
+    const float *W1 = prm;
+    const float *b1 = W1 + (size_t)H * in_dim;
+    const float *W2 = b1 + H;
+    const float *b2 = W2 + (size_t)H * H;
+    const float *W3 = b2 + H;
+    const float *b3 = W3 + H;
+    float h1[256], h2[256];
+    for (int j = 0; j < H; ++j) {
+        float acc = b1[j];
+        for (int i = 0; i < in_dim; ++i) {
+            float prod = W1[(size_t)j * in_dim + i] * in[i];
+            acc = acc + prod;
+        }
+        h1[j] = acc > 0.0f ? acc : 0.0f;
+    }
+    for (int j = 0; j < H; ++j) {
+        float acc = b2[j];
+        for (int i = 0; i < H; ++i) {
+            float prod = W2[(size_t)j * H + i] * h1[i];
+            acc = acc + prod;
+        }
+        h2[j] = acc > 0.0f ? acc : 0.0f;
+    }
+    float out = b3[0];
+    for (int i = 0; i < H; ++i) {
+        float prod = W3[i] * h2[i];
+        out = out + prod;
+    }
+    return out;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Geometry: priority-ordered axis-aligned boxes inside an outer box.        */
+/* A point belongs to the first box that contains it, else to the background */
+/* material.  Containment is decided per axis and is direction aware: inside */
+/* iff lo < p < hi, or p == lo moving in (u >= 0 at lo), or p == hi moving  */
+/* in (u < 0).                                                               */
+/* ------------------------------------------------------------------------ */
+static int o_axis_in(double lo, double hi, double p, double u)
+{
+    if (lo < p && p < hi) return 1;
+    if (p == lo) return u >= 0.0;
+    if (p == hi) return u < 0.0;
+    return 0;
+}
+
+static int o_box_in(const double *lo, const double *hi, const double p[3], const double u[3])
+{
+    return o_axis_in(lo[0], hi[0], p[0], u[0]) && o_axis_in(lo[1], hi[1], p[1], u[1]) &&
+           o_axis_in(lo[2], hi[2], p[2], u[2]);
+}
+
+static int o_locate(const orc_problem *P, const double p[3], const double u[3])
+{
+    for (int b = 0; b < P->n_boxes; ++b)
+        if (o_box_in(P->box_lo + 3 * b, P->box_hi + 3 * b, p, u)) return b;
+    return -1;
+}
+
+static int o_material(const orc_problem *P, int cell)
+{
+    return cell >= 0 ? P->box_mat[cell] : P->background_mat;
+}
+
+/* Distance to the next surface along u (1/u precomputed, unused where u == 0):
+ * exit of the outer box, and for every box either its exit (point inside) or
+ * its entry (slab test, entry >= 0 and entry < exit).  Strict '<' keeps the
+ * first candidate in the order outer box, boxes ascending, axes x,y,z.
+ * Negative exit distances (a point a rounding error outside) become 0. */
+static double o_dist_surface(const orc_problem *P, const double p[3], const double u[3],
+                             const double iu[3], int *axis, double *plane)
+{
+    double best = O_INF;
+    int bax = -1;
+    double bpl = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        if (u[a] == 0.0) continue;
+        double pl = u[a] > 0.0 ? P->outer_hi[a] : P->outer_lo[a];
+        double s = (pl - p[a]) * iu[a];
+        if (!(s > 0.0)) s = 0.0;
+        if (s < best) { best = s; bax = a; bpl = pl; }
+    }
+    for (int b = 0; b < P->n_boxes; ++b) {
+        const double *lo = P->box_lo + 3 * b, *hi = P->box_hi + 3 * b;
+        if (o_box_in(lo, hi, p, u)) {
+            for (int a = 0; a < 3; ++a) {
+                if (u[a] == 0.0) continue;
+                double pl = u[a] > 0.0 ? hi[a] : lo[a];
+                double s = (pl - p[a]) * iu[a];
+                if (!(s > 0.0)) s = 0.0;
+                if (s < best) { best = s; bax = a; bpl = pl; }
+            }
+        } else {
+            double tn = -O_INF, tf = O_INF, tpl = 0.0;
+            int ta = -1, miss = 0;
+            for (int a = 0; a < 3; ++a) {
+                if (u[a] == 0.0) {
+                    if (!o_axis_in(lo[a], hi[a], p[a], 0.0)) miss = 1;
+                    continue;
+                }
+                double s1 = (lo[a] - p[a]) * iu[a];
+                double s2 = (hi[a] - p[a]) * iu[a];
+                double nr = u[a] > 0.0 ? s1 : s2;
+                double fr = u[a] > 0.0 ? s2 : s1;
+                if (nr > tn) { tn = nr; ta = a; tpl = u[a] > 0.0 ? lo[a] : hi[a]; }
+                if (fr < tf) tf = fr;
+            }
+            if (!miss && ta >= 0 && tn < tf && tn >= 0.0 && tn < best) {
+                best = tn; bax = ta; bpl = tpl;
+            }
+        }
+    }
+    *axis = bax;
+    *plane = bpl;
+    return best;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Track-length estimator: a straight segment p + s u, s in [0,d], starting  */
+/* at time t0 with speed v, is cut at every mesh plane and time-bin edge it  */
+/* crosses; each piece adds w * length to tally[g][it][iz][iy][ix].  Edges   */
+/* are lo + k*delta with delta = (hi-lo)/n; crossing distances are computed  */
+/* fresh from the segment start; all axes that reach the minimum advance     */
+/* together; pieces of zero or negative length and pieces outside the mesh   */
+/* are not scored.  An axis with infinite bounds is not cut.                 */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int n[4], bounded[3];
+    double lo[4], delta[4], idelta[4];
+    int G_t;                                /* groups in the tally (1 or G) */
+} o_mesh;
+
+static o_mesh o_mesh_make(const orc_problem *P)
+{
+    o_mesh M;
+    for (int a = 0; a < 4; ++a) {
+        M.n[a] = P->mesh_n[a];
+        M.lo[a] = P->mesh_lo[a];
+        if (a < 3 && isinf(P->mesh_lo[a]) && isinf(P->mesh_hi[a])) {
+            M.bounded[a] = 0;
+            M.delta[a] = O_INF;
+            M.idelta[a] = 0.0;
+        } else {
+            if (a < 3) M.bounded[a] = 1;
+            M.delta[a] = (P->mesh_hi[a] - P->mesh_lo[a]) / (double)P->mesh_n[a];
+            M.idelta[a] = 1.0 / M.delta[a];
+        }
+    }
+    M.G_t = P->mesh_per_group ? P->G : 1;
+    return M;
+}
+
+/* returns pieces scored; tally may be NULL (count only) */
+static int64_t o_score_mesh(const o_mesh *M, const double p[3], const double u[3],
+                            const double iu[3], double t0, double v, double d, double w,
+                            int g, double *tally)
+{
+    int idx[4];
+    double s[4];
+    int64_t pieces = 0;
+    if (!(d > 0.0)) return 0;
+    for (int a = 0; a < 3; ++a) {
+        if (!M->bounded[a]) { idx[a] = 0; s[a] = O_INF; continue; }
+        double q = (p[a] - M->lo[a]) * M->idelta[a];
+        double fq = floor(q);
+        if (fq < -1.0) fq = -1.0;
+        if (fq > (double)M->n[a]) fq = (double)M->n[a];
+        int i = (int)fq;
+        if (q == fq && u[a] < 0.0) i = i - 1;          /* on an edge moving down */
+        if (i < -1) i = -1;
+        idx[a] = i;
+        if (u[a] > 0.0) {
+            if (i >= M->n[a]) return 0;                /* beyond and moving away */
+            double e = M->lo[a] + (double)(i + 1) * M->delta[a];
+            s[a] = (e - p[a]) * iu[a];
+        } else if (u[a] < 0.0) {
+            if (i < 0) return 0;
+            double e = M->lo[a] + (double)i * M->delta[a];
+            s[a] = (e - p[a]) * iu[a];
+        } else {
+            if (i < 0 || i >= M->n[a]) return 0;
+            s[a] = O_INF;
+        }
+    }
+    {
+        double q = (t0 - M->lo[3]) * M->idelta[3];
+        double fq = floor(q);
+        if (fq < -1.0) fq = -1.0;
+        if (fq > (double)M->n[3]) fq = (double)M->n[3];
+        int i = (int)fq;
+        if (i >= M->n[3]) return 0;
+        idx[3] = i;
+        double e = M->lo[3] + (double)(i + 1) * M->delta[3];
+        s[3] = (e - t0) * v;
+    }
+    double sp = 0.0;
+    for (;;) {
+        double sn = d;
+        for (int a = 0; a < 4; ++a)
+            if (s[a] < sn) sn = s[a];
+        if (sn > sp) {
+            int in = 1;
+            for (int a = 0; a < 4; ++a)
+                if (idx[a] < 0 || idx[a] >= M->n[a]) in = 0;
+            if (in) {
+                int gt = M->G_t > 1 ? g : 0;
+                size_t b = ((((size_t)gt * M->n[3] + idx[3]) * M->n[2] + idx[2]) * M->n[1] + idx[1]) *
+                               M->n[0] + idx[0];
+                if (tally) tally[b] += w * (sn - sp);
+                pieces += 1;
+            }
+        }
+        if (sn >= d) break;
+        int done = 0;
+        for (int a = 0; a < 3; ++a) {
+            if (s[a] != sn) continue;
+            if (u[a] > 0.0) {
+                idx[a] += 1;
+                if (idx[a] >= M->n[a]) { done = 1; continue; }
+                double e = M->lo[a] + (double)(idx[a] + 1) * M->delta[a];
+                s[a] = (e - p[a]) * iu[a];
+            } else {
+                idx[a] -= 1;
+                if (idx[a] < 0) { done = 1; continue; }
+                double e = M->lo[a] + (double)idx[a] * M->delta[a];
+                s[a] = (e - p[a]) * iu[a];
+            }
+        }
+        if (s[3] == sn) {
+            idx[3] += 1;
+            if (idx[3] >= M->n[3]) done = 1;
+            else {
+                double e = M->lo[3] + (double)(idx[3] + 1) * M->delta[3];
+                s[3] = (e - t0) * v;
+            }
+        }
+        if (done) break;
+        sp = sn;
+    }
+    return pieces;
+}
+
+/* part of the segment inside the detector box (box clip of [0,d]) */
+static double o_detector_len(const orc_problem *P, const double p[3], const double u[3],
+                             const double iu[3], double d)
+{
+    double si = 0.0, so = d;
+    for (int a = 0; a < 3; ++a) {
+        if (u[a] == 0.0) {
+            if (!(P->det_lo[a] <= p[a] && p[a] <= P->det_hi[a])) return 0.0;
+            continue;
+        }
+        double s1 = (P->det_lo[a] - p[a]) * iu[a];
+        double s2 = (P->det_hi[a] - p[a]) * iu[a];
+        double nr = u[a] > 0.0 ? s1 : s2;
+        double fr = u[a] > 0.0 ? s2 : s1;
+        if (nr > si) si = nr;
+        if (fr < so) so = fr;
+    }
+    return so > si ? so - si : 0.0;
+}
+
+int64_t orc_score_segment(const orc_problem *P, const double p[3], const double u[3],
+                          double t0, double d, double w, int32_t g, double *tally)
+{
+    o_mesh M = o_mesh_make(P);
+    double iu[3];
+    for (int a = 0; a < 3; ++a) iu[a] = u[a] != 0.0 ? 1.0 / u[a] : 0.0;
+    return o_score_mesh(&M, p, u, iu, t0, P->speed[g], d, w, g, tally);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Particle state and the per-history loop                                   */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    double p[3], u[3], t, w;
+    int g, cell, ci;
+    uint32_t tag, k, seq;
+    int alive;
+} o_part;
+
+typedef struct {
+    const orc_problem *P;
+    o_mesh M;
+    orc_result *R;
+    uint64_t seed, hist;
+    double xh;
+    int64_t events;
+    o_part *stack;
+    int sp;
+    int status;
+    /* importance list: distinct coarse cells visited at flight starts */
+    int n_imp;
+    int64_t imp_cell[16];
+    double imp_cnt[16], imp_xsum[16];
+    double ww_lo[4], ww_inv[4];
+} o_ctx;
+
+static void o_trace(o_ctx *C, o_part *q, int type, double aux)
+{
+    orc_result *R = C->R;
+    uint32_t seq = q->seq;
+    q->seq += 1u;
+    if (!R->trace || R->trace_n >= R->trace_cap) return;
+    orc_trace_rec *r = &R->trace[R->trace_n++];
+    r->hist = C->hist;
+    r->tag = q->tag;
+    r->seq = seq;
+    r->type = type;
+    r->g = q->g;
+    r->cell = q->cell;
+    r->k = q->k;
+    r->x = q->p[0]; r->y = q->p[1]; r->z = q->p[2]; r->t = q->t;
+    r->ux = q->u[0]; r->uy = q->u[1]; r->uz = q->u[2]; r->w = q->w;
+    r->aux = aux;
+}
+
+static o_stream o_part_stream(o_ctx *C, const o_part *q)
+{
+    o_stream s = o_stream_make(C->seed, C->hist, C->P->problem_id, q->tag);
+    s.k = q->k;
+    return s;
+}
+
+/* Outer boundary after a surface crossing: every axis on which the point is
+ * outside (direction aware) is handled in x,y,z order: reflective faces put
+ * the point on the face and reverse that direction component, vacuum faces
+ * leak the particle.  A point still outside after that leaks through its first
+ * failing face.  Returns the leak face or -1. */
+static int o_boundary(const orc_problem *P, o_part *q)
+{
+    for (int a = 0; a < 3; ++a) {
+        if (o_axis_in(P->outer_lo[a], P->outer_hi[a], q->p[a], q->u[a])) continue;
+        int side = q->p[a] >= P->outer_hi[a] ? 1 : 0;
+        int face = 2 * a + side;
+        if (P->bc[face] == 1) {
+            q->p[a] = side ? P->outer_hi[a] : P->outer_lo[a];
+            q->u[a] = -q->u[a];
+        } else {
+            return face;
+        }
+    }
+    for (int a = 0; a < 3; ++a) {
+        if (o_axis_in(P->outer_lo[a], P->outer_hi[a], q->p[a], q->u[a])) continue;
+        return 2 * a + (q->p[a] >= P->outer_hi[a] ? 1 : 0);
+    }
+    return -1;
+}
+
+static void o_leak(o_ctx *C, o_part *q, int face)
+{
+    C->R->leak[face] += q->w;
+    C->R->wsum[ORC_W_LEAK] += q->w;
+    C->R->cnt[ORC_C_LEAK] += 1;
+    q->alive = 0;
+}
+
+/* Weight-window check (MLP importance): target w_T = exp(log K - y),
+ * window [w_L, w_U] with w_L = 2 w_T / (1 + r), w_U = r w_L.  Above: split
+ * into n = min(ceil(w / w_T), n_max) copies of weight w/n; the n-1 daughters
+ * go on the LIFO stack with stream tags derived from one parent block.  Below:
+ * roulette, survive iff xi * w_T < w with weight w_T.  No draw otherwise. */
+static void o_ww(o_ctx *C, o_part *q)
+{
+    const orc_problem *P = C->P;
+    float in[4 + 16];
+    int in_dim = 4 + P->G;
+    for (int a = 0; a < 3; ++a)
+        in[a] = (float)(2.0 * ((q->p[a] - C->ww_lo[a]) * C->ww_inv[a]) - 1.0);
+    in[3] = (float)(2.0 * ((q->t - C->ww_lo[3]) * C->ww_inv[3]) - 1.0);
+    for (int g = 0; g < P->G; ++g) in[4 + g] = g == q->g ? 1.0f : 0.0f;
+    float y = orc_mlp_f32(P->ww_params, in_dim, P->ww_hidden, in);
+    double wt = orc_exp(P->ww_logk - (double)y);
+    double wl = (2.0 * wt) / (1.0 + P->ww_ratio);
+    double wu = P->ww_ratio * wl;
+    if (q->w > wu) {
+        double ratio = q->w / wt;
+        int n = ratio >= (double)P->ww_nmax ? P->ww_nmax : (int)ceil(ratio);
+        if (n < 2) return;
+        o_stream s = o_part_stream(C, q);
+        uint32_t blk[4];
+        o_block(&s, blk);
+        q->k = s.k;
+        double wn = q->w / (double)n;
+        q->w = wn;
+        for (int i = 1; i < n; ++i) {
+            if (C->sp >= P->stack_cap) { C->status = ORC_E_STACK; return; }
+            o_part *d = &C->stack[C->sp++];
+            *d = *q;
+            d->tag = blk[0] + (uint32_t)i * 0x9E3779B9u;
+            d->k = 0;
+            d->seq = 0;
+        }
+        C->R->cnt[ORC_C_SPLIT] += (uint64_t)(n - 1);
+        C->R->cnt[ORC_C_PARTICLE] += (uint64_t)(n - 1);
+        o_trace(C, q, ORC_EV_SPLIT, (double)n);
+    } else if (q->w < wl) {
+        o_stream s = o_part_stream(C, q);
+        double xi = o_draw(&s);
+        q->k = s.k;
+        if (xi * wt < q->w) {
+            C->R->wsum[ORC_W_GAIN] += wt - q->w;
+            q->w = wt;
+            C->R->cnt[ORC_C_RR_SURVIVE] += 1;
+            o_trace(C, q, ORC_EV_ROULETTE_SURVIVE, 0.0);
+        } else {
+            C->R->wsum[ORC_W_LOSS] += q->w;
+            C->R->cnt[ORC_C_RR_KILL] += 1;
+            q->alive = 0;
+            o_trace(C, q, ORC_EV_ROULETTE_KILL, 0.0);
+        }
+    }
+}
+
+/* coarse space-time(-group) cell of a point, for the importance estimate */
+static int64_t o_imp_cell(o_ctx *C, const o_part *q)
+{
+    const orc_problem *P = C->P;
+    int ix[4];
+    for (int a = 0; a < 4; ++a) {
+        double x = a < 3 ? q->p[a] : q->t;
+        double lo = a < 3 ? P->outer_lo[a] : 0.0;
+        double hi = a < 3 ? P->outer_hi[a] : P->census[P->n_census - 1];
+        double f = (x - lo) * ((double)P->imp_n[a] / (hi - lo));
+        int i = (int)floor(f);
+        if (i < 0) i = 0;
+        if (i > P->imp_n[a] - 1) i = P->imp_n[a] - 1;
+        ix[a] = i;
+    }
+    int64_t c = q->g;
+    c = c * P->imp_n[3] + ix[3];
+    c = c * P->imp_n[2] + ix[2];
+    c = c * P->imp_n[1] + ix[1];
+    c = c * P->imp_n[0] + ix[0];
+    return c;
+}
+
+/* Forward importance estimate: every flight start in coarse cell c records
+ * the detector score reached so far; at the end of the history, cell c gains
+ * (final score - score at the point) per point and one unit of weight per
+ * point (analog runs: all weights are 1).  At most 16 distinct cells per
+ * history are kept; later new cells are dropped. */
+static void o_imp_point(o_ctx *C, const o_part *q)
+{
+    int64_t c = o_imp_cell(C, q);
+    for (int i = 0; i < C->n_imp; ++i) {
+        if (C->imp_cell[i] == c) {
+            C->imp_cnt[i] += 1.0;
+            C->imp_xsum[i] += C->xh;
+            return;
+        }
+    }
+    if (C->n_imp < 16) {
+        C->imp_cell[C->n_imp] = c;
+        C->imp_cnt[C->n_imp] = 1.0;
+        C->imp_xsum[C->n_imp] = C->xh;
+        C->n_imp += 1;
+    }
+}
+
+/* One flight of particle q: the three candidate distances (census, surface,
+ * collision), the event with the tie order census < surface < collision,
+ * track-length scoring of the flight, the move of Fig. 2, and the event. */
+static void o_flight(o_ctx *C, o_part *q)
+{
+    const orc_problem *P = C->P;
+    orc_result *R = C->R;
+    C->events += 1;
+    if (C->events > P->max_events) { C->status = ORC_E_EVENT_CAP; q->alive = 0; return; }
+    R->cnt[ORC_C_FLIGHT] += 1;
+    if (P->imp_on) o_imp_point(C, q);
+
+    int mat = o_material(P, q->cell);
+    double sig_t = P->sigma_t[mat * P->G + q->g];
+    double v = P->speed[q->g];
+    double iu[3];
+    for (int a = 0; a < 3; ++a) iu[a] = q->u[a] != 0.0 ? 1.0 / q->u[a] : 0.0;
+
+    double tc = P->census[q->ci];
+    double d_t = (tc - q->t) * v;
+    int sax;
+    double spl;
+    double d_s = o_dist_surface(P, q->p, q->u, iu, &sax, &spl);
+    double d_c = O_INF;
+    o_stream st = o_part_stream(C, q);
+    if (sig_t > 0.0) {
+        double xi = o_draw(&st);
+        d_c = (-orc_log(xi)) / sig_t;
+    }
+    q->k = st.k;
+
+    int ev;
+    double d;
+    if (d_t <= d_s && d_t <= d_c) { ev = ORC_EV_CENSUS; d = d_t; }
+    else if (d_s <= d_c) { ev = ORC_EV_SURFACE; d = d_s; }
+    else { ev = ORC_EV_SCATTER; d = d_c; }
+
+    /* track-length scoring of [0, d] */
+    R->cnt[ORC_C_PIECE] += (uint64_t)o_score_mesh(&C->M, q->p, q->u, iu, q->t, v, d, q->w, q->g,
+                                                  R->tally_batch);
+    if (P->has_detector) {
+        double l = o_detector_len(P, q->p, q->u, iu, d);
+        if (l > 0.0) C->xh += q->w * l;
+    }
+    R->wsum[ORC_W_PATH] += q->w * d;
+
+    /* move (Fig. 2) */
+    q->p[0] = q->p[0] + q->u[0] * d;
+    q->p[1] = q->p[1] + q->u[1] * d;
+    q->p[2] = q->p[2] + q->u[2] * d;
+
+    if (ev == ORC_EV_CENSUS) {
+        q->t = tc;
+        if (q->ci == P->n_census - 1) {
+            R->wsum[ORC_W_TIME_END] += q->w;
+            R->cnt[ORC_C_TIME_END] += 1;
+            q->alive = 0;
+            o_trace(C, q, ORC_EV_TIME_END, d);
+        } else {
+            q->ci += 1;
+            R->cnt[ORC_C_CENSUS] += 1;
+            o_trace(C, q, ORC_EV_CENSUS, d);
+        }
+        return;
+    }
+    q->t = q->t + d / v;
+
+    if (ev == ORC_EV_SURFACE) {
+        q->p[sax] = spl;
+        R->cnt[ORC_C_SURFACE] += 1;
+        int face = o_boundary(P, q);
+        if (face >= 0) {
+            o_leak(C, q, face);
+            o_trace(C, q, ORC_EV_LEAK, d);
+            return;
+        }
+        q->cell = o_locate(P, q->p, q->u);
+        o_trace(C, q, ORC_EV_SURFACE, d);
+        if (P->ww_on) o_ww(C, q);
+        return;
+    }
+
+    /* collision */
+    R->cnt[ORC_C_COLLISION] += 1;
+    const double *ss_row = P->sigma_s + ((size_t)mat * P->G + q->g) * P->G;
+    double sig_s = 0.0;
+    for (int h = 0; h < P->G; ++h) sig_s = sig_s + ss_row[h];
+    st = o_part_stream(C, q);
+    if (!P->implicit_capture) {
+        double xi = o_draw(&st);
+        q->k = st.k;
+        if (!(xi * sig_t < sig_s)) {
+            R->wsum[ORC_W_ABSORB] += q->w;
+            R->cnt[ORC_C_ABSORB] += 1;
+            q->alive = 0;
+            o_trace(C, q, ORC_EV_ABSORB, d);
+            return;
+        }
+    } else {
+        double c = sig_s / sig_t;
+        double wn = q->w * c;
+        R->wsum[ORC_W_ABSORB] += q->w - wn;
+        q->w = wn;
+        if (q->w < P->w_cut) {
+            double xi = o_draw(&st);
+            q->k = st.k;
+            if (xi * P->w_surv < q->w) {
+                R->wsum[ORC_W_GAIN] += P->w_surv - q->w;
+                q->w = P->w_surv;
+                R->cnt[ORC_C_CUT_SURVIVE] += 1;
+            } else {
+                R->wsum[ORC_W_LOSS] += q->w;
+                R->cnt[ORC_C_CUT_KILL] += 1;
+                q->alive = 0;
+                o_trace(C, q, ORC_EV_CUTOFF_KILL, d);
+                return;
+            }
+        }
+    }
+    /* scatter: outgoing group by the cumulative row (first g' with
+     * xi * Sigma_s,g < C_g'), then an isotropic direction */
+    if (P->G > 1) {
+        double xi = o_draw(&st);
+        double target = xi * sig_s;
+        double cum = 0.0;
+        int gn = -1, last = 0;
+        for (int h = 0; h < P->G; ++h) {
+            cum = cum + ss_row[h];
+            if (ss_row[h] > 0.0) last = h;
+            if (gn < 0 && target < cum) gn = h;
+        }
+        q->g = gn >= 0 ? gn : last;
+    }
+    o_direction(&st, q->u);
+    q->k = st.k;
+    o_trace(C, q, ORC_EV_SCATTER, d);
+    if (P->ww_on) o_ww(C, q);
+}
+
+/* Source particle of history h: position (box: lo + xi (hi-lo) per axis x,y,z),
+ * time (t0 + xi (t1-t0) when t1 > t0), direction (isotropic or fixed), group,
+ * unit weight; then the cell, and an immediate leak when the point lies on
+ * the outer boundary moving out. */
+static void o_source(o_ctx *C, o_part *q)
+{
+    const orc_problem *P = C->P;
+    memset(q, 0, sizeof(*q));
+    q->tag = 0;
+    q->k = 0;
+    q->seq = 0;
+    o_stream st = o_part_stream(C, q);
+    if (P->src_box) {
+        for (int a = 0; a < 3; ++a) q->p[a] = P->src_lo[a] + o_draw(&st) * (P->src_hi[a] - P->src_lo[a]);
+    } else {
+        for (int a = 0; a < 3; ++a) q->p[a] = P->src_lo[a];
+    }
+    q->t = P->src_t0;
+    if (P->src_t1 > P->src_t0) q->t = P->src_t0 + o_draw(&st) * (P->src_t1 - P->src_t0);
+    if (P->src_isotropic) o_direction(&st, q->u);
+    else for (int a = 0; a < 3; ++a) q->u[a] = P->src_dir[a];
+    q->g = P->src_group;
+    q->w = 1.0;
+    q->k = st.k;
+    q->alive = 1;
+    q->ci = 0;
+    while (q->ci < P->n_census && !(P->census[q->ci] > q->t)) q->ci += 1;
+    C->R->cnt[ORC_C_PARTICLE] += 1;
+    C->R->wsum[ORC_W_SOURCE] += q->w;
+    q->cell = o_locate(P, q->p, q->u);
+    if (q->ci >= P->n_census) {               /* born after the end time */
+        C->R->wsum[ORC_W_TIME_END] += q->w;
+        C->R->cnt[ORC_C_TIME_END] += 1;
+        q->alive = 0;
+        o_trace(C, q, ORC_EV_TIME_END, 0.0);
+        return;
+    }
+    for (int a = 0; a < 3; ++a) {
+        if (!o_axis_in(P->outer_lo[a], P->outer_hi[a], q->p[a], q->u[a])) {
+            o_leak(C, q, 2 * a + (q->p[a] >= P->outer_hi[a] ? 1 : 0));
+            o_trace(C, q, ORC_EV_LEAK, 0.0);
+            return;
+        }
+    }
+    o_trace(C, q, ORC_EV_SOURCE, 0.0);
+}
+
+static int o_history(o_ctx *C, uint64_t h, uint64_t slot)
+{
+    orc_result *R = C->R;
+    C->hist = h;
+    C->xh = 0.0;
+    C->events = 0;
+    C->sp = 0;
+    C->n_imp = 0;
+    R->cnt[ORC_C_HIST] += 1;
+    o_part q;
+    o_source(C, &q);
+    for (;;) {
+        while (q.alive && C->status == ORC_OK) o_flight(C, &q);
+        if (C->status != ORC_OK) return C->status;
+        if (C->sp == 0) break;
+        q = C->stack[--C->sp];
+        q.alive = 1;
+    }
+    R->det[0] += C->xh;
+    R->det[1] += C->xh * C->xh;
+    if (C->xh > 0.0) R->cnt[ORC_C_DET_HIT] += 1;
+    if (R->hist_xh) R->hist_xh[slot] = C->xh;
+    if (C->P->imp_on) {
+        for (int i = 0; i < C->n_imp; ++i) {
+            R->imp_score[C->imp_cell[i]] += C->imp_cnt[i] * C->xh - C->imp_xsum[i];
+            R->imp_weight[C->imp_cell[i]] += C->imp_cnt[i];
+        }
+    }
+    return ORC_OK;
+}
+
+static int o_validate(const orc_problem *P)
+{
+    if (P->G < 1 || P->G > 16 || P->n_mat < 1 || P->n_census < 1) return ORC_E_INVALID;
+    if (P->src_group < 0 || P->src_group >= P->G) return ORC_E_INVALID;
+    for (int a = 0; a < 4; ++a)
+        if (P->mesh_n[a] < 1) return ORC_E_INVALID;
+    for (int i = 1; i < P->n_census; ++i)
+        if (!(P->census[i] > P->census[i - 1])) return ORC_E_INVALID;
+    if (P->n_batches < 1 || P->stack_cap < 0) return ORC_E_INVALID;
+    if (P->ww_on && (P->ww_hidden < 1 || P->ww_hidden > 256 || P->ww_nmax < 2 || !P->ww_params))
+        return ORC_E_INVALID;
+    if ((P->ww_on || P->imp_on) && (isinf(P->outer_lo[0]) || isinf(P->outer_lo[1]) ||
+                                    isinf(P->outer_lo[2]) || isinf(P->outer_hi[0]) ||
+                                    isinf(P->outer_hi[1]) || isinf(P->outer_hi[2])))
+        return ORC_E_INVALID;
+    if (P->imp_on && (P->ww_on || P->implicit_capture)) return ORC_E_INVALID;
+    return ORC_OK;
+}
+
+int orc_run(const orc_problem *P, uint64_t seed, uint64_t hist0, uint64_t n_hist, orc_result *R)
+{
+    int st = o_validate(P);
+    if (st != ORC_OK) return st;
+    o_ctx C;
+    memset(&C, 0, sizeof(C));
+    C.P = P;
+    C.M = o_mesh_make(P);
+    C.R = R;
+    C.seed = seed;
+    C.status = ORC_OK;
+    C.stack = (o_part *)malloc(sizeof(o_part) * (size_t)(P->stack_cap > 0 ? P->stack_cap : 1));
+    for (int a = 0; a < 3; ++a) {
+        C.ww_lo[a] = P->outer_lo[a];
+        C.ww_inv[a] = 1.0 / (P->outer_hi[a] - P->outer_lo[a]);
+    }
+    C.ww_lo[3] = 0.0;
+    C.ww_inv[3] = 1.0 / P->census[P->n_census - 1];
+    size_t nbins = (size_t)C.M.G_t * P->mesh_n[0] * P->mesh_n[1] * P->mesh_n[2] * P->mesh_n[3];
+    const uint64_t B = (uint64_t)P->n_batches;
+    for (uint64_t b = 0; b < B; ++b) {
+        uint64_t lo = (b * n_hist) / B, hi = ((b + 1) * n_hist) / B;
+        if (hi == lo) continue;
+        for (uint64_t i = lo; i < hi; ++i) {
+            st = o_history(&C, hist0 + i, i);
+            if (st != ORC_OK) { free(C.stack); return st; }
+        }
+        double nb = (double)(hi - lo);
+        for (size_t i = 0; i < nbins; ++i) {
+            double sb = R->tally_batch[i];
+            if (sb != 0.0) {
+                R->tally_sum[i] += sb;
+                R->tally_sumsq[i] += sb * sb / nb;
+                R->tally_batch[i] = 0.0;
+            }
+        }
+        R->batches_done += 1;
+    }
+    R->hist_done += n_hist;
+    free(C.stack);
+    return ORC_OK;
+}

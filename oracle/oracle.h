@@ -1,0 +1,141 @@
+/*
+ * CPU oracle for the fixed-source, time-dependent Monte Carlo transport loop
+ * (scatter + absorb, no fission).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library includes, links
+ * or calls this code; only the tests, the smoke check and the CPU-baseline leg
+ * of the benchmark do.  It shares no source with the GPU path.
+ *
+ * The oracle is single threaded, processes histories in id order, and adds
+ * every tally contribution with a plain `+=` in event order (the CPU variant of
+ * the tally add in Fig. 3 of the paper).  Its per-history trajectories are the
+ * definition the GPU kernels must reproduce bit for bit; its tallies are unique
+ * up to summation order.
+ */
+#ifndef MCDC_ORACLE_H
+#define MCDC_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    ORC_OK = 0,
+    ORC_E_INVALID = -1,
+    ORC_E_EVENT_CAP = -4,
+    ORC_E_STACK = -7,
+};
+
+/* trace record types */
+enum {
+    ORC_EV_SOURCE = 0,
+    ORC_EV_SCATTER = 1,
+    ORC_EV_ABSORB = 2,
+    ORC_EV_SURFACE = 3,
+    ORC_EV_LEAK = 4,
+    ORC_EV_CENSUS = 5,
+    ORC_EV_TIME_END = 6,
+    ORC_EV_SPLIT = 7,
+    ORC_EV_ROULETTE_KILL = 8,
+    ORC_EV_ROULETTE_SURVIVE = 9,
+    ORC_EV_CUTOFF_KILL = 10,
+    ORC_EV_CUTOFF_SURVIVE = 11,
+};
+
+/* counters */
+enum {
+    ORC_C_HIST = 0, ORC_C_FLIGHT, ORC_C_PIECE, ORC_C_COLLISION, ORC_C_ABSORB,
+    ORC_C_SURFACE, ORC_C_LEAK, ORC_C_CENSUS, ORC_C_TIME_END, ORC_C_SPLIT,
+    ORC_C_RR_KILL, ORC_C_RR_SURVIVE, ORC_C_CUT_KILL, ORC_C_CUT_SURVIVE,
+    ORC_C_DET_HIT, ORC_C_PARTICLE, ORC_NCOUNT
+};
+/* weight sums */
+enum {
+    ORC_W_SOURCE = 0, ORC_W_LEAK, ORC_W_ABSORB, ORC_W_TIME_END, ORC_W_GAIN,
+    ORC_W_LOSS, ORC_W_PATH, ORC_NWSUM
+};
+
+typedef struct {
+    double outer_lo[3], outer_hi[3];
+    int32_t bc[6];                    /* -x,+x,-y,+y,-z,+z: 0 vacuum, 1 reflective */
+    int32_t n_boxes;
+    const double *box_lo, *box_hi;    /* [n_boxes][3] */
+    const int32_t *box_mat;
+    int32_t background_mat;
+    int32_t n_mat, G;
+    const double *sigma_t;            /* [n_mat][G] */
+    const double *sigma_s;            /* [n_mat][G][G] from-group rows */
+    const double *speed;              /* [G] */
+    int32_t src_box;                  /* 0 point, 1 box */
+    double src_lo[3], src_hi[3], src_t0, src_t1;
+    int32_t src_isotropic;
+    double src_dir[3];
+    int32_t src_group;
+    double mesh_lo[4], mesh_hi[4];
+    int32_t mesh_n[4];
+    int32_t mesh_per_group;
+    int32_t n_census;
+    const double *census;
+    int32_t implicit_capture;
+    double w_cut, w_surv;
+    int32_t has_detector;
+    double det_lo[3], det_hi[3];
+    int32_t imp_on;
+    int32_t imp_n[4];
+    int32_t ww_on, ww_hidden, ww_nmax;
+    const float *ww_params;
+    double ww_logk, ww_ratio;
+    int32_t n_batches;
+    int64_t max_events;
+    int32_t stack_cap;
+    uint32_t problem_id;
+} orc_problem;
+
+typedef struct {
+    uint64_t hist;
+    uint32_t tag, seq;
+    int32_t type, g, cell;
+    uint32_t k;
+    double x, y, z, t, ux, uy, uz, w, aux;
+} orc_trace_rec;
+
+typedef struct {
+    double *tally_batch;      /* [nbins] current batch (scratch, zero on entry) */
+    double *tally_sum;        /* [nbins] sum over batches of S_b              */
+    double *tally_sumsq;      /* [nbins] sum over batches of S_b^2 / N_b      */
+    double det[2];            /* sum x_h, sum x_h^2 over histories            */
+    double leak[6];
+    double wsum[ORC_NWSUM];
+    uint64_t cnt[ORC_NCOUNT];
+    double *imp_score;        /* [coarse cells] or NULL */
+    double *imp_weight;
+    double *hist_xh;          /* [n_hist] per-history detector score or NULL */
+    orc_trace_rec *trace;     /* or NULL */
+    int64_t trace_cap, trace_n;
+    int64_t batches_done;
+    uint64_t hist_done;
+} orc_result;
+
+int orc_run(const orc_problem *P, uint64_t seed, uint64_t hist0, uint64_t n_hist,
+            orc_result *R);
+
+/* primitives exposed for the pin tests */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+double orc_uniform(uint64_t seed, uint64_t hist, uint32_t problem, uint32_t tag, uint32_t k);
+double orc_log(double x);
+double orc_exp(double x);
+/* n isotropic directions from one stream; returns the draws consumed */
+uint32_t orc_directions(uint64_t seed, uint64_t hist, uint32_t n, double *u);
+/* FP32 MLP forward as used by the weight-window check */
+float orc_mlp_f32(const float *params, int32_t in_dim, int32_t hidden, const float *in);
+/* track-length scoring of one straight segment into a mesh (same rules as the
+ * transport loop); returns the number of scored pieces */
+int64_t orc_score_segment(const orc_problem *P, const double p[3], const double u[3],
+                          double t0, double d, double w, int32_t g, double *tally);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

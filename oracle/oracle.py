@@ -1,0 +1,345 @@
+"""ctypes front end of the CPU oracle.  TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the smoke check and the CPU-baseline leg of the benchmark use
+this module.  It marshals the problem dicts built by
+``paper_2409_04668_amd.workloads`` into the oracle's own C structs (declared
+again here, independently of the GPU library's header) and returns numpy
+results.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+
+CFLAGS = ["-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+          "-Wall", "-Wno-unused-function"]
+
+NCOUNT = 16
+NWSUM = 7
+COUNTER_NAMES = ["hist", "flight", "piece", "collision", "absorb", "surface", "leak",
+                 "census", "time_end", "split", "rr_kill", "rr_survive", "cut_kill",
+                 "cut_survive", "det_hit", "particle"]
+WSUM_NAMES = ["source", "leak", "absorb", "time_end", "gain", "loss", "path"]
+
+EV = dict(source=0, scatter=1, absorb=2, surface=3, leak=4, census=5, time_end=6, split=7,
+          roulette_kill=8, roulette_survive=9, cutoff_kill=10, cutoff_survive=11)
+
+
+def build(force: bool = True) -> str:
+    src = os.path.join(HERE, "oracle.c")
+    if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(src):
+        tmp = LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, src, "-lm"])
+        os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+D3 = C.c_double * 3
+D4 = C.c_double * 4
+I4 = C.c_int32 * 4
+I6 = C.c_int32 * 6
+PD = C.POINTER(C.c_double)
+PI = C.POINTER(C.c_int32)
+PF = C.POINTER(C.c_float)
+
+
+class OrcProblem(C.Structure):
+    _fields_ = [
+        ("outer_lo", D3), ("outer_hi", D3), ("bc", I6),
+        ("n_boxes", C.c_int32), ("box_lo", PD), ("box_hi", PD), ("box_mat", PI),
+        ("background_mat", C.c_int32), ("n_mat", C.c_int32), ("G", C.c_int32),
+        ("sigma_t", PD), ("sigma_s", PD), ("speed", PD),
+        ("src_box", C.c_int32), ("src_lo", D3), ("src_hi", D3), ("src_t0", C.c_double),
+        ("src_t1", C.c_double), ("src_isotropic", C.c_int32), ("src_dir", D3),
+        ("src_group", C.c_int32),
+        ("mesh_lo", D4), ("mesh_hi", D4), ("mesh_n", I4), ("mesh_per_group", C.c_int32),
+        ("n_census", C.c_int32), ("census", PD),
+        ("implicit_capture", C.c_int32), ("w_cut", C.c_double), ("w_surv", C.c_double),
+        ("has_detector", C.c_int32), ("det_lo", D3), ("det_hi", D3),
+        ("imp_on", C.c_int32), ("imp_n", I4),
+        ("ww_on", C.c_int32), ("ww_hidden", C.c_int32), ("ww_nmax", C.c_int32),
+        ("ww_params", PF), ("ww_logk", C.c_double), ("ww_ratio", C.c_double),
+        ("n_batches", C.c_int32), ("max_events", C.c_int64), ("stack_cap", C.c_int32),
+        ("problem_id", C.c_uint32),
+    ]
+
+
+class OrcTraceRec(C.Structure):
+    _fields_ = [("hist", C.c_uint64), ("tag", C.c_uint32), ("seq", C.c_uint32),
+                ("type", C.c_int32), ("g", C.c_int32), ("cell", C.c_int32), ("k", C.c_uint32),
+                ("x", C.c_double), ("y", C.c_double), ("z", C.c_double), ("t", C.c_double),
+                ("ux", C.c_double), ("uy", C.c_double), ("uz", C.c_double), ("w", C.c_double),
+                ("aux", C.c_double)]
+
+
+TRACE_DTYPE = np.dtype([("hist", "<u8"), ("tag", "<u4"), ("seq", "<u4"), ("type", "<i4"),
+                        ("g", "<i4"), ("cell", "<i4"), ("k", "<u4"), ("x", "<f8"), ("y", "<f8"),
+                        ("z", "<f8"), ("t", "<f8"), ("ux", "<f8"), ("uy", "<f8"), ("uz", "<f8"),
+                        ("w", "<f8"), ("aux", "<f8")])
+assert TRACE_DTYPE.itemsize == C.sizeof(OrcTraceRec)
+
+
+class OrcResult(C.Structure):
+    _fields_ = [("tally_batch", PD), ("tally_sum", PD), ("tally_sumsq", PD),
+                ("det", C.c_double * 2), ("leak", C.c_double * 6), ("wsum", C.c_double * NWSUM),
+                ("cnt", C.c_uint64 * NCOUNT), ("imp_score", PD), ("imp_weight", PD),
+                ("hist_xh", PD), ("trace", C.POINTER(OrcTraceRec)), ("trace_cap", C.c_int64),
+                ("trace_n", C.c_int64), ("batches_done", C.c_int64), ("hist_done", C.c_uint64)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = C.CDLL(LIB_PATH)
+        L.orc_run.argtypes = [C.POINTER(OrcProblem), C.c_uint64, C.c_uint64, C.c_uint64,
+                              C.POINTER(OrcResult)]
+        L.orc_run.restype = C.c_int
+        L.orc_philox4x32_10.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32),
+                                        C.POINTER(C.c_uint32)]
+        L.orc_philox4x32_10.restype = None
+        L.orc_uniform.argtypes = [C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32]
+        L.orc_uniform.restype = C.c_double
+        L.orc_log.argtypes = [C.c_double]
+        L.orc_log.restype = C.c_double
+        L.orc_exp.argtypes = [C.c_double]
+        L.orc_exp.restype = C.c_double
+        L.orc_directions.argtypes = [C.c_uint64, C.c_uint64, C.c_uint32, PD]
+        L.orc_directions.restype = C.c_uint32
+        L.orc_mlp_f32.argtypes = [PF, C.c_int32, C.c_int32, PF]
+        L.orc_mlp_f32.restype = C.c_float
+        L.orc_score_segment.argtypes = [C.POINTER(OrcProblem), PD, PD, C.c_double, C.c_double,
+                                        C.c_double, C.c_int32, PD]
+        L.orc_score_segment.restype = C.c_int64
+        _lib = L
+    return _lib
+
+
+def _pd(a):
+    return a.ctypes.data_as(PD)
+
+
+class _Problem:
+    """Holds the C struct and keeps the numpy buffers it points to alive."""
+
+    def __init__(self, prob: dict, problem_id: int = 0):
+        self.keep = []
+        s = OrcProblem()
+
+        def arr(x, dt):
+            a = np.ascontiguousarray(np.asarray(x, dtype=dt))
+            self.keep.append(a)
+            return a
+
+        s.outer_lo = D3(*[float(v) for v in prob["outer_lo"]])
+        s.outer_hi = D3(*[float(v) for v in prob["outer_hi"]])
+        s.bc = I6(*[int(v) for v in prob["bc"]])
+        nb = int(np.asarray(prob["box_mat"]).size)
+        s.n_boxes = nb
+        blo = arr(np.asarray(prob["box_lo"], float).reshape(-1, 3) if nb else np.zeros((1, 3)), np.float64)
+        bhi = arr(np.asarray(prob["box_hi"], float).reshape(-1, 3) if nb else np.zeros((1, 3)), np.float64)
+        bm = arr(prob["box_mat"] if nb else np.zeros(1), np.int32)
+        s.box_lo, s.box_hi, s.box_mat = _pd(blo), _pd(bhi), bm.ctypes.data_as(PI)
+        s.background_mat = int(prob["background_mat"])
+        st = arr(prob["sigma_t"], np.float64)
+        M, G = st.shape
+        s.n_mat, s.G = M, G
+        ss = arr(np.asarray(prob["sigma_s"], float).reshape(M, G, G), np.float64)
+        sp = arr(prob["speed"], np.float64)
+        s.sigma_t, s.sigma_s, s.speed = _pd(st), _pd(ss), _pd(sp)
+        src = prob["source"]
+        s.src_box = 1 if src["kind"] == "box" else 0
+        s.src_lo = D3(*[float(v) for v in src["lo"]])
+        s.src_hi = D3(*[float(v) for v in src["hi"]])
+        s.src_t0, s.src_t1 = float(src["t0"]), float(src["t1"])
+        s.src_isotropic = 1 if src["isotropic"] else 0
+        s.src_dir = D3(*[float(v) for v in src["dir"]])
+        s.src_group = int(src["group"])
+        m = prob["mesh"]
+        s.mesh_lo = D4(*[float(v) for v in m["lo"]])
+        s.mesh_hi = D4(*[float(v) for v in m["hi"]])
+        s.mesh_n = I4(*[int(v) for v in m["n"]])
+        s.mesh_per_group = 1 if m["per_group"] else 0
+        cen = arr(prob["census"], np.float64)
+        s.n_census, s.census = cen.size, _pd(cen)
+        s.implicit_capture = 1 if prob["implicit_capture"] else 0
+        s.w_cut, s.w_surv = float(prob["w_cut"]), float(prob["w_surv"])
+        det = prob.get("detector")
+        s.has_detector = 1 if det is not None else 0
+        if det is not None:
+            s.det_lo = D3(*[float(v) for v in det["lo"]])
+            s.det_hi = D3(*[float(v) for v in det["hi"]])
+        imp = prob.get("importance")
+        s.imp_on = 1 if imp is not None else 0
+        if imp is not None:
+            s.imp_n = I4(*[int(v) for v in imp["n"]])
+        ww = prob.get("ww")
+        s.ww_on = 1 if ww is not None else 0
+        if ww is not None:
+            prm = arr(ww["params"], np.float32)
+            s.ww_params = prm.ctypes.data_as(PF)
+            s.ww_hidden = int(ww.get("hidden", 64))
+            s.ww_nmax = int(ww.get("n_max", 10))
+            s.ww_logk = float(ww["logk"])
+            s.ww_ratio = float(ww.get("ratio", 5.0))
+        s.n_batches = int(prob["n_batches"])
+        s.max_events = int(prob["max_events"])
+        s.stack_cap = int(prob["stack_cap"])
+        s.problem_id = problem_id
+        self.s = s
+        mn = [int(v) for v in m["n"]]
+        self.nbins = (G if m["per_group"] else 1) * mn[0] * mn[1] * mn[2] * mn[3]
+        self.n_imp = G * int(np.prod(imp["n"])) if imp is not None else 0
+
+
+class OracleError(RuntimeError):
+    def __init__(self, status):
+        super().__init__(f"oracle returned status {status}")
+        self.status = status
+
+
+class OracleRun:
+    """Accumulating oracle state for one problem (mirrors create/run/get)."""
+
+    def __init__(self, prob: dict, problem_id: int = 0):
+        self.prob = prob
+        self.P = _Problem(prob, problem_id)
+        nb = self.P.nbins
+        self.tally_batch = np.zeros(nb)
+        self.tally_sum = np.zeros(nb)
+        self.tally_sumsq = np.zeros(nb)
+        self.imp_score = np.zeros(max(self.P.n_imp, 1))
+        self.imp_weight = np.zeros(max(self.P.n_imp, 1))
+        self.R = OrcResult()
+        self.R.tally_batch, self.R.tally_sum, self.R.tally_sumsq = (
+            _pd(self.tally_batch), _pd(self.tally_sum), _pd(self.tally_sumsq))
+        if self.P.n_imp:
+            self.R.imp_score, self.R.imp_weight = _pd(self.imp_score), _pd(self.imp_weight)
+        self.n_hist = 0
+        self.last_seconds = 0.0
+
+    def run(self, n_hist: int, seed: int, trace_cap: int = 0, per_history: bool = False):
+        """Transport ``n_hist`` histories with ids continuing from earlier runs.
+        Returns (trace records, per-history detector scores) when asked."""
+        trace = None
+        xh = None
+        if trace_cap:
+            trace = np.zeros(trace_cap, TRACE_DTYPE)
+            self.R.trace = trace.ctypes.data_as(C.POINTER(OrcTraceRec))
+            self.R.trace_cap = trace_cap
+            self.R.trace_n = 0
+        else:
+            self.R.trace = C.POINTER(OrcTraceRec)()
+            self.R.trace_cap = 0
+            self.R.trace_n = 0
+        if per_history:
+            xh = np.zeros(n_hist)
+            self.R.hist_xh = _pd(xh)
+        else:
+            self.R.hist_xh = PD()
+        t0 = time.perf_counter()
+        st = lib().orc_run(C.byref(self.P.s), seed, self.n_hist, n_hist, C.byref(self.R))
+        self.last_seconds = time.perf_counter() - t0
+        if st != 0:
+            raise OracleError(st)
+        self.n_hist += n_hist
+        if trace is not None:
+            trace = trace[: self.R.trace_n].copy()
+        return trace, xh
+
+    # ---- results -------------------------------------------------------
+    @property
+    def counters(self) -> dict:
+        return {k: int(self.R.cnt[i]) for i, k in enumerate(COUNTER_NAMES)}
+
+    @property
+    def wsum(self) -> dict:
+        return {k: float(self.R.wsum[i]) for i, k in enumerate(WSUM_NAMES)}
+
+    @property
+    def leak(self) -> np.ndarray:
+        return np.array(self.R.leak[:])
+
+    @property
+    def detector(self):
+        """(sum x_h, sum x_h^2) over histories."""
+        return float(self.R.det[0]), float(self.R.det[1])
+
+    def mesh_stats(self):
+        """Per-bin mean score per source particle and its standard error from
+        batch means (weighted form for unequal batches)."""
+        N = float(self.n_hist)
+        B = int(self.R.batches_done)
+        mean = self.tally_sum / N
+        if B < 2:
+            return mean, np.full_like(mean, np.nan)
+        var = (self.tally_sumsq - N * mean * mean) / ((B - 1) * N)
+        return mean, np.sqrt(np.maximum(var, 0.0))
+
+    def detector_stats(self):
+        """Mean detector score per history and its standard error."""
+        N = float(self.n_hist)
+        s1, s2 = self.detector
+        m = s1 / N
+        var = (s2 / N - m * m) / (N - 1.0) if N > 1 else float("nan")
+        return m, float(np.sqrt(max(var, 0.0)))
+
+
+def run(prob: dict, n_hist: int, seed: int, **kw) -> OracleRun:
+    r = OracleRun(prob)
+    r.run(n_hist, seed, **kw)
+    return r
+
+
+# ---- primitives ------------------------------------------------------------
+
+def philox(ctr, key):
+    c = (C.c_uint32 * 4)(*ctr)
+    k = (C.c_uint32 * 2)(*key)
+    o = (C.c_uint32 * 4)()
+    lib().orc_philox4x32_10(c, k, o)
+    return list(o)
+
+
+def uniform(seed, hist, problem, tag, k):
+    return lib().orc_uniform(seed, hist, problem, tag, k)
+
+
+def log(x):
+    return lib().orc_log(float(x))
+
+
+def exp(x):
+    return lib().orc_exp(float(x))
+
+
+def directions(seed, hist, n):
+    u = np.zeros((n, 3))
+    k = lib().orc_directions(seed, hist, n, _pd(u))
+    return u, int(k)
+
+
+def mlp_f32(params, in_dim, hidden, x):
+    p = np.ascontiguousarray(params, np.float32)
+    xx = np.ascontiguousarray(x, np.float32)
+    return float(lib().orc_mlp_f32(p.ctypes.data_as(PF), in_dim, hidden, xx.ctypes.data_as(PF)))
+
+
+def score_segment(prob, p, u, t0, d, w=1.0, g=0):
+    P = _Problem(prob)
+    tally = np.zeros(P.nbins)
+    pp = np.ascontiguousarray(p, float)
+    uu = np.ascontiguousarray(u, float)
+    n = lib().orc_score_segment(C.byref(P.s), _pd(pp), _pd(uu), t0, d, w, g, _pd(tally))
+    return tally, int(n)
