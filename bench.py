@@ -1,0 +1,150 @@
+"""Benchmark: histories/s of the analog time-dependent transport loop on the
+3D duct problem (60x100x60 cm box, bent 10x10 cm void duct, 1 cm mesh x 20
+time bins = 7.2e6 FP64 bins, 1e8 histories per step) on one MI355X.
+
+One step = one mcdc_run of 1e8 source histories: 20 batches, each one launch
+of the tracking kernel plus one batch close-out launch, with all inputs
+resident in HBM.  Prints one JSON line with the roofline of the tracking
+kernel (algorithmic bytes = 16 B per FP64 atomic tally update, i.e. per scored
+piece, against the 8 TB/s HBM peak) and the CPU oracle timed on a bounded
+sample of the same workload on this host.
+
+    python bench.py [--gpus 1] [--steps 5] [--warmup 1]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_PIECE = 16.0          # FP64 atomic read-modify-write: 8 B read + 8 B written
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_history_duct_1e8_pmc.txt")
+KERNEL_SOURCES = ["transport_device.hpp", "mcdc_history.hip", "mcdc_internal.hpp"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2409_04668_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per tracking launch from the committed rocprofv3 PMC summary,
+    or None if there is none or the kernel changed since it was taken."""
+    if not os.path.exists(PMC_SUMMARY):
+        return None
+    vals = {}
+    with open(PMC_SUMMARY) as f:
+        for line in f:
+            if ":" in line:
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_sha") != kernel_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(prob, n_sample, seed):
+    from oracle import oracle as O
+    O.build(force=False)
+    r = O.OracleRun(prob)
+    r.run(n_sample, seed)
+    return dict(value=n_sample / r.last_seconds, unit="histories/s", cores=1, kind="oracle",
+                sample=f"{n_sample} histories of the same duct problem, single-threaded C oracle, "
+                       f"{r.last_seconds:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--histories", type=int, default=100_000_000)
+    ap.add_argument("--schedule", choices=["history", "event"], default="history")
+    ap.add_argument("--waves-per-cu", type=int, default=0)
+    ap.add_argument("--cpu-sample", type=int, default=400_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(histories shard by id range across GPUs; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2409_04668_amd import mcdc
+    from paper_2409_04668_amd import workloads as W
+
+    prob = W.config2()
+    sched = mcdc.SCHED_HISTORY if args.schedule == "history" else mcdc.SCHED_EVENT
+    gp = mcdc.Problem(prob, mcdc.make_options(sched, waves_per_cu=args.waves_per_cu))
+    N = args.histories
+    seed = 20260001
+    for i in range(args.warmup):
+        gp.run(N, seed + i)
+    torch.cuda.synchronize()
+    c0 = gp.counters()
+    gp.kernel_time()                       # drop warm-up launches
+    gp.set_kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        gp.run(N, seed + args.warmup + i)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    gp.set_kernel_timing(False)
+    launches, kms = gp.kernel_time()
+    c1 = gp.counters()
+    T = t1 - t0
+    n_done = args.steps * N
+    pieces = c1["pieces"] - c0["pieces"]
+    avg_launch_s = kms / 1e3 / max(launches, 1)
+    bytes_per_launch = BYTES_PER_PIECE * pieces / max(launches, 1)
+    achieved = bytes_per_launch / avg_launch_s / 1e9
+    traffic = measured_traffic()
+    det_mean, det_rel = gp.tallies(mcdc.TALLY_DETECTOR)
+    out = {
+        "metric": "histories/s (analog, FP64 tallies) on the 3D duct problem",
+        "value": n_done / T,
+        "unit": "histories/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * T / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "3D duct 60x100x60 cm, 1 group, 1 cm mesh x 20 t-bins "
+                               "(7.2e6 FP64 bins), analog, 1e8 histories per step",
+                   "histories_per_step": N, "schedule": args.schedule,
+                   "tally_bins": W.n_bins(prob)},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_history", "launches": launches,
+                     "avg_launch_ms": 1e3 * avg_launch_s,
+                     "algorithmic_bytes_per_launch": bytes_per_launch,
+                     "atomic_updates_per_s": pieces / (kms / 1e3) if kms > 0 else None},
+        "pieces_per_history": pieces / n_done,
+        "flights_per_history": (c1["flights"] - c0["flights"]) / n_done,
+        "detector": {"mean": float(det_mean[0]), "rel_err": float(det_rel[0])},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_sample, seed)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

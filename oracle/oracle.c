@@ -492,7 +492,7 @@ typedef struct {
     o_mesh M;
     orc_result *R;
     uint64_t seed, hist;
-    double xh;
+    double xh, path_h;
     int64_t events;
     o_part *stack;
     int sp;
@@ -711,6 +711,7 @@ static void o_flight(o_ctx *C, o_part *q)
         if (l > 0.0) C->xh += q->w * l;
     }
     R->wsum[ORC_W_PATH] += q->w * d;
+    C->path_h += q->w * d;
 
     /* move (Fig. 2) */
     q->p[0] = q->p[0] + q->u[0] * d;
@@ -857,6 +858,7 @@ static int o_history(o_ctx *C, uint64_t h, uint64_t slot)
     orc_result *R = C->R;
     C->hist = h;
     C->xh = 0.0;
+    C->path_h = 0.0;
     C->events = 0;
     C->sp = 0;
     C->n_imp = 0;
@@ -873,7 +875,10 @@ static int o_history(o_ctx *C, uint64_t h, uint64_t slot)
     R->det[0] += C->xh;
     R->det[1] += C->xh * C->xh;
     if (C->xh > 0.0) R->cnt[ORC_C_DET_HIT] += 1;
-    if (R->hist_xh) R->hist_xh[slot] = C->xh;
+    if (R->hist_xh) {
+        R->hist_xh[2 * slot] = C->xh;
+        R->hist_xh[2 * slot + 1] = C->path_h;
+    }
     if (C->P->imp_on) {
         for (int i = 0; i < C->n_imp; ++i) {
             R->imp_score[C->imp_cell[i]] += C->imp_cnt[i] * C->xh - C->imp_xsum[i];

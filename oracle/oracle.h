@@ -111,7 +111,7 @@ typedef struct {
     uint64_t cnt[ORC_NCOUNT];
     double *imp_score;        /* [coarse cells] or NULL */
     double *imp_weight;
-    double *hist_xh;          /* [n_hist] per-history detector score or NULL */
+    double *hist_xh;          /* [n_hist][2] per-history (detector score, sum of w*d) or NULL */
     orc_trace_rec *trace;     /* or NULL */
     int64_t trace_cap, trace_n;
     int64_t batches_done;

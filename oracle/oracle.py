@@ -229,9 +229,11 @@ class OracleRun:
         self.n_hist = 0
         self.last_seconds = 0.0
 
-    def run(self, n_hist: int, seed: int, trace_cap: int = 0, per_history: bool = False):
+    def run(self, n_hist: int, seed: int, trace_cap: int = 0, per_history: bool = False,
+            first_id: int | None = None):
         """Transport ``n_hist`` histories with ids continuing from earlier runs.
-        Returns (trace records, per-history detector scores) when asked."""
+        Returns (trace records, per-history [detector score, sum of w*d]) when
+        asked."""
         trace = None
         xh = None
         if trace_cap:
@@ -244,12 +246,13 @@ class OracleRun:
             self.R.trace_cap = 0
             self.R.trace_n = 0
         if per_history:
-            xh = np.zeros(n_hist)
+            xh = np.zeros((n_hist, 2))
             self.R.hist_xh = _pd(xh)
         else:
             self.R.hist_xh = PD()
         t0 = time.perf_counter()
-        st = lib().orc_run(C.byref(self.P.s), seed, self.n_hist, n_hist, C.byref(self.R))
+        h0 = self.n_hist if first_id is None else int(first_id)
+        st = lib().orc_run(C.byref(self.P.s), seed, h0, n_hist, C.byref(self.R))
         self.last_seconds = time.perf_counter() - t0
         if st != 0:
             raise OracleError(st)

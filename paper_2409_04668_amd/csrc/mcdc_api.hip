@@ -1,0 +1,567 @@
+// Host runtime behind the C ABI: validation, workspace carving, table upload,
+// batch loop and result read-back.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "mcdc_internal.hpp"
+#include "mcdc_runtime.hpp"
+
+namespace mcdc {
+
+thread_local std::string g_err;
+
+int fail(int st, const std::string &msg) {
+    g_err = msg;
+    return st;
+}
+
+int hip_fail(hipError_t e, const char *where) {
+    return fail(MCDC_E_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int validate_desc(const mcdc_problem_desc *d) {
+    if (!d) return fail(MCDC_E_INVALID, "null problem description");
+    if (d->G < 1 || d->G > MCDC_MAX_G) return fail(MCDC_E_INVALID, "G out of range");
+    if (d->n_mat < 1 || d->n_mat > MCDC_MAX_MAT) return fail(MCDC_E_INVALID, "n_mat out of range");
+    if (d->n_boxes < 0 || d->n_boxes > MCDC_MAX_BOXES) return fail(MCDC_E_INVALID, "n_boxes out of range");
+    if (d->n_boxes > 0 && (!d->box_lo || !d->box_hi || !d->box_mat))
+        return fail(MCDC_E_INVALID, "box arrays missing");
+    for (int b = 0; b < d->n_boxes; ++b)
+        if (d->box_mat[b] < 0 || d->box_mat[b] >= d->n_mat) return fail(MCDC_E_INVALID, "box material out of range");
+    if (d->background_mat < 0 || d->background_mat >= d->n_mat)
+        return fail(MCDC_E_INVALID, "background material out of range");
+    if (!d->sigma_t || !d->sigma_s || !d->speed || !d->census) return fail(MCDC_E_INVALID, "table missing");
+    for (int i = 0; i < d->n_mat * d->G; ++i)
+        if (!(d->sigma_t[i] >= 0.0)) return fail(MCDC_E_INVALID, "negative sigma_t");
+    for (int g = 0; g < d->G; ++g)
+        if (!(d->speed[g] > 0.0)) return fail(MCDC_E_INVALID, "speed must be positive");
+    if (d->src_group < 0 || d->src_group >= d->G) return fail(MCDC_E_INVALID, "source group out of range");
+    if (d->n_census < 1 || d->n_census > MCDC_MAX_CENSUS) return fail(MCDC_E_INVALID, "n_census out of range");
+    for (int i = 1; i < d->n_census; ++i)
+        if (!(d->census[i] > d->census[i - 1])) return fail(MCDC_E_INVALID, "census times must increase");
+    for (int a = 0; a < 4; ++a)
+        if (d->mesh_n[a] < 1) return fail(MCDC_E_INVALID, "mesh_n must be >= 1");
+    for (int a = 0; a < 3; ++a) {
+        const bool unb = isinf(d->mesh_lo[a]) && isinf(d->mesh_hi[a]);
+        if (unb && d->mesh_n[a] != 1) return fail(MCDC_E_INVALID, "unbounded mesh axis must have n=1");
+        if (!unb && !(d->mesh_hi[a] > d->mesh_lo[a])) return fail(MCDC_E_INVALID, "mesh bounds");
+    }
+    if (!(d->mesh_hi[3] > d->mesh_lo[3])) return fail(MCDC_E_INVALID, "mesh time bounds");
+    const double nb = (double)(d->mesh_per_group ? d->G : 1) * d->mesh_n[0] * d->mesh_n[1] *
+                      d->mesh_n[2] * d->mesh_n[3];
+    if (nb > 4.0e9) return fail(MCDC_E_INVALID, "tally too large (bins must fit 32 bits)");
+    if (d->n_batches < 1) return fail(MCDC_E_INVALID, "n_batches must be >= 1");
+    if (d->stack_cap < 0 || d->max_events < 1) return fail(MCDC_E_INVALID, "stack_cap/max_events");
+    if (d->imp_on) {
+        for (int a = 0; a < 4; ++a)
+            if (d->imp_n[a] < 1) return fail(MCDC_E_INVALID, "imp_n must be >= 1");
+        if (d->implicit_capture) return fail(MCDC_E_INVALID, "importance estimate needs analog collisions");
+    }
+    if (d->imp_on || d->stack_cap > 0)
+        for (int a = 0; a < 3; ++a)
+            if (isinf(d->outer_lo[a]) || isinf(d->outer_hi[a]))
+                return fail(MCDC_E_INVALID, "weight windows / importance need a finite outer box");
+    return MCDC_OK;
+}
+
+uint32_t desc_nbins(const mcdc_problem_desc *d) {
+    return (uint32_t)((d->mesh_per_group ? d->G : 1) * d->mesh_n[0] * d->mesh_n[1] * d->mesh_n[2] *
+                      d->mesh_n[3]);
+}
+
+size_t desc_nimp(const mcdc_problem_desc *d) {
+    return d->imp_on ? (size_t)d->G * d->imp_n[0] * d->imp_n[1] * d->imp_n[2] * d->imp_n[3] : 0;
+}
+
+Options resolve_options(const mcdc_options *o) {
+    Options r;
+    r.schedule = MCDC_SCHED_HISTORY;
+    r.block = 256;
+    r.waves_per_cu = 16;
+    r.lds_tally = 1;
+    r.event_chunk = 1 << 22;
+    if (o) {
+        if (o->schedule) r.schedule = o->schedule;
+        if (o->block) r.block = o->block;
+        if (o->waves_per_cu) r.waves_per_cu = o->waves_per_cu;
+        r.lds_tally = o->lds_tally;
+        if (o->event_chunk) r.event_chunk = o->event_chunk;
+    }
+    if (r.schedule == MCDC_SCHED_AUTO) r.schedule = MCDC_SCHED_HISTORY;
+    r.grid = history_grid(r.block, r.waves_per_cu);
+    r.n_lanes = (uint64_t)r.grid * r.block;
+    return r;
+}
+
+int check_options(const Options &o) {
+    if (o.block < 64 || o.block > 256 || o.block % 64) return fail(MCDC_E_INVALID, "block must be 64..256, a multiple of 64");
+    if (o.waves_per_cu < 1 || o.waves_per_cu > 64) return fail(MCDC_E_INVALID, "waves_per_cu out of range");
+    if (o.schedule != MCDC_SCHED_HISTORY && o.schedule != MCDC_SCHED_EVENT)
+        return fail(MCDC_E_INVALID, "unknown schedule");
+    return MCDC_OK;
+}
+
+Layout make_layout(const mcdc_problem_desc *d, const Options &o) {
+    Layout L;
+    size_t off = 0;
+    const size_t n_tab = (size_t)d->n_mat * d->G + (size_t)d->n_mat * d->G * d->G + d->G + d->n_census;
+    L.tables = off; off = align_up(off + n_tab * sizeof(double));
+    const size_t nb = desc_nbins(d);
+    L.tally_batch = off; off = align_up(off + nb * sizeof(double));
+    L.tally_sum = off; off = align_up(off + nb * sizeof(double));
+    L.tally_sumsq = off; off = align_up(off + nb * sizeof(double));
+    L.acc = off; off = align_up(off + sizeof(DevAcc));
+    const size_t ni = desc_nimp(d);
+    L.imp_score = off; off = align_up(off + ni * sizeof(double));
+    L.imp_weight = off; off = align_up(off + ni * sizeof(double));
+    L.ww_params = off; off = align_up(off + mcdc_mlp_param_count(4 + d->G) * sizeof(float));
+    const size_t cap = (size_t)d->stack_cap;
+    L.stk_d = off; off = align_up(off + 8 * cap * o.n_lanes * sizeof(double));
+    L.stk_i = off; off = align_up(off + 4 * cap * o.n_lanes * sizeof(int32_t));
+    L.imp_list = off;
+    if (d->imp_on) off = align_up(off + (size_t)kImpList * o.n_lanes * (sizeof(int32_t) + 2 * sizeof(double)));
+    L.event = off;
+    off += event_workspace_bytes(d, o);
+    L.total = align_up(off);
+    return L;
+}
+
+void build_dev_problem(const mcdc_problem_desc *d, char *ws, const Layout &L, DevProblem &P) {
+    memset(&P, 0, sizeof(P));
+    for (int a = 0; a < 3; ++a) {
+        P.outer_lo[a] = d->outer_lo[a];
+        P.outer_hi[a] = d->outer_hi[a];
+    }
+    for (int f = 0; f < 6; ++f) P.bc[f] = d->bc[f];
+    P.n_boxes = d->n_boxes;
+    for (int b = 0; b < d->n_boxes; ++b) {
+        for (int a = 0; a < 3; ++a) {
+            P.box_lo[b][a] = d->box_lo[3 * b + a];
+            P.box_hi[b][a] = d->box_hi[3 * b + a];
+        }
+        P.box_mat[b] = d->box_mat[b];
+    }
+    P.background_mat = d->background_mat;
+    P.n_mat = d->n_mat;
+    P.G = d->G;
+    double *tab = (double *)(ws + L.tables);
+    const size_t nst = (size_t)d->n_mat * d->G, nss = nst * d->G;
+    P.sigma_t = tab;
+    P.sigma_s = tab + nst;
+    P.speed = tab + nst + nss;
+    P.census = tab + nst + nss + d->G;
+    P.src_box = d->src_kind == MCDC_SRC_BOX;
+    P.src_isotropic = d->src_isotropic;
+    P.src_group = d->src_group;
+    P.n_census = d->n_census;
+    for (int a = 0; a < 3; ++a) {
+        P.src_lo[a] = d->src_lo[a];
+        P.src_hi[a] = d->src_hi[a];
+        P.src_dir[a] = d->src_dir[a];
+    }
+    P.src_t0 = d->src_t0;
+    P.src_t1 = d->src_t1;
+    for (int a = 0; a < 4; ++a) {
+        P.mesh_n[a] = d->mesh_n[a];
+        P.mesh_lo[a] = d->mesh_lo[a];
+        if (a < 3 && isinf(d->mesh_lo[a]) && isinf(d->mesh_hi[a])) {
+            P.mesh_bounded[a] = 0;
+            P.mesh_delta[a] = HUGE_VAL;
+            P.mesh_idelta[a] = 0.0;
+        } else {
+            if (a < 3) P.mesh_bounded[a] = 1;
+            P.mesh_delta[a] = (d->mesh_hi[a] - d->mesh_lo[a]) / (double)d->mesh_n[a];
+            P.mesh_idelta[a] = 1.0 / P.mesh_delta[a];
+        }
+    }
+    P.G_t = d->mesh_per_group ? d->G : 1;
+    P.implicit_capture = d->implicit_capture;
+    P.w_cut = d->w_cut;
+    P.w_surv = d->w_surv;
+    P.has_detector = d->has_detector;
+    for (int a = 0; a < 3; ++a) {
+        P.det_lo[a] = d->det_lo[a];
+        P.det_hi[a] = d->det_hi[a];
+    }
+    const double t_end = d->census[d->n_census - 1];
+    P.imp_on = d->imp_on;
+    for (int a = 0; a < 4; ++a) {
+        P.imp_n[a] = d->imp_n[a] < 1 ? 1 : d->imp_n[a];
+        const double lo = a < 3 ? d->outer_lo[a] : 0.0;
+        const double hi = a < 3 ? d->outer_hi[a] : t_end;
+        P.imp_lo[a] = lo;
+        P.imp_f[a] = (double)P.imp_n[a] / (hi - lo);
+    }
+    P.ww_on = 0;
+    P.ww_params = (const float *)(ws + L.ww_params);
+    for (int a = 0; a < 3; ++a) {
+        P.ww_lo[a] = d->outer_lo[a];
+        P.ww_inv[a] = 1.0 / (d->outer_hi[a] - d->outer_lo[a]);
+    }
+    P.ww_lo[3] = 0.0;
+    P.ww_inv[3] = 1.0 / t_end;
+    P.max_events = d->max_events;
+    P.stack_cap = d->stack_cap;
+    P.problem_id = d->problem_id;
+    P.nbins = desc_nbins(d);
+}
+
+void timing_begin(mcdc_problem *h, hipStream_t s) {
+    if (!h->timing) return;
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return;
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return;
+    }
+    (void)hipEventRecord(a, s);
+    h->events.push_back({a, b});
+}
+
+void timing_end(mcdc_problem *h, hipStream_t s) {
+    if (!h->timing || h->events.empty()) return;
+    (void)hipEventRecord(h->events.back().second, s);
+}
+
+static void timing_clear(mcdc_problem *h) {
+    for (auto &p : h->events) {
+        (void)hipEventDestroy(p.first);
+        (void)hipEventDestroy(p.second);
+    }
+    h->events.clear();
+}
+
+std::vector<double> pack_tables(const mcdc_problem_desc *d) {
+    std::vector<double> t;
+    const size_t nst = (size_t)d->n_mat * d->G, nss = nst * d->G;
+    t.insert(t.end(), d->sigma_t, d->sigma_t + nst);
+    t.insert(t.end(), d->sigma_s, d->sigma_s + nss);
+    t.insert(t.end(), d->speed, d->speed + d->G);
+    t.insert(t.end(), d->census, d->census + d->n_census);
+    return t;
+}
+
+}  // namespace mcdc
+
+using namespace mcdc;
+
+extern "C" {
+
+const char *mcdc_last_error(void) { return g_err.c_str(); }
+
+size_t mcdc_mlp_param_count(int32_t in_dim) {
+    const size_t H = kH;
+    return H * (size_t)in_dim + H + H * H + H + H + 1;
+}
+
+int mcdc_workspace_bytes(const mcdc_problem_desc *d, const mcdc_options *opt, size_t *bytes) {
+    int st = validate_desc(d);
+    if (st) return st;
+    Options o = resolve_options(opt);
+    if ((st = check_options(o))) return st;
+    if (!bytes) return fail(MCDC_E_INVALID, "null bytes");
+    *bytes = make_layout(d, o).total;
+    return MCDC_OK;
+}
+
+int mcdc_create_problem(const mcdc_problem_desc *d, const mcdc_options *opt, void *dev_ws,
+                        size_t bytes, mcdc_handle *out) {
+    int st = validate_desc(d);
+    if (st) return st;
+    if (!out || !dev_ws) return fail(MCDC_E_INVALID, "null workspace or handle");
+    Options o = resolve_options(opt);
+    if ((st = check_options(o))) return st;
+    Layout L = make_layout(d, o);
+    if (bytes < L.total) return fail(MCDC_E_NOMEM, "workspace too small: need " + std::to_string(L.total));
+    auto *h = new mcdc_problem();
+    h->desc = *d;
+    h->opt = o;
+    h->L = L;
+    h->ws = (char *)dev_ws;
+    h->nbins = desc_nbins(d);
+    h->nimp = desc_nimp(d);
+    build_dev_problem(d, h->ws, L, h->P);
+    std::vector<double> tab = pack_tables(d);
+    hipError_t e = hipMemcpy(h->ws + L.tables, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(h->ws + L.tally_batch, 0, L.ww_params - L.tally_batch);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        delete h;
+        return hip_fail(e, "create_problem upload");
+    }
+    if (o.schedule == MCDC_SCHED_EVENT && (st = event_init(h))) {
+        delete h;
+        return st;
+    }
+    *out = h;
+    return MCDC_OK;
+}
+
+int mcdc_set_kernel_timing(mcdc_handle h, int on) {
+    if (!h) return fail(MCDC_E_INVALID, "null handle");
+    h->timing = on != 0;
+    return MCDC_OK;
+}
+
+int mcdc_kernel_time(mcdc_handle h, uint64_t *launches, double *total_ms) {
+    if (!h || !launches || !total_ms) return fail(MCDC_E_INVALID, "null argument");
+    double ms = 0.0;
+    for (auto &p : h->events) {
+        hipError_t e = hipEventSynchronize(p.second);
+        float t = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, p.first, p.second);
+        if (e != hipSuccess) {
+            timing_clear(h);
+            return hip_fail(e, "kernel_time");
+        }
+        ms += t;
+    }
+    *launches = h->events.size();
+    *total_ms = ms;
+    timing_clear(h);
+    return MCDC_OK;
+}
+
+void mcdc_destroy_problem(mcdc_handle h) {
+    if (!h) return;
+    timing_clear(h);
+    event_destroy(h);
+    batch_destroy(h);
+    delete h;
+}
+
+int mcdc_set_trace(mcdc_handle h, mcdc_trace_rec *buf, uint64_t cap, uint64_t *count) {
+    if (!h) return fail(MCDC_E_INVALID, "null handle");
+    if (buf && !count) return fail(MCDC_E_INVALID, "trace needs a device counter");
+    h->trace = buf;
+    h->trace_cap = buf ? cap : 0;
+    h->trace_count = (unsigned long long *)count;
+    return MCDC_OK;
+}
+
+int mcdc_set_history_scores(mcdc_handle h, double *dev_xh) {
+    if (!h) return fail(MCDC_E_INVALID, "null handle");
+    h->xh_out = dev_xh;
+    return MCDC_OK;
+}
+
+int mcdc_set_ww_mlp(mcdc_handle h, const float *params, size_t n, double logk, double ratio,
+                    int32_t n_max) {
+    if (!h) return fail(MCDC_E_INVALID, "null handle");
+    if (!params) {
+        h->P.ww_on = 0;
+        return MCDC_OK;
+    }
+    if (h->desc.stack_cap < 1) return fail(MCDC_E_STATE, "problem was created with stack_cap = 0");
+    if (h->desc.imp_on) return fail(MCDC_E_STATE, "weight windows and the importance estimate exclude each other");
+    if (n != mcdc_mlp_param_count(4 + h->desc.G)) return fail(MCDC_E_INVALID, "wrong parameter count");
+    if (!(ratio >= 1.0) || n_max < 2) return fail(MCDC_E_INVALID, "ratio >= 1 and n_max >= 2 required");
+    hipError_t e = hipMemcpy(h->ws + h->L.ww_params, params, n * sizeof(float), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "set_ww_mlp");
+    h->P.ww_on = 1;
+    h->P.ww_logk = logk;
+    h->P.ww_ratio = ratio;
+    h->P.ww_nmax = n_max;
+    return MCDC_OK;
+}
+
+RunArgs base_args(mcdc_handle h, uint64_t seed) {
+    RunArgs A;
+    memset(&A, 0, sizeof(A));
+    A.seed = seed;
+    A.tally = (double *)(h->ws + h->L.tally_batch);
+    A.acc = (DevAcc *)(h->ws + h->L.acc);
+    A.imp_score = (double *)(h->ws + h->L.imp_score);
+    A.imp_weight = (double *)(h->ws + h->L.imp_weight);
+    A.xh_out = h->xh_out;
+    A.trace = h->trace;
+    A.trace_cap = h->trace_cap;
+    A.trace_count = h->trace_count;
+    A.stk_d = (double *)(h->ws + h->L.stk_d);
+    A.stk_i = (int32_t *)(h->ws + h->L.stk_i);
+    const uint64_t Ln = h->opt.n_lanes;
+    A.imp_cell = (int32_t *)(h->ws + h->L.imp_list);
+    A.imp_cnt = (double *)(h->ws + h->L.imp_list + align_up(kImpList * Ln * sizeof(int32_t)));
+    A.imp_xsum = A.imp_cnt + kImpList * Ln;
+    A.n_lanes = Ln;
+    return A;
+}
+
+int mcdc_run(mcdc_handle h, uint64_t n, uint64_t seed, void *stream) {
+    if (!h) return fail(MCDC_E_INVALID, "null handle");
+    if (h->is_batch) return fail(MCDC_E_STATE, "batched handle: use mcdc_run_batch");
+    if (h->n_hist + n >= (1ull << 48)) return fail(MCDC_E_INVALID, "history ids exhausted (2^48)");
+    hipStream_t s = (hipStream_t)stream;
+    const uint64_t B = (uint64_t)h->desc.n_batches;
+    const uint64_t h0 = h->n_hist;
+    RunArgs A = base_args(h, seed);
+    A.h_run0 = h0;
+    double *batch = (double *)(h->ws + h->L.tally_batch);
+    double *sum = (double *)(h->ws + h->L.tally_sum);
+    double *sumsq = (double *)(h->ws + h->L.tally_sumsq);
+    const bool lds = h->opt.lds_tally && h->nbins <= (uint32_t)kLdsTallyMaxBins;
+    for (uint64_t b = 0; b < B; ++b) {
+        const uint64_t lo = (b * n) / B, hi = ((b + 1) * n) / B;
+        if (hi == lo) continue;
+        A.h_begin = h0 + lo;
+        A.h_end = h0 + hi;
+        hipError_t e;
+        if (h->opt.schedule == MCDC_SCHED_EVENT) {
+            int st = event_run_range(h, A, s);
+            if (st) return st;
+            e = hipSuccess;
+        } else {
+            timing_begin(h, s);
+            e = launch_history(h->P, A, h->opt.grid, h->opt.block, lds, s);
+            timing_end(h, s);
+        }
+        if (e == hipSuccess) e = launch_closeout(batch, sum, sumsq, h->nbins, (double)(hi - lo), s);
+        if (e != hipSuccess) return hip_fail(e, "run launch");
+        h->batches += 1;
+    }
+    h->n_hist += n;
+    return MCDC_OK;
+}
+
+int read_acc(mcdc_handle h, DevAcc &acc, hipStream_t s) {
+    hipError_t e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = hipMemcpy(&acc, h->ws + h->L.acc, sizeof(DevAcc), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "read accumulators");
+    if (acc.status != 0) return fail(acc.status, "a run failed on the device (status " + std::to_string(acc.status) + ")");
+    return MCDC_OK;
+}
+
+int mcdc_tally_bins(mcdc_handle h, size_t *n) {
+    if (!h || !n) return fail(MCDC_E_INVALID, "null argument");
+    *n = h->nbins;
+    return MCDC_OK;
+}
+
+int mcdc_get_raw(mcdc_handle h, double *tsum, double *tsumsq, size_t n, void *stream) {
+    if (!h) return fail(MCDC_E_INVALID, "null handle");
+    if (n != h->nbins) return fail(MCDC_E_INVALID, "wrong bin count");
+    DevAcc acc;
+    int st = read_acc(h, acc, (hipStream_t)stream);
+    if (st) return st;
+    hipError_t e = hipSuccess;
+    if (tsum) e = hipMemcpy(tsum, h->ws + h->L.tally_sum, n * sizeof(double), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && tsumsq)
+        e = hipMemcpy(tsumsq, h->ws + h->L.tally_sumsq, n * sizeof(double), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "get_raw");
+    return MCDC_OK;
+}
+
+void fill_counters(const DevAcc &a, mcdc_counters *o) {
+    const unsigned long long *c = a.cnt;
+    o->histories = c[C_HIST]; o->flights = c[C_FLIGHT]; o->pieces = c[C_PIECE];
+    o->collisions = c[C_COLLISION]; o->absorptions = c[C_ABSORB]; o->surfaces = c[C_SURFACE];
+    o->leaks = c[C_LEAK]; o->census_stops = c[C_CENSUS]; o->time_ends = c[C_TIME_END];
+    o->splits = c[C_SPLIT]; o->rr_kills = c[C_RR_KILL]; o->rr_survivals = c[C_RR_SURVIVE];
+    o->cutoff_kills = c[C_CUT_KILL]; o->cutoff_survivals = c[C_CUT_SURVIVE];
+    o->detector_hits = c[C_DET_HIT]; o->particles = c[C_PARTICLE];
+    o->w_source = a.wsum[W_SOURCE]; o->w_leak = a.wsum[W_LEAK]; o->w_absorb = a.wsum[W_ABSORB];
+    o->w_time_end = a.wsum[W_TIME_END]; o->w_gain = a.wsum[W_GAIN]; o->w_loss = a.wsum[W_LOSS];
+    o->path = a.wsum[W_PATH];
+    for (int f = 0; f < 6; ++f) o->leak[f] = a.leak[f];
+    o->det_sum = a.det[0];
+    o->det_sumsq = a.det[1];
+    o->status = a.status;
+}
+
+int mcdc_get_counters(mcdc_handle h, mcdc_counters *out, void *stream) {
+    if (!h || !out) return fail(MCDC_E_INVALID, "null argument");
+    DevAcc acc;
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e == hipSuccess) e = hipMemcpy(&acc, h->ws + h->L.acc, sizeof(DevAcc), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "get_counters");
+    memset(out, 0, sizeof(*out));
+    fill_counters(acc, out);
+    out->batches = h->batches;
+    out->n_hist = h->n_hist;
+    return MCDC_OK;
+}
+
+int mcdc_get_tallies(mcdc_handle h, int kind, double *mean, double *rel, size_t n, void *stream) {
+    if (!h || !mean) return fail(MCDC_E_INVALID, "null argument");
+    DevAcc acc;
+    int st = read_acc(h, acc, (hipStream_t)stream);
+    if (st) return st;
+    const double N = (double)h->n_hist;
+    if (h->n_hist == 0) return fail(MCDC_E_STATE, "no histories run yet");
+    if (kind == MCDC_TALLY_DETECTOR) {
+        if (n != 1) return fail(MCDC_E_INVALID, "detector tally has 1 value");
+        const double m = acc.det[0] / N;
+        mean[0] = m;
+        if (rel) {
+            const double var = N > 1 ? (acc.det[1] / N - m * m) / (N - 1.0) : NAN;
+            rel[0] = m > 0.0 ? sqrt(var > 0.0 ? var : 0.0) / m : 0.0;
+        }
+        return MCDC_OK;
+    }
+    if (kind == MCDC_TALLY_LEAKAGE) {
+        if (n != 6) return fail(MCDC_E_INVALID, "leakage tally has 6 values");
+        for (int f = 0; f < 6; ++f) {
+            mean[f] = acc.leak[f] / N;
+            if (rel) rel[f] = NAN;
+        }
+        return MCDC_OK;
+    }
+    if (kind != MCDC_TALLY_MESH) return fail(MCDC_E_INVALID, "unknown tally kind");
+    if (n != h->nbins) return fail(MCDC_E_INVALID, "wrong bin count");
+    std::vector<double> s(n), s2(n);
+    hipError_t e = hipMemcpy(s.data(), h->ws + h->L.tally_sum, n * sizeof(double), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(s2.data(), h->ws + h->L.tally_sumsq, n * sizeof(double), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "get_tallies");
+    double vol = 1.0;
+    for (int a = 0; a < 4; ++a)
+        if (a == 3 || h->P.mesh_bounded[a]) vol *= h->P.mesh_delta[a];
+    const double B = (double)h->batches;
+    for (size_t i = 0; i < n; ++i) {
+        const double m = s[i] / N;
+        mean[i] = m / vol;
+        if (rel) {
+            if (B < 2 || m <= 0.0) {
+                rel[i] = B < 2 ? NAN : 0.0;
+            } else {
+                const double var = (s2[i] - N * m * m) / ((B - 1.0) * N);
+                rel[i] = sqrt(var > 0.0 ? var : 0.0) / m;
+            }
+        }
+    }
+    return MCDC_OK;
+}
+
+int mcdc_reset_tallies(mcdc_handle h, void *stream) {
+    if (!h) return fail(MCDC_E_INVALID, "null handle");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = hipMemset(h->ws + h->L.tally_batch, 0, h->L.ww_params - h->L.tally_batch);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "reset_tallies");
+    h->batches = 0;
+    h->n_hist = 0;
+    return MCDC_OK;
+}
+
+int mcdc_get_importance(mcdc_handle h, double *score, double *weight, size_t n, void *stream) {
+    if (!h) return fail(MCDC_E_INVALID, "null handle");
+    if (!h->desc.imp_on || n != h->nimp) return fail(MCDC_E_INVALID, "importance not enabled or wrong size");
+    DevAcc acc;
+    int st = read_acc(h, acc, (hipStream_t)stream);
+    if (st) return st;
+    hipError_t e = hipSuccess;
+    if (score) e = hipMemcpy(score, h->ws + h->L.imp_score, n * sizeof(double), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && weight)
+        e = hipMemcpy(weight, h->ws + h->L.imp_weight, n * sizeof(double), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "get_importance");
+    return MCDC_OK;
+}
+
+}  // extern "C"

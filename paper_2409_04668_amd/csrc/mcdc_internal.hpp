@@ -1,0 +1,103 @@
+// Internal declarations shared by the HIP translation units of libmcdc.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <type_traits>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/mcdc.h"
+
+namespace mcdc {
+
+constexpr int kMaxBoxes = MCDC_MAX_BOXES;
+constexpr int kMaxG = MCDC_MAX_G;
+constexpr int kH = MCDC_MLP_HIDDEN;
+constexpr int kImpList = 16;                 // distinct coarse cells kept per history
+constexpr int kLdsTallyMaxBins = 7680;       // 60 KiB of FP64 LDS tile
+
+// counters (device accumulator layout)
+enum {
+    C_HIST = 0, C_FLIGHT, C_PIECE, C_COLLISION, C_ABSORB, C_SURFACE, C_LEAK, C_CENSUS,
+    C_TIME_END, C_SPLIT, C_RR_KILL, C_RR_SURVIVE, C_CUT_KILL, C_CUT_SURVIVE, C_DET_HIT,
+    C_PARTICLE, N_CNT
+};
+enum { W_SOURCE = 0, W_LEAK, W_ABSORB, W_TIME_END, W_GAIN, W_LOSS, W_PATH, N_WSUM };
+
+// trace record types
+enum {
+    EV_SOURCE = 0, EV_SCATTER = 1, EV_ABSORB = 2, EV_SURFACE = 3, EV_LEAK = 4, EV_CENSUS = 5,
+    EV_TIME_END = 6, EV_SPLIT = 7, EV_RR_KILL = 8, EV_RR_SURVIVE = 9, EV_CUT_KILL = 10,
+    EV_CUT_SURVIVE = 11,
+};
+
+struct DevAcc {
+    unsigned long long cnt[N_CNT];
+    double wsum[N_WSUM];
+    double leak[6];
+    double det[2];
+    int status;
+    int pad;
+};
+
+// Problem tables as seen by the kernels (passed by value; < 2 KiB).
+struct DevProblem {
+    double outer_lo[3], outer_hi[3];
+    double box_lo[kMaxBoxes][3], box_hi[kMaxBoxes][3];
+    int32_t box_mat[kMaxBoxes];
+    int32_t bc[6];
+    int32_t n_boxes, background_mat, n_mat, G;
+    const double *sigma_t, *sigma_s, *speed, *census;   // device
+    int32_t src_box, src_isotropic, src_group, n_census;
+    double src_lo[3], src_hi[3], src_t0, src_t1, src_dir[3];
+    double mesh_lo[4], mesh_delta[4], mesh_idelta[4];
+    int32_t mesh_n[4], mesh_bounded[3], G_t;
+    int32_t implicit_capture;
+    double w_cut, w_surv;
+    int32_t has_detector;
+    double det_lo[3], det_hi[3];
+    int32_t imp_on;
+    int32_t imp_n[4];
+    double imp_lo[4], imp_f[4];
+    int32_t ww_on, ww_nmax;
+    const float *ww_params;                               // device
+    double ww_logk, ww_ratio, ww_lo[4], ww_inv[4];
+    int64_t max_events;
+    int32_t stack_cap;
+    uint32_t problem_id;
+    uint32_t nbins;
+};
+
+// Per-launch arguments of the tracking kernels.
+struct RunArgs {
+    uint64_t seed;
+    uint64_t h_begin, h_end, h_run0;
+    double *tally;                       // current-batch accumulator [nbins]
+    DevAcc *acc;
+    double *imp_score, *imp_weight;
+    double *xh_out;
+    mcdc_trace_rec *trace;
+    uint64_t trace_cap;
+    unsigned long long *trace_count;
+    double *stk_d;                       // [8][stack_cap][n_lanes]
+    int32_t *stk_i;                      // [4][stack_cap][n_lanes]
+    int32_t *imp_cell;                   // [kImpList][n_lanes]
+    double *imp_cnt, *imp_xsum;          // [kImpList][n_lanes]
+    uint64_t n_lanes;
+};
+
+struct Layout {                          // workspace carving (byte offsets)
+    size_t tables, tally_batch, tally_sum, tally_sumsq, acc, imp_score, imp_weight, ww_params,
+        stk_d, stk_i, imp_list, event, total;
+};
+
+// launch helpers implemented in the kernel translation units
+hipError_t launch_history(const DevProblem &P, const RunArgs &A, int grid, int block,
+                          bool lds_tally, hipStream_t s);
+hipError_t launch_closeout(double *batch, double *sum, double *sumsq, uint32_t n, double nb,
+                           hipStream_t s);
+int history_grid(int block, int waves_per_cu);
+
+}  // namespace mcdc

@@ -1,0 +1,62 @@
+// Host-side handle state shared by the runtime translation units.
+#pragma once
+
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "mcdc_internal.hpp"
+
+namespace mcdc {
+
+struct Options {
+    int schedule, block, waves_per_cu, lds_tally;
+    int64_t event_chunk;
+    int grid;
+    uint64_t n_lanes;
+};
+
+struct EventState;
+struct BatchState;
+
+}  // namespace mcdc
+
+struct mcdc_problem {
+    mcdc_problem_desc desc;
+    mcdc::Options opt;
+    mcdc::Layout L;
+    mcdc::DevProblem P;
+    char *ws = nullptr;
+    uint32_t nbins = 0;
+    size_t nimp = 0;
+    uint64_t n_hist = 0;
+    int64_t batches = 0;
+    mcdc_trace_rec *trace = nullptr;
+    uint64_t trace_cap = 0;
+    unsigned long long *trace_count = nullptr;
+    double *xh_out = nullptr;
+    bool is_batch = false;
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+    mcdc::EventState *ev = nullptr;
+    mcdc::BatchState *batch = nullptr;
+};
+
+namespace mcdc {
+
+int fail(int st, const std::string &msg);
+int hip_fail(hipError_t e, const char *where);
+// kernel timing: record a start event before / a stop event after a launch
+void timing_begin(mcdc_problem *h, hipStream_t s);
+void timing_end(mcdc_problem *h, hipStream_t s);
+
+// event-based schedule (mcdc_event.hip)
+size_t event_workspace_bytes(const mcdc_problem_desc *d, const Options &o);
+int event_init(mcdc_problem *h);
+int event_run_range(mcdc_problem *h, const RunArgs &A, hipStream_t s);
+void event_destroy(mcdc_problem *h);
+
+// batched problems (mcdc_batch.hip)
+void batch_destroy(mcdc_problem *h);
+
+}  // namespace mcdc

@@ -1,0 +1,416 @@
+// Device-side transport arithmetic for gfx950.
+//
+// Every routine here is written so that, compiled with -ffp-contract=off and
+// IEEE binary64 division/sqrt, it rounds exactly as the definition of the
+// method does: the same operations on the same operands in the same order.
+// That makes each history's trajectory reproducible bit for bit on any
+// schedule.  Sources of the definitions:
+//  - move: position += direction * distance, time += distance / speed (paper,
+//    Fig. 2);
+//  - the events that end a flight or a particle: capture, time or space
+//    boundary, time census, implicit capture (paper, Sec. "MC/DC on CPUs",
+//    transport-loop paragraph);
+//  - tallies accumulated by atomic adds on the GPU (paper, Fig. 3);
+//  - counter-based random numbers (paper, Sec. "Monte Carlo Neutron Transport
+//    and MC/DC", list of developments): Philox4x32-10 of Salmon et al. (SC'11).
+#pragma once
+
+#include "mcdc_internal.hpp"
+
+namespace mcdc {
+
+#define MCDC_DEV __device__ __forceinline__
+
+constexpr double kInf = __builtin_huge_val();
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 and the per-particle stream.
+// counter = (k, tag, hist low 32, hist bits 32..47 | problem << 16), key = seed.
+// ---------------------------------------------------------------------------
+struct Rng {
+    uint32_t key0, key1, tag, c2, c3, k;
+};
+
+MCDC_DEV void philox10(uint32_t &c0, uint32_t &c1, uint32_t &c2, uint32_t &c3, uint32_t k0,
+                       uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t lo0 = 0xD2511F53u * c0;
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo1 = 0xCD9E8D57u * c2;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t n0 = hi1 ^ c1 ^ k0;
+        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+    }
+}
+
+MCDC_DEV Rng make_rng(uint64_t seed, uint64_t hist, uint32_t problem, uint32_t tag, uint32_t k) {
+    Rng r;
+    r.key0 = (uint32_t)seed;
+    r.key1 = (uint32_t)(seed >> 32);
+    r.tag = tag;
+    r.c2 = (uint32_t)hist;
+    r.c3 = (uint32_t)((hist >> 32) & 0xFFFFu) | (problem << 16);
+    r.k = k;
+    return r;
+}
+
+MCDC_DEV void rng_block(Rng &r, uint32_t out[4]) {
+    uint32_t c0 = r.k, c1 = r.tag, c2 = r.c2, c3 = r.c3;
+    philox10(c0, c1, c2, c3, r.key0, r.key1);
+    r.k += 1u;
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+// xi = ((u >> 12) + 0.5) * 2^-52, u = (r1 << 32) | r0  -> exact, in (0,1)
+MCDC_DEV double rng_uniform(Rng &r) {
+    uint32_t c0 = r.k, c1 = r.tag, c2 = r.c2, c3 = r.c3;
+    philox10(c0, c1, c2, c3, r.key0, r.key1);
+    r.k += 1u;
+    const uint64_t u = ((uint64_t)c1 << 32) | (uint64_t)c0;
+    return ((double)(u >> 12) + 0.5) * 0x1p-52;
+}
+
+// ---------------------------------------------------------------------------
+// Natural log and exp built from +,-,*,/ only (Cody-Waite reduction with a
+// split ln 2; odd atanh series through f^21; Taylor degree 13), so that the
+// result does not depend on the device math library.
+// ---------------------------------------------------------------------------
+constexpr double kLn2Hi = 0x1.62e42feep-1;
+constexpr double kLn2Lo = 0x1.a39ef35793c76p-33;
+constexpr double kInvLn2 = 1.4426950408889634;
+constexpr double kSqrt2 = 1.4142135623730951;
+
+MCDC_DEV double own_log(double x) {
+    const uint64_t b = (uint64_t)__double_as_longlong(x);
+    int e = (int)((b >> 52) & 0x7FFu) - 1023;
+    double m = __longlong_as_double((long long)((b & 0x000FFFFFFFFFFFFFull) | 0x3FF0000000000000ull));
+    if (m > kSqrt2) {
+        m = m * 0.5;
+        e = e + 1;
+    }
+    const double f = (m - 1.0) / (m + 1.0);
+    const double s = f * f;
+    double p = 1.0 / 21.0;
+    p = p * s + 1.0 / 19.0;
+    p = p * s + 1.0 / 17.0;
+    p = p * s + 1.0 / 15.0;
+    p = p * s + 1.0 / 13.0;
+    p = p * s + 1.0 / 11.0;
+    p = p * s + 1.0 / 9.0;
+    p = p * s + 1.0 / 7.0;
+    p = p * s + 1.0 / 5.0;
+    p = p * s + 1.0 / 3.0;
+    const double lm = 2.0 * f + (2.0 * f) * (s * p);
+    const double de = (double)e;
+    return de * kLn2Hi + (de * kLn2Lo + lm);
+}
+
+MCDC_DEV double own_exp(double x) {
+    if (x > 700.0) x = 700.0;
+    if (x < -700.0) x = -700.0;
+    const double n = floor(x * kInvLn2 + 0.5);
+    const double r = (x - n * kLn2Hi) - n * kLn2Lo;
+    double p = 1.0 / 6227020800.0;
+    p = p * r + 1.0 / 479001600.0;
+    p = p * r + 1.0 / 39916800.0;
+    p = p * r + 1.0 / 3628800.0;
+    p = p * r + 1.0 / 362880.0;
+    p = p * r + 1.0 / 40320.0;
+    p = p * r + 1.0 / 5040.0;
+    p = p * r + 1.0 / 720.0;
+    p = p * r + 1.0 / 120.0;
+    p = p * r + 1.0 / 24.0;
+    p = p * r + 1.0 / 6.0;
+    p = p * r + 0.5;
+    p = p * r + 1.0;
+    p = p * r + 1.0;
+    const long long ni = (long long)n;
+    const double scale = __longlong_as_double((ni + 1023) << 52);
+    return p * scale;
+}
+
+// Isotropic direction by Marsaglia's (1972) rejection method.
+MCDC_DEV void iso_direction(Rng &r, double &ux, double &uy, double &uz) {
+    double a, b, s;
+    for (;;) {
+        a = 2.0 * rng_uniform(r) - 1.0;
+        b = 2.0 * rng_uniform(r) - 1.0;
+        s = a * a + b * b;
+        if (s < 1.0 && s > 0.0) break;
+    }
+    const double q = __builtin_sqrt(1.0 - s);
+    ux = (2.0 * a) * q;
+    uy = (2.0 * b) * q;
+    uz = 1.0 - 2.0 * s;
+}
+
+// ---------------------------------------------------------------------------
+// Particle state in registers.
+// ---------------------------------------------------------------------------
+struct Part {
+    double x[3], u[3], t, w;
+    int32_t g, cell, ci;
+    uint32_t tag, k, seq;
+    bool alive;
+};
+
+// ---------------------------------------------------------------------------
+// Geometry: priority-ordered boxes, direction-aware containment per axis:
+// inside iff lo < p < hi, or p == lo with u >= 0, or p == hi with u < 0.
+// ---------------------------------------------------------------------------
+MCDC_DEV bool axis_in(double lo, double hi, double p, double u) {
+    if (lo < p && p < hi) return true;
+    if (p == lo) return u >= 0.0;
+    if (p == hi) return u < 0.0;
+    return false;
+}
+
+MCDC_DEV bool box_in(const double lo[3], const double hi[3], const double p[3], const double u[3]) {
+    return axis_in(lo[0], hi[0], p[0], u[0]) && axis_in(lo[1], hi[1], p[1], u[1]) &&
+           axis_in(lo[2], hi[2], p[2], u[2]);
+}
+
+MCDC_DEV int locate(const DevProblem &P, const double p[3], const double u[3]) {
+    for (int b = 0; b < P.n_boxes; ++b)
+        if (box_in(P.box_lo[b], P.box_hi[b], p, u)) return b;
+    return -1;
+}
+
+// Next surface along u: outer-box exit, then per box its exit (inside) or
+// slab-test entry (0 <= entry < exit).  First strict minimum wins in the order
+// outer box, boxes ascending, axes x,y,z; negative exits clamp to 0.
+MCDC_DEV double dist_surface(const DevProblem &P, const double p[3], const double u[3],
+                             const double iu[3], int &axis, double &plane) {
+    double best = kInf;
+    int bax = -1;
+    double bpl = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (u[a] == 0.0) continue;
+        const double pl = u[a] > 0.0 ? P.outer_hi[a] : P.outer_lo[a];
+        double s = (pl - p[a]) * iu[a];
+        if (!(s > 0.0)) s = 0.0;
+        if (s < best) { best = s; bax = a; bpl = pl; }
+    }
+    for (int b = 0; b < P.n_boxes; ++b) {
+        const double *lo = P.box_lo[b];
+        const double *hi = P.box_hi[b];
+        if (box_in(lo, hi, p, u)) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                if (u[a] == 0.0) continue;
+                const double pl = u[a] > 0.0 ? hi[a] : lo[a];
+                double s = (pl - p[a]) * iu[a];
+                if (!(s > 0.0)) s = 0.0;
+                if (s < best) { best = s; bax = a; bpl = pl; }
+            }
+        } else {
+            double tn = -kInf, tf = kInf, tpl = 0.0;
+            int ta = -1;
+            bool miss = false;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                if (u[a] == 0.0) {
+                    if (!axis_in(lo[a], hi[a], p[a], 0.0)) miss = true;
+                    continue;
+                }
+                const double s1 = (lo[a] - p[a]) * iu[a];
+                const double s2 = (hi[a] - p[a]) * iu[a];
+                const double nr = u[a] > 0.0 ? s1 : s2;
+                const double fr = u[a] > 0.0 ? s2 : s1;
+                if (nr > tn) { tn = nr; ta = a; tpl = u[a] > 0.0 ? lo[a] : hi[a]; }
+                if (fr < tf) tf = fr;
+            }
+            if (!miss && ta >= 0 && tn < tf && tn >= 0.0 && tn < best) {
+                best = tn; bax = ta; bpl = tpl;
+            }
+        }
+    }
+    axis = bax;
+    plane = bpl;
+    return best;
+}
+
+// Part of [0,d] inside the detector box.
+MCDC_DEV double detector_len(const DevProblem &P, const double p[3], const double u[3],
+                             const double iu[3], double d) {
+    double si = 0.0, so = d;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (u[a] == 0.0) {
+            if (!(P.det_lo[a] <= p[a] && p[a] <= P.det_hi[a])) return 0.0;
+            continue;
+        }
+        const double s1 = (P.det_lo[a] - p[a]) * iu[a];
+        const double s2 = (P.det_hi[a] - p[a]) * iu[a];
+        const double nr = u[a] > 0.0 ? s1 : s2;
+        const double fr = u[a] > 0.0 ? s2 : s1;
+        if (nr > si) si = nr;
+        if (fr < so) so = fr;
+    }
+    return so > si ? so - si : 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Tally targets: FP64 atomics into global memory, or into an LDS tile that
+// the kernel flushes to global memory when it ends.
+// ---------------------------------------------------------------------------
+struct GlobalTally {
+    double *base;
+    MCDC_DEV void add(uint32_t i, double v) const { unsafeAtomicAdd(base + i, v); }
+};
+struct LdsTally {
+    double *base;
+    MCDC_DEV void add(uint32_t i, double v) const { atomicAdd(base + i, v); }
+};
+
+// Track-length scoring of the segment p + s u, s in [0,d], from time t0 at
+// speed v: the segment is cut at every mesh plane and time edge it crosses
+// (edges lo + k*delta; crossing distances recomputed from the segment start;
+// all axes at the minimum advance together); each in-mesh piece of positive
+// length adds w * length to tally[g][it][iz][iy][ix].  Returns the pieces.
+template <class T>
+MCDC_DEV uint32_t score_mesh(const DevProblem &P, const double p[3], const double u[3],
+                             const double iu[3], double t0, double v, double d, double w, int g,
+                             const T &tally) {
+    if (!(d > 0.0)) return 0;
+    int idx[4];
+    double s[4];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (!P.mesh_bounded[a]) { idx[a] = 0; s[a] = kInf; continue; }
+        const double q = (p[a] - P.mesh_lo[a]) * P.mesh_idelta[a];
+        double fq = floor(q);
+        if (fq < -1.0) fq = -1.0;
+        if (fq > (double)P.mesh_n[a]) fq = (double)P.mesh_n[a];
+        int i = (int)fq;
+        if (q == fq && u[a] < 0.0) i = i - 1;
+        if (i < -1) i = -1;
+        idx[a] = i;
+        if (u[a] > 0.0) {
+            if (i >= P.mesh_n[a]) return 0;
+            const double e = P.mesh_lo[a] + (double)(i + 1) * P.mesh_delta[a];
+            s[a] = (e - p[a]) * iu[a];
+        } else if (u[a] < 0.0) {
+            if (i < 0) return 0;
+            const double e = P.mesh_lo[a] + (double)i * P.mesh_delta[a];
+            s[a] = (e - p[a]) * iu[a];
+        } else {
+            if (i < 0 || i >= P.mesh_n[a]) return 0;
+            s[a] = kInf;
+        }
+    }
+    {
+        const double q = (t0 - P.mesh_lo[3]) * P.mesh_idelta[3];
+        double fq = floor(q);
+        if (fq < -1.0) fq = -1.0;
+        if (fq > (double)P.mesh_n[3]) fq = (double)P.mesh_n[3];
+        const int i = (int)fq;
+        if (i >= P.mesh_n[3]) return 0;
+        idx[3] = i;
+        const double e = P.mesh_lo[3] + (double)(i + 1) * P.mesh_delta[3];
+        s[3] = (e - t0) * v;
+    }
+    const uint32_t n0 = P.mesh_n[0], n1 = P.mesh_n[1], n2 = P.mesh_n[2], n3 = P.mesh_n[3];
+    const uint32_t gbase = (uint32_t)(P.G_t > 1 ? g : 0) * n3;
+    uint32_t pieces = 0;
+    double sp = 0.0;
+    for (;;) {
+        double sn = d;
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+            if (s[a] < sn) sn = s[a];
+        if (sn > sp) {
+            const bool in = (uint32_t)idx[0] < n0 && (uint32_t)idx[1] < n1 &&
+                            (uint32_t)idx[2] < n2 && (uint32_t)idx[3] < n3;
+            if (in) {
+                const uint32_t b =
+                    (((gbase + (uint32_t)idx[3]) * n2 + (uint32_t)idx[2]) * n1 + (uint32_t)idx[1]) *
+                        n0 + (uint32_t)idx[0];
+                tally.add(b, w * (sn - sp));
+                pieces += 1;
+            }
+        }
+        if (sn >= d) break;
+        bool done = false;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            if (s[a] != sn) continue;
+            if (u[a] > 0.0) {
+                idx[a] += 1;
+                if (idx[a] >= P.mesh_n[a]) { done = true; continue; }
+                const double e = P.mesh_lo[a] + (double)(idx[a] + 1) * P.mesh_delta[a];
+                s[a] = (e - p[a]) * iu[a];
+            } else {
+                idx[a] -= 1;
+                if (idx[a] < 0) { done = true; continue; }
+                const double e = P.mesh_lo[a] + (double)idx[a] * P.mesh_delta[a];
+                s[a] = (e - p[a]) * iu[a];
+            }
+        }
+        if (s[3] == sn) {
+            idx[3] += 1;
+            if (idx[3] >= P.mesh_n[3]) {
+                done = true;
+            } else {
+                const double e = P.mesh_lo[3] + (double)(idx[3] + 1) * P.mesh_delta[3];
+                s[3] = (e - t0) * v;
+            }
+        }
+        if (done) break;
+        sp = sn;
+    }
+    return pieces;
+}
+
+// ---------------------------------------------------------------------------
+// FP32 log-importance MLP: in -> 64 -> 64 -> 1, ReLU; each neuron starts from
+// its bias and adds weight*input products for ascending inputs, as separate
+// float multiplies and adds.  Layout W1[64][in], b1, W2[64][64], b2, W3, b3.
+// ---------------------------------------------------------------------------
+MCDC_DEV float mlp_infer(const float *__restrict__ prm, int in_dim, const float in[4 + kMaxG]) {
+    const float *W1 = prm;
+    const float *b1 = W1 + kH * in_dim;
+    const float *W2 = b1 + kH;
+    const float *b2 = W2 + kH * kH;
+    const float *W3 = b2 + kH;
+    const float *b3 = W3 + kH;
+    float h1[kH];
+#pragma unroll
+    for (int j = 0; j < kH; ++j) {
+        float acc = b1[j];
+#pragma unroll
+        for (int i = 0; i < 4 + kMaxG; ++i) {
+            if (i < in_dim) {
+                const float prod = W1[j * in_dim + i] * in[i];
+                acc = acc + prod;
+            }
+        }
+        h1[j] = acc > 0.0f ? acc : 0.0f;
+    }
+    float out = b3[0];
+    for (int j = 0; j < kH; ++j) {
+        float acc = b2[j];
+        const float *row = W2 + j * kH;
+#pragma unroll
+        for (int i = 0; i < kH; ++i) {
+            const float prod = row[i] * h1[i];
+            acc = acc + prod;
+        }
+        const float h2 = acc > 0.0f ? acc : 0.0f;
+        const float prod = W3[j] * h2;
+        out = out + prod;
+    }
+    return out;
+}
+
+}  // namespace mcdc

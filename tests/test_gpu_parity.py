@@ -1,0 +1,163 @@
+"""GPU parity: the HIP history kernel against the CPU oracle on the same seeded
+inputs.  Per-history traces and per-history (detector score, path) must be
+bit-identical; tally sums agree to 1e-10 relative (only the order of FP64
+additions differs); integer counters are exact."""
+import numpy as np
+import pytest
+
+from oracle import mlp as M
+from oracle import oracle as O
+from paper_2409_04668_amd import workloads as W
+
+from gpu_util import assert_close_sums, full_parity, run_pair
+
+pytestmark = pytest.mark.gpu
+
+
+def _mcdc():
+    from paper_2409_04668_amd import mcdc
+    return mcdc
+
+
+@pytest.mark.parametrize("lds", [1, 0])
+def test_slab_history_parity(lds):
+    mc = _mcdc()
+    full_parity(W.config1(), 3000, seed=101, trace_cap=60000,
+                options=mc.make_options(mc.SCHED_HISTORY, lds_tally=lds))
+
+
+def test_slab_implicit_capture_parity():
+    p = W.config1()
+    p["implicit_capture"] = True
+    full_parity(p, 2000, seed=102, trace_cap=200000)
+
+
+def test_duct_parity_with_census_steps():
+    p = W.config2(n_census=4)
+    p["mesh"]["n"] = np.array([12, 20, 12, 8], np.int32)     # several tiles, ragged vs census
+    full_parity(p, 3000, seed=103, trace_cap=200000)
+
+
+def test_duct_full_mesh_parity():
+    full_parity(W.config2(), 2000, seed=104, trace_cap=100000)
+
+
+def test_multigroup_parity():
+    p = W.config3()
+    full_parity(p, 400, seed=105, trace_cap=200000)
+
+
+def test_multigroup_implicit_parity():
+    p = W.config3()
+    p["implicit_capture"] = True
+    p["mesh"]["n"] = np.array([6, 10, 6, 5], np.int32)
+    full_parity(p, 200, seed=106, trace_cap=400000)
+
+
+def test_reflective_infinite_medium_parity():
+    p = W.infinite_medium([0.5, 0.8, 1.0], [[0.3, 0, 0], [0.2, 0.4, 0], [0.1, 0.3, 0.5]],
+                          [1.0, 3.0, 10.0], half=2.0, t_end=3.0, nt=6)
+    p["mesh"]["n"] = np.array([4, 4, 4, 6], np.int32)
+    full_parity(p, 500, seed=107, trace_cap=400000)
+
+
+def _ww_box():
+    p = W._base(1)
+    p["outer_lo"] = np.zeros(3)
+    p["outer_hi"] = np.full(3, 20.0)
+    p["sigma_t"] = np.array([[0.5]])
+    p["sigma_s"] = np.array([[[0.4]]])
+    p["source"] = dict(kind="point", lo=np.full(3, 10.0), hi=np.full(3, 10.0), t0=0.0, t1=0.0,
+                       isotropic=True, dir=np.array([1.0, 0.0, 0.0]), group=0)
+    p["mesh"] = dict(lo=np.array([0.0, 0.0, 0.0, 0.0]), hi=np.array([20.0, 20.0, 20.0, 40.0]),
+                     n=np.array([10, 5, 5, 4], np.int32), per_group=False)
+    p["census"] = np.array([40.0])
+    p["detector"] = dict(lo=np.array([16.0, 0.0, 0.0]), hi=np.array([20.0, 20.0, 20.0]))
+    return p
+
+
+def test_weight_window_parity_random_mlp():
+    p = _ww_box()
+    prm = M.init_params(5, 64, seed=3) * np.float32(0.3)
+    p["ww"] = dict(params=prm, hidden=64, logk=0.0, ratio=5.0, n_max=10)
+    p["stack_cap"] = 256
+    gp, orc = full_parity(p, 1500, seed=108, trace_cap=400000)
+    c = orc.counters
+    assert c["split"] > 100 and c["rr_kill"] > 100
+
+
+def test_weight_window_parity_duct():
+    p = W.config2()
+    p["mesh"]["n"] = np.array([6, 10, 6, 4], np.int32)
+    prm = M.init_params(5, 64, seed=5) * np.float32(0.2)
+    p["ww"] = dict(params=prm, hidden=64, logk=0.3, ratio=5.0, n_max=10)
+    p["stack_cap"] = 256
+    full_parity(p, 800, seed=109, trace_cap=400000)
+
+
+def test_importance_estimate_parity():
+    p = W.config2()
+    p["mesh"]["n"] = np.array([6, 10, 6, 4], np.int32)
+    p["importance"] = W.coarse_importance_grid()
+    gp, orc = full_parity(p, 4000, seed=110)
+    s, w = gp.importance()
+    assert_close_sums(s, orc.imp_score, what="imp_score")
+    assert_close_sums(w, orc.imp_weight, what="imp_weight")
+
+
+def test_ragged_and_accumulating_runs():
+    p = W.config1()
+    # fewer histories than batches, then more runs continuing the history ids
+    for n in (0, 1, 7):
+        full_parity(p, n, seed=111, trace_cap=1000)
+    full_parity(p, 333, seed=112, trace_cap=20000, runs=3)
+
+
+def test_event_cap_reports_error():
+    mc = _mcdc()
+    p = W.infinite_medium(1.0, [[0.99]], [1.0], half=5.0, t_end=1e6, nt=1)
+    p["max_events"] = 5
+    gp = mc.Problem(p)
+    gp.run(100, 1)
+    with pytest.raises(mc.McdcError) as e:
+        gp.tallies(mc.TALLY_DETECTOR)
+    assert e.value.status == mc.E_EVENT_CAP
+    with pytest.raises(O.OracleError):
+        O.run(p, 100, 1)
+
+
+def test_invalid_desc_rejected():
+    mc = _mcdc()
+    p = W.config1()
+    p["census"] = np.array([5.0, 4.0])
+    with pytest.raises(mc.McdcError) as e:
+        mc.Problem(p)
+    assert e.value.status == mc.E_INVALID
+
+
+def test_full_size_duct_sampled_histories():
+    """Config-2 at full size (1e8 histories, bench launch configuration):
+    sampled histories recomputed one by one by the oracle match bit for bit;
+    all track length is scored (conservation) and weight balances."""
+    mc = _mcdc()
+    n = 100_000_000
+    p = W.config2()
+    gp = mc.Problem(p)
+    gp.set_history_scores(n)
+    gp.run(n, seed=2026)
+    hs = gp.history_scores()
+    rng = np.random.default_rng(0)
+    ids = np.unique(np.concatenate([[0, 1, n - 1], rng.integers(0, n, 40),
+                                    np.nonzero(hs[:, 0] > 0)[0][:20]]))
+    q = dict(p)
+    q["n_batches"] = 1
+    for i in ids:
+        r = O.OracleRun(q)
+        _, ho = r.run(1, 2026, per_history=True, first_id=int(i))
+        assert np.array_equal(ho[0], hs[i]), (i, ho[0], hs[i])
+    c = gp.counters()
+    s, _ = gp.raw()
+    assert c["histories"] == n and c["particles"] == n
+    assert abs(s.sum() - c["path"]) <= 1e-9 * c["path"]
+    assert c["w_source"] == c["w_leak"] + c["w_absorb"] + c["w_time_end"]
+    assert c["leaks"] + c["absorptions"] + c["time_ends"] == n
