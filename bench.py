@@ -74,7 +74,7 @@ def main():
     ap.add_argument("--histories", type=int, default=100_000_000)
     ap.add_argument("--schedule", choices=["history", "event"], default="history")
     ap.add_argument("--waves-per-cu", type=int, default=0)
-    ap.add_argument("--cpu-sample", type=int, default=400_000)
+    ap.add_argument("--cpu-sample", type=int, default=8_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:

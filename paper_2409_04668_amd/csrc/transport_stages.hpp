@@ -1,0 +1,344 @@
+// The transport loop split into stages: source, flight (distances, event
+// selection, scoring, move, census), surface crossing, collision, weight-window
+// check.  The history-based kernel calls them back to back for one particle;
+// the event-based kernels call each stage over a compacted queue of particles.
+// A context object supplies what belongs to the particle's history (its id for
+// the random streams, its detector score, its flight count, where split
+// daughters go), so both schedules share one definition of the arithmetic.
+#pragma once
+
+#include "transport_device.hpp"
+
+namespace mcdc {
+
+struct Shared {
+    unsigned long long cnt[N_CNT];
+    double wsum[N_WSUM];
+    double leak[6];
+};
+
+MCDC_DEV void shared_zero(Shared &S) {
+    for (int i = threadIdx.x; i < N_CNT; i += blockDim.x) S.cnt[i] = 0ull;
+    for (int i = threadIdx.x; i < N_WSUM; i += blockDim.x) S.wsum[i] = 0.0;
+    for (int i = threadIdx.x; i < 6; i += blockDim.x) S.leak[i] = 0.0;
+}
+
+// after a __syncthreads(): one global atomic per non-zero entry
+MCDC_DEV void shared_flush(const Shared &S, DevAcc *acc) {
+    for (int i = threadIdx.x; i < N_CNT; i += blockDim.x)
+        if (S.cnt[i]) atomicAdd(&acc->cnt[i], S.cnt[i]);
+    for (int i = threadIdx.x; i < N_WSUM; i += blockDim.x)
+        if (S.wsum[i] != 0.0) unsafeAtomicAdd(&acc->wsum[i], S.wsum[i]);
+    for (int i = threadIdx.x; i < 6; i += blockDim.x)
+        if (S.leak[i] != 0.0) unsafeAtomicAdd(&acc->leak[i], S.leak[i]);
+}
+
+MCDC_DEV void trace_rec(const RunArgs &A, uint64_t hist, Part &q, int type, double aux) {
+    const uint32_t seq = q.seq;
+    q.seq += 1u;
+    if (A.trace == nullptr) return;
+    const unsigned long long i = atomicAdd(A.trace_count, 1ull);
+    if (i >= A.trace_cap) return;
+    mcdc_trace_rec r;
+    r.hist = hist;
+    r.tag = q.tag;
+    r.seq = seq;
+    r.type = type;
+    r.g = q.g;
+    r.cell = q.cell;
+    r.k = q.k;
+    r.x = q.x[0]; r.y = q.x[1]; r.z = q.x[2]; r.t = q.t;
+    r.ux = q.u[0]; r.uy = q.u[1]; r.uz = q.u[2]; r.w = q.w;
+    r.aux = aux;
+    A.trace[i] = r;
+}
+
+MCDC_DEV void set_status(const RunArgs &A, int st) { atomicMin(&A.acc->status, st); }
+
+// outer boundary after a surface crossing; returns the leak face or -1
+MCDC_DEV int boundary(const DevProblem &P, Part &q) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (axis_in(P.outer_lo[a], P.outer_hi[a], q.x[a], q.u[a])) continue;
+        const int side = q.x[a] >= P.outer_hi[a] ? 1 : 0;
+        const int face = 2 * a + side;
+        if (P.bc[face] == MCDC_REFLECTIVE) {
+            q.x[a] = side ? P.outer_hi[a] : P.outer_lo[a];
+            q.u[a] = -q.u[a];
+        } else {
+            return face;
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (axis_in(P.outer_lo[a], P.outer_hi[a], q.x[a], q.u[a])) continue;
+        return 2 * a + (q.x[a] >= P.outer_hi[a] ? 1 : 0);
+    }
+    return -1;
+}
+
+MCDC_DEV void leak(Shared &S, Part &q, int face) {
+    atomicAdd(&S.leak[face], q.w);
+    atomicAdd(&S.wsum[W_LEAK], q.w);
+    atomicAdd(&S.cnt[C_LEAK], 1ull);
+    q.alive = false;
+}
+
+// Weight-window check: split above the window into n = min(ceil(w / w_T),
+// n_max) copies (daughters get stream tags from one parent Philox block),
+// roulette below it, nothing (and no draw) inside.
+template <class Ctx>
+MCDC_DEV void ww_check(const DevProblem &P, const RunArgs &A, Shared &S, Ctx &C, Part &q) {
+    float in[4 + kMaxG];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) in[a] = (float)(2.0 * ((q.x[a] - P.ww_lo[a]) * P.ww_inv[a]) - 1.0);
+    in[3] = (float)(2.0 * ((q.t - P.ww_lo[3]) * P.ww_inv[3]) - 1.0);
+#pragma unroll
+    for (int g = 0; g < kMaxG; ++g) in[4 + g] = g == q.g ? 1.0f : 0.0f;
+    const float y = mlp_infer(P.ww_params, 4 + P.G, in);
+    const double wt = own_exp(P.ww_logk - (double)y);
+    const double wl = (2.0 * wt) / (1.0 + P.ww_ratio);
+    const double wu = P.ww_ratio * wl;
+    if (q.w > wu) {
+        const double ratio = q.w / wt;
+        const int n = ratio >= (double)P.ww_nmax ? P.ww_nmax : (int)ceil(ratio);
+        if (n < 2) return;
+        Rng r = make_rng(A.seed, C.hist(), P.problem_id, q.tag, q.k);
+        uint32_t blk[4];
+        rng_block(r, blk);
+        q.k = r.k;
+        const double wn = q.w / (double)n;
+        q.w = wn;
+        for (int i = 1; i < n; ++i) {
+            Part d = q;
+            d.tag = blk[0] + (uint32_t)i * 0x9E3779B9u;
+            d.k = 0;
+            d.seq = 0;
+            if (!C.push_daughter(d)) return;
+        }
+        atomicAdd(&S.cnt[C_SPLIT], (unsigned long long)(n - 1));
+        atomicAdd(&S.cnt[C_PARTICLE], (unsigned long long)(n - 1));
+        trace_rec(A, C.hist(), q, EV_SPLIT, (double)n);
+    } else if (q.w < wl) {
+        Rng r = make_rng(A.seed, C.hist(), P.problem_id, q.tag, q.k);
+        const double xi = rng_uniform(r);
+        q.k = r.k;
+        if (xi * wt < q.w) {
+            atomicAdd(&S.wsum[W_GAIN], wt - q.w);
+            q.w = wt;
+            atomicAdd(&S.cnt[C_RR_SURVIVE], 1ull);
+            trace_rec(A, C.hist(), q, EV_RR_SURVIVE, 0.0);
+        } else {
+            atomicAdd(&S.wsum[W_LOSS], q.w);
+            atomicAdd(&S.cnt[C_RR_KILL], 1ull);
+            q.alive = false;
+            trace_rec(A, C.hist(), q, EV_RR_KILL, 0.0);
+        }
+    }
+}
+
+// Source particle of the context's history: position, birth time, direction,
+// group, unit weight, cell; leaks at once when born on the outer boundary
+// moving out.
+template <class Ctx>
+MCDC_DEV void stage_source(const DevProblem &P, const RunArgs &A, Shared &S, Ctx &C, Part &q) {
+    q.tag = 0;
+    q.k = 0;
+    q.seq = 0;
+    Rng r = make_rng(A.seed, C.hist(), P.problem_id, 0u, 0u);
+    if (P.src_box) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) q.x[a] = P.src_lo[a] + rng_uniform(r) * (P.src_hi[a] - P.src_lo[a]);
+    } else {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) q.x[a] = P.src_lo[a];
+    }
+    q.t = P.src_t0;
+    if (P.src_t1 > P.src_t0) q.t = P.src_t0 + rng_uniform(r) * (P.src_t1 - P.src_t0);
+    if (P.src_isotropic) {
+        iso_direction(r, q.u[0], q.u[1], q.u[2]);
+    } else {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) q.u[a] = P.src_dir[a];
+    }
+    q.g = P.src_group;
+    q.w = 1.0;
+    q.k = r.k;
+    q.alive = true;
+    q.ci = 0;
+    while (q.ci < P.n_census && !(P.census[q.ci] > q.t)) q.ci += 1;
+    atomicAdd(&S.cnt[C_PARTICLE], 1ull);
+    atomicAdd(&S.wsum[W_SOURCE], q.w);
+    q.cell = locate(P, q.x, q.u);
+    if (q.ci >= P.n_census) {
+        atomicAdd(&S.wsum[W_TIME_END], q.w);
+        atomicAdd(&S.cnt[C_TIME_END], 1ull);
+        q.alive = false;
+        trace_rec(A, C.hist(), q, EV_TIME_END, 0.0);
+        return;
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (!axis_in(P.outer_lo[a], P.outer_hi[a], q.x[a], q.u[a])) {
+            leak(S, q, 2 * a + (q.x[a] >= P.outer_hi[a] ? 1 : 0));
+            trace_rec(A, C.hist(), q, EV_LEAK, 0.0);
+            return;
+        }
+    }
+    trace_rec(A, C.hist(), q, EV_SOURCE, 0.0);
+}
+
+// Flight: census, surface and collision distances; the event (ties: census,
+// then surface, then collision); track-length scoring; the move of Fig. 2;
+// census and end-of-time handling.  Returns EV_CENSUS (particle continues),
+// EV_TIME_END or -1 (particle ended), EV_SURFACE or EV_SCATTER (the surface or
+// collision stage comes next; `d` is the flight length).
+template <class T, class Ctx>
+MCDC_DEV int stage_flight(const DevProblem &P, const RunArgs &A, Shared &S, const T &tally, Ctx &C,
+                          Part &q, double &d, uint32_t &n_piece, double &path) {
+    if (!C.count_flight()) {
+        set_status(A, MCDC_E_EVENT_CAP);
+        q.alive = false;
+        return -1;
+    }
+    C.imp_point(P, q);
+    const int mat = q.cell >= 0 ? P.box_mat[q.cell] : P.background_mat;
+    const double sig_t = P.sigma_t[mat * P.G + q.g];
+    const double v = P.speed[q.g];
+    double iu[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) iu[a] = q.u[a] != 0.0 ? 1.0 / q.u[a] : 0.0;
+
+    const double tc = P.census[q.ci];
+    const double d_t = (tc - q.t) * v;
+    int sax;
+    double spl;
+    const double d_s = dist_surface(P, q.x, q.u, iu, sax, spl);
+    double d_c = kInf;
+    Rng r = make_rng(A.seed, C.hist(), P.problem_id, q.tag, q.k);
+    if (sig_t > 0.0) {
+        const double xi = rng_uniform(r);
+        d_c = (-own_log(xi)) / sig_t;
+    }
+    q.k = r.k;
+
+    int ev;
+    if (d_t <= d_s && d_t <= d_c) { ev = EV_CENSUS; d = d_t; }
+    else if (d_s <= d_c) { ev = EV_SURFACE; d = d_s; }
+    else { ev = EV_SCATTER; d = d_c; }
+
+    n_piece += score_mesh(P, q.x, q.u, iu, q.t, v, d, q.w, q.g, tally);
+    if (P.has_detector) {
+        const double l = detector_len(P, q.x, q.u, iu, d);
+        if (l > 0.0) C.add_score(q.w * l);
+    }
+    const double wd = q.w * d;
+    path += wd;
+    C.add_path(wd);
+
+    q.x[0] = q.x[0] + q.u[0] * d;
+    q.x[1] = q.x[1] + q.u[1] * d;
+    q.x[2] = q.x[2] + q.u[2] * d;
+
+    if (ev == EV_CENSUS) {
+        q.t = tc;
+        if (q.ci == P.n_census - 1) {
+            atomicAdd(&S.wsum[W_TIME_END], q.w);
+            atomicAdd(&S.cnt[C_TIME_END], 1ull);
+            q.alive = false;
+            trace_rec(A, C.hist(), q, EV_TIME_END, d);
+            return EV_TIME_END;
+        }
+        q.ci += 1;
+        atomicAdd(&S.cnt[C_CENSUS], 1ull);
+        trace_rec(A, C.hist(), q, EV_CENSUS, d);
+        return EV_CENSUS;
+    }
+    q.t = q.t + d / v;
+    if (ev == EV_SURFACE) {
+        // snap the crossing coordinate onto the plane (select, no dynamic index)
+        if (sax == 0) q.x[0] = spl;
+        else if (sax == 1) q.x[1] = spl;
+        else if (sax == 2) q.x[2] = spl;
+    }
+    return ev;
+}
+
+// Surface crossing: outer boundary (leak / reflect), new cell, weight window.
+template <class Ctx>
+MCDC_DEV void stage_surface(const DevProblem &P, const RunArgs &A, Shared &S, Ctx &C, Part &q,
+                            double d) {
+    atomicAdd(&S.cnt[C_SURFACE], 1ull);
+    const int face = boundary(P, q);
+    if (face >= 0) {
+        leak(S, q, face);
+        trace_rec(A, C.hist(), q, EV_LEAK, d);
+        return;
+    }
+    q.cell = locate(P, q.x, q.u);
+    trace_rec(A, C.hist(), q, EV_SURFACE, d);
+    if (Ctx::kWW && P.ww_on) ww_check(P, A, S, C, q);
+}
+
+// Collision: analog absorption or implicit capture with weight cutoff, then
+// the outgoing group (cumulative row) and an isotropic direction; weight window.
+template <class Ctx>
+MCDC_DEV void stage_collision(const DevProblem &P, const RunArgs &A, Shared &S, Ctx &C, Part &q,
+                              double d) {
+    atomicAdd(&S.cnt[C_COLLISION], 1ull);
+    const int mat = q.cell >= 0 ? P.box_mat[q.cell] : P.background_mat;
+    const double sig_t = P.sigma_t[mat * P.G + q.g];
+    const double *ss_row = P.sigma_s + (mat * P.G + q.g) * P.G;
+    double sig_s = 0.0;
+    for (int h = 0; h < P.G; ++h) sig_s = sig_s + ss_row[h];
+    Rng r = make_rng(A.seed, C.hist(), P.problem_id, q.tag, q.k);
+    if (!P.implicit_capture) {
+        const double xi = rng_uniform(r);
+        q.k = r.k;
+        if (!(xi * sig_t < sig_s)) {
+            atomicAdd(&S.wsum[W_ABSORB], q.w);
+            atomicAdd(&S.cnt[C_ABSORB], 1ull);
+            q.alive = false;
+            trace_rec(A, C.hist(), q, EV_ABSORB, d);
+            return;
+        }
+    } else {
+        const double c = sig_s / sig_t;
+        const double wn = q.w * c;
+        atomicAdd(&S.wsum[W_ABSORB], q.w - wn);
+        q.w = wn;
+        if (q.w < P.w_cut) {
+            const double xi = rng_uniform(r);
+            q.k = r.k;
+            if (xi * P.w_surv < q.w) {
+                atomicAdd(&S.wsum[W_GAIN], P.w_surv - q.w);
+                q.w = P.w_surv;
+                atomicAdd(&S.cnt[C_CUT_SURVIVE], 1ull);
+            } else {
+                atomicAdd(&S.wsum[W_LOSS], q.w);
+                atomicAdd(&S.cnt[C_CUT_KILL], 1ull);
+                q.alive = false;
+                trace_rec(A, C.hist(), q, EV_CUT_KILL, d);
+                return;
+            }
+        }
+    }
+    if (P.G > 1) {
+        const double xi = rng_uniform(r);
+        const double target = xi * sig_s;
+        double cum = 0.0;
+        int gn = -1, last = 0;
+        for (int h = 0; h < P.G; ++h) {
+            cum = cum + ss_row[h];
+            if (ss_row[h] > 0.0) last = h;
+            if (gn < 0 && target < cum) gn = h;
+        }
+        q.g = gn >= 0 ? gn : last;
+    }
+    iso_direction(r, q.u[0], q.u[1], q.u[2]);
+    q.k = r.k;
+    trace_rec(A, C.hist(), q, EV_SCATTER, d);
+    if (Ctx::kWW && P.ww_on) ww_check(P, A, S, C, q);
+}
+
+}  // namespace mcdc

@@ -1,0 +1,91 @@
+"""GPU tests of the learned-importance part: the hand-written MLP kernels
+against the FP64 oracle (forward, gradient, Adam), the in-kernel FP32
+inference through weight-window parity, and the end-to-end gain of the
+trained network over the analog run."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import mlp as M
+
+pytestmark = pytest.mark.gpu
+
+IN, H = 5, 64
+
+
+def _data(n, seed):
+    rng = np.random.default_rng(seed)
+    X = np.concatenate([rng.uniform(-1, 1, (n, 4)), np.ones((n, 1))], axis=1).astype(np.float32)
+    y = (np.sin(2 * X[:, 0]) + X[:, 1] * X[:, 2] - 0.5 * X[:, 3]).astype(np.float32)
+    wt = rng.uniform(0.5, 2.0, n).astype(np.float32)
+    return X, y, wt
+
+
+def test_mlp_forward_matches_oracle():
+    from paper_2409_04668_amd import learned_ww as L
+    p = M.init_params(IN, H, seed=1)
+    X, _, _ = _data(3000, 2)
+    got = L.gpu_forward(p, X)
+    ref, _ = M.forward(p.astype(np.float64), X.astype(np.float64), IN, H)
+    assert np.max(np.abs(got - ref)) <= 2e-5 * (np.max(np.abs(ref)) + 1)
+
+
+def test_mlp_gradient_matches_oracle():
+    import ctypes as C
+    import torch
+    from paper_2409_04668_amd import mcdc
+    p = M.init_params(IN, H, seed=3)
+    X, y, wt = _data(2500, 4)          # several chunks and a ragged tail
+    dev = torch.device("cuda:0")
+    tp = torch.from_numpy(p).to(dev)
+    tX, ty, tw = (torch.from_numpy(a).to(dev) for a in (X, y, wt))
+    tg = torch.zeros_like(tp)
+    tl = torch.zeros(1, dtype=torch.float32, device=dev)
+    scr = torch.empty(int(mcdc._lib.mcdc_mlp_scratch_bytes(IN, len(X))), dtype=torch.uint8, device=dev)
+    mcdc.check(mcdc._lib.mcdc_mlp_grad(mcdc._ptr(tp), IN, mcdc._ptr(tX), mcdc._ptr(ty),
+                                       mcdc._ptr(tw), len(X), mcdc._ptr(tg), mcdc._ptr(tl),
+                                       mcdc._ptr(scr), mcdc._stream_ptr()), "grad")
+    g = tg.cpu().numpy().astype(np.float64)
+    ref = M.grad(p.astype(np.float64), X.astype(np.float64), y.astype(np.float64),
+                 wt.astype(np.float64), IN, H)
+    lref = M.loss(p.astype(np.float64), X, y, wt, IN, H)
+    assert abs(tl.item() - lref) <= 1e-4 * lref
+    assert np.linalg.norm(g - ref) <= 1e-4 * np.linalg.norm(ref)
+    assert np.max(np.abs(g - ref)) <= 1e-4 * np.max(np.abs(ref))
+
+
+def test_mlp_adam_training_matches_oracle_and_decreases_loss():
+    from paper_2409_04668_amd import learned_ww as L
+    X, y, wt = _data(2000, 5)
+    p0 = L._init_params(IN, 7)
+    params, losses, _ = L.gpu_train(X, y, wt, steps=50, lr=1e-3, params=p0)
+    ref = p0.astype(np.float64)
+    m = np.zeros_like(ref)
+    v = np.zeros_like(ref)
+    ref_losses = []
+    for step in range(1, 51):
+        ref_losses.append(M.loss(ref, X, y, wt, IN, H))
+        ref, m, v = M.adam_step(ref, M.grad(ref, X, y, wt, IN, H), m, v, step, 1e-3)
+    assert np.max(np.abs(losses - np.array(ref_losses)) / np.array(ref_losses)) < 1e-3
+    assert np.max(np.abs(params - ref)) < 1e-3 * max(1.0, np.max(np.abs(ref)))
+    assert all(b < a for a, b in zip(losses, losses[1:]))
+
+
+@pytest.mark.slow
+def test_learned_weight_windows_gain_fom_and_stay_unbiased():
+    """Small end-to-end pipeline on the duct problem: importance estimate from
+    analog runs, GPU training, weight windows; detector mean agrees with the
+    analog run within 3 sigma and the FOM at equal relative error improves."""
+    from paper_2409_04668_amd import learned_ww as L
+    from paper_2409_04668_amd import workloads as W
+    p = W.config2()
+    ww, info = L.build_ww(p, n_runs=8, n_per_run=1_000_000, steps=1500)
+    assert info["loss_last"] < info["loss_first"]
+    pw = W.config4(ww)
+    pw["stack_cap"] = 256
+    a = L.fom_at_target(p, seed=500, target=0.03, pilot=2_000_000)
+    w = L.fom_at_target(pw, seed=600, target=0.03, pilot=200_000)
+    z = abs(a["mean"] - w["mean"]) / math.hypot(a["mean"] * a["rel_err"], w["mean"] * w["rel_err"])
+    assert z < 3.5, (a, w)
+    assert w["fom"] > a["fom"], (a, w)

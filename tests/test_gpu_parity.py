@@ -76,10 +76,29 @@ def _ww_box():
     return p
 
 
-def test_weight_window_parity_random_mlp():
+def ramp_mlp(slope, noise_seed=None):
+    """y = slope * xhat_x (one ReLU path), optionally plus a small random net."""
+    prm = np.zeros(M.n_params(5, 64), np.float32)
+    o = 0
+    prm[o] = 1.0                            # W1[0][0]
+    o += 64 * 5
+    prm[o] = 1.0                            # b1[0]
+    o += 64
+    prm[o] = 1.0                            # W2[0][0]
+    o += 64 * 64 + 64
+    prm[o] = slope                          # W3[0]
+    o += 64
+    prm[o] = -slope                         # b3
+    if noise_seed is not None:
+        noise = M.init_params(5, 64, seed=noise_seed) * np.float32(0.02)
+        noise[0] = noise[64 * 5] = noise[64 * 5 + 64] = 0.0
+        prm = prm + noise
+    return prm
+
+
+def test_weight_window_parity_ramp_mlp():
     p = _ww_box()
-    prm = M.init_params(5, 64, seed=3) * np.float32(0.3)
-    p["ww"] = dict(params=prm, hidden=64, logk=0.0, ratio=5.0, n_max=10)
+    p["ww"] = dict(params=ramp_mlp(2.0, noise_seed=3), hidden=64, logk=0.0, ratio=5.0, n_max=10)
     p["stack_cap"] = 256
     gp, orc = full_parity(p, 1500, seed=108, trace_cap=400000)
     c = orc.counters
@@ -89,10 +108,71 @@ def test_weight_window_parity_random_mlp():
 def test_weight_window_parity_duct():
     p = W.config2()
     p["mesh"]["n"] = np.array([6, 10, 6, 4], np.int32)
-    prm = M.init_params(5, 64, seed=5) * np.float32(0.2)
-    p["ww"] = dict(params=prm, hidden=64, logk=0.3, ratio=5.0, n_max=10)
+    p["ww"] = dict(params=ramp_mlp(-1.5, noise_seed=5), hidden=64, logk=0.3, ratio=5.0, n_max=10)
     p["stack_cap"] = 256
-    full_parity(p, 800, seed=109, trace_cap=400000)
+    gp, orc = full_parity(p, 800, seed=109, trace_cap=400000)
+    assert orc.counters["split"] > 10
+
+
+# ---------------------------------------------------------------------------
+# event-based schedule: same per-particle trajectories, other execution order
+# ---------------------------------------------------------------------------
+
+def _ev(chunk=0):
+    mc = _mcdc()
+    return mc.make_options(mc.SCHED_EVENT, event_chunk=chunk)
+
+
+def test_event_schedule_slab_parity():
+    full_parity(W.config1(), 3000, seed=121, trace_cap=60000, options=_ev())
+
+
+def test_event_schedule_duct_census_parity_small_chunks():
+    p = W.config2(n_census=5)
+    p["mesh"]["n"] = np.array([12, 20, 12, 10], np.int32)
+    # chunks of 1000 histories: several chunks per batch and a ragged last chunk
+    full_parity(p, 4321, seed=122, trace_cap=300000, options=_ev(1000))
+
+
+def test_event_schedule_multigroup_implicit_parity():
+    p = W.config3()
+    p["implicit_capture"] = True
+    p["mesh"]["n"] = np.array([6, 10, 6, 5], np.int32)
+    full_parity(p, 300, seed=123, trace_cap=600000, options=_ev())
+
+
+def test_event_schedule_weight_windows():
+    """With splitting, a history's particles run in another order, so the
+    per-history sums may round differently; trajectories stay identical."""
+    from gpu_util import assert_counters, assert_traces_equal, run_pair
+    p = _ww_box()
+    p["ww"] = dict(params=ramp_mlp(2.0, noise_seed=3), hidden=64, logk=0.0, ratio=5.0, n_max=10)
+    p["stack_cap"] = 256
+    gp, orc, tg, to, hg, ho = run_pair(p, 1500, 124, trace_cap=400000, options=_ev())
+    assert_traces_equal(tg[0], to[0])
+    np.testing.assert_allclose(hg[0], ho[0], rtol=1e-12, atol=0)
+    s, s2 = gp.raw()
+    assert_close_sums(s, orc.tally_sum, what="tally_sum")
+    assert_counters(gp.counters(), orc)
+
+
+def test_history_and_event_schedules_agree_at_scale():
+    """2e6 duct histories: both schedules give identical per-history results."""
+    mc = _mcdc()
+    p = W.config2(n_census=4)
+    n = 2_000_000
+    out = []
+    for opt in (mc.make_options(mc.SCHED_HISTORY), _ev(1 << 20)):
+        gp = mc.Problem(p, opt)
+        gp.set_history_scores(n)
+        gp.run(n, 31)
+        out.append((gp.history_scores(), gp.raw()[0], gp.counters()))
+        gp.close()
+    (h1, s1, c1), (h2, s2, c2) = out
+    assert np.array_equal(h1, h2)
+    assert_close_sums(s1, s2, what="tally")
+    for k in ("histories", "flights", "pieces", "collisions", "leaks", "census_stops", "time_ends"):
+        assert c1[k] == c2[k], k
 
 
 def test_importance_estimate_parity():
