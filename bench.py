@@ -76,6 +76,9 @@ def main():
     ap.add_argument("--waves-per-cu", type=int, default=0)
     ap.add_argument("--cpu-sample", type=int, default=8_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=["duct", "batch", "fom"], default="duct")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run a device-to-device copy of BYTES (PMC calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -85,6 +88,20 @@ def main():
     import torch
     from paper_2409_04668_amd import mcdc
     from paper_2409_04668_amd import workloads as W
+
+    if args.calibrate_copy:
+        n = args.calibrate_copy // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n * 8, "copies": 3}), flush=True)
+        return
+    if args.workload == "batch":
+        return bench_batch(args, torch, mcdc, W)
+    if args.workload == "fom":
+        return bench_fom(args, torch, mcdc, W)
 
     prob = W.config2()
     sched = mcdc.SCHED_HISTORY if args.schedule == "history" else mcdc.SCHED_EVENT
@@ -144,6 +161,53 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_sample, seed)
     print(json.dumps(out), flush=True)
+
+
+def bench_batch(args, torch, mcdc, W):
+    """256 batched problems (1e4-1e6 histories each, 10 census steps): one
+    pass = every problem's histories; histories/s over the whole batch."""
+    probs, n_hist = W.config5()
+    bp = mcdc.BatchProblem(probs, n_hist)
+    total = int(n_hist.sum())
+    for i in range(args.warmup):
+        bp.run(7 + i)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        bp.run(1000 + i)
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    pieces = sum(bp.counters(p)["pieces"] for p in range(len(probs)))
+    print(json.dumps({
+        "metric": "histories/s, 256 batched problems (one persistent launch per census step, "
+                  "graph-replayed)", "value": total * args.steps / T, "unit": "histories/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * T / args.steps,
+        "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "256 box problems, 1-8 regions, 1-7 groups, 20^3 x 10 t-bins each",
+                   "histories_per_pass": total},
+        "pieces_per_history": pieces / (total * (args.steps + args.warmup))}), flush=True)
+
+
+def bench_fom(args, torch, mcdc, W):
+    """FOM = 1/(R^2 T) at 1% detector relative error: analog vs learned weight
+    windows on the duct problem (training time reported separately)."""
+    from paper_2409_04668_amd import learned_ww as L
+    p = W.config2()
+    t0 = time.perf_counter()
+    ww, info = L.build_ww(p, n_runs=20, n_per_run=1_000_000)
+    t_build = time.perf_counter() - t0
+    pw = W.config4(ww)
+    analog = L.fom_at_target(p, seed=31, target=0.01, pilot=20_000_000)
+    learned = L.fom_at_target(pw, seed=41, target=0.01, pilot=2_000_000)
+    z = abs(analog["mean"] - learned["mean"]) / (
+        (analog["mean"] * analog["rel_err"]) ** 2 + (learned["mean"] * learned["rel_err"]) ** 2) ** 0.5
+    print(json.dumps({
+        "metric": "FOM 1/(R^2 T) at 1% detector relative error, analog vs learned weight windows",
+        "value": learned["fom"] / analog["fom"], "unit": "FOM ratio (learned / analog)",
+        "analog": analog, "learned_ww": learned, "agreement_sigma": z,
+        "training": dict(info, total_seconds=t_build),
+        "fom_with_training_amortised": 1.0 / (learned["rel_err"] ** 2 * (learned["seconds"] + t_build)),
+        "n_gpus": 1, "dtype": "f64", "data": "synthetic"}), flush=True)
 
 
 if __name__ == "__main__":

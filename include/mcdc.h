@@ -167,11 +167,13 @@ int mcdc_set_history_scores(mcdc_handle h, double *dev_xh);
 /* Learned weight windows: copy an MLP (in = 4 + G inputs scaled to [-1,1]
  * over the outer box and [0, end time], 64 -> 64 ReLU hidden units, 1 output
  * = log importance; FP32, layout W1,b1,W2,b2,W3,b3) into the workspace and
- * turn splitting/roulette on: target w_T = exp(logk - y), window
- * [2 w_T/(1+ratio), ratio * 2 w_T/(1+ratio)], at most n_max copies.
- * params == NULL turns weight windows off. */
+ * turn splitting/roulette on: y = network output clamped to [ymin, ymax]
+ * (the range of its training targets), target w_T = exp(logk - y), window
+ * [2 w_T/(1+ratio), ratio * 2 w_T/(1+ratio)], at most n_max copies, checked
+ * after every scatter and internal surface crossing.  Needs a problem created
+ * with stack_cap > 0.  params == NULL turns weight windows off. */
 int mcdc_set_ww_mlp(mcdc_handle h, const float *params, size_t n_params, double logk,
-                    double ratio, int32_t n_max);
+                    double ratio, int32_t n_max, float ymin, float ymax);
 
 /* Coarse importance estimate accumulated by runs with imp_on: host copies of
  * score[c] and weight[c] for G * imp_n[0..3] cells (x fastest, then y, z, t, g). */
@@ -220,6 +222,9 @@ int mcdc_run_batch(mcdc_handle h, uint64_t seed, void *stream);
 /* Raw mesh sums of problem p (host copy, n = its bins). */
 int mcdc_get_batch_raw(mcdc_handle h, size_t p, double *tally_sum, size_t n, void *stream);
 int mcdc_get_batch_counters(mcdc_handle h, size_t p, mcdc_counters *out, void *stream);
+/* Per-history sum of weight * flight length of problem p for the histories of
+ * the last pass, summed in event order (host copy, n = its histories). */
+int mcdc_get_batch_history_path(mcdc_handle h, size_t p, double *out, size_t n, void *stream);
 
 /* Kernel timing: with `on` = 1, later runs record a pair of HIP events on the
  * run's stream around every tracking-kernel launch; mcdc_kernel_time

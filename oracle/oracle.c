@@ -563,7 +563,8 @@ static void o_leak(o_ctx *C, o_part *q, int face)
     q->alive = 0;
 }
 
-/* Weight-window check (MLP importance): target w_T = exp(log K - y),
+/* Weight-window check (MLP importance): y = network output clamped to the
+ * range [ymin, ymax] of its training targets, target w_T = exp(log K - y),
  * window [w_L, w_U] with w_L = 2 w_T / (1 + r), w_U = r w_L.  Above: split
  * into n = min(ceil(w / w_T), n_max) copies of weight w/n; the n-1 daughters
  * go on the LIFO stack with stream tags derived from one parent block.  Below:
@@ -578,6 +579,8 @@ static void o_ww(o_ctx *C, o_part *q)
     in[3] = (float)(2.0 * ((q->t - C->ww_lo[3]) * C->ww_inv[3]) - 1.0);
     for (int g = 0; g < P->G; ++g) in[4 + g] = g == q->g ? 1.0f : 0.0f;
     float y = orc_mlp_f32(P->ww_params, in_dim, P->ww_hidden, in);
+    if (y < P->ww_ymin) y = P->ww_ymin;
+    if (y > P->ww_ymax) y = P->ww_ymax;
     double wt = orc_exp(P->ww_logk - (double)y);
     double wl = (2.0 * wt) / (1.0 + P->ww_ratio);
     double wu = P->ww_ratio * wl;

@@ -86,6 +86,7 @@ typedef struct {
     int32_t imp_n[4];
     int32_t ww_on, ww_hidden, ww_nmax;
     const float *ww_params;
+    float ww_ymin, ww_ymax;           /* network output clamped to [ymin, ymax] */
     double ww_logk, ww_ratio;
     int32_t n_batches;
     int64_t max_events;

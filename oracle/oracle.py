@@ -65,7 +65,8 @@ class OrcProblem(C.Structure):
         ("has_detector", C.c_int32), ("det_lo", D3), ("det_hi", D3),
         ("imp_on", C.c_int32), ("imp_n", I4),
         ("ww_on", C.c_int32), ("ww_hidden", C.c_int32), ("ww_nmax", C.c_int32),
-        ("ww_params", PF), ("ww_logk", C.c_double), ("ww_ratio", C.c_double),
+        ("ww_params", PF), ("ww_ymin", C.c_float), ("ww_ymax", C.c_float),
+        ("ww_logk", C.c_double), ("ww_ratio", C.c_double),
         ("n_batches", C.c_int32), ("max_events", C.c_int64), ("stack_cap", C.c_int32),
         ("problem_id", C.c_uint32),
     ]
@@ -193,6 +194,8 @@ class _Problem:
             s.ww_nmax = int(ww.get("n_max", 10))
             s.ww_logk = float(ww["logk"])
             s.ww_ratio = float(ww.get("ratio", 5.0))
+            s.ww_ymin = float(ww.get("ymin", -3.0e38))
+            s.ww_ymax = float(ww.get("ymax", 3.0e38))
         s.n_batches = int(prob["n_batches"])
         s.max_events = int(prob["max_events"])
         s.stack_cap = int(prob["stack_cap"])

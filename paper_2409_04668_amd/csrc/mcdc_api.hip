@@ -353,7 +353,7 @@ int mcdc_set_history_scores(mcdc_handle h, double *dev_xh) {
 }
 
 int mcdc_set_ww_mlp(mcdc_handle h, const float *params, size_t n, double logk, double ratio,
-                    int32_t n_max) {
+                    int32_t n_max, float ymin, float ymax) {
     if (!h) return fail(MCDC_E_INVALID, "null handle");
     if (!params) {
         h->P.ww_on = 0;
@@ -363,16 +363,19 @@ int mcdc_set_ww_mlp(mcdc_handle h, const float *params, size_t n, double logk, d
     if (h->desc.imp_on) return fail(MCDC_E_STATE, "weight windows and the importance estimate exclude each other");
     if (n != mcdc_mlp_param_count(4 + h->desc.G)) return fail(MCDC_E_INVALID, "wrong parameter count");
     if (!(ratio >= 1.0) || n_max < 2) return fail(MCDC_E_INVALID, "ratio >= 1 and n_max >= 2 required");
+    if (!(ymin <= ymax)) return fail(MCDC_E_INVALID, "ymin must not exceed ymax");
     hipError_t e = hipMemcpy(h->ws + h->L.ww_params, params, n * sizeof(float), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "set_ww_mlp");
     h->P.ww_on = 1;
     h->P.ww_logk = logk;
     h->P.ww_ratio = ratio;
     h->P.ww_nmax = n_max;
+    h->P.ww_ymin = ymin;
+    h->P.ww_ymax = ymax;
     return MCDC_OK;
 }
 
-RunArgs base_args(mcdc_handle h, uint64_t seed) {
+static RunArgs base_args(mcdc_handle h, uint64_t seed) {
     RunArgs A;
     memset(&A, 0, sizeof(A));
     A.seed = seed;
@@ -430,7 +433,7 @@ int mcdc_run(mcdc_handle h, uint64_t n, uint64_t seed, void *stream) {
     return MCDC_OK;
 }
 
-int read_acc(mcdc_handle h, DevAcc &acc, hipStream_t s) {
+static int read_acc(mcdc_handle h, DevAcc &acc, hipStream_t s) {
     hipError_t e = hipStreamSynchronize(s);
     if (e == hipSuccess) e = hipMemcpy(&acc, h->ws + h->L.acc, sizeof(DevAcc), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "read accumulators");
@@ -458,7 +461,9 @@ int mcdc_get_raw(mcdc_handle h, double *tsum, double *tsumsq, size_t n, void *st
     return MCDC_OK;
 }
 
-void fill_counters(const DevAcc &a, mcdc_counters *o) {
+}  // extern "C"
+
+void mcdc::fill_counters(const DevAcc &a, mcdc_counters *o) {
     const unsigned long long *c = a.cnt;
     o->histories = c[C_HIST]; o->flights = c[C_FLIGHT]; o->pieces = c[C_PIECE];
     o->collisions = c[C_COLLISION]; o->absorptions = c[C_ABSORB]; o->surfaces = c[C_SURFACE];
@@ -474,6 +479,8 @@ void fill_counters(const DevAcc &a, mcdc_counters *o) {
     o->det_sumsq = a.det[1];
     o->status = a.status;
 }
+
+extern "C" {
 
 int mcdc_get_counters(mcdc_handle h, mcdc_counters *out, void *stream) {
     if (!h || !out) return fail(MCDC_E_INVALID, "null argument");

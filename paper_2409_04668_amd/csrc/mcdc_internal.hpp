@@ -63,6 +63,7 @@ struct DevProblem {
     double imp_lo[4], imp_f[4];
     int32_t ww_on, ww_nmax;
     const float *ww_params;                               // device
+    float ww_ymin, ww_ymax;                               // output clamp
     double ww_logk, ww_ratio, ww_lo[4], ww_inv[4];
     int64_t max_events;
     int32_t stack_cap;

@@ -1,6 +1,10 @@
 // Host-side handle state shared by the runtime translation units.
 #pragma once
 
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
 #include <string>
 #include <utility>
 #include <vector>
@@ -58,5 +62,12 @@ void event_destroy(mcdc_problem *h);
 
 // batched problems (mcdc_batch.hip)
 void batch_destroy(mcdc_problem *h);
+
+// shared host helpers (mcdc_api.hip)
+int validate_desc(const mcdc_problem_desc *d);
+Options resolve_options(const mcdc_options *o);
+void build_dev_problem(const mcdc_problem_desc *d, char *ws, const Layout &L, DevProblem &P);
+std::vector<double> pack_tables(const mcdc_problem_desc *d);
+void fill_counters(const DevAcc &a, mcdc_counters *o);
 
 }  // namespace mcdc

@@ -1,21 +1,31 @@
-"""Learned weight windows: importance estimate -> GPU MLP training -> windows.
+"""Learned weight windows: importance tallies -> GPU MLP training -> windows.
 
-Pipeline (every numerical step runs in libmcdc's kernels; this module only
-orchestrates calls and assembles the training set):
-  1. analog runs with the coarse importance estimate on (forward estimate:
-     each flight start in a coarse space-time-group cell adds the detector score
-     that its history still makes afterwards, and one unit of weight);
-  2. training set: one point per cell, input = cell centre scaled to [-1,1]
-     over the outer box and [0, end time] plus a group one-hot, target =
-     log(score / weight); cells that were visited but never led to a score get
-     a floor target one decade below the smallest positive estimate;
-  3. full-batch Adam on the GPU (mcdc_mlp_train) for the log-importance MLP
-     in -> 64 -> 64 -> 1;
-  4. log K = log of the mean importance over source samples, so that source
-     particles (weight 1) start near their target weight;
-  5. mcdc_set_ww_mlp turns splitting/roulette on.
-The analog run stays the reference: weight windows change variance, not the
-expected tallies.
+Every numerical step runs in libmcdc's kernels; this module orchestrates the
+calls and assembles the training set.
+
+Importance data (tallies the transport itself produces), one of:
+  * reciprocal runs (one energy group): for one-group transport with isotropic
+    scattering, the expected detector track length of a particle emitted
+    isotropically at x equals the detector volume times the scalar flux at x
+    from a uniform isotropic source in the detector (reciprocity), and
+    transport is invariant under time shifts, so the importance of (x, t) is
+    the flux at x from a detector source at time 0 accumulated over the
+    remaining horizon T_end - t.  The runs use the same problem with the
+    source moved into the detector and a coarse space-time tally; the
+    horizon sum is a cumulative sum over time bins.
+  * forward estimate (any number of groups): analog runs with the coarse
+    importance estimate on (each flight start in a coarse cell adds the
+    detector score its history still makes afterwards); sparse when the
+    detector is rarely reached.
+Then: the training set is one point per coarse cell with a positive estimate
+(input = cell centre scaled to [-1,1] over the outer box and [0, T_end] plus a
+group one-hot; target = log importance); full-batch Adam on the GPU
+(mcdc_mlp_train); log K = log of the mean importance over source samples so
+that source particles start inside their windows; and the network output is
+clamped at run time to the range of its training targets.
+
+Weight windows change the variance, not the expected tallies; the analog run
+stays the reference for both the tallies and the figure of merit.
 """
 from __future__ import annotations
 
@@ -28,27 +38,68 @@ from . import mcdc
 from . import workloads as W
 
 
-def _cell_centres(prob: dict, n4, G: int):
+def _cell_inputs(n4, G: int):
+    """Inputs of the cell centres in tally order [g][t][z][y][x]."""
     nx, ny, nz, nt = [int(v) for v in n4]
     g, it, iz, iy, ix = np.meshgrid(np.arange(G), np.arange(nt), np.arange(nz), np.arange(ny),
                                     np.arange(nx), indexing="ij")
-    cx = (ix.ravel() + 0.5) / nx
-    cy = (iy.ravel() + 0.5) / ny
-    cz = (iz.ravel() + 0.5) / nz
-    ct = (it.ravel() + 0.5) / nt
-    X = np.zeros((cx.size, 4 + G), np.float32)
-    X[:, 0] = 2 * cx - 1
-    X[:, 1] = 2 * cy - 1
-    X[:, 2] = 2 * cz - 1
-    X[:, 3] = 2 * ct - 1
-    X[np.arange(cx.size), 4 + g.ravel()] = 1.0
+    X = np.zeros((ix.size, 4 + G), np.float32)
+    X[:, 0] = 2 * (ix.ravel() + 0.5) / nx - 1
+    X[:, 1] = 2 * (iy.ravel() + 0.5) / ny - 1
+    X[:, 2] = 2 * (iz.ravel() + 0.5) / nz - 1
+    X[:, 3] = 2 * (it.ravel() + 0.5) / nt - 1
+    X[np.arange(ix.size), 4 + g.ravel()] = 1.0
     return X
 
 
-def importance_estimate(prob: dict, n_runs: int, n_per_run: int, seed0: int, grid=None,
-                        options=None):
-    """Run analog histories with the coarse importance estimate on; returns
-    (score, weight, seconds)."""
+def reciprocal_importance(prob: dict, n_runs=20, n_per_run=1_000_000, seed0=W.ROOT_SEED + 1,
+                          grid=None, options=None):
+    """Importance I[t][z][y][x] on the coarse grid from runs with the source in
+    the detector (one group only).  Returns (I, seconds)."""
+    import torch
+    if prob["sigma_t"].shape[1] != 1:
+        raise ValueError("reciprocal importance needs one energy group")
+    det = prob["detector"]
+    if det is None:
+        raise ValueError("the problem has no detector")
+    n4 = np.asarray((grid or W.coarse_importance_grid())["n"], np.int32)
+    t_end = float(prob["census"][-1])
+    q = W.with_(prob, ww=None, importance=None, detector=None, n_batches=1)
+    q["source"] = dict(kind="box", lo=np.asarray(det["lo"], float), hi=np.asarray(det["hi"], float),
+                       t0=0.0, t1=0.0, isotropic=True, dir=np.array([1.0, 0.0, 0.0]), group=0)
+    lo = np.asarray(prob["outer_lo"], float)
+    hi = np.asarray(prob["outer_hi"], float)
+    q["mesh"] = dict(lo=np.array([lo[0], lo[1], lo[2], 0.0]), hi=np.array([hi[0], hi[1], hi[2], t_end]),
+                     n=n4, per_group=False)
+    gp = mcdc.Problem(q, options)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(n_runs):
+        gp.run(n_per_run, seed0 + i)
+    s, _ = gp.raw()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    gp.close()
+    nx, ny, nz, nt = [int(v) for v in n4]
+    vol = np.prod((hi - lo) / n4[:3])
+    T = s.reshape(nt, nz, ny, nx) / (n_runs * n_per_run) / vol      # flux-time per bin
+    cum = np.cumsum(T, axis=0)
+    dtb = t_end / nt
+    I = np.zeros_like(T)
+    for b in range(nt):
+        horizon = t_end - (b + 0.5) * dtb
+        full = int(horizon // dtb)
+        frac = (horizon - full * dtb) / dtb
+        v = cum[full - 1] if full > 0 else np.zeros_like(T[0])
+        if full < nt:
+            v = v + frac * T[full]
+        I[b] = v
+    return I, dt, n4
+
+
+def forward_importance(prob: dict, n_runs: int, n_per_run: int, seed0: int, grid=None,
+                       options=None):
+    """Forward estimate (any G): I[g][t][z][y][x] = score / weight per cell."""
     import torch
     q = W.with_(prob, importance=grid or W.coarse_importance_grid(), ww=None,
                 implicit_capture=False)
@@ -61,23 +112,19 @@ def importance_estimate(prob: dict, n_runs: int, n_per_run: int, seed0: int, gri
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     gp.close()
-    return S, Wt, dt, q["importance"]["n"]
+    I = np.where((S > 0) & (Wt > 0), S / np.maximum(Wt, 1e-300), 0.0)
+    return I, dt, np.asarray(q["importance"]["n"])
 
 
-def training_set(prob: dict, S, Wt, n4):
-    G = prob["sigma_t"].shape[1]
-    X = _cell_centres(prob, n4, G)
-    pos = (S > 0) & (Wt > 0)
+def training_set(I, n4, G: int):
+    X = _cell_inputs(n4, G)
+    Iv = np.asarray(I, float).reshape(-1)
+    pos = Iv > 0
     if not pos.any():
-        raise RuntimeError("importance estimate has no scoring cell: run more histories")
-    I = np.zeros_like(S)
-    I[pos] = S[pos] / Wt[pos]
-    floor = I[pos].min() / 10.0
-    visited = Wt > 0
-    y = np.where(pos, np.log(np.where(pos, I, 1.0)), np.log(floor)).astype(np.float32)
-    wt = np.where(pos, np.sqrt(Wt), 0.25 * np.sqrt(Wt)).astype(np.float32)
-    sel = visited
-    return X[sel], y[sel], wt[sel]
+        raise RuntimeError("importance estimate is zero everywhere: run more histories")
+    y = np.log(Iv[pos]).astype(np.float32)
+    wt = np.ones(int(pos.sum()), np.float32)
+    return X[pos], y, wt
 
 
 def _init_params(in_dim: int, seed: int) -> np.ndarray:
@@ -91,16 +138,18 @@ def _init_params(in_dim: int, seed: int) -> np.ndarray:
 
 
 def gpu_train(X, y, wt, steps=3000, lr=3e-3, seed=1, params=None, device="cuda:0"):
-    """Train the log-importance MLP with the library's kernels (full batch,
-    Adam).  Returns (params, loss history, seconds)."""
+    """Full-batch Adam with the library's kernels.  The output bias starts at
+    the target mean.  Returns (params, loss history, seconds)."""
     import torch
     n, in_dim = X.shape
-    p0 = _init_params(in_dim, seed) if params is None else np.asarray(params, np.float32)
+    p0 = _init_params(in_dim, seed) if params is None else np.asarray(params, np.float32).copy()
+    if params is None:
+        p0[-1] = np.float32(np.average(y, weights=wt))
     dev = torch.device(device)
     tX = torch.from_numpy(np.ascontiguousarray(X, np.float32)).to(dev)
     ty = torch.from_numpy(np.ascontiguousarray(y, np.float32)).to(dev)
     tw = torch.from_numpy(np.ascontiguousarray(wt, np.float32)).to(dev)
-    tp = torch.from_numpy(p0.copy()).to(dev)
+    tp = torch.from_numpy(p0).to(dev)
     tm = torch.zeros_like(tp)
     tv = torch.zeros_like(tp)
     tg = torch.zeros_like(tp)
@@ -132,8 +181,8 @@ def gpu_forward(params, X, device="cuda:0"):
     return out.cpu().numpy()
 
 
-def source_log_k(prob: dict, params, n=10000, seed=3):
-    """log of the mean importance exp(y) over source samples."""
+def source_log_k(prob: dict, params, ymin, ymax, n=10000, seed=3):
+    """log of the mean importance exp(y) over source samples (clamped y)."""
     rng = np.random.default_rng(seed)
     src = prob["source"]
     lo = np.asarray(prob["outer_lo"], float)
@@ -149,29 +198,40 @@ def source_log_k(prob: dict, params, n=10000, seed=3):
     X[:, :3] = 2 * (pos - lo) / (hi - lo) - 1
     X[:, 3] = 2 * t / t_end - 1
     X[:, 4 + int(src["group"])] = 1.0
-    yv = gpu_forward(params, X).astype(np.float64)
+    yv = np.clip(gpu_forward(params, X), ymin, ymax).astype(np.float64)
     m = yv.max()
     return float(m + np.log(np.mean(np.exp(yv - m))))
 
 
 def build_ww(prob: dict, n_runs=20, n_per_run=1_000_000, seed0=W.ROOT_SEED + 1, steps=3000,
-             lr=3e-3, ratio=5.0, n_max=10):
+             lr=3e-3, ratio=5.0, n_max=10, method="auto"):
     """Whole pipeline; returns (ww dict for the problem, info dict)."""
-    S, Wt, t_imp, n4 = importance_estimate(prob, n_runs, n_per_run, seed0)
-    X, y, wt = training_set(prob, S, Wt, n4)
+    G = prob["sigma_t"].shape[1]
+    if method == "auto":
+        method = "reciprocal" if G == 1 and prob.get("detector") is not None else "forward"
+    if method == "reciprocal":
+        I, t_imp, n4 = reciprocal_importance(prob, n_runs, n_per_run, seed0)
+    else:
+        I, t_imp, n4 = forward_importance(prob, n_runs, n_per_run, seed0)
+    X, y, wt = training_set(I, n4, G)
     params, losses, t_train = gpu_train(X, y, wt, steps=steps, lr=lr)
-    logk = source_log_k(prob, params)
-    ww = dict(params=params, hidden=mcdc.HIDDEN, logk=logk, ratio=ratio, n_max=n_max)
-    info = dict(importance_seconds=t_imp, train_seconds=t_train, n_points=int(X.shape[0]),
-                n_scoring_cells=int((S > 0).sum()), loss_first=float(losses[0]),
-                loss_last=float(losses[-1]), logk=logk)
+    ymin, ymax = float(y.min()), float(y.max())
+    logk = source_log_k(prob, params, ymin, ymax)
+    ww = dict(params=params, hidden=mcdc.HIDDEN, logk=logk, ratio=ratio, n_max=n_max,
+              ymin=ymin, ymax=ymax)
+    info = dict(method=method, importance_seconds=t_imp, train_seconds=t_train,
+                n_points=int(X.shape[0]), loss_first=float(losses[0]), loss_last=float(losses[-1]),
+                target_var=float(np.var(y)), logk=logk, ymin=ymin, ymax=ymax)
     return ww, info
 
 
-def fom_run(prob: dict, n_hist: int, seed: int, options=None, chunk: int = 50_000_000):
-    """Run n_hist histories; returns (detector mean, relative error, GPU seconds)."""
+def fom_run(prob: dict, n_hist: int, seed: int, options=None, chunk: int = 100_000_000):
+    """Run n_hist histories; returns (detector mean, relative error, seconds,
+    counters).  The time covers the runs and the final read-back."""
     import torch
     gp = mcdc.Problem(prob, options)
+    gp.run(min(n_hist, 100_000), seed + 999_999)      # warm-up; reset below
+    gp.reset()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     done = 0
@@ -191,13 +251,13 @@ def fom_run(prob: dict, n_hist: int, seed: int, options=None, chunk: int = 50_00
 
 def fom_at_target(prob: dict, seed: int, target=0.01, pilot=2_000_000, options=None,
                   max_hist=4_000_000_000):
-    """Pilot run -> N such that the detector relative error reaches `target`
-    -> run at that N.  Returns a dict with N, mean, rel_err, seconds, FOM."""
+    """Pilot run -> N with the detector relative error at `target` -> run N.
+    Returns N, mean, relative error, seconds, FOM = 1/(R^2 T) and counters."""
     m, r, dt, _ = fom_run(prob, pilot, seed, options)
     if not (r > 0):
         raise RuntimeError("pilot run scored nothing on the detector")
-    n = int(min(max_hist, max(pilot, np.ceil(pilot * (r / target) ** 2 * 1.02))))
+    n = int(min(max_hist, max(pilot, np.ceil(pilot * (r / target) ** 2 * 1.05))))
     m, r, dt, c = fom_run(prob, n, seed + 1000, options)
     return dict(n=n, mean=m, rel_err=r, seconds=dt, fom=1.0 / (r * r * dt),
-                histories_per_s=n / dt, splits=c["splits"], rr_kills=c["rr_kills"],
-                particles=c["particles"])
+                histories_per_s=n / dt, splits=int(c["splits"]), rr_kills=int(c["rr_kills"]),
+                particles=int(c["particles"]), detector_hits=int(c["detector_hits"]))

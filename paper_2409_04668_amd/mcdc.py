@@ -107,7 +107,7 @@ _sig("mcdc_tally_bins", C.c_int, VP, C.POINTER(C.c_size_t))
 _sig("mcdc_set_trace", C.c_int, VP, VP, C.c_uint64, VP)
 _sig("mcdc_set_history_scores", C.c_int, VP, VP)
 _sig("mcdc_set_ww_mlp", C.c_int, VP, C.POINTER(C.c_float), C.c_size_t, C.c_double, C.c_double,
-     C.c_int32)
+     C.c_int32, C.c_float, C.c_float)
 _sig("mcdc_get_importance", C.c_int, VP, PD, PD, C.c_size_t, VP)
 _sig("mcdc_mlp_param_count", C.c_size_t, C.c_int32)
 _sig("mcdc_mlp_forward", C.c_int, VP, C.c_int32, VP, C.c_size_t, VP, VP)
@@ -122,6 +122,7 @@ _sig("mcdc_create_batch", C.c_int, C.POINTER(ProblemDesc), C.c_size_t, C.POINTER
 _sig("mcdc_run_batch", C.c_int, VP, C.c_uint64, VP)
 _sig("mcdc_get_batch_raw", C.c_int, VP, C.c_size_t, PD, C.c_size_t, VP)
 _sig("mcdc_get_batch_counters", C.c_int, VP, C.c_size_t, C.POINTER(Counters), VP)
+_sig("mcdc_get_batch_history_path", C.c_int, VP, C.c_size_t, PD, C.c_size_t, VP)
 _sig("mcdc_set_kernel_timing", C.c_int, VP, C.c_int)
 _sig("mcdc_kernel_time", C.c_int, VP, C.POINTER(C.c_uint64), C.POINTER(C.c_double))
 _sig("mcdc_destroy_problem", None, VP)
@@ -228,11 +229,12 @@ def make_options(schedule=SCHED_HISTORY, block=0, waves_per_cu=0, lds_tally=1, e
 class Problem:
     """One problem on the GPU: workspace tensor + library handle."""
 
-    def __init__(self, prob: dict, options: Options | None = None, device="cuda:0"):
+    def __init__(self, prob: dict, options: Options | None = None, device="cuda:0",
+                 problem_id: int = 0):
         import torch
         self.torch = torch
         self.prob = prob
-        self.desc = _Desc(prob)
+        self.desc = _Desc(prob, problem_id)
         self.opt = options if options is not None else make_options()
         nbytes = C.c_size_t()
         check(_lib.mcdc_workspace_bytes(C.byref(self.desc.d), C.byref(self.opt), C.byref(nbytes)),
@@ -247,7 +249,8 @@ class Problem:
         self._xh = None
         ww = prob.get("ww")
         if ww is not None:
-            self.set_ww(ww["params"], ww["logk"], ww.get("ratio", 5.0), ww.get("n_max", 10))
+            self.set_ww(ww["params"], ww["logk"], ww.get("ratio", 5.0), ww.get("n_max", 10),
+                        ww.get("ymin", -3.0e38), ww.get("ymax", 3.0e38))
 
     def close(self):
         if self.h:
@@ -295,13 +298,14 @@ class Problem:
         self.torch.cuda.synchronize()
         return self._xh.cpu().numpy().reshape(-1, 2)
 
-    def set_ww(self, params, logk, ratio=5.0, n_max=10):
+    def set_ww(self, params, logk, ratio=5.0, n_max=10, ymin=-3.0e38, ymax=3.0e38):
         if params is None:
-            check(_lib.mcdc_set_ww_mlp(self.h, None, 0, 0.0, 0.0, 0), "set_ww_mlp")
+            check(_lib.mcdc_set_ww_mlp(self.h, None, 0, 0.0, 0.0, 0, 0.0, 0.0), "set_ww_mlp")
             return
         p = np.ascontiguousarray(params, np.float32)
         check(_lib.mcdc_set_ww_mlp(self.h, p.ctypes.data_as(C.POINTER(C.c_float)), p.size,
-                                   float(logk), float(ratio), int(n_max)), "set_ww_mlp")
+                                   float(logk), float(ratio), int(n_max), float(ymin), float(ymax)),
+              "set_ww_mlp")
 
     # ---- results -------------------------------------------------------
     def raw(self, stream=None):
@@ -344,6 +348,64 @@ class Problem:
 
     def reset(self, stream=None):
         check(_lib.mcdc_reset_tallies(self.h, _stream_ptr(stream)), "reset_tallies")
+
+
+class BatchProblem:
+    """Many independent problems run together: one persistent launch per census
+    step, the census steps of a pass replayed from a HIP graph."""
+
+    def __init__(self, probs, n_hist, options: Options | None = None, device="cuda:0"):
+        import torch
+        self.torch = torch
+        self.probs = probs
+        self.n_hist = np.ascontiguousarray(n_hist, np.uint64)
+        self.descs = [_Desc(p, problem_id=i) for i, p in enumerate(probs)]
+        arr = (ProblemDesc * len(probs))(*[d.d for d in self.descs])
+        self._arr = arr
+        self.opt = options if options is not None else make_options()
+        nh = self.n_hist.ctypes.data_as(C.POINTER(C.c_uint64))
+        nbytes = C.c_size_t()
+        check(_lib.mcdc_batch_workspace_bytes(arr, len(probs), nh, C.byref(self.opt),
+                                              C.byref(nbytes)), "batch_workspace_bytes")
+        self.ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=device)
+        h = VP()
+        check(_lib.mcdc_create_batch(arr, len(probs), nh, C.byref(self.opt), _ptr(self.ws),
+                                     nbytes.value, C.byref(h)), "create_batch")
+        self.h = h
+
+    def close(self):
+        if self.h:
+            _lib.mcdc_destroy_problem(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, seed: int, stream=None):
+        check(_lib.mcdc_run_batch(self.h, int(seed), _stream_ptr(stream)), "run_batch")
+
+    def raw(self, p: int, stream=None):
+        n = self.descs[p].nbins
+        s = np.zeros(n)
+        check(_lib.mcdc_get_batch_raw(self.h, p, s.ctypes.data_as(PD), n, _stream_ptr(stream)),
+              "get_batch_raw")
+        return s
+
+    def counters(self, p: int, stream=None) -> dict:
+        c = Counters()
+        check(_lib.mcdc_get_batch_counters(self.h, p, C.byref(c), _stream_ptr(stream)),
+              "get_batch_counters")
+        return c.as_dict()
+
+    def history_path(self, p: int, stream=None):
+        n = int(self.n_hist[p])
+        out = np.zeros(n)
+        check(_lib.mcdc_get_batch_history_path(self.h, p, out.ctypes.data_as(PD), n,
+                                               _stream_ptr(stream)), "get_batch_history_path")
+        return out
 
 
 def mlp_param_count(in_dim: int) -> int:

@@ -69,7 +69,8 @@ def test_mlp_adam_training_matches_oracle_and_decreases_loss():
         ref, m, v = M.adam_step(ref, M.grad(ref, X, y, wt, IN, H), m, v, step, 1e-3)
     assert np.max(np.abs(losses - np.array(ref_losses)) / np.array(ref_losses)) < 1e-3
     assert np.max(np.abs(params - ref)) < 1e-3 * max(1.0, np.max(np.abs(ref)))
-    assert all(b < a for a, b in zip(losses, losses[1:]))
+    assert losses[-1] < 0.8 * losses[0]
+    assert all(b <= a * (1 + 1e-3) for a, b in zip(losses, losses[1:]))
 
 
 @pytest.mark.slow
@@ -80,12 +81,13 @@ def test_learned_weight_windows_gain_fom_and_stay_unbiased():
     from paper_2409_04668_amd import learned_ww as L
     from paper_2409_04668_amd import workloads as W
     p = W.config2()
-    ww, info = L.build_ww(p, n_runs=8, n_per_run=1_000_000, steps=1500)
-    assert info["loss_last"] < info["loss_first"]
+    ww, info = L.build_ww(p, n_runs=4, n_per_run=1_000_000, steps=1500)
+    assert info["loss_last"] < 0.2 * info["target_var"], info
     pw = W.config4(ww)
     pw["stack_cap"] = 256
-    a = L.fom_at_target(p, seed=500, target=0.03, pilot=2_000_000)
-    w = L.fom_at_target(pw, seed=600, target=0.03, pilot=200_000)
+    a = L.fom_at_target(p, seed=500, target=0.03, pilot=4_000_000)
+    w = L.fom_at_target(pw, seed=600, target=0.03, pilot=400_000)
     z = abs(a["mean"] - w["mean"]) / math.hypot(a["mean"] * a["rel_err"], w["mean"] * w["rel_err"])
+    print("analog", a, "\nlearned WW", w, "\ninfo", info)
     assert z < 3.5, (a, w)
-    assert w["fom"] > a["fom"], (a, w)
+    assert w["fom"] > 1.5 * a["fom"], (a, w)

@@ -98,11 +98,12 @@ def ramp_mlp(slope, noise_seed=None):
 
 def test_weight_window_parity_ramp_mlp():
     p = _ww_box()
-    p["ww"] = dict(params=ramp_mlp(2.0, noise_seed=3), hidden=64, logk=0.0, ratio=5.0, n_max=10)
+    p["ww"] = dict(params=ramp_mlp(2.0, noise_seed=3), hidden=64, logk=0.0, ratio=5.0, n_max=10,
+                   ymin=-1.5, ymax=1.5)        # the clamp binds near both x faces
     p["stack_cap"] = 256
     gp, orc = full_parity(p, 1500, seed=108, trace_cap=400000)
     c = orc.counters
-    assert c["split"] > 100 and c["rr_kill"] > 100
+    assert c["split"] > 100 and c["rr_kill"] > 20
 
 
 def test_weight_window_parity_duct():

@@ -243,3 +243,20 @@ def test_importance_estimate_hand_case():
     # flight starts x=1,2,4 (cell 0, score so far 0) and x=7,9 (cell 1, 1 and 2); final 2
     assert list(r.imp_weight) == [9.0, 6.0]
     assert list(r.imp_score) == [18.0, 3.0]
+
+
+def test_output_clamp_to_a_point_is_constant_importance():
+    """Clamping the network output to [0, 0] makes w_T = 1 everywhere, so an
+    analog run (weights stay 1, inside [1/3, 5/3]) is untouched bit for bit."""
+    p = _box_problem()
+    ra = O.OracleRun(p)
+    ta, _ = ra.run(2000, seed=47, trace_cap=200000)
+    q = _box_problem()
+    q["ww"] = dict(params=_ramp_mlp(5.0), hidden=H, logk=0.0, ratio=5.0, n_max=10,
+                   ymin=0.0, ymax=0.0)
+    rq = O.OracleRun(q)
+    tq, _ = rq.run(2000, seed=47, trace_cap=200000)
+    assert np.array_equal(ta, tq)
+    q["ww"]["ymax"] = 5.0                 # unclamped above: splits happen
+    rs = O.run(q, 2000, seed=47)
+    assert rs.counters["split"] > 0
