@@ -26,7 +26,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_PIECE = 16.0          # FP64 atomic read-modify-write: 8 B read + 8 B written
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_history_duct_1e8_pmc.txt")
-KERNEL_SOURCES = ["transport_device.hpp", "mcdc_history.hip", "mcdc_internal.hpp"]
+KERNEL_SOURCES = ["transport_device.hpp", "transport_stages.hpp", "mcdc_history.hip",
+                  "mcdc_internal.hpp"]
 
 
 def kernel_hash() -> str:
@@ -76,6 +77,7 @@ def main():
     ap.add_argument("--waves-per-cu", type=int, default=0)
     ap.add_argument("--cpu-sample", type=int, default=8_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tile", action="store_true", help="tally straight to HBM atomics")
     ap.add_argument("--workload", choices=["duct", "batch", "fom"], default="duct")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a device-to-device copy of BYTES (PMC calibration)")
@@ -105,7 +107,13 @@ def main():
 
     prob = W.config2()
     sched = mcdc.SCHED_HISTORY if args.schedule == "history" else mcdc.SCHED_EVENT
-    gp = mcdc.Problem(prob, mcdc.make_options(sched, waves_per_cu=args.waves_per_cu))
+    tile, tile_frac = None, 0.0
+    if sched == mcdc.SCHED_HISTORY and not args.no_tile:
+        # the autotuner places the LDS hot tile from a short pilot run (setup,
+        # not timed)
+        from paper_2409_04668_amd import autotune
+        tile, tile_frac = autotune.plan_hot_tile(prob, pilot=1_000_000)
+    gp = mcdc.Problem(prob, mcdc.make_options(sched, waves_per_cu=args.waves_per_cu, tile=tile))
     N = args.histories
     seed = 20260001
     for i in range(args.warmup):
@@ -147,7 +155,10 @@ def main():
         "config": {"workload": "3D duct 60x100x60 cm, 1 group, 1 cm mesh x 20 t-bins "
                                "(7.2e6 FP64 bins), analog, 1e8 histories per step",
                    "histories_per_step": N, "schedule": args.schedule,
-                   "tally_bins": W.n_bins(prob)},
+                   "tally_bins": W.n_bins(prob),
+                   "lds_hot_tile": None if tile is None else
+                   {"lo_xyztg": [int(v) for v in tile[0]], "n_xyztg": [int(v) for v in tile[1]],
+                    "pilot_track_length_fraction": tile_frac}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_history", "launches": launches,
@@ -158,6 +169,20 @@ def main():
         "flights_per_history": (c1["flights"] - c0["flights"]) / n_done,
         "detector": {"mean": float(det_mean[0]), "rel_err": float(det_rel[0])},
     }
+    # measured ceilings: FP64 atomics scattered over an array of the tally's
+    # size (fully random, and in runs of 8 consecutive bins like the mesh
+    # walk), and a streaming copy
+    nb = W.n_bins(prob)
+    per_launch = int(pieces / max(launches, 1))
+    ceil_rand = mcdc.micro_atomic_rate(nb, per_launch, run=1)
+    ceil_run8 = mcdc.micro_atomic_rate(nb, per_launch, run=8)
+    copy_bw = mcdc.micro_copy_rate()
+    ach_atomics = pieces / (kms / 1e3) if kms > 0 else 0.0
+    out["measured_ceilings"] = {
+        "fp64_atomics_random_per_s": ceil_rand, "fp64_atomics_runs8_per_s": ceil_run8,
+        "copy_GBps": copy_bw / 1e9,
+        "atomic_frac_of_random_ceiling": ach_atomics / ceil_rand if ceil_rand else None,
+        "atomic_frac_of_runs8_ceiling": ach_atomics / ceil_run8 if ceil_run8 else None}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_sample, seed)
     print(json.dumps(out), flush=True)

@@ -100,8 +100,17 @@ typedef struct {
     int32_t block;                     /* work-items per workgroup (multiple of 64) */
     int32_t waves_per_cu;              /* persistent-grid occupancy target        */
     int32_t lds_tally;                 /* 1 allow, 0 forbid an LDS tally tile     */
-    int64_t event_chunk;               /* event mode: histories resident at once  */
+    int64_t event_chunk;               /* event mode: histories resident at once;
+                                          batched runs: entries per work chunk    */
+    /* History schedule: a sub-box of the tally mesh held in LDS per workgroup
+     * (bins [tile_lo, tile_lo + tile_n) along x, y, z, t, group), flushed to
+     * HBM at the end of each launch; all tile_n > 0 enables it (at most
+     * MCDC_MAX_TILE_BINS bins; workgroups of 1024 work-items).  Place it where
+     * most track-length pieces fall (e.g. from a pilot run's tally). */
+    int32_t tile_lo[5], tile_n[5];
 } mcdc_options;
+
+#define MCDC_MAX_TILE_BINS 19456
 
 /* Counters (all runs since create / reset). */
 typedef struct {
@@ -232,6 +241,16 @@ int mcdc_get_batch_history_path(mcdc_handle h, size_t p, double *out, size_t n, 
  * call and their summed duration in milliseconds (then forgets them). */
 int mcdc_set_kernel_timing(mcdc_handle h, int on);
 int mcdc_kernel_time(mcdc_handle h, uint64_t *launches, double *total_ms);
+
+/* Micro-benchmarks for the measured roofline ceilings (not on the transport
+ * path).  mcdc_micro_atomics: n_items work-items each add 1.0 to per_item bins
+ * of dev_buf[n_bins], in runs of `run` consecutive bins starting at hashed
+ * positions (run = 1: uniformly scattered).  mcdc_micro_copy: stream `bytes`
+ * (a multiple of 32) from dev_src to dev_dst.  Both are asynchronous on
+ * `stream`; the caller times them. */
+int mcdc_micro_atomics(double *dev_buf, uint64_t n_bins, uint64_t n_items, uint32_t per_item,
+                       uint32_t run, void *stream);
+int mcdc_micro_copy(const void *dev_src, void *dev_dst, size_t bytes, void *stream);
 
 void mcdc_destroy_problem(mcdc_handle h);
 const char *mcdc_last_error(void);

@@ -101,6 +101,67 @@ def tune_single(prob, pilot=2_000_000, waves=(8, 12, 16, 24, 32), event_chunks=(
     return res
 
 
+def grow_tile(density: np.ndarray, max_bins: int):
+    """Box over a 5-D density [g][t][z][y][x] (any non-negative weights) of at
+    most max_bins bins: start at the densest bin and repeatedly add the face
+    slab (10 candidates) with the largest mass per added bin.  Returns
+    (lo, n) in x, y, z, t, g order and the captured fraction."""
+    D = np.asarray(density, float)
+    total = D.sum()
+    idx = np.unravel_index(int(np.argmax(D)), D.shape)
+    lo = list(idx)
+    hi = [i + 1 for i in idx]
+    vol = 1
+    while True:
+        best = None
+        for ax in range(5):
+            ext = hi[ax] - lo[ax]
+            add = vol // ext
+            if vol + add > max_bins:
+                continue
+            for side in (0, 1):
+                k = lo[ax] - 1 if side == 0 else hi[ax]
+                if k < 0 or k >= D.shape[ax]:
+                    continue
+                sl = [slice(lo[a], hi[a]) for a in range(5)]
+                sl[ax] = slice(k, k + 1)
+                gain = D[tuple(sl)].sum() / add
+                if best is None or gain > best[0]:
+                    best = (gain, ax, side, add)
+        if best is None or best[0] <= 0.0:
+            break
+        _, ax, side, add = best
+        if side == 0:
+            lo[ax] -= 1
+        else:
+            hi[ax] += 1
+        vol += add
+    frac = D[tuple(slice(lo[a], hi[a]) for a in range(5))].sum() / total if total > 0 else 0.0
+    # density axes are (g, t, z, y, x); options want (x, y, z, t, g)
+    order = [4, 3, 2, 1, 0]
+    return ([lo[a] for a in order], [hi[a] - lo[a] for a in order]), float(frac)
+
+
+def plan_hot_tile(prob, pilot=2_000_000, max_bins=None, seed=4242):
+    """Pilot run -> LDS hot tile over the bins with the most track length.
+    Returns (tile, captured fraction) or (None, 0) when the whole mesh fits
+    the ordinary LDS tile anyway."""
+    max_bins = max_bins or mcdc.MAX_TILE_BINS
+    from . import workloads as W
+    nb = W.n_bins(prob)
+    if nb <= 7680:
+        return None, 0.0
+    q = W.with_(prob, n_batches=1, ww=None, importance=None)
+    gp = mcdc.Problem(q, mcdc.make_options(mcdc.SCHED_HISTORY))
+    gp.run(pilot, seed)
+    s, _ = gp.raw()
+    gp.close()
+    m = prob["mesh"]
+    nx, ny, nz, nt = [int(v) for v in m["n"]]
+    G = prob["sigma_t"].shape[1] if m["per_group"] else 1
+    return grow_tile(s.reshape(G, nt, nz, ny, nx), max_bins)
+
+
 def tune_batch(probs, n_hist, chunks=(512, 2048, 8192), waves=(8, 16), cache_path=DEFAULT_CACHE,
                use_cache=True, seed=777):
     """Chunk size and occupancy of the batched persistent kernel."""

@@ -87,21 +87,39 @@ Options resolve_options(const mcdc_options *o) {
     r.waves_per_cu = 16;
     r.lds_tally = 1;
     r.event_chunk = 1 << 22;
+    r.tile_bins = 0;
+    for (int a = 0; a < 5; ++a) r.tile_lo[a] = r.tile_n[a] = 0;
     if (o) {
         if (o->schedule) r.schedule = o->schedule;
         if (o->block) r.block = o->block;
         if (o->waves_per_cu) r.waves_per_cu = o->waves_per_cu;
         r.lds_tally = o->lds_tally;
         if (o->event_chunk) r.event_chunk = o->event_chunk;
+        bool on = o->lds_tally != 0;
+        uint64_t bins = 1;
+        for (int a = 0; a < 5; ++a) {
+            r.tile_lo[a] = o->tile_lo[a];
+            r.tile_n[a] = o->tile_n[a];
+            on = on && o->tile_n[a] > 0;
+            bins *= (uint64_t)(o->tile_n[a] > 0 ? o->tile_n[a] : 0);
+        }
+        if (on) r.tile_bins = bins > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)bins;
     }
     if (r.schedule == MCDC_SCHED_AUTO) r.schedule = MCDC_SCHED_HISTORY;
+    // the hot tile runs one 1024-work-item workgroup per CU-share of LDS
+    if (r.tile_bins && r.schedule == MCDC_SCHED_HISTORY) r.block = 1024;
+    else r.tile_bins = 0;
     r.grid = history_grid(r.block, r.waves_per_cu);
     r.n_lanes = (uint64_t)r.grid * r.block;
     return r;
 }
 
 int check_options(const Options &o) {
-    if (o.block < 64 || o.block > 256 || o.block % 64) return fail(MCDC_E_INVALID, "block must be 64..256, a multiple of 64");
+    if (o.tile_bins) {
+        if (o.tile_bins > MCDC_MAX_TILE_BINS) return fail(MCDC_E_INVALID, "hot tile larger than MCDC_MAX_TILE_BINS");
+    } else if (o.block < 64 || o.block > 256 || o.block % 64) {
+        return fail(MCDC_E_INVALID, "block must be 64..256, a multiple of 64");
+    }
     if (o.waves_per_cu < 1 || o.waves_per_cu > 64) return fail(MCDC_E_INVALID, "waves_per_cu out of range");
     if (o.schedule != MCDC_SCHED_HISTORY && o.schedule != MCDC_SCHED_EVENT)
         return fail(MCDC_E_INVALID, "unknown schedule");
@@ -288,6 +306,20 @@ int mcdc_create_problem(const mcdc_problem_desc *d, const mcdc_options *opt, voi
     h->nbins = desc_nbins(d);
     h->nimp = desc_nimp(d);
     build_dev_problem(d, h->ws, L, h->P);
+    if (o.tile_bins) {
+        // the hot tile must lie inside the mesh (x, y, z, t, group)
+        const int32_t ext[5] = {d->mesh_n[0], d->mesh_n[1], d->mesh_n[2], d->mesh_n[3],
+                                d->mesh_per_group ? d->G : 1};
+        for (int a = 0; a < 5; ++a) {
+            if (o.tile_lo[a] < 0 || o.tile_lo[a] + o.tile_n[a] > ext[a]) {
+                delete h;
+                return fail(MCDC_E_INVALID, "hot tile outside the mesh");
+            }
+            h->P.hot_lo[a] = (uint32_t)o.tile_lo[a];
+            h->P.hot_n[a] = (uint32_t)o.tile_n[a];
+        }
+        h->P.hot_bins = o.tile_bins;
+    }
     std::vector<double> tab = pack_tables(d);
     hipError_t e = hipMemcpy(h->ws + L.tables, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(h->ws + L.tally_batch, 0, L.ww_params - L.tally_batch);

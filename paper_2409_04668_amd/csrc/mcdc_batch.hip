@@ -81,6 +81,7 @@ struct BatchCtx {
     uint64_t hist_id;
     uint64_t slot;
     MCDC_DEV uint64_t hist() const { return hist_id; }
+    MCDC_DEV const float *mlp_params(const DevProblem &Pp) const { return Pp.ww_params; }
     // one particle per history (no weight windows in batched runs): the
     // history's flight count lives in the particle's bank slot
     MCDC_DEV bool count_flight() {
@@ -98,7 +99,7 @@ struct TileTally {
     double *lds;
     double *glob;
     uint32_t lo, hi;
-    MCDC_DEV void add(uint32_t i, double v) const {
+    MCDC_DEV void add(uint32_t i, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, double v) const {
         if (i >= lo && i < hi) atomicAdd(lds + (i - lo), v);
         else unsafeAtomicAdd(glob + i, v);
     }

@@ -91,7 +91,9 @@ struct EvCtx {
     const RunArgs &A;
     const EvBank &B;
     uint32_t slot;
+    const float *prm;                    // MLP weights (LDS copy in the interaction kernels)
     MCDC_DEV uint64_t hist() const { return A.h_begin + slot; }
+    MCDC_DEV const float *mlp_params(const DevProblem &) const { return prm; }
     MCDC_DEV bool count_flight() {
         uint32_t e;
         if (WW) e = atomicAdd(&B.events[slot], 1u) + 1u;
@@ -136,7 +138,7 @@ __global__ void __launch_bounds__(256) k_ev_source(DevProblem P, RunArgs A, EvBa
             B.xh[s] = 0.0;
             B.path[s] = 0.0;
             B.events[s] = 0u;
-            EvCtx<WW> C{P, A, B, s};
+            EvCtx<WW> C{P, A, B, s, P.ww_params};
             Part q;
             stage_source(P, A, S, C, q);
             alive = q.alive;
@@ -170,7 +172,7 @@ __global__ void __launch_bounds__(256) k_ev_flight(DevProblem P, RunArgs A, EvBa
             double d;
             uint32_t slot;
             bank_load(B, j, q, d, slot);
-            EvCtx<WW> C{P, A, B, slot};
+            EvCtx<WW> C{P, A, B, slot, P.ww_params};
             ev = stage_flight(P, A, S, tally, C, q, d, n_piece, path);
             if (ev >= 0) n_flight += 1;
             if (q.alive) bank_store(B, j, q, d, slot);
@@ -190,7 +192,14 @@ __global__ void __launch_bounds__(256) k_ev_flight(DevProblem P, RunArgs A, EvBa
 template <bool SURF, bool WW>
 __global__ void __launch_bounds__(256) k_ev_interact(DevProblem P, RunArgs A, EvBank B) {
     __shared__ Shared S;
+    // weight-window network in LDS: every lane of a wave reads the same
+    // weight at the same time (broadcast), instead of from HBM
+    __shared__ float s_prm[WW ? kH * (4 + kMaxG) + kH + kH * kH + kH + kH + 1 : 1];
     shared_zero(S);
+    if (WW) {
+        const int np = kH * (4 + P.G) + kH + kH * kH + kH + kH + 1;
+        for (int i = threadIdx.x; i < np; i += blockDim.x) s_prm[i] = P.ww_params[i];
+    }
     __syncthreads();
     const uint32_t nxt = B.ctl->nxt;
     const uint32_t n = SURF ? B.ctl->n_surf : B.ctl->n_coll;
@@ -206,7 +215,7 @@ __global__ void __launch_bounds__(256) k_ev_interact(DevProblem P, RunArgs A, Ev
             double d;
             uint32_t slot;
             bank_load(B, j, q, d, slot);
-            EvCtx<WW> C{P, A, B, slot};
+            EvCtx<WW> C{P, A, B, slot, WW ? s_prm : P.ww_params};
             if (SURF) stage_surface(P, A, S, C, q, d);
             else stage_collision(P, A, S, C, q, d);
             alive = q.alive;

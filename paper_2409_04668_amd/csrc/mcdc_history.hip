@@ -66,6 +66,7 @@ struct HistCtx {
     int sp, n_imp;
 
     MCDC_DEV uint64_t hist() const { return id; }
+    MCDC_DEV const float *mlp_params(const DevProblem &Pp) const { return Pp.ww_params; }
     MCDC_DEV bool count_flight() {
         events += 1;
         return events <= P.max_events;
@@ -139,13 +140,38 @@ MCDC_DEV void finish_history(const RunArgs &A, Shared &S, const HistCtx<WW, IMP>
     }
 }
 
-template <bool LDS, bool WW, bool IMP>
-__global__ void __launch_bounds__(256) k_history(DevProblem P, RunArgs A) {
+// LDS modes: 0 = tally in HBM, 1 = whole mesh in LDS, 2 = hot tile in LDS.
+template <int LDS>
+struct TallyFor { using type = GlobalTally; };
+template <>
+struct TallyFor<1> { using type = LdsTally; };
+template <>
+struct TallyFor<2> { using type = HotTileTally; };
+
+MCDC_DEV GlobalTally make_tally(GlobalTally *, const DevProblem &, const RunArgs &A, double *) {
+    return GlobalTally{A.tally};
+}
+MCDC_DEV LdsTally make_tally(LdsTally *, const DevProblem &, const RunArgs &, double *lds) {
+    return LdsTally{lds};
+}
+MCDC_DEV HotTileTally make_tally(HotTileTally *, const DevProblem &P, const RunArgs &A, double *lds) {
+    HotTileTally t;
+    t.lds = lds;
+    t.glob = A.tally;
+    for (int a = 0; a < 5; ++a) {
+        t.lo[a] = P.hot_lo[a];
+        t.n[a] = P.hot_n[a];
+    }
+    return t;
+}
+
+template <int LDS, bool WW, bool IMP>
+__global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_history(DevProblem P, RunArgs A) {
     extern __shared__ double s_tile[];
     __shared__ Shared S;
     shared_zero(S);
-    if (LDS)
-        for (uint32_t i = threadIdx.x; i < P.nbins; i += blockDim.x) s_tile[i] = 0.0;
+    const uint32_t tile_bins = LDS == 1 ? P.nbins : (LDS == 2 ? P.hot_bins : 0u);
+    for (uint32_t i = threadIdx.x; i < tile_bins; i += blockDim.x) s_tile[i] = 0.0;
     __syncthreads();
 
     const uint64_t lane = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -157,7 +183,8 @@ __global__ void __launch_bounds__(256) k_history(DevProblem P, RunArgs A) {
     q.alive = false;
     HistCtx<WW, IMP> H{P, A, lane, 0, 0.0, 0.0, 0, 0, 0};
     bool in_hist = false;
-    typename std::conditional<LDS, LdsTally, GlobalTally>::type tally{LDS ? s_tile : A.tally};
+    using Tally = typename TallyFor<LDS>::type;
+    const Tally tally = make_tally((Tally *)nullptr, P, A, s_tile);
 
     for (;;) {
         if (!q.alive) {
@@ -200,10 +227,26 @@ __global__ void __launch_bounds__(256) k_history(DevProblem P, RunArgs A) {
     atomicAdd(&S.cnt[C_PIECE], (unsigned long long)n_piece);
     atomicAdd(&S.wsum[W_PATH], path);
     __syncthreads();
-    if (LDS) {
+    if (LDS == 1) {
         for (uint32_t i = threadIdx.x; i < P.nbins; i += blockDim.x) {
             const double v = s_tile[i];
             if (v != 0.0) unsafeAtomicAdd(&A.tally[i], v);
+        }
+    } else if (LDS == 2) {
+        // tile bin j -> mesh bin: walk the tile in x-fastest order
+        const uint32_t nx = P.hot_n[0], ny = P.hot_n[1], nz = P.hot_n[2], nt = P.hot_n[3];
+        const uint32_t mx = P.mesh_n[0], my = P.mesh_n[1], mz = P.mesh_n[2], mt = P.mesh_n[3];
+        for (uint32_t j = threadIdx.x; j < P.hot_bins; j += blockDim.x) {
+            const double v = s_tile[j];
+            if (v == 0.0) continue;
+            uint32_t r = j;
+            const uint32_t x = r % nx + P.hot_lo[0]; r /= nx;
+            const uint32_t y = r % ny + P.hot_lo[1]; r /= ny;
+            const uint32_t z = r % nz + P.hot_lo[2]; r /= nz;
+            const uint32_t t = r % nt + P.hot_lo[3]; r /= nt;
+            const uint32_t g = r + P.hot_lo[4];
+            const uint32_t b = (((g * mt + t) * mz + z) * my + y) * mx + x;
+            unsafeAtomicAdd(&A.tally[b], v);
         }
     }
     shared_flush(S, A.acc);
@@ -236,18 +279,29 @@ int history_grid(int block, int waves_per_cu) {
 
 hipError_t launch_history(const DevProblem &P, const RunArgs &A, int grid, int block,
                           bool lds_tally, hipStream_t s) {
-    const size_t shm = lds_tally ? (size_t)P.nbins * sizeof(double) : 0;
+    const int mode = P.hot_bins ? 2 : (lds_tally ? 1 : 0);
+    const size_t shm = mode == 2 ? (size_t)P.hot_bins * sizeof(double)
+                                 : (mode == 1 ? (size_t)P.nbins * sizeof(double) : 0);
     const bool ww = P.ww_on != 0, imp = P.imp_on != 0;
-#define MCDC_LAUNCH(L, W, I) \
-    hipLaunchKernelGGL((k_history<L, W, I>), dim3(grid), dim3(block), shm, s, P, A)
-    if (lds_tally) {
-        if (ww) MCDC_LAUNCH(true, true, false);
-        else if (imp) MCDC_LAUNCH(true, false, true);
-        else MCDC_LAUNCH(true, false, false);
+#define MCDC_LAUNCH(L, W, I)                                                                   \
+    do {                                                                                       \
+        if (shm > 65536)                                                                       \
+            (void)hipFuncSetAttribute((const void *)k_history<L, W, I>,                        \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);   \
+        hipLaunchKernelGGL((k_history<L, W, I>), dim3(grid), dim3(block), shm, s, P, A);       \
+    } while (0)
+    if (mode == 2) {
+        if (ww) MCDC_LAUNCH(2, true, false);
+        else if (imp) MCDC_LAUNCH(2, false, true);
+        else MCDC_LAUNCH(2, false, false);
+    } else if (mode == 1) {
+        if (ww) MCDC_LAUNCH(1, true, false);
+        else if (imp) MCDC_LAUNCH(1, false, true);
+        else MCDC_LAUNCH(1, false, false);
     } else {
-        if (ww) MCDC_LAUNCH(false, true, false);
-        else if (imp) MCDC_LAUNCH(false, false, true);
-        else MCDC_LAUNCH(false, false, false);
+        if (ww) MCDC_LAUNCH(0, true, false);
+        else if (imp) MCDC_LAUNCH(0, false, true);
+        else MCDC_LAUNCH(0, false, false);
     }
 #undef MCDC_LAUNCH
     return hipGetLastError();

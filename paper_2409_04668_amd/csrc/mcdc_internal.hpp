@@ -69,6 +69,8 @@ struct DevProblem {
     int32_t stack_cap;
     uint32_t problem_id;
     uint32_t nbins;
+    uint32_t hot_lo[5], hot_n[5];        // LDS hot tile (x, y, z, t, g); hot_bins 0 = off
+    uint32_t hot_bins;
 };
 
 // Per-launch arguments of the tracking kernels.

@@ -16,6 +16,8 @@ namespace mcdc {
 struct Options {
     int schedule, block, waves_per_cu, lds_tally;
     int64_t event_chunk;
+    int32_t tile_lo[5], tile_n[5];
+    uint32_t tile_bins;                  // 0: no hot tile
     int grid;
     uint64_t n_lanes;
 };

@@ -264,13 +264,34 @@ MCDC_DEV double detector_len(const DevProblem &P, const double p[3], const doubl
 // Tally targets: FP64 atomics into global memory, or into an LDS tile that
 // the kernel flushes to global memory when it ends.
 // ---------------------------------------------------------------------------
+// add(flat bin, g, t, z, y, x indices, value)
 struct GlobalTally {
     double *base;
-    MCDC_DEV void add(uint32_t i, double v) const { unsafeAtomicAdd(base + i, v); }
+    MCDC_DEV void add(uint32_t i, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, double v) const {
+        unsafeAtomicAdd(base + i, v);
+    }
 };
 struct LdsTally {
     double *base;
-    MCDC_DEV void add(uint32_t i, double v) const { atomicAdd(base + i, v); }
+    MCDC_DEV void add(uint32_t i, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, double v) const {
+        atomicAdd(base + i, v);
+    }
+};
+// A sub-box of the (g, t, z, y, x) mesh privatised in LDS (the bins that take
+// most of the updates); every other bin goes to HBM atomics.
+struct HotTileTally {
+    double *lds, *glob;
+    uint32_t lo[5], n[5];                    // x, y, z, t, g
+    MCDC_DEV void add(uint32_t i, uint32_t g, uint32_t t, uint32_t z, uint32_t y, uint32_t x,
+                      double v) const {
+        const uint32_t dx = x - lo[0], dy = y - lo[1], dz = z - lo[2], dt = t - lo[3], dg = g - lo[4];
+        if (dx < n[0] && dy < n[1] && dz < n[2] && dt < n[3] && dg < n[4]) {
+            const uint32_t j = (((dg * n[3] + dt) * n[2] + dz) * n[1] + dy) * n[0] + dx;
+            atomicAdd(lds + j, v);
+        } else {
+            unsafeAtomicAdd(glob + i, v);
+        }
+    }
 };
 
 // Track-length scoring of the segment p + s u, s in [0,d], from time t0 at
@@ -321,7 +342,8 @@ MCDC_DEV uint32_t score_mesh(const DevProblem &P, const double p[3], const doubl
         s[3] = (e - t0) * v;
     }
     const uint32_t n0 = P.mesh_n[0], n1 = P.mesh_n[1], n2 = P.mesh_n[2], n3 = P.mesh_n[3];
-    const uint32_t gbase = (uint32_t)(P.G_t > 1 ? g : 0) * n3;
+    const uint32_t gt = (uint32_t)(P.G_t > 1 ? g : 0);
+    const uint32_t gbase = gt * n3;
     uint32_t pieces = 0;
     double sp = 0.0;
     for (;;) {
@@ -336,7 +358,8 @@ MCDC_DEV uint32_t score_mesh(const DevProblem &P, const double p[3], const doubl
                 const uint32_t b =
                     (((gbase + (uint32_t)idx[3]) * n2 + (uint32_t)idx[2]) * n1 + (uint32_t)idx[1]) *
                         n0 + (uint32_t)idx[0];
-                tally.add(b, w * (sn - sp));
+                tally.add(b, gt, (uint32_t)idx[3], (uint32_t)idx[2], (uint32_t)idx[1],
+                          (uint32_t)idx[0], w * (sn - sp));
                 pieces += 1;
             }
         }

@@ -95,7 +95,7 @@ MCDC_DEV void ww_check(const DevProblem &P, const RunArgs &A, Shared &S, Ctx &C,
     in[3] = (float)(2.0 * ((q.t - P.ww_lo[3]) * P.ww_inv[3]) - 1.0);
 #pragma unroll
     for (int g = 0; g < kMaxG; ++g) in[4 + g] = g == q.g ? 1.0f : 0.0f;
-    float y = mlp_infer(P.ww_params, 4 + P.G, in);
+    float y = mlp_infer(C.mlp_params(P), 4 + P.G, in);
     if (y < P.ww_ymin) y = P.ww_ymin;          // clamp to the training-target range
     if (y > P.ww_ymax) y = P.ww_ymax;
     const double wt = own_exp(P.ww_logk - (double)y);

@@ -56,7 +56,11 @@ class ProblemDesc(C.Structure):
 
 class Options(C.Structure):
     _fields_ = [("schedule", C.c_int32), ("block", C.c_int32), ("waves_per_cu", C.c_int32),
-                ("lds_tally", C.c_int32), ("event_chunk", C.c_int64)]
+                ("lds_tally", C.c_int32), ("event_chunk", C.c_int64),
+                ("tile_lo", C.c_int32 * 5), ("tile_n", C.c_int32 * 5)]
+
+
+MAX_TILE_BINS = 19456
 
 
 COUNTER_FIELDS = ["histories", "flights", "pieces", "collisions", "absorptions", "surfaces",
@@ -123,6 +127,8 @@ _sig("mcdc_run_batch", C.c_int, VP, C.c_uint64, VP)
 _sig("mcdc_get_batch_raw", C.c_int, VP, C.c_size_t, PD, C.c_size_t, VP)
 _sig("mcdc_get_batch_counters", C.c_int, VP, C.c_size_t, C.POINTER(Counters), VP)
 _sig("mcdc_get_batch_history_path", C.c_int, VP, C.c_size_t, PD, C.c_size_t, VP)
+_sig("mcdc_micro_atomics", C.c_int, VP, C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32, VP)
+_sig("mcdc_micro_copy", C.c_int, VP, VP, C.c_size_t, VP)
 _sig("mcdc_set_kernel_timing", C.c_int, VP, C.c_int)
 _sig("mcdc_kernel_time", C.c_int, VP, C.POINTER(C.c_uint64), C.POINTER(C.c_double))
 _sig("mcdc_destroy_problem", None, VP)
@@ -219,10 +225,16 @@ class _Desc:
         self.nimp = G * int(np.prod(imp["n"])) if imp is not None else 0
 
 
-def make_options(schedule=SCHED_HISTORY, block=0, waves_per_cu=0, lds_tally=1, event_chunk=0):
+def make_options(schedule=SCHED_HISTORY, block=0, waves_per_cu=0, lds_tally=1, event_chunk=0,
+                 tile=None):
+    """tile = (lo[5], n[5]) in bins along x, y, z, t, group: LDS hot tile."""
     o = Options()
     o.schedule, o.block, o.waves_per_cu, o.lds_tally, o.event_chunk = (
         schedule, block, waves_per_cu, lds_tally, event_chunk)
+    if tile is not None:
+        lo, n = tile
+        o.tile_lo = (C.c_int32 * 5)(*[int(v) for v in lo])
+        o.tile_n = (C.c_int32 * 5)(*[int(v) for v in n])
     return o
 
 
@@ -406,6 +418,44 @@ class BatchProblem:
         check(_lib.mcdc_get_batch_history_path(self.h, p, out.ctypes.data_as(PD), n,
                                                _stream_ptr(stream)), "get_batch_history_path")
         return out
+
+
+def micro_atomic_rate(n_bins: int, n_updates: int, run: int = 1, per_item: int = 64, reps: int = 3):
+    """Measured FP64 atomic-add rate (updates/s) into an n_bins array."""
+    import torch
+    buf = torch.zeros(n_bins, dtype=torch.float64, device="cuda")
+    n_items = max(1, n_updates // per_item)
+    best = 0.0
+    for _ in range(reps + 1):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        check(_lib.mcdc_micro_atomics(_ptr(buf), n_bins, n_items, per_item, run, _stream_ptr()),
+              "micro_atomics")
+        b.record()
+        b.synchronize()
+        best = max(best, n_items * per_item / (a.elapsed_time(b) / 1e3))
+    total = float(buf.sum().item())
+    assert total == float(n_items * per_item * (reps + 1)), "atomic micro-benchmark lost updates"
+    return best
+
+
+def micro_copy_rate(n_bytes: int = 1 << 30, reps: int = 3):
+    """Measured device-to-device streaming rate (bytes moved / s, read + write)."""
+    import torch
+    n = n_bytes // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    best = 0.0
+    for _ in range(reps + 1):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        check(_lib.mcdc_micro_copy(_ptr(src), _ptr(dst), n * 8, _stream_ptr()), "micro_copy")
+        b.record()
+        b.synchronize()
+        best = max(best, 2 * n * 8 / (a.elapsed_time(b) / 1e3))
+    return best
 
 
 def mlp_param_count(in_dim: int) -> int:

@@ -242,3 +242,51 @@ def test_full_size_duct_sampled_histories():
     assert abs(s.sum() - c["path"]) <= 1e-9 * c["path"]
     assert c["w_source"] == c["w_leak"] + c["w_absorb"] + c["w_time_end"]
     assert c["leaks"] + c["absorptions"] + c["time_ends"] == n
+
+
+# ---------------------------------------------------------------------------
+# LDS hot tile: a sub-box of the mesh privatised per workgroup
+# ---------------------------------------------------------------------------
+
+def test_hot_tile_parity_duct():
+    mc = _mcdc()
+    p = W.config2(n_census=3)
+    tile = ([2, 3, 1, 0, 0], [10, 12, 9, 6, 1])        # x, y, z, t, g
+    full_parity(p, 3000, seed=131, trace_cap=200000,
+                options=mc.make_options(mc.SCHED_HISTORY, tile=tile))
+
+
+def test_hot_tile_parity_multigroup_partial_groups():
+    mc = _mcdc()
+    p = W.config3()
+    tile = ([0, 0, 0, 0, 3], [12, 12, 10, 2, 4])       # groups 3..6 only
+    full_parity(p, 400, seed=132, trace_cap=300000,
+                options=mc.make_options(mc.SCHED_HISTORY, tile=tile))
+
+
+def test_hot_tile_rejects_outside_mesh():
+    mc = _mcdc()
+    with pytest.raises(mc.McdcError) as e:
+        mc.Problem(W.config2(), mc.make_options(tile=([55, 0, 0, 0, 0], [10, 2, 2, 1, 1])))
+    assert e.value.status == mc.E_INVALID
+
+
+def test_planned_tile_at_full_size_matches_plain_run():
+    """The autotuner's tile for the full duct problem: same per-history
+    results and tallies (to reordering) as the run without a tile."""
+    mc = _mcdc()
+    from paper_2409_04668_amd import autotune
+    p = W.config2()
+    tile, frac = autotune.plan_hot_tile(p, pilot=1_000_000)
+    assert tile is not None and frac > 0.5
+    n = 5_000_000
+    res = []
+    for opt in (mc.make_options(mc.SCHED_HISTORY), mc.make_options(mc.SCHED_HISTORY, tile=tile)):
+        gp = mc.Problem(p, opt)
+        gp.set_history_scores(n)
+        gp.run(n, 77)
+        res.append((gp.history_scores(), gp.raw()[0], gp.counters()))
+        gp.close()
+    assert np.array_equal(res[0][0], res[1][0])
+    assert_close_sums(res[0][1], res[1][1], what="tally")
+    assert res[0][2]["pieces"] == res[1][2]["pieces"]

@@ -1,0 +1,32 @@
+"""Host-side logic that needs no GPU: the autotuner's hot-tile planner and the
+workload generators."""
+import numpy as np
+
+from paper_2409_04668_amd import workloads as W
+
+
+def test_grow_tile_finds_planted_box():
+    from paper_2409_04668_amd.autotune import grow_tile
+    rng = np.random.default_rng(0)
+    D = 0.001 * rng.random((2, 20, 30, 40, 30))
+    D[1, 3:7, 5:15, 10:22, 4:16] += 1.0 + rng.random((4, 10, 12, 12))
+    (lo, n), frac = grow_tile(D, 4 * 10 * 12 * 12)
+    assert list(lo) == [4, 10, 5, 3, 1] and list(n) == [12, 12, 10, 4, 1]
+    assert frac > 0.9
+    (lo2, n2), _ = grow_tile(D, 100)
+    assert int(np.prod(n2)) <= 100
+
+
+def test_config_shapes():
+    assert W.n_bins(W.config1()) == 2000
+    assert W.n_bins(W.config2()) == 60 * 100 * 60 * 20
+    assert W.n_bins(W.config3()) == 60 * 100 * 60 * 20 * 7
+    p3 = W.config3()
+    rows = p3["sigma_s"].sum(axis=2)
+    assert np.all(rows <= p3["sigma_t"] * 0.9 + 1e-15) and np.all(rows >= p3["sigma_t"] * 0.3 - 1e-15)
+    assert np.all(np.triu(p3["sigma_s"][0], 1) == 0)          # downscatter only
+    probs, nh = W.config5()
+    assert len(probs) == 256 and nh.min() >= 10_000 and nh.max() <= 1_000_000
+    for p in probs[:20]:
+        assert 1 <= p["sigma_t"].shape[1] <= 7 and p["mesh"]["n"][3] == len(p["census"]) == 10
+        assert 0 <= len(p["box_mat"]) <= 7
