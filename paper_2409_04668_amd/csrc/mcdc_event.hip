@@ -216,8 +216,8 @@ __global__ void __launch_bounds__(256) k_ev_interact(DevProblem P, RunArgs A, Ev
             uint32_t slot;
             bank_load(B, j, q, d, slot);
             EvCtx<WW> C{P, A, B, slot, WW ? s_prm : P.ww_params};
-            if (SURF) stage_surface(P, A, S, C, q, d);
-            else stage_collision(P, A, S, C, q, d);
+            const bool due = SURF ? stage_surface(P, A, S, C, q, d) : stage_collision(P, A, S, C, q, d);
+            if (WW && due) ww_check(P, A, S, C, q);
             alive = q.alive;
             if (alive) bank_store(B, j, q, d, slot);
         }

@@ -186,7 +186,23 @@ __global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_history(DevProblem P,
     using Tally = typename TallyFor<LDS>::type;
     const Tally tally = make_tally((Tally *)nullptr, P, A, s_tile);
 
+    bool ww_due = false;                    // a weight-window check waits for this lane
     for (;;) {
+        if (WW) {
+            // Weight-window checks run batched: a lane that needs one waits
+            // (its particle does not move) until at least half of the wave's
+            // active lanes wait, then they evaluate the network together.
+            // The check sees exactly the state it would have seen at once.
+            const uint64_t due = __ballot(ww_due);
+            if (due && 2 * __popcll(due) >= __popcll(__ballot(true))) {
+                if (ww_due) {
+                    ww_check(P, A, S, H, q);
+                    ww_due = false;
+                }
+                continue;
+            }
+            if (ww_due) continue;
+        }
         if (!q.alive) {
             if (WW && H.sp > 0) {
                 H.sp -= 1;
@@ -213,9 +229,9 @@ __global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_history(DevProblem P,
         double d;
         const int ev = stage_flight(P, A, S, tally, H, q, d, n_piece, path);
         if (ev == EV_SURFACE) {
-            stage_surface(P, A, S, H, q, d);
+            ww_due = stage_surface(P, A, S, H, q, d);
         } else if (ev == EV_SCATTER) {
-            stage_collision(P, A, S, H, q, d);
+            ww_due = stage_collision(P, A, S, H, q, d);
         } else if (ev < 0) {
             H.sp = 0;                       // event cap: the history is abandoned
         }

@@ -266,26 +266,29 @@ MCDC_DEV int stage_flight(const DevProblem &P, const RunArgs &A, Shared &S, cons
     return ev;
 }
 
-// Surface crossing: outer boundary (leak / reflect), new cell, weight window.
+// Surface crossing: outer boundary (leak / reflect), new cell.  Returns true
+// when a weight-window check is due (the caller runs ww_check before the
+// particle moves again, possibly batched with other lanes).
 template <class Ctx>
-MCDC_DEV void stage_surface(const DevProblem &P, const RunArgs &A, Shared &S, Ctx &C, Part &q,
+MCDC_DEV bool stage_surface(const DevProblem &P, const RunArgs &A, Shared &S, Ctx &C, Part &q,
                             double d) {
     atomicAdd(&S.cnt[C_SURFACE], 1ull);
     const int face = boundary(P, q);
     if (face >= 0) {
         leak(S, q, face);
         trace_rec(A, C.hist(), q, EV_LEAK, d);
-        return;
+        return false;
     }
     q.cell = locate(P, q.x, q.u);
     trace_rec(A, C.hist(), q, EV_SURFACE, d);
-    if (Ctx::kWW && P.ww_on) ww_check(P, A, S, C, q);
+    return Ctx::kWW && P.ww_on;
 }
 
 // Collision: analog absorption or implicit capture with weight cutoff, then
-// the outgoing group (cumulative row) and an isotropic direction; weight window.
+// the outgoing group (cumulative row) and an isotropic direction.  Returns
+// true when a weight-window check is due.
 template <class Ctx>
-MCDC_DEV void stage_collision(const DevProblem &P, const RunArgs &A, Shared &S, Ctx &C, Part &q,
+MCDC_DEV bool stage_collision(const DevProblem &P, const RunArgs &A, Shared &S, Ctx &C, Part &q,
                               double d) {
     atomicAdd(&S.cnt[C_COLLISION], 1ull);
     const int mat = q.cell >= 0 ? P.box_mat[q.cell] : P.background_mat;
@@ -302,7 +305,7 @@ MCDC_DEV void stage_collision(const DevProblem &P, const RunArgs &A, Shared &S, 
             atomicAdd(&S.cnt[C_ABSORB], 1ull);
             q.alive = false;
             trace_rec(A, C.hist(), q, EV_ABSORB, d);
-            return;
+            return false;
         }
     } else {
         const double c = sig_s / sig_t;
@@ -321,7 +324,7 @@ MCDC_DEV void stage_collision(const DevProblem &P, const RunArgs &A, Shared &S, 
                 atomicAdd(&S.cnt[C_CUT_KILL], 1ull);
                 q.alive = false;
                 trace_rec(A, C.hist(), q, EV_CUT_KILL, d);
-                return;
+                return false;
             }
         }
     }
@@ -340,7 +343,7 @@ MCDC_DEV void stage_collision(const DevProblem &P, const RunArgs &A, Shared &S, 
     iso_direction(r, q.u[0], q.u[1], q.u[2]);
     q.k = r.k;
     trace_rec(A, C.hist(), q, EV_SCATTER, d);
-    if (Ctx::kWW && P.ww_on) ww_check(P, A, S, C, q);
+    return Ctx::kWW && P.ww_on;
 }
 
 }  // namespace mcdc

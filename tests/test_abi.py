@@ -43,3 +43,38 @@ def test_binding_imports_and_validates_on_cpu():
     assert st == mcdc.E_INVALID
     assert b"census" in mcdc._lib.mcdc_last_error()
     assert mcdc.mlp_param_count(5) == 4609
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libmcdc.so not built")
+def test_failure_paths_without_gpu():
+    """Errors are reported as status codes with a message before any device
+    work: workspace too small, bad options, bad tiles, bad batches."""
+    import numpy as np
+    from paper_2409_04668_amd import mcdc, workloads as W
+    d = mcdc._Desc(W.config2())
+    n = ctypes.c_size_t()
+    opt = mcdc.make_options()
+    assert mcdc._lib.mcdc_workspace_bytes(ctypes.byref(d.d), ctypes.byref(opt), ctypes.byref(n)) == 0
+    h = ctypes.c_void_p()
+    fake = ctypes.c_void_p(0x1000)            # never dereferenced: the size check fails first
+    st = mcdc._lib.mcdc_create_problem(ctypes.byref(d.d), ctypes.byref(opt), fake, n.value - 256,
+                                       ctypes.byref(h))
+    assert st == mcdc.E_NOMEM and b"too small" in mcdc._lib.mcdc_last_error()
+    bad = mcdc.make_options(block=100)
+    assert mcdc._lib.mcdc_workspace_bytes(ctypes.byref(d.d), ctypes.byref(bad),
+                                          ctypes.byref(n)) == mcdc.E_INVALID
+    big = mcdc.make_options(tile=([0, 0, 0, 0, 0], [60, 100, 60, 20, 1]))
+    assert mcdc._lib.mcdc_workspace_bytes(ctypes.byref(d.d), ctypes.byref(big),
+                                          ctypes.byref(n)) == mcdc.E_INVALID
+    p = W.config2()
+    p["box_mat"] = np.array([0, 1, 7, 1], np.int32)          # material out of range
+    bd = mcdc._Desc(p)
+    assert mcdc._lib.mcdc_workspace_bytes(ctypes.byref(bd.d), ctypes.byref(opt),
+                                          ctypes.byref(n)) == mcdc.E_INVALID
+    # batched problems must share their census count
+    probs = [W.batch_problem(1), W.batch_problem(2, nt=5)]
+    descs = [mcdc._Desc(q, i) for i, q in enumerate(probs)]
+    arr = (mcdc.ProblemDesc * 2)(*[x.d for x in descs])
+    nh = (ctypes.c_uint64 * 2)(10, 10)
+    st = mcdc._lib.mcdc_batch_workspace_bytes(arr, 2, nh, ctypes.byref(opt), ctypes.byref(n))
+    assert st == mcdc.E_INVALID and b"census" in mcdc._lib.mcdc_last_error()
