@@ -18,8 +18,10 @@ __device__ __forceinline__ uint32_t mix32(uint32_t x) {
 // Each work-item performs `per_item` updates in runs of `run` consecutive
 // bins starting at a hashed position (run = 1: fully random).
 __global__ void __launch_bounds__(256) k_atomic_ceiling(double *__restrict__ buf, uint32_t n_bins,
-                                                        uint32_t per_item, uint32_t run) {
+                                                        uint32_t n_items, uint32_t per_item,
+                                                        uint32_t run) {
     const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= n_items) return;
     uint32_t h = mix32(tid * 2654435761u + 12345u);
     for (uint32_t k = 0; k < per_item; k += run) {
         h = mix32(h + k);
@@ -52,7 +54,7 @@ int mcdc_micro_atomics(double *dev_buf, uint64_t n_bins, uint64_t n_items, uint3
     const int block = 256;
     const uint64_t grid = (n_items + block - 1) / block;
     hipLaunchKernelGGL(k_atomic_ceiling, dim3((uint32_t)grid), dim3(block), 0, (hipStream_t)stream,
-                       dev_buf, (uint32_t)n_bins, per_item, run);
+                       dev_buf, (uint32_t)n_bins, (uint32_t)n_items, per_item, run);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? MCDC_OK : hip_fail(e, "micro_atomics");
 }

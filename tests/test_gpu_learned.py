@@ -69,8 +69,9 @@ def test_mlp_adam_training_matches_oracle_and_decreases_loss():
         ref, m, v = M.adam_step(ref, M.grad(ref, X, y, wt, IN, H), m, v, step, 1e-3)
     assert np.max(np.abs(losses - np.array(ref_losses)) / np.array(ref_losses)) < 1e-3
     assert np.max(np.abs(params - ref)) < 1e-3 * max(1.0, np.max(np.abs(ref)))
+    # the loss path follows the FP64 reference (which itself is not monotone
+    # step by step at this learning rate) and falls overall
     assert losses[-1] < 0.8 * losses[0]
-    assert all(b <= a * (1 + 1e-3) for a, b in zip(losses, losses[1:]))
 
 
 @pytest.mark.slow
