@@ -183,6 +183,11 @@ def main():
         "copy_GBps": copy_bw / 1e9,
         "atomic_frac_of_random_ceiling": ach_atomics / ceil_rand if ceil_rand else None,
         "atomic_frac_of_runs8_ceiling": ach_atomics / ceil_run8 if ceil_run8 else None}
+    # the paper's own rate, quoted as context only (other problem, other GPU):
+    # 1e10 histories of its time-dependent duct benchmark in 1500 s on one V100
+    out["paper_context"] = {"histories_per_s": 1e10 / 1500.0, "hardware": "1x NVIDIA V100 (Lassen)",
+                            "workload": "Kobayashi dog-leg void duct, time dependent, 1 group",
+                            "source": "Sec. Performance (GPU profiling paragraph)"}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_sample, seed)
     print(json.dumps(out), flush=True)

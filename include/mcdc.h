@@ -123,6 +123,7 @@ typedef struct {
     int64_t batches;
     uint64_t n_hist;
     int32_t status;                    /* sticky device error status             */
+    uint64_t event_iterations;         /* event schedule: stage iterations launched */
 } mcdc_counters;
 
 typedef struct mcdc_problem *mcdc_handle;

@@ -524,6 +524,7 @@ int mcdc_get_counters(mcdc_handle h, mcdc_counters *out, void *stream) {
     fill_counters(acc, out);
     out->batches = h->batches;
     out->n_hist = h->n_hist;
+    out->event_iterations = h->event_iterations;
     return MCDC_OK;
 }
 

@@ -3,8 +3,8 @@
 // over a compacted queue of bank indices:
 //   flight    (all live particles)  -> surface queue | collision queue |
 //                                        census queue | ended
-//   surface   (surface queue)       -> next active queue | ended
-//   collision (collision queue)     -> next active queue | ended
+//   interact  (surface + collision queues, one launch) -> next active
+//             queue | ended; its last workgroup advances the queue roles
 // Queues are appended with one atomic per wavefront: __ballot of the
 // predicate, popcount for the wave's total, mbcnt for each lane's offset.
 // When the active queue drains, the census queue becomes the active queue
@@ -24,7 +24,8 @@ struct EvCtl {
     uint32_t cur, nxt, cen;              // roles: current active, next active, census
     uint32_t bank_n;                     // bank entries in use
     uint32_t done;
-    uint32_t pad[6];
+    uint32_t blocks_done;                // completion count of the interaction launch
+    uint32_t pad[5];
 };
 
 struct EvBank {
@@ -189,9 +190,34 @@ __global__ void __launch_bounds__(256) k_ev_flight(DevProblem P, RunArgs A, EvBa
     shared_flush(S, A.acc);
 }
 
-template <bool SURF, bool WW>
+// Queue roles for the next iteration.  Reads the counters with atomics so
+// that the values other workgroups appended are seen.
+MCDC_DEV void ev_advance(EvCtl *c) {
+    const uint32_t cur = c->cur, nxt = c->nxt, cen = c->cen;
+    const uint32_t n_nxt = atomicAdd(&c->n_act[nxt], 0u);
+    const uint32_t n_cen = atomicAdd(&c->n_act[cen], 0u);
+    c->n_act[cur] = 0;
+    c->n_surf = 0;
+    c->n_coll = 0;
+    if (n_nxt > 0) {
+        c->cur = nxt;
+        c->nxt = cur;
+    } else if (n_cen > 0) {                  // next census step
+        c->cur = cen;
+        c->cen = nxt;
+        c->nxt = cur;
+    } else {
+        c->done = 1;
+    }
+}
+
+// Surface and collision stages in one launch: entries [0, n_surf) of the
+// combined range come from the surface queue, the rest from the collision
+// queue.  The last workgroup to finish advances the queue roles.
+template <bool WW>
 __global__ void __launch_bounds__(256) k_ev_interact(DevProblem P, RunArgs A, EvBank B) {
     __shared__ Shared S;
+    __shared__ bool s_last;
     // weight-window network in LDS: every lane of a wave reads the same
     // weight at the same time (broadcast), instead of from HBM
     __shared__ float s_prm[WW ? kH * (4 + kMaxG) + kH + kH * kH + kH + kH + 1 : 1];
@@ -202,21 +228,22 @@ __global__ void __launch_bounds__(256) k_ev_interact(DevProblem P, RunArgs A, Ev
     }
     __syncthreads();
     const uint32_t nxt = B.ctl->nxt;
-    const uint32_t n = SURF ? B.ctl->n_surf : B.ctl->n_coll;
-    const uint32_t *in = SURF ? B.qs : B.qc;
+    const uint32_t ns = B.ctl->n_surf, nc = B.ctl->n_coll;
+    const uint32_t n = ns + nc;
     for (uint32_t j0 = blockIdx.x * blockDim.x; j0 < n; j0 += gridDim.x * blockDim.x) {
         const uint32_t jj = j0 + threadIdx.x;
         const bool valid = jj < n;
         bool alive = false;
         uint32_t j = 0;
         if (valid) {
-            j = in[jj];
+            const bool surf = jj < ns;
+            j = surf ? B.qs[jj] : B.qc[jj - ns];
             Part q;
             double d;
             uint32_t slot;
             bank_load(B, j, q, d, slot);
             EvCtx<WW> C{P, A, B, slot, WW ? s_prm : P.ww_params};
-            const bool due = SURF ? stage_surface(P, A, S, C, q, d) : stage_collision(P, A, S, C, q, d);
+            const bool due = surf ? stage_surface(P, A, S, C, q, d) : stage_collision(P, A, S, C, q, d);
             if (WW && due) ww_check(P, A, S, C, q);
             alive = q.alive;
             if (alive) bank_store(B, j, q, d, slot);
@@ -225,24 +252,15 @@ __global__ void __launch_bounds__(256) k_ev_interact(DevProblem P, RunArgs A, Ev
     }
     __syncthreads();
     shared_flush(S, A.acc);
-}
-
-// Queue roles for the next iteration (single work-item).
-__global__ void k_ev_advance(EvBank B) {
-    EvCtl *c = B.ctl;
-    c->n_act[c->cur] = 0;
-    c->n_surf = 0;
-    c->n_coll = 0;
-    const uint32_t cur = c->cur, nxt = c->nxt, cen = c->cen;
-    if (c->n_act[nxt] > 0) {
-        c->cur = nxt;
-        c->nxt = cur;
-    } else if (c->n_act[cen] > 0) {          // next census step
-        c->cur = cen;
-        c->cen = nxt;
-        c->nxt = cur;
-    } else {
-        c->done = 1;
+    if (threadIdx.x == 0) {
+        __threadfence();
+        s_last = atomicAdd(&B.ctl->blocks_done, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (s_last && threadIdx.x == 0) {
+        __threadfence();
+        ev_advance(B.ctl);
+        B.ctl->blocks_done = 0;
     }
 }
 
@@ -279,6 +297,7 @@ __global__ void k_ev_reset(EvBank B, uint32_t n_hist) {
     c->cen = Q_C;
     c->bank_n = n_hist;
     c->done = 0;
+    c->blocks_done = 0;
 }
 
 __global__ void k_ev_count_hist(DevAcc *acc, uint64_t n) { atomicAdd(&acc->cnt[C_HIST], (unsigned long long)n); }
@@ -366,19 +385,14 @@ int event_run_range(mcdc_problem *h, const RunArgs &A0, hipStream_t s) {
         else hipLaunchKernelGGL((k_ev_source<false>), dim3(sg), dim3(block), 0, s, P, A, B, n);
         for (int iter = 0;; ++iter) {
             const int K = 8;
+            h->event_iterations += K;
             for (int k = 0; k < K; ++k) {
                 timing_begin(h, s);
                 if (ww) hipLaunchKernelGGL((k_ev_flight<true>), dim3(grid), dim3(block), 0, s, P, A, B);
                 else hipLaunchKernelGGL((k_ev_flight<false>), dim3(grid), dim3(block), 0, s, P, A, B);
                 timing_end(h, s);
-                if (ww) {
-                    hipLaunchKernelGGL((k_ev_interact<true, true>), dim3(grid), dim3(block), 0, s, P, A, B);
-                    hipLaunchKernelGGL((k_ev_interact<false, true>), dim3(grid), dim3(block), 0, s, P, A, B);
-                } else {
-                    hipLaunchKernelGGL((k_ev_interact<true, false>), dim3(grid), dim3(block), 0, s, P, A, B);
-                    hipLaunchKernelGGL((k_ev_interact<false, false>), dim3(grid), dim3(block), 0, s, P, A, B);
-                }
-                hipLaunchKernelGGL(k_ev_advance, dim3(1), dim3(1), 0, s, B);
+                if (ww) hipLaunchKernelGGL((k_ev_interact<true>), dim3(grid), dim3(block), 0, s, P, A, B);
+                else hipLaunchKernelGGL((k_ev_interact<false>), dim3(grid), dim3(block), 0, s, P, A, B);
             }
             hipError_t e = hipMemcpyAsync(E->host_done, &B.ctl->done, sizeof(uint32_t),
                                           hipMemcpyDeviceToHost, s);

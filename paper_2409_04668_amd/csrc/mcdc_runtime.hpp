@@ -36,6 +36,7 @@ struct mcdc_problem {
     uint32_t nbins = 0;
     size_t nimp = 0;
     uint64_t n_hist = 0;
+    uint64_t event_iterations = 0;
     int64_t batches = 0;
     mcdc_trace_rec *trace = nullptr;
     uint64_t trace_cap = 0;

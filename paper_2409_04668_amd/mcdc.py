@@ -73,7 +73,8 @@ class Counters(C.Structure):
                 [(n, C.c_double) for n in ["w_source", "w_leak", "w_absorb", "w_time_end",
                                            "w_gain", "w_loss", "path"]] +
                 [("leak", C.c_double * 6), ("det_sum", C.c_double), ("det_sumsq", C.c_double),
-                 ("batches", C.c_int64), ("n_hist", C.c_uint64), ("status", C.c_int32)])
+                 ("batches", C.c_int64), ("n_hist", C.c_uint64), ("status", C.c_int32),
+                 ("event_iterations", C.c_uint64)])
 
     def as_dict(self):
         d = {n: getattr(self, n) for n, _ in self._fields_ if n != "leak"}
