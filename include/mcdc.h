@@ -185,6 +185,21 @@ int mcdc_set_history_scores(mcdc_handle h, double *dev_xh);
 int mcdc_set_ww_mlp(mcdc_handle h, const float *params, size_t n_params, double logk,
                     double ratio, int32_t n_max, float ymin, float ymax);
 
+/* Weight-window map: evaluate the network set by mcdc_set_ww_mlp once at the
+ * centre of every cell of a regular map, n = (nx, ny, nz, nt) cells over the
+ * outer box and [0, end time] per group (centre inputs 2 (i + 1/2)/n - 1), and
+ * from then on take w_T at a check from the map cell that holds the particle
+ * (per axis floor(s n), s the point's fraction of the range, clamped to
+ * [0, n-1]).  dev_map is caller-owned device memory of at least
+ * G * nx * ny * nz * nt doubles (layout [g][t][z][y][x], filled with w_T on
+ * `stream`; it must stay allocated while the map is in use).  Each n[a] lies
+ * in [1, 65536] and the map holds at most 2^26 cells.  dev_map == NULL goes
+ * back to evaluating the network at every check; mcdc_set_ww_mlp also does,
+ * so a new network needs a new call.  MCDC_E_STATE without a network,
+ * MCDC_E_NOMEM when capacity (in doubles) is too small. */
+int mcdc_set_ww_map(mcdc_handle h, const int32_t n[4], double *dev_map, size_t capacity,
+                    void *stream);
+
 /* Coarse importance estimate accumulated by runs with imp_on: host copies of
  * score[c] and weight[c] for G * imp_n[0..3] cells (x fastest, then y, z, t, g). */
 int mcdc_get_importance(mcdc_handle h, double *score, double *weight, size_t n, void *stream);

@@ -502,6 +502,7 @@ typedef struct {
     int64_t imp_cell[16];
     double imp_cnt[16], imp_xsum[16];
     double ww_lo[4], ww_inv[4];
+    double *ww_map;           /* window map (NULL: network at every check) */
 } o_ctx;
 
 static void o_trace(o_ctx *C, o_part *q, int type, double aux)
@@ -563,25 +564,98 @@ static void o_leak(o_ctx *C, o_part *q, int face)
     q->alive = 0;
 }
 
-/* Weight-window check (MLP importance): y = network output clamped to the
- * range [ymin, ymax] of its training targets, target w_T = exp(log K - y),
- * window [w_L, w_U] with w_L = 2 w_T / (1 + r), w_U = r w_L.  Above: split
- * into n = min(ceil(w / w_T), n_max) copies of weight w/n; the n-1 daughters
- * go on the LIFO stack with stream tags derived from one parent block.  Below:
+/* Window target from the network: y = network output at the normalised point
+ * (2 s - 1 per axis, s the fraction of the outer box / of the last census
+ * time, group one-hot), clamped to the range [ymin, ymax] of its training
+ * targets; w_T = exp(log K - y). */
+static double o_ww_net(const orc_problem *P, const float *in_xt, int32_t g)
+{
+    float in[4 + 16];
+    for (int a = 0; a < 4; ++a) in[a] = in_xt[a];
+    for (int j = 0; j < P->G; ++j) in[4 + j] = j == g ? 1.0f : 0.0f;
+    float y = orc_mlp_f32(P->ww_params, 4 + P->G, P->ww_hidden, in);
+    if (y < P->ww_ymin) y = P->ww_ymin;
+    if (y > P->ww_ymax) y = P->ww_ymax;
+    return orc_exp(P->ww_logk - (double)y);
+}
+
+static int o_has_map(const orc_problem *P)
+{
+    return P->ww_on && P->ww_map_n[0] > 0 && P->ww_map_n[1] > 0 && P->ww_map_n[2] > 0 &&
+           P->ww_map_n[3] > 0;
+}
+
+static void o_ww_norm(const orc_problem *P, double lo[4], double inv[4])
+{
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = P->outer_lo[a];
+        inv[a] = 1.0 / (P->outer_hi[a] - P->outer_lo[a]);
+    }
+    lo[3] = 0.0;
+    inv[3] = 1.0 / P->census[P->n_census - 1];
+}
+
+/* map cell: per axis i = floor(s n) clamped to [0, n-1] */
+static int64_t o_map_cell(const orc_problem *P, const double lo[4], const double inv[4],
+                          const double p[3], double t, int32_t g)
+{
+    int64_t c = g;
+    for (int a = 3; a >= 0; --a) {
+        double v = a < 3 ? p[a] : t;
+        double sa = (v - lo[a]) * inv[a];
+        double f = floor(sa * (double)P->ww_map_n[a]);
+        int64_t i = f < 0.0 ? 0 : (f >= (double)P->ww_map_n[a] ? P->ww_map_n[a] - 1 : (int64_t)f);
+        c = c * P->ww_map_n[a] + i;
+    }
+    return c;
+}
+
+int64_t orc_ww_map(const orc_problem *P, double *out)
+{
+    if (!o_has_map(P)) return -1;
+    const int32_t *n = P->ww_map_n;
+    int64_t c = 0;
+    for (int32_t g = 0; g < P->G; ++g)
+        for (int32_t it = 0; it < n[3]; ++it)
+            for (int32_t iz = 0; iz < n[2]; ++iz)
+                for (int32_t iy = 0; iy < n[1]; ++iy)
+                    for (int32_t ix = 0; ix < n[0]; ++ix) {
+                        const int32_t idx[4] = {ix, iy, iz, it};
+                        float in[4];
+                        for (int a = 0; a < 4; ++a)
+                            in[a] = (float)(2.0 * (((double)idx[a] + 0.5) / (double)n[a]) - 1.0);
+                        out[c++] = o_ww_net(P, in, g);
+                    }
+    return c;
+}
+
+int64_t orc_ww_map_cell(const orc_problem *P, const double p[3], double t, int32_t g)
+{
+    if (!o_has_map(P)) return -1;
+    double lo[4], inv[4];
+    o_ww_norm(P, lo, inv);
+    return o_map_cell(P, lo, inv, p, t, g);
+}
+
+/* Weight-window check: target w_T from the network at the particle's point
+ * (or, with a map, at the centre of its map cell), window [w_L, w_U] with
+ * w_L = 2 w_T / (1 + r), w_U = r w_L.  Above: split into
+ * n = min(ceil(w / w_T), n_max) copies of weight w/n; the n-1 daughters go on
+ * the LIFO stack with stream tags derived from one parent block.  Below:
  * roulette, survive iff xi * w_T < w with weight w_T.  No draw otherwise. */
 static void o_ww(o_ctx *C, o_part *q)
 {
     const orc_problem *P = C->P;
-    float in[4 + 16];
-    int in_dim = 4 + P->G;
-    for (int a = 0; a < 3; ++a)
-        in[a] = (float)(2.0 * ((q->p[a] - C->ww_lo[a]) * C->ww_inv[a]) - 1.0);
-    in[3] = (float)(2.0 * ((q->t - C->ww_lo[3]) * C->ww_inv[3]) - 1.0);
-    for (int g = 0; g < P->G; ++g) in[4 + g] = g == q->g ? 1.0f : 0.0f;
-    float y = orc_mlp_f32(P->ww_params, in_dim, P->ww_hidden, in);
-    if (y < P->ww_ymin) y = P->ww_ymin;
-    if (y > P->ww_ymax) y = P->ww_ymax;
-    double wt = orc_exp(P->ww_logk - (double)y);
+    double wt;
+    if (C->ww_map) {
+        wt = C->ww_map[o_map_cell(P, C->ww_lo, C->ww_inv, q->p, q->t, q->g)];
+    } else {
+        float in[4];
+        for (int a = 0; a < 3; ++a)
+            in[a] = (float)(2.0 * ((q->p[a] - C->ww_lo[a]) * C->ww_inv[a]) - 1.0);
+        in[3] = (float)(2.0 * ((q->t - C->ww_lo[3]) * C->ww_inv[3]) - 1.0);
+        wt = o_ww_net(P, in, q->g);
+    }
     double wl = (2.0 * wt) / (1.0 + P->ww_ratio);
     double wu = P->ww_ratio * wl;
     if (q->w > wu) {
@@ -907,6 +981,17 @@ static int o_validate(const orc_problem *P)
                                     isinf(P->outer_hi[1]) || isinf(P->outer_hi[2])))
         return ORC_E_INVALID;
     if (P->imp_on && (P->ww_on || P->implicit_capture)) return ORC_E_INVALID;
+    if (P->ww_on) {
+        int pos = 0, zero = 0;
+        for (int a = 0; a < 4; ++a) {
+            if (P->ww_map_n[a] > 0) ++pos;
+            if (P->ww_map_n[a] == 0) ++zero;
+        }
+        if (!(pos == 4 || zero == 4)) return ORC_E_INVALID;
+        if (pos == 4 && (double)P->ww_map_n[0] * P->ww_map_n[1] * P->ww_map_n[2] *
+                                    P->ww_map_n[3] * P->G > (double)(1 << 26))
+            return ORC_E_INVALID;
+    }
     return ORC_OK;
 }
 
@@ -922,12 +1007,13 @@ int orc_run(const orc_problem *P, uint64_t seed, uint64_t hist0, uint64_t n_hist
     C.seed = seed;
     C.status = ORC_OK;
     C.stack = (o_part *)malloc(sizeof(o_part) * (size_t)(P->stack_cap > 0 ? P->stack_cap : 1));
-    for (int a = 0; a < 3; ++a) {
-        C.ww_lo[a] = P->outer_lo[a];
-        C.ww_inv[a] = 1.0 / (P->outer_hi[a] - P->outer_lo[a]);
+    o_ww_norm(P, C.ww_lo, C.ww_inv);
+    if (o_has_map(P)) {
+        size_t cells = (size_t)P->G * P->ww_map_n[0] * P->ww_map_n[1] * P->ww_map_n[2] *
+                       P->ww_map_n[3];
+        C.ww_map = (double *)malloc(sizeof(double) * cells);
+        orc_ww_map(P, C.ww_map);
     }
-    C.ww_lo[3] = 0.0;
-    C.ww_inv[3] = 1.0 / P->census[P->n_census - 1];
     size_t nbins = (size_t)C.M.G_t * P->mesh_n[0] * P->mesh_n[1] * P->mesh_n[2] * P->mesh_n[3];
     const uint64_t B = (uint64_t)P->n_batches;
     for (uint64_t b = 0; b < B; ++b) {
@@ -935,7 +1021,7 @@ int orc_run(const orc_problem *P, uint64_t seed, uint64_t hist0, uint64_t n_hist
         if (hi == lo) continue;
         for (uint64_t i = lo; i < hi; ++i) {
             st = o_history(&C, hist0 + i, i);
-            if (st != ORC_OK) { free(C.stack); return st; }
+            if (st != ORC_OK) { free(C.stack); free(C.ww_map); return st; }
         }
         double nb = (double)(hi - lo);
         for (size_t i = 0; i < nbins; ++i) {
@@ -950,5 +1036,6 @@ int orc_run(const orc_problem *P, uint64_t seed, uint64_t hist0, uint64_t n_hist
     }
     R->hist_done += n_hist;
     free(C.stack);
+    free(C.ww_map);
     return ORC_OK;
 }

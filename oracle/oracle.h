@@ -88,6 +88,9 @@ typedef struct {
     const float *ww_params;
     float ww_ymin, ww_ymax;           /* network output clamped to [ymin, ymax] */
     double ww_logk, ww_ratio;
+    int32_t ww_map_n[4];              /* all > 0: targets from a cell-centre map of the
+                                         network, (nx, ny, nz, nt) cells; 0: network
+                                         evaluated at every check */
     int32_t n_batches;
     int64_t max_events;
     int32_t stack_cap;
@@ -131,6 +134,12 @@ double orc_exp(double x);
 uint32_t orc_directions(uint64_t seed, uint64_t hist, uint32_t n, double *u);
 /* FP32 MLP forward as used by the weight-window check */
 float orc_mlp_f32(const float *params, int32_t in_dim, int32_t hidden, const float *in);
+/* weight-window map: w_T at the centre of every map cell, layout
+ * [g][it][iz][iy][ix]; returns the number of cells, or -1 when the problem has
+ * no map */
+int64_t orc_ww_map(const orc_problem *P, double *out);
+/* map cell of a point (x, y, z, t, g) under the same rules as the check */
+int64_t orc_ww_map_cell(const orc_problem *P, const double p[3], double t, int32_t g);
 /* track-length scoring of one straight segment into a mesh (same rules as the
  * transport loop); returns the number of scored pieces */
 int64_t orc_score_segment(const orc_problem *P, const double p[3], const double u[3],

@@ -66,7 +66,7 @@ class OrcProblem(C.Structure):
         ("imp_on", C.c_int32), ("imp_n", I4),
         ("ww_on", C.c_int32), ("ww_hidden", C.c_int32), ("ww_nmax", C.c_int32),
         ("ww_params", PF), ("ww_ymin", C.c_float), ("ww_ymax", C.c_float),
-        ("ww_logk", C.c_double), ("ww_ratio", C.c_double),
+        ("ww_logk", C.c_double), ("ww_ratio", C.c_double), ("ww_map_n", I4),
         ("n_batches", C.c_int32), ("max_events", C.c_int64), ("stack_cap", C.c_int32),
         ("problem_id", C.c_uint32),
     ]
@@ -123,6 +123,10 @@ def lib():
         L.orc_score_segment.argtypes = [C.POINTER(OrcProblem), PD, PD, C.c_double, C.c_double,
                                         C.c_double, C.c_int32, PD]
         L.orc_score_segment.restype = C.c_int64
+        L.orc_ww_map.argtypes = [C.POINTER(OrcProblem), PD]
+        L.orc_ww_map.restype = C.c_int64
+        L.orc_ww_map_cell.argtypes = [C.POINTER(OrcProblem), PD, C.c_double, C.c_int32]
+        L.orc_ww_map_cell.restype = C.c_int64
         _lib = L
     return _lib
 
@@ -196,6 +200,8 @@ class _Problem:
             s.ww_ratio = float(ww.get("ratio", 5.0))
             s.ww_ymin = float(ww.get("ymin", -3.0e38))
             s.ww_ymax = float(ww.get("ymax", 3.0e38))
+            if ww.get("map") is not None:
+                s.ww_map_n = I4(*[int(v) for v in ww["map"]])
         s.n_batches = int(prob["n_batches"])
         s.max_events = int(prob["max_events"])
         s.stack_cap = int(prob["stack_cap"])
@@ -349,3 +355,21 @@ def score_segment(prob, p, u, t0, d, w=1.0, g=0):
     uu = np.ascontiguousarray(u, float)
     n = lib().orc_score_segment(C.byref(P.s), _pd(pp), _pd(uu), t0, d, w, g, _pd(tally))
     return tally, int(n)
+
+
+def ww_map(prob):
+    """Weight-window map w_T[g][it][iz][iy][ix] of a problem whose ``ww`` has a ``map``."""
+    P = _Problem(prob)
+    n = [int(v) for v in prob["ww"]["map"]]
+    out = np.zeros(P.s.G * n[0] * n[1] * n[2] * n[3])
+    c = lib().orc_ww_map(C.byref(P.s), _pd(out))
+    if c < 0:
+        raise ValueError("problem has no weight-window map")
+    return out.reshape(P.s.G, n[3], n[2], n[1], n[0])
+
+
+def ww_map_cell(prob, p, t, g=0):
+    """Flat map cell that the check uses for the point (p, t) in group g."""
+    P = _Problem(prob)
+    pp = np.ascontiguousarray(p, float)
+    return int(lib().orc_ww_map_cell(C.byref(P.s), _pd(pp), float(t), int(g)))

@@ -389,6 +389,7 @@ int mcdc_set_ww_mlp(mcdc_handle h, const float *params, size_t n, double logk, d
     if (!h) return fail(MCDC_E_INVALID, "null handle");
     if (!params) {
         h->P.ww_on = 0;
+        h->P.ww_map = nullptr;
         return MCDC_OK;
     }
     if (h->desc.stack_cap < 1) return fail(MCDC_E_STATE, "problem was created with stack_cap = 0");
@@ -399,6 +400,8 @@ int mcdc_set_ww_mlp(mcdc_handle h, const float *params, size_t n, double logk, d
     hipError_t e = hipMemcpy(h->ws + h->L.ww_params, params, n * sizeof(float), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "set_ww_mlp");
     h->P.ww_on = 1;
+    h->P.ww_map = nullptr;                // a new network invalidates any baked map
+    for (int a = 0; a < 4; ++a) h->P.ww_map_n[a] = 0;
     h->P.ww_logk = logk;
     h->P.ww_ratio = ratio;
     h->P.ww_nmax = n_max;

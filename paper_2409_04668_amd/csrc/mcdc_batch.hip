@@ -75,6 +75,7 @@ struct BatchState {
 
 struct BatchCtx {
     static constexpr bool kWW = false;
+    static constexpr bool kWWMap = false;
     const DevProblem &P;
     const RunArgs &A;
     const BDev &D;

@@ -85,16 +85,16 @@ MCDC_DEV void wave_append(uint32_t *queue, uint32_t *count, uint32_t value, bool
 }
 
 // Per-history context of a banked particle.
-template <bool WW>
+template <int WW>
 struct EvCtx {
-    static constexpr bool kWW = WW;
+    static constexpr bool kWW = WW != 0;
+    static constexpr bool kWWMap = WW == 2;
     const DevProblem &P;
     const RunArgs &A;
     const EvBank &B;
     uint32_t slot;
-    const float *prm;                    // MLP weights (LDS copy in the interaction kernels)
     MCDC_DEV uint64_t hist() const { return A.h_begin + slot; }
-    MCDC_DEV const float *mlp_params(const DevProblem &) const { return prm; }
+    MCDC_DEV const float *mlp_params(const DevProblem &Pp) const { return Pp.ww_params; }
     MCDC_DEV bool count_flight() {
         uint32_t e;
         if (WW) e = atomicAdd(&B.events[slot], 1u) + 1u;
@@ -139,7 +139,7 @@ __global__ void __launch_bounds__(256) k_ev_source(DevProblem P, RunArgs A, EvBa
             B.xh[s] = 0.0;
             B.path[s] = 0.0;
             B.events[s] = 0u;
-            EvCtx<WW> C{P, A, B, s, P.ww_params};
+            EvCtx<WW> C{P, A, B, s};
             Part q;
             stage_source(P, A, S, C, q);
             alive = q.alive;
@@ -173,7 +173,7 @@ __global__ void __launch_bounds__(256) k_ev_flight(DevProblem P, RunArgs A, EvBa
             double d;
             uint32_t slot;
             bank_load(B, j, q, d, slot);
-            EvCtx<WW> C{P, A, B, slot, P.ww_params};
+            EvCtx<WW> C{P, A, B, slot};
             ev = stage_flight(P, A, S, tally, C, q, d, n_piece, path);
             if (ev >= 0) n_flight += 1;
             if (q.alive) bank_store(B, j, q, d, slot);
@@ -213,19 +213,13 @@ MCDC_DEV void ev_advance(EvCtl *c) {
 
 // Surface and collision stages in one launch: entries [0, n_surf) of the
 // combined range come from the surface queue, the rest from the collision
-// queue.  The last workgroup to finish advances the queue roles.
-template <bool WW>
+// queue.  The last workgroup to finish advances the queue roles.  WW: 0 none,
+// 1 network at each check, 2 baked window map.
+template <int WW>
 __global__ void __launch_bounds__(256) k_ev_interact(DevProblem P, RunArgs A, EvBank B) {
     __shared__ Shared S;
     __shared__ bool s_last;
-    // weight-window network in LDS: every lane of a wave reads the same
-    // weight at the same time (broadcast), instead of from HBM
-    __shared__ float s_prm[WW ? kH * (4 + kMaxG) + kH + kH * kH + kH + kH + 1 : 1];
     shared_zero(S);
-    if (WW) {
-        const int np = kH * (4 + P.G) + kH + kH * kH + kH + kH + 1;
-        for (int i = threadIdx.x; i < np; i += blockDim.x) s_prm[i] = P.ww_params[i];
-    }
     __syncthreads();
     const uint32_t nxt = B.ctl->nxt;
     const uint32_t ns = B.ctl->n_surf, nc = B.ctl->n_coll;
@@ -242,9 +236,9 @@ __global__ void __launch_bounds__(256) k_ev_interact(DevProblem P, RunArgs A, Ev
             double d;
             uint32_t slot;
             bank_load(B, j, q, d, slot);
-            EvCtx<WW> C{P, A, B, slot, WW ? s_prm : P.ww_params};
+            EvCtx<WW> C{P, A, B, slot};
             const bool due = surf ? stage_surface(P, A, S, C, q, d) : stage_collision(P, A, S, C, q, d);
-            if (WW && due) ww_check(P, A, S, C, q);
+            if (WW != 0 && due) ww_check(P, A, S, C, q);
             alive = q.alive;
             if (alive) bank_store(B, j, q, d, slot);
         }
@@ -391,8 +385,9 @@ int event_run_range(mcdc_problem *h, const RunArgs &A0, hipStream_t s) {
                 if (ww) hipLaunchKernelGGL((k_ev_flight<true>), dim3(grid), dim3(block), 0, s, P, A, B);
                 else hipLaunchKernelGGL((k_ev_flight<false>), dim3(grid), dim3(block), 0, s, P, A, B);
                 timing_end(h, s);
-                if (ww) hipLaunchKernelGGL((k_ev_interact<true>), dim3(grid), dim3(block), 0, s, P, A, B);
-                else hipLaunchKernelGGL((k_ev_interact<false>), dim3(grid), dim3(block), 0, s, P, A, B);
+                if (!ww) hipLaunchKernelGGL((k_ev_interact<0>), dim3(grid), dim3(block), 0, s, P, A, B);
+                else if (P.ww_map) hipLaunchKernelGGL((k_ev_interact<2>), dim3(grid), dim3(block), 0, s, P, A, B);
+                else hipLaunchKernelGGL((k_ev_interact<1>), dim3(grid), dim3(block), 0, s, P, A, B);
             }
             hipError_t e = hipMemcpyAsync(E->host_done, &B.ctl->done, sizeof(uint32_t),
                                           hipMemcpyDeviceToHost, s);

@@ -53,10 +53,12 @@ MCDC_DEV void stack_pop(const RunArgs &A, uint64_t lane, int cap, int depth, Par
     q.alive = true;
 }
 
-// Per-work-item history context (registers).
-template <bool WW, bool IMP>
+// Per-work-item history context (registers).  WW: 0 no weight windows,
+// 1 network evaluated at each check, 2 baked window map.
+template <int WW, bool IMP>
 struct HistCtx {
-    static constexpr bool kWW = WW;
+    static constexpr bool kWW = WW != 0;
+    static constexpr bool kWWMap = WW == 2;
     const DevProblem &P;
     const RunArgs &A;
     uint64_t lane;
@@ -118,7 +120,7 @@ struct HistCtx {
     }
 };
 
-template <bool WW, bool IMP>
+template <int WW, bool IMP>
 MCDC_DEV void finish_history(const RunArgs &A, Shared &S, const HistCtx<WW, IMP> &H) {
     if (H.xh != 0.0) {
         unsafeAtomicAdd(&A.acc->det[0], H.xh);
@@ -165,7 +167,7 @@ MCDC_DEV HotTileTally make_tally(HotTileTally *, const DevProblem &P, const RunA
     return t;
 }
 
-template <int LDS, bool WW, bool IMP>
+template <int LDS, int WW, bool IMP>
 __global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_history(DevProblem P, RunArgs A) {
     extern __shared__ double s_tile[];
     __shared__ Shared S;
@@ -188,7 +190,7 @@ __global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_history(DevProblem P,
 
     bool ww_due = false;                    // a weight-window check waits for this lane
     for (;;) {
-        if (WW) {
+        if (WW == 1) {
             // Weight-window checks run batched: a lane that needs one waits
             // (its particle does not move) until at least half of the wave's
             // active lanes wait, then they evaluate the network together.
@@ -234,6 +236,10 @@ __global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_history(DevProblem P,
             ww_due = stage_collision(P, A, S, H, q, d);
         } else if (ev < 0) {
             H.sp = 0;                       // event cap: the history is abandoned
+        }
+        if (WW == 2 && ww_due) {            // a map read is cheap: check at once
+            ww_check(P, A, S, H, q);
+            ww_due = false;
         }
         if (ev >= 0) n_flight += 1;
     }
@@ -298,7 +304,8 @@ hipError_t launch_history(const DevProblem &P, const RunArgs &A, int grid, int b
     const int mode = P.hot_bins ? 2 : (lds_tally ? 1 : 0);
     const size_t shm = mode == 2 ? (size_t)P.hot_bins * sizeof(double)
                                  : (mode == 1 ? (size_t)P.nbins * sizeof(double) : 0);
-    const bool ww = P.ww_on != 0, imp = P.imp_on != 0;
+    const int ww = P.ww_on ? (P.ww_map ? 2 : 1) : 0;
+    const bool imp = P.imp_on != 0;
 #define MCDC_LAUNCH(L, W, I)                                                                   \
     do {                                                                                       \
         if (shm > 65536)                                                                       \
@@ -307,17 +314,20 @@ hipError_t launch_history(const DevProblem &P, const RunArgs &A, int grid, int b
         hipLaunchKernelGGL((k_history<L, W, I>), dim3(grid), dim3(block), shm, s, P, A);       \
     } while (0)
     if (mode == 2) {
-        if (ww) MCDC_LAUNCH(2, true, false);
-        else if (imp) MCDC_LAUNCH(2, false, true);
-        else MCDC_LAUNCH(2, false, false);
+        if (ww == 2) MCDC_LAUNCH(2, 2, false);
+        else if (ww == 1) MCDC_LAUNCH(2, 1, false);
+        else if (imp) MCDC_LAUNCH(2, 0, true);
+        else MCDC_LAUNCH(2, 0, false);
     } else if (mode == 1) {
-        if (ww) MCDC_LAUNCH(1, true, false);
-        else if (imp) MCDC_LAUNCH(1, false, true);
-        else MCDC_LAUNCH(1, false, false);
+        if (ww == 2) MCDC_LAUNCH(1, 2, false);
+        else if (ww == 1) MCDC_LAUNCH(1, 1, false);
+        else if (imp) MCDC_LAUNCH(1, 0, true);
+        else MCDC_LAUNCH(1, 0, false);
     } else {
-        if (ww) MCDC_LAUNCH(0, true, false);
-        else if (imp) MCDC_LAUNCH(0, false, true);
-        else MCDC_LAUNCH(0, false, false);
+        if (ww == 2) MCDC_LAUNCH(0, 2, false);
+        else if (ww == 1) MCDC_LAUNCH(0, 1, false);
+        else if (imp) MCDC_LAUNCH(0, 0, true);
+        else MCDC_LAUNCH(0, 0, false);
     }
 #undef MCDC_LAUNCH
     return hipGetLastError();

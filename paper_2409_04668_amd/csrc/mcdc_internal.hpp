@@ -65,6 +65,8 @@ struct DevProblem {
     const float *ww_params;                               // device
     float ww_ymin, ww_ymax;                               // output clamp
     double ww_logk, ww_ratio, ww_lo[4], ww_inv[4];
+    const double *ww_map;                // device w_T per map cell, or null (network per check)
+    int32_t ww_map_n[4];
     int64_t max_events;
     int32_t stack_cap;
     uint32_t problem_id;

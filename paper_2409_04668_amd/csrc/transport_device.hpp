@@ -399,14 +399,21 @@ MCDC_DEV uint32_t score_mesh(const DevProblem &P, const double p[3], const doubl
 // FP32 log-importance MLP: in -> 64 -> 64 -> 1, ReLU; each neuron starts from
 // its bias and adds weight*input products for ascending inputs, as separate
 // float multiplies and adds.  Layout W1[64][in], b1, W2[64][64], b2, W3, b3.
+// The weights are the same for every lane and read-only during a launch, so
+// they are read through the constant address space: uniform scalar loads
+// into SGPRs that the vector multiplies take as operands, with no LDS copy
+// and no per-lane vector loads.  `prm` must point to global memory.
 // ---------------------------------------------------------------------------
-MCDC_DEV float mlp_infer(const float *__restrict__ prm, int in_dim, const float in[4 + kMaxG]) {
-    const float *W1 = prm;
-    const float *b1 = W1 + kH * in_dim;
-    const float *W2 = b1 + kH;
-    const float *b2 = W2 + kH * kH;
-    const float *W3 = b2 + kH;
-    const float *b3 = W3 + kH;
+typedef const __attribute__((address_space(4))) float cfloat_t;
+
+MCDC_DEV float mlp_infer(const float *__restrict__ gprm, int in_dim, const float in[4 + kMaxG]) {
+    cfloat_t *prm = (cfloat_t *)(uintptr_t)gprm;
+    cfloat_t *W1 = prm;
+    cfloat_t *b1 = W1 + kH * in_dim;
+    cfloat_t *W2 = b1 + kH;
+    cfloat_t *b2 = W2 + kH * kH;
+    cfloat_t *W3 = b2 + kH;
+    cfloat_t *b3 = W3 + kH;
     float h1[kH];
 #pragma unroll
     for (int j = 0; j < kH; ++j) {
@@ -423,7 +430,7 @@ MCDC_DEV float mlp_infer(const float *__restrict__ prm, int in_dim, const float 
     float out = b3[0];
     for (int j = 0; j < kH; ++j) {
         float acc = b2[j];
-        const float *row = W2 + j * kH;
+        cfloat_t *row = W2 + j * kH;
 #pragma unroll
         for (int i = 0; i < kH; ++i) {
             const float prod = row[i] * h1[i];
@@ -434,6 +441,37 @@ MCDC_DEV float mlp_infer(const float *__restrict__ prm, int in_dim, const float 
         out = out + prod;
     }
     return out;
+}
+
+// Map cell of a point for the weight-window map: per axis floor(s n) of the
+// fraction s of the outer box (of the last census time), clamped to [0, n-1];
+// layout [g][t][z][y][x].
+MCDC_DEV int64_t ww_map_cell(const DevProblem &P, const Part &q) {
+    int64_t c = q.g;
+#pragma unroll
+    for (int a = 3; a >= 0; --a) {
+        const double v = a == 3 ? q.t : (a == 2 ? q.x[2] : (a == 1 ? q.x[1] : q.x[0]));
+        const double sa = (v - P.ww_lo[a]) * P.ww_inv[a];
+        const double f = floor(sa * (double)P.ww_map_n[a]);
+        const int64_t i = f < 0.0 ? 0 : (f >= (double)P.ww_map_n[a] ? P.ww_map_n[a] - 1 : (int64_t)f);
+        c = c * P.ww_map_n[a] + i;
+    }
+    return c;
+}
+
+// Window target from the network: output y at the normalised point (2 s - 1
+// per axis, group one-hot), clamped to its training-target range, and
+// w_T = exp(log K - y).
+MCDC_DEV double ww_net_target(const DevProblem &P, const float *prm, const float xt[4], int g) {
+    float in[4 + kMaxG];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) in[a] = xt[a];
+#pragma unroll
+    for (int j = 0; j < kMaxG; ++j) in[4 + j] = j == g ? 1.0f : 0.0f;
+    float y = mlp_infer(prm, 4 + P.G, in);
+    if (y < P.ww_ymin) y = P.ww_ymin;
+    if (y > P.ww_ymax) y = P.ww_ymax;
+    return own_exp(P.ww_logk - (double)y);
 }
 
 }  // namespace mcdc

@@ -86,19 +86,20 @@ MCDC_DEV void leak(Shared &S, Part &q, int face) {
 
 // Weight-window check: split above the window into n = min(ceil(w / w_T),
 // n_max) copies (daughters get stream tags from one parent Philox block),
-// roulette below it, nothing (and no draw) inside.
+// roulette below it, nothing (and no draw) inside.  w_T comes from the
+// network at the particle's point, or from the map cell that holds it.
 template <class Ctx>
 MCDC_DEV void ww_check(const DevProblem &P, const RunArgs &A, Shared &S, Ctx &C, Part &q) {
-    float in[4 + kMaxG];
+    double wt;
+    if (Ctx::kWWMap) {
+        wt = P.ww_map[ww_map_cell(P, q)];
+    } else {
+        float xt[4];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) in[a] = (float)(2.0 * ((q.x[a] - P.ww_lo[a]) * P.ww_inv[a]) - 1.0);
-    in[3] = (float)(2.0 * ((q.t - P.ww_lo[3]) * P.ww_inv[3]) - 1.0);
-#pragma unroll
-    for (int g = 0; g < kMaxG; ++g) in[4 + g] = g == q.g ? 1.0f : 0.0f;
-    float y = mlp_infer(C.mlp_params(P), 4 + P.G, in);
-    if (y < P.ww_ymin) y = P.ww_ymin;          // clamp to the training-target range
-    if (y > P.ww_ymax) y = P.ww_ymax;
-    const double wt = own_exp(P.ww_logk - (double)y);
+        for (int a = 0; a < 3; ++a) xt[a] = (float)(2.0 * ((q.x[a] - P.ww_lo[a]) * P.ww_inv[a]) - 1.0);
+        xt[3] = (float)(2.0 * ((q.t - P.ww_lo[3]) * P.ww_inv[3]) - 1.0);
+        wt = ww_net_target(P, C.mlp_params(P), xt, q.g);
+    }
     const double wl = (2.0 * wt) / (1.0 + P.ww_ratio);
     const double wu = P.ww_ratio * wl;
     if (q.w > wu) {

@@ -204,8 +204,10 @@ def source_log_k(prob: dict, params, ymin, ymax, n=10000, seed=3):
 
 
 def build_ww(prob: dict, n_runs=20, n_per_run=1_000_000, seed0=W.ROOT_SEED + 1, steps=3000,
-             lr=3e-3, ratio=5.0, n_max=10, method="auto"):
-    """Whole pipeline; returns (ww dict for the problem, info dict)."""
+             lr=3e-3, ratio=5.0, n_max=10, method="auto", map_dims=None):
+    """Whole pipeline; returns (ww dict for the problem, info dict).  With
+    ``map_dims`` = (nx, ny, nz, nt) the transport reads w_T from the network
+    baked onto that cell-centre map instead of evaluating it at every check."""
     G = prob["sigma_t"].shape[1]
     if method == "auto":
         method = "reciprocal" if G == 1 and prob.get("detector") is not None else "forward"
@@ -218,7 +220,7 @@ def build_ww(prob: dict, n_runs=20, n_per_run=1_000_000, seed0=W.ROOT_SEED + 1, 
     ymin, ymax = float(y.min()), float(y.max())
     logk = source_log_k(prob, params, ymin, ymax)
     ww = dict(params=params, hidden=mcdc.HIDDEN, logk=logk, ratio=ratio, n_max=n_max,
-              ymin=ymin, ymax=ymax)
+              ymin=ymin, ymax=ymax, map=None if map_dims is None else tuple(map_dims))
     info = dict(method=method, importance_seconds=t_imp, train_seconds=t_train,
                 n_points=int(X.shape[0]), loss_first=float(losses[0]), loss_last=float(losses[-1]),
                 target_var=float(np.var(y)), logk=logk, ymin=ymin, ymax=ymax)

@@ -113,6 +113,7 @@ _sig("mcdc_set_trace", C.c_int, VP, VP, C.c_uint64, VP)
 _sig("mcdc_set_history_scores", C.c_int, VP, VP)
 _sig("mcdc_set_ww_mlp", C.c_int, VP, C.POINTER(C.c_float), C.c_size_t, C.c_double, C.c_double,
      C.c_int32, C.c_float, C.c_float)
+_sig("mcdc_set_ww_map", C.c_int, VP, C.POINTER(C.c_int32), VP, C.c_size_t, VP)
 _sig("mcdc_get_importance", C.c_int, VP, PD, PD, C.c_size_t, VP)
 _sig("mcdc_mlp_param_count", C.c_size_t, C.c_int32)
 _sig("mcdc_mlp_forward", C.c_int, VP, C.c_int32, VP, C.c_size_t, VP, VP)
@@ -260,10 +261,13 @@ class Problem:
         self.nbins = self.desc.nbins
         self._trace = None
         self._xh = None
+        self._ww_map = None
         ww = prob.get("ww")
         if ww is not None:
             self.set_ww(ww["params"], ww["logk"], ww.get("ratio", 5.0), ww.get("n_max", 10),
                         ww.get("ymin", -3.0e38), ww.get("ymax", 3.0e38))
+            if ww.get("map") is not None:
+                self.set_ww_map(ww["map"])
 
     def close(self):
         if self.h:
@@ -312,6 +316,7 @@ class Problem:
         return self._xh.cpu().numpy().reshape(-1, 2)
 
     def set_ww(self, params, logk, ratio=5.0, n_max=10, ymin=-3.0e38, ymax=3.0e38):
+        self._ww_map = None                     # a new network drops the baked map
         if params is None:
             check(_lib.mcdc_set_ww_mlp(self.h, None, 0, 0.0, 0.0, 0, 0.0, 0.0), "set_ww_mlp")
             return
@@ -319,6 +324,25 @@ class Problem:
         check(_lib.mcdc_set_ww_mlp(self.h, p.ctypes.data_as(C.POINTER(C.c_float)), p.size,
                                    float(logk), float(ratio), int(n_max), float(ymin), float(ymax)),
               "set_ww_mlp")
+
+    def set_ww_map(self, dims, stream=None):
+        """Bake the network onto a (nx, ny, nz, nt) cell-centre window map
+        (device tensor owned here); ``dims=None`` returns to per-check inference."""
+        if dims is None:
+            check(_lib.mcdc_set_ww_map(self.h, None, None, 0, None), "set_ww_map")
+            self._ww_map = None
+            return
+        n = (C.c_int32 * 4)(*[int(v) for v in dims])
+        cells = self.desc.d.G * int(np.prod([int(v) for v in dims]))
+        buf = self.torch.empty(max(cells, 1), dtype=self.torch.float64, device=self.ws.device)
+        check(_lib.mcdc_set_ww_map(self.h, n, _ptr(buf), cells, _stream_ptr(stream)),
+              "set_ww_map")
+        self._ww_map = buf
+
+    def ww_map(self):
+        """The baked window targets w_T as a host array [g][t][z][y][x]."""
+        self.torch.cuda.synchronize()
+        return self._ww_map.cpu().numpy()
 
     # ---- results -------------------------------------------------------
     def raw(self, stream=None):

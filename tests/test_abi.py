@@ -78,3 +78,6 @@ def test_failure_paths_without_gpu():
     nh = (ctypes.c_uint64 * 2)(10, 10)
     st = mcdc._lib.mcdc_batch_workspace_bytes(arr, 2, nh, ctypes.byref(opt), ctypes.byref(n))
     assert st == mcdc.E_INVALID and b"census" in mcdc._lib.mcdc_last_error()
+    # the weight-window map needs a handle
+    dims = (ctypes.c_int32 * 4)(4, 4, 4, 4)
+    assert mcdc._lib.mcdc_set_ww_map(None, dims, None, 0, None) == mcdc.E_INVALID

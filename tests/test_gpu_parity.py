@@ -115,6 +115,47 @@ def test_weight_window_parity_duct():
     assert orc.counters["split"] > 10
 
 
+def test_ww_map_bake_bit_exact():
+    """The device bake of the window map equals the oracle's map bit for bit."""
+    mc = _mcdc()
+    p = _ww_box()
+    p["ww"] = dict(params=M.init_params(5, 64, seed=21), hidden=64, logk=0.2, ratio=5.0,
+                   n_max=10, ymin=-0.4, ymax=0.6, map=(7, 5, 3, 4))
+    p["stack_cap"] = 256
+    gp = mc.Problem(p)
+    got = gp.ww_map()
+    want = O.ww_map(p).reshape(-1)
+    assert got.shape == want.shape and np.array_equal(got, want)
+    gp.close()
+
+
+def test_ww_map_parity_history():
+    p = _ww_box()
+    p["ww"] = dict(params=ramp_mlp(2.0, noise_seed=3), hidden=64, logk=0.0, ratio=5.0, n_max=10,
+                   ymin=-1.5, ymax=1.5, map=(10, 4, 4, 8))
+    p["stack_cap"] = 256
+    gp, orc = full_parity(p, 1500, seed=110, trace_cap=400000)
+    c = orc.counters
+    assert c["split"] > 100 and c["rr_kill"] > 20
+
+
+def test_ww_map_parity_duct_event():
+    """Duct with a baked map under the event schedule: identical trajectories."""
+    from gpu_util import assert_counters, assert_traces_equal, run_pair
+    p = W.config2()
+    p["mesh"]["n"] = np.array([6, 10, 6, 4], np.int32)
+    p["ww"] = dict(params=ramp_mlp(-1.5, noise_seed=5), hidden=64, logk=0.3, ratio=5.0, n_max=10,
+                   map=(12, 20, 12, 10))
+    p["stack_cap"] = 256
+    gp, orc, tg, to, hg, ho = run_pair(p, 800, 111, trace_cap=400000, options=_ev())
+    assert_traces_equal(tg[0], to[0])
+    np.testing.assert_allclose(hg[0], ho[0], rtol=1e-12, atol=0)
+    s, s2 = gp.raw()
+    assert_close_sums(s, orc.tally_sum, what="tally_sum")
+    assert_counters(gp.counters(), orc)
+    assert orc.counters["split"] > 10
+
+
 # ---------------------------------------------------------------------------
 # event-based schedule: same per-particle trajectories, other execution order
 # ---------------------------------------------------------------------------

@@ -260,3 +260,113 @@ def test_output_clamp_to_a_point_is_constant_importance():
     q["ww"]["ymax"] = 5.0                 # unclamped above: splits happen
     rs = O.run(q, 2000, seed=47)
     assert rs.counters["split"] > 0
+
+
+# ---------------------------------------------------------------------------
+# weight-window map (network evaluated once per map cell centre)
+# ---------------------------------------------------------------------------
+
+def test_ww_map_is_network_at_cell_centres():
+    p = _box_problem()
+    prm = M.init_params(IN, H, seed=5)
+    dims = (3, 4, 5, 2)
+    # clamp range inside the network's output range so some cells are clamped
+    p["ww"] = dict(params=prm, hidden=H, logk=0.3, ratio=5.0, n_max=10, ymin=-0.5, ymax=0.5,
+                   map=dims)
+    got = O.ww_map(p)
+    assert got.shape == (1, dims[3], dims[2], dims[1], dims[0])
+    idx = np.stack(np.meshgrid(*[np.arange(n) for n in dims], indexing="ij"), -1).reshape(-1, 4)
+    X = np.zeros((len(idx), IN))
+    X[:, :4] = (2.0 * ((idx + 0.5) / np.array(dims)) - 1.0).astype(np.float32)
+    X[:, 4] = 1.0
+    y = np.clip(M.forward(prm, X, IN, H)[0], -0.5, 0.5)
+    want = np.exp(0.3 - y)
+    clamped = (y == -0.5) | (y == 0.5)
+    assert clamped.any() and (~clamped).any()
+    g = got[0].transpose(3, 2, 1, 0).reshape(-1)          # -> [ix][iy][iz][it]
+    assert np.allclose(g, want, rtol=2e-6, atol=0)
+
+
+def test_ww_map_cell_matches_floor_rule():
+    p = _box_problem()
+    dims = (7, 3, 5, 4)
+    p["ww"] = dict(params=np.zeros(M.n_params(IN, H), np.float32), hidden=H, logk=0.0,
+                   map=dims)
+    rng = np.random.default_rng(11)
+    pts = rng.uniform(-2.0, 22.0, (400, 3))
+    pts[:5] = [[0.0, 0.0, 0.0], [20.0, 20.0, 20.0], [10.0, 10.0, 10.0],
+               [20.0 / 7.0 * 3.0, 1e-300, 19.999999], [-1e-12, 20.0 + 1e-12, 4.0]]
+    ts = rng.uniform(-1.0, 41.0, 400)
+    ts[:3] = [0.0, 40.0, 10.0]
+    for pt, t in zip(pts, ts):
+        want = 0
+        for a in (3, 2, 1, 0):
+            v = t if a == 3 else pt[a]
+            span = 40.0 if a == 3 else 20.0
+            i = math.floor(v / span * dims[a])
+            i = min(max(i, 0), dims[a] - 1)
+            want = want * dims[a] + i
+        got = O.ww_map_cell(p, pt, t)
+        # the oracle scales by 1/span: allow a one-cell difference only on exact cell faces
+        if got != want:
+            f = [(t if a == 3 else pt[a]) / (40.0 if a == 3 else 20.0) * dims[a] for a in range(4)]
+            assert any(abs(x - round(x)) < 1e-12 for x in f), (pt, t, got, want)
+
+
+def test_ww_map_split_hand_case():
+    """Void problem with one interior box (faces x=11, x=12), ramp network
+    y = 6 xhat, map 10 cells along x.  At x=11 the map cell is 5 (centre
+    xhat = 0.1): w_T = exp(-0.6), so weight 1 splits in two; at x=12 the cell
+    is 6 (centre xhat = 0.3): w_T = exp(-1.8) ~ 0.165, window [0.055, 0.275],
+    so each half splits into ceil(0.5 / 0.165) = 4 copies of 0.125.  The
+    network at the crossing point itself (xhat = 0.2) would give no split."""
+    p = _box_problem()
+    p["sigma_t"] = np.array([[0.0]])
+    p["sigma_s"] = np.array([[[0.0]]])
+    p["source"]["isotropic"] = False
+    p["box_lo"] = np.array([[11.0, 0.0, 0.0]])
+    p["box_hi"] = np.array([[12.0, 20.0, 20.0]])
+    p["box_mat"] = np.array([0], np.int32)
+    p["ww"] = dict(params=_ramp_mlp(6.0), hidden=H, logk=0.0, ratio=5.0, n_max=10,
+                   map=(10, 1, 1, 1))
+    r = O.OracleRun(p)
+    tr, _ = r.run(1, seed=1, trace_cap=100)
+    sp = tr[tr["type"] == O.EV["split"]]
+    assert [int(s["aux"]) for s in sp] == [2, 4, 4]
+    assert [float(s["x"]) for s in sp] == [11.0, 12.0, 12.0]
+    assert [float(s["w"]) for s in sp] == [0.5, 0.125, 0.125]
+    assert math.ceil(0.5 / math.exp(-1.8)) == 4
+    assert abs(r.leak[1] - 1.0) < 1e-15 and r.counters["particle"] == 8
+
+
+def test_ww_map_unbiased():
+    p = _box_problem()
+    N = 20000
+    ra = O.run(p, N, seed=43)
+    q = _box_problem()
+    q["ww"] = dict(params=_ramp_mlp(2.0), hidden=H, logk=0.0, ratio=5.0, n_max=10,
+                   map=(10, 4, 4, 8))
+    rw = O.run(q, N, seed=44)
+    c = rw.counters
+    assert c["split"] > 1000 and c["rr_kill"] > 1000
+    ws = rw.wsum
+    lhs = ws["source"] + ws["gain"] - ws["loss"]
+    rhs = ws["leak"] + ws["absorb"] + ws["time_end"]
+    assert abs(lhs - rhs) <= 1e-9 * ws["source"]
+    ma, sa = ra.mesh_stats()
+    mw, sw = rw.mesh_stats()
+    ok = (ma > 0) & (mw > 0)
+    z = np.abs(ma - mw)[ok] / np.sqrt(sa[ok] ** 2 + sw[ok] ** 2)
+    assert np.mean(z < 3) > 0.95 and np.max(z) < 5
+    da, dsa = ra.detector_stats()
+    dw, dsw = rw.detector_stats()
+    assert abs(da - dw) < 3.5 * math.hypot(dsa, dsw)
+    assert dsw / dw < dsa / da
+
+
+def test_ww_map_invalid_dims_rejected():
+    q = _box_problem()
+    q["ww"] = dict(params=np.zeros(M.n_params(IN, H), np.float32), hidden=H, logk=0.0,
+                   map=(4, 0, 4, 4))
+    with pytest.raises(Exception):
+        O.run(q, 10, seed=1)
