@@ -6,8 +6,10 @@ One step = one mcdc_run of 1e8 source histories: 20 batches, each one launch
 of the tracking kernel plus one batch close-out launch, with all inputs
 resident in HBM.  Prints one JSON line with the roofline of the tracking
 kernel (algorithmic bytes = 16 B per FP64 atomic tally update, i.e. per scored
-piece, against the 8 TB/s HBM peak) and the CPU oracle timed on a bounded
-sample of the same workload on this host.
+piece, against the 8 TB/s HBM peak), the figure of merit 1/(R^2 T) at 1%
+detector relative error of the analog run against the learned weight windows
+(block "fom", measured after the timed steps), and the CPU oracle timed on a
+bounded sample of the same workload on this host.
 
     python bench.py [--gpus 1] [--steps 5] [--warmup 1]
 """
@@ -77,6 +79,8 @@ def main():
     ap.add_argument("--waves-per-cu", type=int, default=0)
     ap.add_argument("--cpu-sample", type=int, default=8_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fom", action="store_true",
+                    help="skip the analog vs learned-weight-window FOM comparison")
     ap.add_argument("--no-tile", action="store_true", help="tally straight to HBM atomics")
     ap.add_argument("--workload", choices=["duct", "batch", "fom"], default="duct")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
@@ -188,6 +192,9 @@ def main():
     out["paper_context"] = {"histories_per_s": 1e10 / 1500.0, "hardware": "1x NVIDIA V100 (Lassen)",
                             "workload": "Kobayashi dog-leg void duct, time dependent, 1 group",
                             "source": "Sec. Performance (GPU profiling paragraph)"}
+    gp.close()
+    if not args.no_fom:
+        out["fom"] = fom_comparison(mcdc, W)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_sample, seed)
     print(json.dumps(out), flush=True)
@@ -218,25 +225,42 @@ def bench_batch(args, torch, mcdc, W):
         "pieces_per_history": pieces / (total * (args.steps + args.warmup))}), flush=True)
 
 
-def bench_fom(args, torch, mcdc, W):
-    """FOM = 1/(R^2 T) at 1% detector relative error: analog vs learned weight
-    windows on the duct problem (training time reported separately)."""
+WW_MAP_DIMS = (30, 50, 30, 20)      # 2 cm cells x 10 s: network baked per cell centre
+
+
+def fom_comparison(mcdc, W, target=0.01):
+    """FOM = 1/(R^2 T) at `target` detector relative error on the duct
+    problem: analog (history schedule) vs learned weight windows (importance
+    from 20 x 1e6 analog histories, network trained on the GPU, baked onto a
+    2 cm x 10 s window map; event schedule, since a history's split chain runs
+    serially on one lane in the history schedule).  Each side: a pilot run
+    sets N for the target error, then N histories are timed.  Training and
+    baking are setup, reported beside it."""
     from paper_2409_04668_amd import learned_ww as L
     p = W.config2()
     t0 = time.perf_counter()
-    ww, info = L.build_ww(p, n_runs=20, n_per_run=1_000_000)
+    ww, info = L.build_ww(p, n_runs=20, n_per_run=1_000_000, map_dims=WW_MAP_DIMS)
     t_build = time.perf_counter() - t0
     pw = W.config4(ww)
-    analog = L.fom_at_target(p, seed=31, target=0.01, pilot=20_000_000)
-    learned = L.fom_at_target(pw, seed=41, target=0.01, pilot=2_000_000)
+    analog = L.fom_at_target(p, seed=31, target=target, pilot=20_000_000)
+    learned = L.fom_at_target(pw, seed=41, target=target, pilot=4_000_000,
+                              options=mcdc.make_options(mcdc.SCHED_EVENT))
     z = abs(analog["mean"] - learned["mean"]) / (
         (analog["mean"] * analog["rel_err"]) ** 2 + (learned["mean"] * learned["rel_err"]) ** 2) ** 0.5
+    return {"target_rel_err": target, "ratio": learned["fom"] / analog["fom"],
+            "analog": dict(analog, schedule="history"),
+            "learned_ww": dict(learned, schedule="event", window_map=list(WW_MAP_DIMS)),
+            "agreement_sigma": z, "training": dict(info, total_seconds=t_build),
+            "fom_with_training_amortised": 1.0 / (learned["rel_err"] ** 2 *
+                                                  (learned["seconds"] + t_build))}
+
+
+def bench_fom(args, torch, mcdc, W):
+    """FOM at 1% detector relative error, analog vs learned weight windows."""
+    f = fom_comparison(mcdc, W)
     print(json.dumps({
         "metric": "FOM 1/(R^2 T) at 1% detector relative error, analog vs learned weight windows",
-        "value": learned["fom"] / analog["fom"], "unit": "FOM ratio (learned / analog)",
-        "analog": analog, "learned_ww": learned, "agreement_sigma": z,
-        "training": dict(info, total_seconds=t_build),
-        "fom_with_training_amortised": 1.0 / (learned["rel_err"] ** 2 * (learned["seconds"] + t_build)),
+        "value": f["ratio"], "unit": "FOM ratio (learned / analog)", **f,
         "n_gpus": 1, "dtype": "f64", "data": "synthetic"}), flush=True)
 
 

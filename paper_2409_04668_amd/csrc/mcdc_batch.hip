@@ -92,7 +92,7 @@ struct BatchCtx {
     MCDC_DEV void add_score(double) {}
     MCDC_DEV void add_path(double v) { D.bd[8 * D.cap + slot] += v; }
     MCDC_DEV void imp_point(const DevProblem &, const Part &) {}
-    MCDC_DEV bool push_daughter(const Part &) { return false; }
+    MCDC_DEV bool push_daughters(const Part &, uint32_t, int) { return false; }
 };
 
 // LDS tile for one time slice of one problem; other bins go to HBM.

@@ -106,24 +106,65 @@ struct EvCtx {
         else B.xh[slot] += v;
     }
     MCDC_DEV void add_path(double v) {
+        if (!A.xh_out) return;           // the per-history path is an output only
         if (WW) unsafeAtomicAdd(&B.path[slot], v);
         else B.path[slot] += v;
     }
     MCDC_DEV void imp_point(const DevProblem &, const Part &) {}
-    // daughters: new bank entry, appended to the next active queue
-    MCDC_DEV bool push_daughter(const Part &d) {
-        const uint32_t j = atomicAdd(&B.ctl->bank_n, 1u);
-        if (j >= B.cap) {
-            set_status(A, MCDC_E_BANK);
-            return false;
-        }
-        bank_store(B, j, d, 0.0, slot);
-        const uint32_t nx = B.ctl->nxt;
-        const uint32_t pos = atomicAdd(&B.ctl->n_act[nx], 1u);
-        B.q[(size_t)nx * B.cap + pos] = j;
+    // daughters are only recorded here: the interaction kernel allocates
+    // bank entries and queue places for a whole wave at once
+    uint32_t split_n = 0, split_tag0 = 0;
+    MCDC_DEV bool push_daughters(const Part &, uint32_t tag0, int n) {
+        split_n = (uint32_t)n;
+        split_tag0 = tag0;
         return true;
     }
 };
+
+// Inclusive prefix sum over the 64 lanes of a wave (all lanes active).
+MCDC_DEV uint32_t wave_scan_incl(uint32_t x) {
+    const int lane = (int)__lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    return x;
+}
+
+// Write the recorded daughters of every lane of the wave: one atomic per wave
+// on the bank size and one on the next active queue, then each lane writes
+// its n-1 daughters (the parent state with tag0 + i * golden, k = seq = 0)
+// at its offset.  Entries past the bank capacity are dropped with an error.
+MCDC_DEV void wave_write_daughters(const RunArgs &A, const EvBank &B, const Part &q, uint32_t slot,
+                                   uint32_t nd, uint32_t tag0) {
+    const uint32_t incl = wave_scan_incl(nd);
+    const uint32_t total = __shfl(incl, 63);
+    if (total == 0) return;
+    const int lane = (int)__lane_id();
+    const uint32_t nx = B.ctl->nxt;
+    uint32_t jb = 0, qb = 0;
+    if (lane == 0) {
+        jb = atomicAdd(&B.ctl->bank_n, total);
+        qb = atomicAdd(&B.ctl->n_act[nx], total);
+    }
+    jb = __shfl(jb, 0);
+    qb = __shfl(qb, 0);
+    const uint32_t off = incl - nd;
+    for (uint32_t i = 0; i < nd; ++i) {
+        const uint64_t j = (uint64_t)jb + off + i;
+        if (j >= B.cap) {
+            set_status(A, MCDC_E_BANK);
+            break;
+        }
+        Part d = q;
+        d.tag = tag0 + (i + 1u) * 0x9E3779B9u;
+        d.k = 0;
+        d.seq = 0;
+        bank_store(B, (uint32_t)j, d, 0.0, slot);
+        B.q[(size_t)nx * B.cap + qb + off + i] = (uint32_t)j;
+    }
+}
 
 template <bool WW>
 __global__ void __launch_bounds__(256) k_ev_source(DevProblem P, RunArgs A, EvBank B, uint32_t n) {
@@ -229,6 +270,8 @@ __global__ void __launch_bounds__(256) k_ev_interact(DevProblem P, RunArgs A, Ev
         const bool valid = jj < n;
         bool alive = false;
         uint32_t j = 0;
+        uint32_t nd = 0, tag0 = 0, dslot = 0;     // recorded daughters of this lane
+        Part dq;
         if (valid) {
             const bool surf = jj < ns;
             j = surf ? B.qs[jj] : B.qc[jj - ns];
@@ -241,7 +284,14 @@ __global__ void __launch_bounds__(256) k_ev_interact(DevProblem P, RunArgs A, Ev
             if (WW != 0 && due) ww_check(P, A, S, C, q);
             alive = q.alive;
             if (alive) bank_store(B, j, q, d, slot);
+            if (WW != 0 && C.split_n > 1) {
+                nd = C.split_n - 1;
+                tag0 = C.split_tag0;
+                dq = q;
+                dslot = slot;
+            }
         }
+        if (WW != 0) wave_write_daughters(A, B, dq, dslot, nd, tag0);
         wave_append(B.q + (size_t)nxt * B.cap, &B.ctl->n_act[nxt], j, valid && alive);
     }
     __syncthreads();

@@ -75,13 +75,19 @@ struct HistCtx {
     }
     MCDC_DEV void add_score(double v) { xh += v; }
     MCDC_DEV void add_path(double v) { path += v; }
-    MCDC_DEV bool push_daughter(const Part &d) {
-        if (sp >= P.stack_cap) {
-            set_status(A, MCDC_E_STACK);
-            return false;
+    MCDC_DEV bool push_daughters(const Part &q, uint32_t tag0, int n) {
+        for (int i = 1; i < n; ++i) {
+            if (sp >= P.stack_cap) {
+                set_status(A, MCDC_E_STACK);
+                return false;
+            }
+            Part d = q;
+            d.tag = tag0 + (uint32_t)i * 0x9E3779B9u;
+            d.k = 0;
+            d.seq = 0;
+            stack_push(A, lane, P.stack_cap, sp, d);
+            sp += 1;
         }
-        stack_push(A, lane, P.stack_cap, sp, d);
-        sp += 1;
         return true;
     }
     // forward importance estimate: record the score so far at each flight

@@ -112,13 +112,9 @@ MCDC_DEV void ww_check(const DevProblem &P, const RunArgs &A, Shared &S, Ctx &C,
         q.k = r.k;
         const double wn = q.w / (double)n;
         q.w = wn;
-        for (int i = 1; i < n; ++i) {
-            Part d = q;
-            d.tag = blk[0] + (uint32_t)i * 0x9E3779B9u;
-            d.k = 0;
-            d.seq = 0;
-            if (!C.push_daughter(d)) return;
-        }
+        // daughters i = 1..n-1: the parent's state with tag blk[0] + i * golden,
+        // fresh counter and sequence (the context stores or defers them)
+        if (!C.push_daughters(q, blk[0], n)) return;
         atomicAdd(&S.cnt[C_SPLIT], (unsigned long long)(n - 1));
         atomicAdd(&S.cnt[C_PARTICLE], (unsigned long long)(n - 1));
         trace_rec(A, C.hist(), q, EV_SPLIT, (double)n);

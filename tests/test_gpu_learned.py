@@ -77,18 +77,25 @@ def test_mlp_adam_training_matches_oracle_and_decreases_loss():
 @pytest.mark.slow
 def test_learned_weight_windows_gain_fom_and_stay_unbiased():
     """Small end-to-end pipeline on the duct problem: importance estimate from
-    analog runs, GPU training, weight windows; detector mean agrees with the
-    analog run within 3 sigma and the FOM at equal relative error improves."""
+    analog runs, GPU training, network baked onto a window map, weight windows
+    under the event schedule.  The detector mean agrees with the analog run
+    within 3.5 sigma, the variance per history drops by more than 5x, and the
+    FOM at equal relative error beats the analog run."""
     from paper_2409_04668_amd import learned_ww as L
+    from paper_2409_04668_amd import mcdc
     from paper_2409_04668_amd import workloads as W
     p = W.config2()
-    ww, info = L.build_ww(p, n_runs=4, n_per_run=1_000_000, steps=1500)
+    ww, info = L.build_ww(p, n_runs=4, n_per_run=1_000_000, steps=1500,
+                          map_dims=(30, 50, 30, 20))
     assert info["loss_last"] < 0.2 * info["target_var"], info
     pw = W.config4(ww)
-    pw["stack_cap"] = 256
-    a = L.fom_at_target(p, seed=500, target=0.03, pilot=4_000_000)
-    w = L.fom_at_target(pw, seed=600, target=0.03, pilot=400_000)
+    a = L.fom_at_target(p, seed=500, target=0.02, pilot=10_000_000)
+    w = L.fom_at_target(pw, seed=600, target=0.02, pilot=2_000_000,
+                        options=mcdc.make_options(mcdc.SCHED_EVENT))
     z = abs(a["mean"] - w["mean"]) / math.hypot(a["mean"] * a["rel_err"], w["mean"] * w["rel_err"])
     print("analog", a, "\nlearned WW", w, "\ninfo", info)
     assert z < 3.5, (a, w)
-    assert w["fom"] > 1.5 * a["fom"], (a, w)
+    var_a = a["rel_err"] ** 2 * a["n"]
+    var_w = w["rel_err"] ** 2 * w["n"]
+    assert var_w < var_a / 5.0, (a, w)
+    assert w["fom"] > a["fom"], (a, w)
