@@ -244,7 +244,7 @@ def fom_comparison(mcdc, W, target=0.01):
     pw = W.config4(ww)
     analog = L.fom_at_target(p, seed=31, target=target, pilot=20_000_000)
     learned = L.fom_at_target(pw, seed=41, target=target, pilot=4_000_000,
-                              options=mcdc.make_options(mcdc.SCHED_EVENT))
+                              options=mcdc.make_options(mcdc.SCHED_EVENT, event_chunk=1 << 23))
     z = abs(analog["mean"] - learned["mean"]) / (
         (analog["mean"] * analog["rel_err"]) ** 2 + (learned["mean"] * learned["rel_err"]) ** 2) ** 0.5
     return {"target_rel_err": target, "ratio": learned["fom"] / analog["fom"],

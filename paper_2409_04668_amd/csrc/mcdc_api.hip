@@ -57,7 +57,7 @@ int validate_desc(const mcdc_problem_desc *d) {
     const double nb = (double)(d->mesh_per_group ? d->G : 1) * d->mesh_n[0] * d->mesh_n[1] *
                       d->mesh_n[2] * d->mesh_n[3];
     if (nb > 4.0e9) return fail(MCDC_E_INVALID, "tally too large (bins must fit 32 bits)");
-    if (d->n_batches < 1) return fail(MCDC_E_INVALID, "n_batches must be >= 1");
+    if (d->n_batches < 1 || d->n_batches > 65535) return fail(MCDC_E_INVALID, "n_batches must lie in [1, 65535]");
     if (d->stack_cap < 0 || d->max_events < 1) return fail(MCDC_E_INVALID, "stack_cap/max_events");
     if (d->imp_on) {
         for (int a = 0; a < 4; ++a)
@@ -132,7 +132,10 @@ Layout make_layout(const mcdc_problem_desc *d, const Options &o) {
     const size_t n_tab = (size_t)d->n_mat * d->G + (size_t)d->n_mat * d->G * d->G + d->G + d->n_census;
     L.tables = off; off = align_up(off + n_tab * sizeof(double));
     const size_t nb = desc_nbins(d);
-    L.tally_batch = off; off = align_up(off + nb * sizeof(double));
+    // the event schedule keeps every batch of a run resident (one slice per
+    // batch) so a run drains its particle bank once, not once per batch
+    const size_t nslices = o.schedule == MCDC_SCHED_EVENT ? (size_t)d->n_batches : 1;
+    L.tally_batch = off; off = align_up(off + nslices * nb * sizeof(double));
     L.tally_sum = off; off = align_up(off + nb * sizeof(double));
     L.tally_sumsq = off; off = align_up(off + nb * sizeof(double));
     L.acc = off; off = align_up(off + sizeof(DevAcc));
@@ -445,21 +448,35 @@ int mcdc_run(mcdc_handle h, uint64_t n, uint64_t seed, void *stream) {
     double *sum = (double *)(h->ws + h->L.tally_sum);
     double *sumsq = (double *)(h->ws + h->L.tally_sumsq);
     const bool lds = h->opt.lds_tally && h->nbins <= (uint32_t)kLdsTallyMaxBins;
+    if (h->opt.schedule == MCDC_SCHED_EVENT) {
+        // one pass over all histories of the run; each particle scores into
+        // the slice of its history's batch; then every batch is closed out
+        if (n == 0) return MCDC_OK;
+        A.h_begin = h0;
+        A.h_end = h0 + n;
+        A.run_n = n;
+        A.run_batches = B;
+        int st = event_run_range(h, A, s);
+        if (st) return st;
+        for (uint64_t b = 0; b < B; ++b) {
+            const uint64_t lo = (b * n) / B, hi = ((b + 1) * n) / B;
+            if (hi == lo) continue;
+            hipError_t e = launch_closeout(batch + b * (uint64_t)h->nbins, sum, sumsq, h->nbins,
+                                           (double)(hi - lo), s);
+            if (e != hipSuccess) return hip_fail(e, "run launch");
+            h->batches += 1;
+        }
+        h->n_hist += n;
+        return MCDC_OK;
+    }
     for (uint64_t b = 0; b < B; ++b) {
         const uint64_t lo = (b * n) / B, hi = ((b + 1) * n) / B;
         if (hi == lo) continue;
         A.h_begin = h0 + lo;
         A.h_end = h0 + hi;
-        hipError_t e;
-        if (h->opt.schedule == MCDC_SCHED_EVENT) {
-            int st = event_run_range(h, A, s);
-            if (st) return st;
-            e = hipSuccess;
-        } else {
-            timing_begin(h, s);
-            e = launch_history(h->P, A, h->opt.grid, h->opt.block, lds, s);
-            timing_end(h, s);
-        }
+        timing_begin(h, s);
+        hipError_t e = launch_history(h->P, A, h->opt.grid, h->opt.block, lds, s);
+        timing_end(h, s);
         if (e == hipSuccess) e = launch_closeout(batch, sum, sumsq, h->nbins, (double)(hi - lo), s);
         if (e != hipSuccess) return hip_fail(e, "run launch");
         h->batches += 1;

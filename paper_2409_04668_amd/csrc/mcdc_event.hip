@@ -200,7 +200,6 @@ __global__ void __launch_bounds__(256) k_ev_flight(DevProblem P, RunArgs A, EvBa
     const uint32_t cur = B.ctl->cur, cen = B.ctl->cen;
     const uint32_t n = B.ctl->n_act[cur];
     const uint32_t *in = B.q + (size_t)cur * B.cap;
-    GlobalTally tally{A.tally};
     uint32_t n_piece = 0, n_flight = 0;
     double path = 0.0;
     for (uint32_t j0 = blockIdx.x * blockDim.x; j0 < n; j0 += gridDim.x * blockDim.x) {
@@ -215,6 +214,11 @@ __global__ void __launch_bounds__(256) k_ev_flight(DevProblem P, RunArgs A, EvBa
             uint32_t slot;
             bank_load(B, j, q, d, slot);
             EvCtx<WW> C{P, A, B, slot};
+            // batch b of the history (run-relative id r) holds ids
+            // [floor(b n / B), floor((b+1) n / B)): b = floor(((r+1) B - 1) / n)
+            const uint64_t r = A.h_begin + slot - A.h_run0;
+            const uint64_t b = ((r + 1) * A.run_batches - 1) / A.run_n;
+            GlobalTally tally{A.tally + b * (uint64_t)P.nbins};
             ev = stage_flight(P, A, S, tally, C, q, d, n_piece, path);
             if (ev >= 0) n_flight += 1;
             if (q.alive) bank_store(B, j, q, d, slot);

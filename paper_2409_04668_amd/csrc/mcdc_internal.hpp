@@ -79,7 +79,10 @@ struct DevProblem {
 struct RunArgs {
     uint64_t seed;
     uint64_t h_begin, h_end, h_run0;
-    double *tally;                       // current-batch accumulator [nbins]
+    uint64_t run_n;                      // histories of the whole run (event schedule)
+    uint64_t run_batches;                // batches of the run (event schedule)
+    double *tally;                       // current-batch accumulator [nbins]; event
+                                         // schedule: [run_batches][nbins] slices
     DevAcc *acc;
     double *imp_score, *imp_weight;
     double *xh_out;

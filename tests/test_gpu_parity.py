@@ -195,6 +195,7 @@ def test_event_schedule_weight_windows():
     np.testing.assert_allclose(hg[0], ho[0], rtol=1e-12, atol=0)
     s, s2 = gp.raw()
     assert_close_sums(s, orc.tally_sum, what="tally_sum")
+    assert_close_sums(s2, orc.tally_sumsq, what="tally_sumsq")    # batch slices
     assert_counters(gp.counters(), orc)
 
 
@@ -208,11 +209,12 @@ def test_history_and_event_schedules_agree_at_scale():
         gp = mc.Problem(p, opt)
         gp.set_history_scores(n)
         gp.run(n, 31)
-        out.append((gp.history_scores(), gp.raw()[0], gp.counters()))
+        out.append((gp.history_scores(), gp.raw(), gp.counters()))
         gp.close()
     (h1, s1, c1), (h2, s2, c2) = out
     assert np.array_equal(h1, h2)
-    assert_close_sums(s1, s2, what="tally")
+    assert_close_sums(s1[0], s2[0], what="tally")
+    assert_close_sums(s1[1], s2[1], what="tally_sumsq")
     for k in ("histories", "flights", "pieces", "collisions", "leaks", "census_stops", "time_ends"):
         assert c1[k] == c2[k], k
 
