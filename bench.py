@@ -193,6 +193,18 @@ def main():
                             "workload": "Kobayashi dog-leg void duct, time dependent, 1 group",
                             "source": "Sec. Performance (GPU profiling paragraph)"}
     gp.close()
+    # the same step under the other schedule (event-based: staged kernels over
+    # compacted queues), one timed step after a warm-up, as a comparison
+    other = "event" if args.schedule == "history" else "history"
+    osched = mcdc.SCHED_EVENT if other == "event" else mcdc.SCHED_HISTORY
+    go = mcdc.Problem(prob, mcdc.make_options(osched, event_chunk=1 << 24))
+    go.run(N, seed)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    go.run(N, seed + 1)
+    torch.cuda.synchronize()
+    out["other_schedule"] = {"schedule": other, "histories_per_s": N / (time.perf_counter() - t0)}
+    go.close()
     if not args.no_fom:
         out["fom"] = fom_comparison(mcdc, W)
     if not args.no_cpu_baseline:

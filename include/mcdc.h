@@ -50,7 +50,8 @@ typedef enum {
 enum { MCDC_VACUUM = 0, MCDC_REFLECTIVE = 1 };
 enum { MCDC_SRC_POINT = 0, MCDC_SRC_BOX = 1 };
 enum { MCDC_SCHED_AUTO = 0, MCDC_SCHED_HISTORY = 1, MCDC_SCHED_EVENT = 2 };
-enum { MCDC_TALLY_MESH = 0, MCDC_TALLY_DETECTOR = 1, MCDC_TALLY_LEAKAGE = 2 };
+enum { MCDC_TALLY_MESH = 0, MCDC_TALLY_DETECTOR = 1, MCDC_TALLY_LEAKAGE = 2,
+       MCDC_TALLY_COLLISION = 3 };
 
 #define MCDC_MAX_BOXES 16
 #define MCDC_MAX_MAT 16
@@ -80,6 +81,9 @@ typedef struct {
     double mesh_lo[4], mesh_hi[4];     /* x,y,z,t; an x/y/z axis with both bounds */
     int32_t mesh_n[4];                 /*   infinite is not cut (n must be 1)     */
     int32_t mesh_per_group;            /* tally per group or summed over groups   */
+    int32_t col_tally;                 /* 1: also a collision-estimator tally on
+                                          the mesh (w / Sigma_t per collision in
+                                          the bin of the collision point)         */
     int32_t n_census;                  /* increasing census times, last = end     */
     const double *census;
     int32_t implicit_capture;          /* 0 analog; 1 implicit with weight cutoff */
@@ -145,15 +149,22 @@ int mcdc_run(mcdc_handle h, uint64_t n_histories, uint64_t seed, void *stream);
 
 /* Synchronise `stream` and copy results to the host: per-bin mean score per
  * source history divided by bin volume and time width (MCDC_TALLY_MESH,
- * n = bins), the detector mean track length per history (n = 1), or the
- * leaked weight per face per history (n = 6); rel_err may be NULL.
- * Returns the sticky device error status if a run failed. */
+ * n = bins; MCDC_TALLY_COLLISION the same from the collision estimator, for
+ * problems created with col_tally), the detector mean track length per
+ * history (n = 1), or the leaked weight per face per history (n = 6);
+ * rel_err may be NULL.  Returns the sticky device error status if a run
+ * failed. */
 int mcdc_get_tallies(mcdc_handle h, int kind, double *mean, double *rel_err, size_t n,
                      void *stream);
 
 /* Raw accumulators (host copies): tally_sum[n] = sum of batch sums,
  * tally_sumsq[n] = sum of (batch sum)^2 / batch size; either may be NULL. */
 int mcdc_get_raw(mcdc_handle h, double *tally_sum, double *tally_sumsq, size_t n, void *stream);
+
+/* The same raw accumulators of the collision-estimator tally (problems
+ * created with col_tally; MCDC_E_STATE otherwise). */
+int mcdc_get_raw_collision(mcdc_handle h, double *col_sum, double *col_sumsq, size_t n,
+                           void *stream);
 int mcdc_get_counters(mcdc_handle h, mcdc_counters *out, void *stream);
 int mcdc_reset_tallies(mcdc_handle h, void *stream);
 int mcdc_tally_bins(mcdc_handle h, size_t *n);

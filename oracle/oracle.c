@@ -358,6 +358,25 @@ static o_mesh o_mesh_make(const orc_problem *P)
     return M;
 }
 
+/* mesh bin holding a point (x, y, z, t) in group g: per axis floor((p - lo) /
+ * delta); -1 when the point lies outside the mesh (an unbounded axis is one
+ * bin) */
+static int64_t o_point_bin(const o_mesh *M, const double p[3], double t, int g)
+{
+    int64_t c = M->G_t > 1 ? g : 0;
+    for (int a = 3; a >= 0; --a) {
+        int64_t i = 0;
+        if (a == 3 || M->bounded[a]) {
+            double v = a == 3 ? t : p[a];
+            double f = floor((v - M->lo[a]) * M->idelta[a]);
+            if (f < 0.0 || f >= (double)M->n[a]) return -1;
+            i = (int64_t)f;
+        }
+        c = c * M->n[a] + i;
+    }
+    return c;
+}
+
 /* returns pieces scored; tally may be NULL (count only) */
 static int64_t o_score_mesh(const o_mesh *M, const double p[3], const double u[3],
                             const double iu[3], double t0, double v, double d, double w,
@@ -826,8 +845,14 @@ static void o_flight(o_ctx *C, o_part *q)
         return;
     }
 
-    /* collision */
+    /* collision; the collision estimator scores w / Sigma_t (weight before
+     * the collision) into the bin of the collision point: its expectation is
+     * the track length the bin receives */
     R->cnt[ORC_C_COLLISION] += 1;
+    if (P->col_tally) {
+        int64_t b = o_point_bin(&C->M, q->p, q->t, q->g);
+        if (b >= 0) R->col_batch[b] += q->w / sig_t;
+    }
     const double *ss_row = P->sigma_s + ((size_t)mat * P->G + q->g) * P->G;
     double sig_s = 0.0;
     for (int h = 0; h < P->G; ++h) sig_s = sig_s + ss_row[h];
@@ -999,6 +1024,7 @@ int orc_run(const orc_problem *P, uint64_t seed, uint64_t hist0, uint64_t n_hist
 {
     int st = o_validate(P);
     if (st != ORC_OK) return st;
+    if (P->col_tally && (!R->col_batch || !R->col_sum || !R->col_sumsq)) return ORC_E_INVALID;
     o_ctx C;
     memset(&C, 0, sizeof(C));
     C.P = P;
@@ -1030,6 +1056,14 @@ int orc_run(const orc_problem *P, uint64_t seed, uint64_t hist0, uint64_t n_hist
                 R->tally_sum[i] += sb;
                 R->tally_sumsq[i] += sb * sb / nb;
                 R->tally_batch[i] = 0.0;
+            }
+            if (P->col_tally) {
+                double cb = R->col_batch[i];
+                if (cb != 0.0) {
+                    R->col_sum[i] += cb;
+                    R->col_sumsq[i] += cb * cb / nb;
+                    R->col_batch[i] = 0.0;
+                }
             }
         }
         R->batches_done += 1;

@@ -91,6 +91,7 @@ typedef struct {
     int32_t ww_map_n[4];              /* all > 0: targets from a cell-centre map of the
                                          network, (nx, ny, nz, nt) cells; 0: network
                                          evaluated at every check */
+    int32_t col_tally;                /* also a collision-estimator mesh tally */
     int32_t n_batches;
     int64_t max_events;
     int32_t stack_cap;
@@ -109,6 +110,7 @@ typedef struct {
     double *tally_batch;      /* [nbins] current batch (scratch, zero on entry) */
     double *tally_sum;        /* [nbins] sum over batches of S_b              */
     double *tally_sumsq;      /* [nbins] sum over batches of S_b^2 / N_b      */
+    double *col_batch, *col_sum, *col_sumsq;  /* collision estimator, same layout */
     double det[2];            /* sum x_h, sum x_h^2 over histories            */
     double leak[6];
     double wsum[ORC_NWSUM];

@@ -67,6 +67,7 @@ class OrcProblem(C.Structure):
         ("ww_on", C.c_int32), ("ww_hidden", C.c_int32), ("ww_nmax", C.c_int32),
         ("ww_params", PF), ("ww_ymin", C.c_float), ("ww_ymax", C.c_float),
         ("ww_logk", C.c_double), ("ww_ratio", C.c_double), ("ww_map_n", I4),
+        ("col_tally", C.c_int32),
         ("n_batches", C.c_int32), ("max_events", C.c_int64), ("stack_cap", C.c_int32),
         ("problem_id", C.c_uint32),
     ]
@@ -89,6 +90,7 @@ assert TRACE_DTYPE.itemsize == C.sizeof(OrcTraceRec)
 
 class OrcResult(C.Structure):
     _fields_ = [("tally_batch", PD), ("tally_sum", PD), ("tally_sumsq", PD),
+                ("col_batch", PD), ("col_sum", PD), ("col_sumsq", PD),
                 ("det", C.c_double * 2), ("leak", C.c_double * 6), ("wsum", C.c_double * NWSUM),
                 ("cnt", C.c_uint64 * NCOUNT), ("imp_score", PD), ("imp_weight", PD),
                 ("hist_xh", PD), ("trace", C.POINTER(OrcTraceRec)), ("trace_cap", C.c_int64),
@@ -202,6 +204,7 @@ class _Problem:
             s.ww_ymax = float(ww.get("ymax", 3.0e38))
             if ww.get("map") is not None:
                 s.ww_map_n = I4(*[int(v) for v in ww["map"]])
+        s.col_tally = 1 if prob.get("collision_tally") else 0
         s.n_batches = int(prob["n_batches"])
         s.max_events = int(prob["max_events"])
         s.stack_cap = int(prob["stack_cap"])
@@ -233,6 +236,12 @@ class OracleRun:
         self.R = OrcResult()
         self.R.tally_batch, self.R.tally_sum, self.R.tally_sumsq = (
             _pd(self.tally_batch), _pd(self.tally_sum), _pd(self.tally_sumsq))
+        if prob.get("collision_tally"):
+            self.col_batch = np.zeros(nb)
+            self.col_sum = np.zeros(nb)
+            self.col_sumsq = np.zeros(nb)
+            self.R.col_batch, self.R.col_sum, self.R.col_sumsq = (
+                _pd(self.col_batch), _pd(self.col_sum), _pd(self.col_sumsq))
         if self.P.n_imp:
             self.R.imp_score, self.R.imp_weight = _pd(self.imp_score), _pd(self.imp_weight)
         self.n_hist = 0
@@ -288,15 +297,18 @@ class OracleRun:
         """(sum x_h, sum x_h^2) over histories."""
         return float(self.R.det[0]), float(self.R.det[1])
 
-    def mesh_stats(self):
+    def mesh_stats(self, estimator: str = "track"):
         """Per-bin mean score per source particle and its standard error from
-        batch means (weighted form for unequal batches)."""
+        batch means (weighted form for unequal batches); estimator "track"
+        (track length) or "collision"."""
         N = float(self.n_hist)
         B = int(self.R.batches_done)
-        mean = self.tally_sum / N
+        s1, s2 = ((self.tally_sum, self.tally_sumsq) if estimator == "track"
+                  else (self.col_sum, self.col_sumsq))
+        mean = s1 / N
         if B < 2:
             return mean, np.full_like(mean, np.nan)
-        var = (self.tally_sumsq - N * mean * mean) / ((B - 1) * N)
+        var = (s2 - N * mean * mean) / ((B - 1) * N)
         return mean, np.sqrt(np.maximum(var, 0.0))
 
     def detector_stats(self):

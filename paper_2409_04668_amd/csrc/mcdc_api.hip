@@ -59,6 +59,7 @@ int validate_desc(const mcdc_problem_desc *d) {
     if (nb > 4.0e9) return fail(MCDC_E_INVALID, "tally too large (bins must fit 32 bits)");
     if (d->n_batches < 1 || d->n_batches > 65535) return fail(MCDC_E_INVALID, "n_batches must lie in [1, 65535]");
     if (d->stack_cap < 0 || d->max_events < 1) return fail(MCDC_E_INVALID, "stack_cap/max_events");
+    if (d->col_tally != 0 && d->col_tally != 1) return fail(MCDC_E_INVALID, "col_tally must be 0 or 1");
     if (d->imp_on) {
         for (int a = 0; a < 4; ++a)
             if (d->imp_n[a] < 1) return fail(MCDC_E_INVALID, "imp_n must be >= 1");
@@ -138,6 +139,10 @@ Layout make_layout(const mcdc_problem_desc *d, const Options &o) {
     L.tally_batch = off; off = align_up(off + nslices * nb * sizeof(double));
     L.tally_sum = off; off = align_up(off + nb * sizeof(double));
     L.tally_sumsq = off; off = align_up(off + nb * sizeof(double));
+    const size_t nc = d->col_tally ? nb : 0;      // collision estimator, same layout
+    L.col_batch = off; off = align_up(off + nslices * nc * sizeof(double));
+    L.col_sum = off; off = align_up(off + nc * sizeof(double));
+    L.col_sumsq = off; off = align_up(off + nc * sizeof(double));
     L.acc = off; off = align_up(off + sizeof(DevAcc));
     const size_t ni = desc_nimp(d);
     L.imp_score = off; off = align_up(off + ni * sizeof(double));
@@ -203,6 +208,7 @@ void build_dev_problem(const mcdc_problem_desc *d, char *ws, const Layout &L, De
         }
     }
     P.G_t = d->mesh_per_group ? d->G : 1;
+    P.col_on = d->col_tally;
     P.implicit_capture = d->implicit_capture;
     P.w_cut = d->w_cut;
     P.w_surv = d->w_surv;
@@ -418,6 +424,7 @@ static RunArgs base_args(mcdc_handle h, uint64_t seed) {
     memset(&A, 0, sizeof(A));
     A.seed = seed;
     A.tally = (double *)(h->ws + h->L.tally_batch);
+    A.col = h->desc.col_tally ? (double *)(h->ws + h->L.col_batch) : nullptr;
     A.acc = (DevAcc *)(h->ws + h->L.acc);
     A.imp_score = (double *)(h->ws + h->L.imp_score);
     A.imp_weight = (double *)(h->ws + h->L.imp_weight);
@@ -447,6 +454,10 @@ int mcdc_run(mcdc_handle h, uint64_t n, uint64_t seed, void *stream) {
     double *batch = (double *)(h->ws + h->L.tally_batch);
     double *sum = (double *)(h->ws + h->L.tally_sum);
     double *sumsq = (double *)(h->ws + h->L.tally_sumsq);
+    double *cbatch = (double *)(h->ws + h->L.col_batch);
+    double *csum = (double *)(h->ws + h->L.col_sum);
+    double *csumsq = (double *)(h->ws + h->L.col_sumsq);
+    const bool col = h->desc.col_tally != 0;
     const bool lds = h->opt.lds_tally && h->nbins <= (uint32_t)kLdsTallyMaxBins;
     if (h->opt.schedule == MCDC_SCHED_EVENT) {
         // one pass over all histories of the run; each particle scores into
@@ -463,6 +474,9 @@ int mcdc_run(mcdc_handle h, uint64_t n, uint64_t seed, void *stream) {
             if (hi == lo) continue;
             hipError_t e = launch_closeout(batch + b * (uint64_t)h->nbins, sum, sumsq, h->nbins,
                                            (double)(hi - lo), s);
+            if (e == hipSuccess && col)
+                e = launch_closeout(cbatch + b * (uint64_t)h->nbins, csum, csumsq, h->nbins,
+                                    (double)(hi - lo), s);
             if (e != hipSuccess) return hip_fail(e, "run launch");
             h->batches += 1;
         }
@@ -478,6 +492,8 @@ int mcdc_run(mcdc_handle h, uint64_t n, uint64_t seed, void *stream) {
         hipError_t e = launch_history(h->P, A, h->opt.grid, h->opt.block, lds, s);
         timing_end(h, s);
         if (e == hipSuccess) e = launch_closeout(batch, sum, sumsq, h->nbins, (double)(hi - lo), s);
+        if (e == hipSuccess && col)
+            e = launch_closeout(cbatch, csum, csumsq, h->nbins, (double)(hi - lo), s);
         if (e != hipSuccess) return hip_fail(e, "run launch");
         h->batches += 1;
     }
@@ -510,6 +526,22 @@ int mcdc_get_raw(mcdc_handle h, double *tsum, double *tsumsq, size_t n, void *st
     if (e == hipSuccess && tsumsq)
         e = hipMemcpy(tsumsq, h->ws + h->L.tally_sumsq, n * sizeof(double), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "get_raw");
+    return MCDC_OK;
+}
+
+int mcdc_get_raw_collision(mcdc_handle h, double *csum, double *csumsq, size_t n, void *stream) {
+    if (!h) return fail(MCDC_E_INVALID, "null handle");
+    if (h->is_batch || !h->desc.col_tally)
+        return fail(MCDC_E_STATE, "problem created without the collision estimator");
+    if (n != h->nbins) return fail(MCDC_E_INVALID, "wrong bin count");
+    DevAcc acc;
+    int st = read_acc(h, acc, (hipStream_t)stream);
+    if (st) return st;
+    hipError_t e = hipSuccess;
+    if (csum) e = hipMemcpy(csum, h->ws + h->L.col_sum, n * sizeof(double), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && csumsq)
+        e = hipMemcpy(csumsq, h->ws + h->L.col_sumsq, n * sizeof(double), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "get_raw_collision");
     return MCDC_OK;
 }
 
@@ -573,11 +605,16 @@ int mcdc_get_tallies(mcdc_handle h, int kind, double *mean, double *rel, size_t 
         }
         return MCDC_OK;
     }
-    if (kind != MCDC_TALLY_MESH) return fail(MCDC_E_INVALID, "unknown tally kind");
+    if (kind != MCDC_TALLY_MESH && kind != MCDC_TALLY_COLLISION)
+        return fail(MCDC_E_INVALID, "unknown tally kind");
+    if (kind == MCDC_TALLY_COLLISION && !h->desc.col_tally)
+        return fail(MCDC_E_STATE, "problem created without the collision estimator");
     if (n != h->nbins) return fail(MCDC_E_INVALID, "wrong bin count");
+    const size_t o1 = kind == MCDC_TALLY_MESH ? h->L.tally_sum : h->L.col_sum;
+    const size_t o2 = kind == MCDC_TALLY_MESH ? h->L.tally_sumsq : h->L.col_sumsq;
     std::vector<double> s(n), s2(n);
-    hipError_t e = hipMemcpy(s.data(), h->ws + h->L.tally_sum, n * sizeof(double), hipMemcpyDeviceToHost);
-    if (e == hipSuccess) e = hipMemcpy(s2.data(), h->ws + h->L.tally_sumsq, n * sizeof(double), hipMemcpyDeviceToHost);
+    hipError_t e = hipMemcpy(s.data(), h->ws + o1, n * sizeof(double), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(s2.data(), h->ws + o2, n * sizeof(double), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "get_tallies");
     double vol = 1.0;
     for (int a = 0; a < 4; ++a)

@@ -76,6 +76,7 @@ struct BatchState {
 struct BatchCtx {
     static constexpr bool kWW = false;
     static constexpr bool kWWMap = false;
+    MCDC_DEV double *col_tally() const { return nullptr; }
     const DevProblem &P;
     const RunArgs &A;
     const BDev &D;
@@ -353,6 +354,7 @@ static int bvalidate(const mcdc_problem_desc *ds, size_t n, const uint64_t *nh) 
         if (ds[p].n_census != nc) return fail(MCDC_E_INVALID, "all batched problems need the same number of census steps");
         if (ds[p].imp_on || ds[p].stack_cap > 0) return fail(MCDC_E_INVALID, "batched problems run analog/implicit transport without weight windows");
         if (ds[p].has_detector) return fail(MCDC_E_INVALID, "batched problems have no detector tally");
+        if (ds[p].col_tally) return fail(MCDC_E_INVALID, "batched problems have no collision-estimator tally");
         if (nh[p] > 0xFFFFFFF0ull) return fail(MCDC_E_INVALID, "too many histories in one problem");
         cap += nh[p];
     }

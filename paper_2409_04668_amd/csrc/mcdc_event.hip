@@ -94,6 +94,13 @@ struct EvCtx {
     const EvBank &B;
     uint32_t slot;
     MCDC_DEV uint64_t hist() const { return A.h_begin + slot; }
+    // batch b of the history (run-relative id r) holds ids
+    // [floor(b n / B), floor((b+1) n / B)): b = floor(((r+1) B - 1) / n)
+    MCDC_DEV uint64_t batch() const {
+        const uint64_t r = A.h_begin + slot - A.h_run0;
+        return ((r + 1) * A.run_batches - 1) / A.run_n;
+    }
+    MCDC_DEV double *col_tally() const { return A.col + batch() * (uint64_t)P.nbins; }
     MCDC_DEV const float *mlp_params(const DevProblem &Pp) const { return Pp.ww_params; }
     MCDC_DEV bool count_flight() {
         uint32_t e;
@@ -214,11 +221,7 @@ __global__ void __launch_bounds__(256) k_ev_flight(DevProblem P, RunArgs A, EvBa
             uint32_t slot;
             bank_load(B, j, q, d, slot);
             EvCtx<WW> C{P, A, B, slot};
-            // batch b of the history (run-relative id r) holds ids
-            // [floor(b n / B), floor((b+1) n / B)): b = floor(((r+1) B - 1) / n)
-            const uint64_t r = A.h_begin + slot - A.h_run0;
-            const uint64_t b = ((r + 1) * A.run_batches - 1) / A.run_n;
-            GlobalTally tally{A.tally + b * (uint64_t)P.nbins};
+            GlobalTally tally{A.tally + C.batch() * (uint64_t)P.nbins};
             ev = stage_flight(P, A, S, tally, C, q, d, n_piece, path);
             if (ev >= 0) n_flight += 1;
             if (q.alive) bank_store(B, j, q, d, slot);

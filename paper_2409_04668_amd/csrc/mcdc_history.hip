@@ -68,6 +68,7 @@ struct HistCtx {
     int sp, n_imp;
 
     MCDC_DEV uint64_t hist() const { return id; }
+    MCDC_DEV double *col_tally() const { return A.col; }
     MCDC_DEV const float *mlp_params(const DevProblem &Pp) const { return Pp.ww_params; }
     MCDC_DEV bool count_flight() {
         events += 1;

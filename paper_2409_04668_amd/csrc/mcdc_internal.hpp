@@ -54,6 +54,7 @@ struct DevProblem {
     double src_lo[3], src_hi[3], src_t0, src_t1, src_dir[3];
     double mesh_lo[4], mesh_delta[4], mesh_idelta[4];
     int32_t mesh_n[4], mesh_bounded[3], G_t;
+    int32_t col_on;                      // collision-estimator tally
     int32_t implicit_capture;
     double w_cut, w_surv;
     int32_t has_detector;
@@ -83,6 +84,7 @@ struct RunArgs {
     uint64_t run_batches;                // batches of the run (event schedule)
     double *tally;                       // current-batch accumulator [nbins]; event
                                          // schedule: [run_batches][nbins] slices
+    double *col;                         // collision estimator, same layout as tally
     DevAcc *acc;
     double *imp_score, *imp_weight;
     double *xh_out;
@@ -97,7 +99,8 @@ struct RunArgs {
 };
 
 struct Layout {                          // workspace carving (byte offsets)
-    size_t tables, tally_batch, tally_sum, tally_sumsq, acc, imp_score, imp_weight, ww_params,
+    size_t tables, tally_batch, tally_sum, tally_sumsq, col_batch, col_sum, col_sumsq, acc,
+        imp_score, imp_weight, ww_params,
         stk_d, stk_i, imp_list, event, total;
 };
 

@@ -443,6 +443,25 @@ MCDC_DEV float mlp_infer(const float *__restrict__ gprm, int in_dim, const float
     return out;
 }
 
+// Mesh bin holding a point (x, y, z, t) in group g, for the collision
+// estimator: per axis floor((p - lo) / delta); -1 outside the mesh (an
+// unbounded axis is one bin).
+MCDC_DEV int64_t mesh_point_bin(const DevProblem &P, const double p[3], double t, int g) {
+    int64_t c = P.G_t > 1 ? g : 0;
+#pragma unroll
+    for (int a = 3; a >= 0; --a) {
+        int64_t i = 0;
+        if (a == 3 || P.mesh_bounded[a]) {
+            const double v = a == 3 ? t : (a == 2 ? p[2] : (a == 1 ? p[1] : p[0]));
+            const double f = floor((v - P.mesh_lo[a]) * P.mesh_idelta[a]);
+            if (f < 0.0 || f >= (double)P.mesh_n[a]) return -1;
+            i = (int64_t)f;
+        }
+        c = c * P.mesh_n[a] + i;
+    }
+    return c;
+}
+
 // Map cell of a point for the weight-window map: per axis floor(s n) of the
 // fraction s of the outer box (of the last census time), clamped to [0, n-1];
 // layout [g][t][z][y][x].

@@ -290,6 +290,10 @@ MCDC_DEV bool stage_collision(const DevProblem &P, const RunArgs &A, Shared &S, 
     atomicAdd(&S.cnt[C_COLLISION], 1ull);
     const int mat = q.cell >= 0 ? P.box_mat[q.cell] : P.background_mat;
     const double sig_t = P.sigma_t[mat * P.G + q.g];
+    if (P.col_on) {                      // collision estimator: w / Sigma_t at the point
+        const int64_t b = mesh_point_bin(P, q.x, q.t, q.g);
+        if (b >= 0) unsafeAtomicAdd(C.col_tally() + b, q.w / sig_t);
+    }
     const double *ss_row = P.sigma_s + (mat * P.G + q.g) * P.G;
     double sig_s = 0.0;
     for (int h = 0; h < P.G; ++h) sig_s = sig_s + ss_row[h];

@@ -12,6 +12,11 @@ import ctypes as C
 import os
 
 import numpy as np
+# PyTorch first: its bundled HIP runtime and the one libmcdc.so links against
+# share the soname libamdhip64.so.7, and the copy loaded first serves the whole
+# process.  Loading torch's copy first keeps torch and the library on one
+# runtime, the one torch was built with.
+import torch  # noqa: F401  (import order matters)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmcdc.so")
@@ -25,7 +30,7 @@ _lib = C.CDLL(LIB_PATH)
 OK = 0
 E_INVALID, E_NOMEM, E_HIP, E_EVENT_CAP, E_CANCELLED, E_STATE, E_STACK, E_BANK = -1, -2, -3, -4, -5, -6, -7, -8
 SCHED_AUTO, SCHED_HISTORY, SCHED_EVENT = 0, 1, 2
-TALLY_MESH, TALLY_DETECTOR, TALLY_LEAKAGE = 0, 1, 2
+TALLY_MESH, TALLY_DETECTOR, TALLY_LEAKAGE, TALLY_COLLISION = 0, 1, 2, 3
 MAX_G = 8
 HIDDEN = 64
 
@@ -46,7 +51,8 @@ class ProblemDesc(C.Structure):
         ("src_kind", C.c_int32), ("src_lo", D3), ("src_hi", D3), ("src_t0", C.c_double),
         ("src_t1", C.c_double), ("src_isotropic", C.c_int32), ("src_dir", D3),
         ("src_group", C.c_int32), ("mesh_lo", D4), ("mesh_hi", D4), ("mesh_n", I4),
-        ("mesh_per_group", C.c_int32), ("n_census", C.c_int32), ("census", PD),
+        ("mesh_per_group", C.c_int32), ("col_tally", C.c_int32),
+        ("n_census", C.c_int32), ("census", PD),
         ("implicit_capture", C.c_int32), ("w_cut", C.c_double), ("w_surv", C.c_double),
         ("has_detector", C.c_int32), ("det_lo", D3), ("det_hi", D3), ("imp_on", C.c_int32),
         ("imp_n", I4), ("n_batches", C.c_int32), ("max_events", C.c_int64),
@@ -106,6 +112,7 @@ _sig("mcdc_create_problem", C.c_int, C.POINTER(ProblemDesc), C.POINTER(Options),
 _sig("mcdc_run", C.c_int, VP, C.c_uint64, C.c_uint64, VP)
 _sig("mcdc_get_tallies", C.c_int, VP, C.c_int, PD, PD, C.c_size_t, VP)
 _sig("mcdc_get_raw", C.c_int, VP, PD, PD, C.c_size_t, VP)
+_sig("mcdc_get_raw_collision", C.c_int, VP, PD, PD, C.c_size_t, VP)
 _sig("mcdc_get_counters", C.c_int, VP, C.POINTER(Counters), VP)
 _sig("mcdc_reset_tallies", C.c_int, VP, VP)
 _sig("mcdc_tally_bins", C.c_int, VP, C.POINTER(C.c_size_t))
@@ -202,6 +209,7 @@ class _Desc:
         d.mesh_hi = D4(*map(float, m["hi"]))
         d.mesh_n = I4(*map(int, m["n"]))
         d.mesh_per_group = 1 if m["per_group"] else 0
+        d.col_tally = 1 if prob.get("collision_tally") else 0
         cen = arr(prob["census"], np.float64)
         d.n_census, d.census = cen.size, cen.ctypes.data_as(PD)
         d.implicit_capture = 1 if prob["implicit_capture"] else 0
@@ -352,8 +360,16 @@ class Problem:
                                 _stream_ptr(stream)), "get_raw")
         return s, s2
 
+    def raw_collision(self, stream=None):
+        s = np.zeros(self.nbins)
+        s2 = np.zeros(self.nbins)
+        check(_lib.mcdc_get_raw_collision(self.h, s.ctypes.data_as(PD), s2.ctypes.data_as(PD),
+                                          self.nbins, _stream_ptr(stream)), "get_raw_collision")
+        return s, s2
+
     def tallies(self, kind=TALLY_MESH, stream=None):
-        n = {TALLY_MESH: self.nbins, TALLY_DETECTOR: 1, TALLY_LEAKAGE: 6}[kind]
+        n = {TALLY_MESH: self.nbins, TALLY_DETECTOR: 1, TALLY_LEAKAGE: 6,
+             TALLY_COLLISION: self.nbins}[kind]
         m = np.zeros(n)
         r = np.zeros(n)
         check(_lib.mcdc_get_tallies(self.h, kind, m.ctypes.data_as(PD), r.ctypes.data_as(PD), n,

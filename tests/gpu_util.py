@@ -89,5 +89,9 @@ def full_parity(prob, n, seed, trace_cap=0, options=None, runs=1):
     s, s2 = gp.raw()
     assert_close_sums(s, orc.tally_sum, what="tally_sum")
     assert_close_sums(s2, orc.tally_sumsq, what="tally_sumsq")
+    if prob.get("collision_tally"):
+        c, c2 = gp.raw_collision()
+        assert_close_sums(c, orc.col_sum, what="col_sum")
+        assert_close_sums(c2, orc.col_sumsq, what="col_sumsq")
     assert_counters(gp.counters(), orc)
     return gp, orc

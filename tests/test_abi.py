@@ -5,6 +5,7 @@ import os
 import re
 
 import pytest
+import torch  # noqa: F401  (load torch's HIP runtime before the library; same soname)
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "mcdc.h")

@@ -333,3 +333,65 @@ def test_planned_tile_at_full_size_matches_plain_run():
     assert np.array_equal(res[0][0], res[1][0])
     assert_close_sums(res[0][1], res[1][1], what="tally")
     assert res[0][2]["pieces"] == res[1][2]["pieces"]
+
+
+# ---------------------------------------------------------------------------
+# collision-estimator mesh tally
+# ---------------------------------------------------------------------------
+
+def _col_box():
+    p = W._base(1)
+    p["outer_lo"] = np.zeros(3)
+    p["outer_hi"] = np.full(3, 10.0)
+    p["box_lo"] = np.array([[4.0, 0.0, 0.0]])
+    p["box_hi"] = np.array([[7.0, 10.0, 10.0]])
+    p["box_mat"] = np.array([1], np.int32)
+    p["sigma_t"] = np.array([[0.4], [1.5]])
+    p["sigma_s"] = np.array([[[0.3]], [[1.2]]])
+    p["source"] = dict(kind="box", lo=np.array([1.0, 1.0, 1.0]), hi=np.array([9.0, 9.0, 9.0]),
+                       t0=0.0, t1=3.0, isotropic=True, dir=np.array([1.0, 0.0, 0.0]), group=0)
+    p["mesh"] = dict(lo=np.array([2.0, 0.0, 1.0, 0.0]), hi=np.array([9.0, 10.0, 8.0, 8.0]),
+                     n=np.array([7, 4, 5, 6], np.int32), per_group=False)
+    p["census"] = np.array([5.0, 12.0])
+    p["n_batches"] = 3
+    p["collision_tally"] = True
+    return p
+
+
+def test_collision_tally_parity_history():
+    gp, orc = full_parity(_col_box(), 3000, seed=131, trace_cap=300000)
+    assert orc.col_sum.sum() > 0
+
+
+def test_collision_tally_parity_event_and_multigroup_implicit():
+    p = W.config3()
+    p["implicit_capture"] = True
+    p["mesh"]["n"] = np.array([6, 10, 6, 5], np.int32)
+    p["collision_tally"] = True
+    full_parity(p, 300, seed=132, trace_cap=600000, options=_ev())
+    full_parity(p, 300, seed=133, trace_cap=600000)
+
+
+def test_collision_tally_parity_duct_census_event_chunks():
+    p = W.config2(n_census=5)
+    p["mesh"]["n"] = np.array([12, 20, 12, 10], np.int32)
+    p["collision_tally"] = True
+    full_parity(p, 4321, seed=134, trace_cap=300000, options=_ev(1000))
+
+
+def test_collision_tally_agrees_with_track_length_on_gpu():
+    """1e7 duct histories: the two estimators of the same flux agree per bin
+    within their statistical errors."""
+    mc = _mcdc()
+    p = W.config2()
+    p["mesh"]["n"] = np.array([12, 20, 12, 4], np.int32)
+    p["collision_tally"] = True
+    gp = mc.Problem(p)
+    gp.run(10_000_000, 135)
+    mt, rt = gp.tallies(mc.TALLY_MESH)
+    mcol, rc = gp.tallies(mc.TALLY_COLLISION)
+    ok = (mt > 0) & (mcol > 0) & np.isfinite(rt) & np.isfinite(rc)
+    assert ok.sum() > 500
+    z = np.abs(mt - mcol)[ok] / np.hypot(mt * rt, mcol * rc)[ok]
+    assert np.mean(z < 3) > 0.95 and np.max(z) < 6
+    gp.close()
