@@ -81,6 +81,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fom", action="store_true",
                     help="skip the analog vs learned-weight-window FOM comparison")
+    ap.add_argument("--no-other-schedule", action="store_true",
+                    help="skip the comparison step under the other schedule")
     ap.add_argument("--no-tile", action="store_true", help="tally straight to HBM atomics")
     ap.add_argument("--workload", choices=["duct", "batch", "fom"], default="duct")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
@@ -195,16 +197,31 @@ def main():
     gp.close()
     # the same step under the other schedule (event-based: staged kernels over
     # compacted queues), one timed step after a warm-up, as a comparison
-    other = "event" if args.schedule == "history" else "history"
-    osched = mcdc.SCHED_EVENT if other == "event" else mcdc.SCHED_HISTORY
-    go = mcdc.Problem(prob, mcdc.make_options(osched, event_chunk=1 << 24))
-    go.run(N, seed)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    go.run(N, seed + 1)
-    torch.cuda.synchronize()
-    out["other_schedule"] = {"schedule": other, "histories_per_s": N / (time.perf_counter() - t0)}
-    go.close()
+    if not args.no_other_schedule:
+        other = "event" if args.schedule == "history" else "history"
+        osched = mcdc.SCHED_EVENT if other == "event" else mcdc.SCHED_HISTORY
+        go = mcdc.Problem(prob, mcdc.make_options(osched, event_chunk=1 << 24))
+        go.run(N, seed)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        go.run(N, seed + 1)
+        torch.cuda.synchronize()
+        out["other_schedule"] = {"schedule": other,
+                                 "histories_per_s": N / (time.perf_counter() - t0)}
+        go.close()
+    if not args.no_other_schedule:
+        # the same step with the collision estimator as a second mesh tally
+        pc = dict(prob, collision_tally=True)
+        gc = mcdc.Problem(pc, mcdc.make_options(sched, waves_per_cu=args.waves_per_cu, tile=tile))
+        gc.run(N, seed)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gc.run(N, seed + 1)
+        torch.cuda.synchronize()
+        rate = N / (time.perf_counter() - t0)
+        out["with_collision_estimator"] = {"histories_per_s": rate,
+                                           "relative_to_track_length_only": rate / out["value"]}
+        gc.close()
     if not args.no_fom:
         out["fom"] = fom_comparison(mcdc, W)
     if not args.no_cpu_baseline:

@@ -252,14 +252,38 @@ def fom_run(prob: dict, n_hist: int, seed: int, options=None, chunk: int = 100_0
 
 
 def fom_at_target(prob: dict, seed: int, target=0.01, pilot=2_000_000, options=None,
-                  max_hist=4_000_000_000):
-    """Pilot run -> N with the detector relative error at `target` -> run N.
-    Returns N, mean, relative error, seconds, FOM = 1/(R^2 T) and counters."""
+                  max_hist=4_000_000_000, tol=1.04, max_topups=4):
+    """Pilot run -> N with the detector relative error at `target` -> run N,
+    then top up (same problem, history ids continue) while the measured
+    relative error exceeds tol * target.  Returns N, mean, relative error,
+    seconds (all timed runs and read-backs), FOM = 1/(R^2 T) and counters."""
+    import torch
     m, r, dt, _ = fom_run(prob, pilot, seed, options)
     if not (r > 0):
         raise RuntimeError("pilot run scored nothing on the detector")
     n = int(min(max_hist, max(pilot, np.ceil(pilot * (r / target) ** 2 * 1.05))))
-    m, r, dt, c = fom_run(prob, n, seed + 1000, options)
-    return dict(n=n, mean=m, rel_err=r, seconds=dt, fom=1.0 / (r * r * dt),
-                histories_per_s=n / dt, splits=int(c["splits"]), rr_kills=int(c["rr_kills"]),
+    gp = mcdc.Problem(prob, options)
+    gp.run(min(n, 100_000), seed + 999_999)            # warm-up; reset below
+    gp.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done, i, todo = 0, 0, n
+    for _ in range(max_topups + 1):
+        while todo > 0:
+            k = min(todo, 100_000_000)
+            gp.run(k, seed + 1000 + i)
+            done += k
+            todo -= k
+            i += 1
+        mm, rr = gp.tallies(mcdc.TALLY_DETECTOR)
+        m, r = float(mm[0]), float(rr[0])
+        if r <= tol * target or done >= max_hist:
+            break
+        todo = int(min(max_hist - done, np.ceil(done * ((r / target) ** 2 * 1.05 - 1.0))))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    c = gp.counters()
+    gp.close()
+    return dict(n=done, mean=m, rel_err=r, seconds=dt, fom=1.0 / (r * r * dt),
+                histories_per_s=done / dt, splits=int(c["splits"]), rr_kills=int(c["rr_kills"]),
                 particles=int(c["particles"]), detector_hits=int(c["detector_hits"]))
