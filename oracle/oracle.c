@@ -522,6 +522,7 @@ typedef struct {
     double imp_cnt[16], imp_xsum[16];
     double ww_lo[4], ww_inv[4];
     double *ww_map;           /* window map (NULL: network at every check) */
+    int census_hit;           /* the last flight stopped at an intermediate census */
 } o_ctx;
 
 static void o_trace(o_ctx *C, o_part *q, int type, double aux)
@@ -824,6 +825,7 @@ static void o_flight(o_ctx *C, o_part *q)
         } else {
             q->ci += 1;
             R->cnt[ORC_C_CENSUS] += 1;
+            C->census_hit = 1;
             o_trace(C, q, ORC_EV_CENSUS, d);
         }
         return;
@@ -990,6 +992,177 @@ static int o_history(o_ctx *C, uint64_t h, uint64_t slot)
     return ORC_OK;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Population control at census (census-synchronised batches).               */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    o_part *p;
+    uint64_t *slot;            /* history index within the batch */
+    size_t n, cap;
+} o_bank;
+
+static void o_bank_push(o_bank *b, const o_part *q, uint64_t slot)
+{
+    if (b->n == b->cap) {
+        b->cap = b->cap ? 2 * b->cap : 1024;
+        b->p = (o_part *)realloc(b->p, b->cap * sizeof(o_part));
+        b->slot = (uint64_t *)realloc(b->slot, b->cap * sizeof(uint64_t));
+    }
+    b->p[b->n] = *q;
+    b->slot[b->n] = slot;
+    b->n += 1;
+}
+
+/* Transport one banked particle (and the weight-window daughters it makes)
+ * until each dies or stops at the next intermediate census, where it is
+ * banked for the next step.  The history's running sums live in per-slot
+ * arrays between the particle's visits. */
+static int o_pc_transport(o_ctx *C, o_part q, uint64_t slot, uint64_t hist_first, o_bank *next,
+                          double *xh, double *ph, int64_t *ev)
+{
+    C->hist = hist_first + slot;
+    C->xh = xh[slot];
+    C->path_h = ph[slot];
+    C->events = ev[slot];
+    C->sp = 0;
+    for (;;) {
+        while (q.alive && C->status == ORC_OK) {
+            C->census_hit = 0;
+            o_flight(C, &q);
+            if (C->census_hit) {
+                o_bank_push(next, &q, slot);
+                q.alive = 0;
+            }
+        }
+        if (C->status != ORC_OK) break;
+        if (C->sp == 0) break;
+        q = C->stack[--C->sp];
+        q.alive = 1;
+    }
+    xh[slot] = C->xh;
+    ph[slot] = C->path_h;
+    ev[slot] = C->events;
+    return C->status;
+}
+
+/* Splitting-roulette population control of a census bank to M particles,
+ * M = round(pc_target * histories of the batch).  The bank's total weight is
+ * summed exactly as integers floor(w * 2^32); the target weight is
+ * w_T = (sum * 2^-32) / M.  Each particle draws one xi from its own stream:
+ * below w_T it survives with probability w / w_T (xi * w_T < w) at weight
+ * w_T; otherwise it becomes n = floor(w / w_T + xi) >= 1 particles of weight
+ * w_T, the n - 1 copies taking stream tags from one further block of its
+ * stream (tag + i * golden ratio, as for splits).  The expected weight of
+ * every particle is kept, so tallies stay unbiased. */
+static void o_pc_apply(o_ctx *C, o_bank *b, uint64_t n_batch_hist, uint64_t hist_first)
+{
+    const orc_problem *P = C->P;
+    orc_result *R = C->R;
+    if (b->n == 0) return;
+    uint64_t wq = 0;
+    for (size_t i = 0; i < b->n; ++i) wq += (uint64_t)floor(b->p[i].w * 4294967296.0);
+    double M = floor(P->pc_target * (double)n_batch_hist + 0.5);
+    if (M < 1.0) M = 1.0;
+    const double wt = ((double)wq * 0x1p-32) / M;
+    if (!(wt > 0.0)) return;
+    o_bank out = {0};
+    for (size_t i = 0; i < b->n; ++i) {
+        o_part q = b->p[i];
+        const uint64_t slot = b->slot[i];
+        C->hist = hist_first + slot;
+        o_stream st = o_part_stream(C, &q);
+        const double xi = o_draw(&st);
+        const double w = q.w;
+        if (w < wt) {
+            q.k = st.k;
+            if (xi * wt < w) {
+                R->wsum[ORC_W_GAIN] += wt - w;
+                q.w = wt;
+                o_trace(C, &q, ORC_EV_PC_KEEP, 1.0);
+                o_bank_push(&out, &q, slot);
+            } else {
+                R->wsum[ORC_W_LOSS] += w;
+                R->cnt[ORC_C_PC_KILL] += 1;
+                o_trace(C, &q, ORC_EV_PC_KILL, 0.0);
+            }
+            continue;
+        }
+        const double nf = floor(w / wt + xi);
+        const int64_t n = (int64_t)nf;
+        const double tot = nf * wt;
+        if (tot > w) R->wsum[ORC_W_GAIN] += tot - w;
+        else R->wsum[ORC_W_LOSS] += w - tot;
+        uint32_t blk[4] = {0, 0, 0, 0};
+        if (n >= 2) o_block(&st, blk);
+        q.k = st.k;
+        q.w = wt;
+        o_trace(C, &q, ORC_EV_PC_KEEP, nf);
+        o_bank_push(&out, &q, slot);
+        for (int64_t m = 1; m < n; ++m) {
+            o_part d = q;
+            d.tag = blk[0] + (uint32_t)m * 0x9E3779B9u;
+            d.k = 0;
+            d.seq = 0;
+            o_bank_push(&out, &d, slot);
+        }
+        if (n >= 2) {
+            R->cnt[ORC_C_PC_COPY] += (uint64_t)(n - 1);
+            R->cnt[ORC_C_PARTICLE] += (uint64_t)(n - 1);
+        }
+    }
+    free(b->p);
+    free(b->slot);
+    *b = out;
+}
+
+/* One batch [lo, hi) of the run, census step by census step: transport every
+ * particle of the bank to death or the next intermediate census, apply
+ * population control to the new census bank, repeat; then the per-history
+ * detector statistics. */
+static int o_batch_pc(o_ctx *C, uint64_t hist0, uint64_t lo, uint64_t hi)
+{
+    orc_result *R = C->R;
+    const uint64_t nb = hi - lo;
+    const uint64_t first = hist0 + lo;
+    double *xh = (double *)calloc(nb, sizeof(double));
+    double *ph = (double *)calloc(nb, sizeof(double));
+    int64_t *ev = (int64_t *)calloc(nb, sizeof(int64_t));
+    o_bank bank = {0}, next = {0};
+    int st = ORC_OK;
+    for (uint64_t j = 0; j < nb; ++j) {
+        C->hist = first + j;
+        R->cnt[ORC_C_HIST] += 1;
+        o_part q;
+        o_source(C, &q);
+        if (q.alive) o_bank_push(&bank, &q, j);
+    }
+    while (bank.n > 0 && st == ORC_OK) {
+        next.n = 0;
+        for (size_t i = 0; i < bank.n && st == ORC_OK; ++i)
+            st = o_pc_transport(C, bank.p[i], bank.slot[i], first, &next, xh, ph, ev);
+        if (st != ORC_OK) break;
+        o_pc_apply(C, &next, nb, first);
+        o_bank tmp = bank;
+        bank = next;
+        next = tmp;
+    }
+    if (st == ORC_OK) {
+        for (uint64_t j = 0; j < nb; ++j) {
+            R->det[0] += xh[j];
+            R->det[1] += xh[j] * xh[j];
+            if (xh[j] > 0.0) R->cnt[ORC_C_DET_HIT] += 1;
+            if (R->hist_xh) {
+                R->hist_xh[2 * (lo + j)] = xh[j];
+                R->hist_xh[2 * (lo + j) + 1] = ph[j];
+            }
+        }
+    }
+    free(bank.p); free(bank.slot); free(next.p); free(next.slot);
+    free(xh); free(ph); free(ev);
+    return st;
+}
+
 static int o_validate(const orc_problem *P)
 {
     if (P->G < 1 || P->G > 16 || P->n_mat < 1 || P->n_census < 1) return ORC_E_INVALID;
@@ -1006,6 +1179,7 @@ static int o_validate(const orc_problem *P)
                                     isinf(P->outer_hi[1]) || isinf(P->outer_hi[2])))
         return ORC_E_INVALID;
     if (P->imp_on && (P->ww_on || P->implicit_capture)) return ORC_E_INVALID;
+    if (P->pc_on && (P->imp_on || !(P->pc_target > 0.0))) return ORC_E_INVALID;
     if (P->ww_on) {
         int pos = 0, zero = 0;
         for (int a = 0; a < 4; ++a) {
@@ -1045,9 +1219,14 @@ int orc_run(const orc_problem *P, uint64_t seed, uint64_t hist0, uint64_t n_hist
     for (uint64_t b = 0; b < B; ++b) {
         uint64_t lo = (b * n_hist) / B, hi = ((b + 1) * n_hist) / B;
         if (hi == lo) continue;
-        for (uint64_t i = lo; i < hi; ++i) {
-            st = o_history(&C, hist0 + i, i);
+        if (P->pc_on) {
+            st = o_batch_pc(&C, hist0, lo, hi);
             if (st != ORC_OK) { free(C.stack); free(C.ww_map); return st; }
+        } else {
+            for (uint64_t i = lo; i < hi; ++i) {
+                st = o_history(&C, hist0 + i, i);
+                if (st != ORC_OK) { free(C.stack); free(C.ww_map); return st; }
+            }
         }
         double nb = (double)(hi - lo);
         for (size_t i = 0; i < nbins; ++i) {

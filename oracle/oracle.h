@@ -42,6 +42,8 @@ enum {
     ORC_EV_ROULETTE_SURVIVE = 9,
     ORC_EV_CUTOFF_KILL = 10,
     ORC_EV_CUTOFF_SURVIVE = 11,
+    ORC_EV_PC_KILL = 12,          /* population control at a census: removed        */
+    ORC_EV_PC_KEEP = 13,          /* population control: kept as aux copies        */
 };
 
 /* counters */
@@ -49,7 +51,7 @@ enum {
     ORC_C_HIST = 0, ORC_C_FLIGHT, ORC_C_PIECE, ORC_C_COLLISION, ORC_C_ABSORB,
     ORC_C_SURFACE, ORC_C_LEAK, ORC_C_CENSUS, ORC_C_TIME_END, ORC_C_SPLIT,
     ORC_C_RR_KILL, ORC_C_RR_SURVIVE, ORC_C_CUT_KILL, ORC_C_CUT_SURVIVE,
-    ORC_C_DET_HIT, ORC_C_PARTICLE, ORC_NCOUNT
+    ORC_C_DET_HIT, ORC_C_PARTICLE, ORC_C_PC_KILL, ORC_C_PC_COPY, ORC_NCOUNT
 };
 /* weight sums */
 enum {
@@ -92,6 +94,10 @@ typedef struct {
                                          network, (nx, ny, nz, nt) cells; 0: network
                                          evaluated at every check */
     int32_t col_tally;                /* also a collision-estimator mesh tally */
+    int32_t pc_on;                    /* population control at every intermediate
+                                         census: a batch's histories advance census
+                                         step by census step together */
+    double pc_target;                 /* census population per source history   */
     int32_t n_batches;
     int64_t max_events;
     int32_t stack_cap;

@@ -21,15 +21,16 @@ LIB_PATH = os.path.join(HERE, "liboracle.so")
 CFLAGS = ["-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
           "-Wall", "-Wno-unused-function"]
 
-NCOUNT = 16
+NCOUNT = 18
 NWSUM = 7
 COUNTER_NAMES = ["hist", "flight", "piece", "collision", "absorb", "surface", "leak",
                  "census", "time_end", "split", "rr_kill", "rr_survive", "cut_kill",
-                 "cut_survive", "det_hit", "particle"]
+                 "cut_survive", "det_hit", "particle", "pc_kill", "pc_copy"]
 WSUM_NAMES = ["source", "leak", "absorb", "time_end", "gain", "loss", "path"]
 
 EV = dict(source=0, scatter=1, absorb=2, surface=3, leak=4, census=5, time_end=6, split=7,
-          roulette_kill=8, roulette_survive=9, cutoff_kill=10, cutoff_survive=11)
+          roulette_kill=8, roulette_survive=9, cutoff_kill=10, cutoff_survive=11, pc_kill=12,
+          pc_keep=13)
 
 
 def build(force: bool = True) -> str:
@@ -67,7 +68,7 @@ class OrcProblem(C.Structure):
         ("ww_on", C.c_int32), ("ww_hidden", C.c_int32), ("ww_nmax", C.c_int32),
         ("ww_params", PF), ("ww_ymin", C.c_float), ("ww_ymax", C.c_float),
         ("ww_logk", C.c_double), ("ww_ratio", C.c_double), ("ww_map_n", I4),
-        ("col_tally", C.c_int32),
+        ("col_tally", C.c_int32), ("pc_on", C.c_int32), ("pc_target", C.c_double),
         ("n_batches", C.c_int32), ("max_events", C.c_int64), ("stack_cap", C.c_int32),
         ("problem_id", C.c_uint32),
     ]
@@ -205,6 +206,9 @@ class _Problem:
             if ww.get("map") is not None:
                 s.ww_map_n = I4(*[int(v) for v in ww["map"]])
         s.col_tally = 1 if prob.get("collision_tally") else 0
+        pc = prob.get("population_control")
+        s.pc_on = 1 if pc is not None else 0
+        s.pc_target = float(pc["target"]) if pc is not None else 0.0
         s.n_batches = int(prob["n_batches"])
         s.max_events = int(prob["max_events"])
         s.stack_cap = int(prob["stack_cap"])

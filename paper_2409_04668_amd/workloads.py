@@ -25,6 +25,8 @@ Problem dict schema (all lengths in cm, times in s):
 ``detector``                 None or dict(lo[3], hi[3])
 ``n_batches``                batches for the mesh-tally statistics
 ``collision_tally``          bool; also score the collision estimator w/Sigma_t on the mesh
+``population_control``       None or dict(target): splitting-roulette of every intermediate
+                             census bank to `target` particles per source history
 ``max_events``               flight cap per history
 ``stack_cap``                LIFO depth for split daughters per history
 ``importance``               None or dict(n[4]) coarse space-time grid
@@ -61,7 +63,7 @@ def _base(G: int = 1) -> dict:
         census=np.array([1.0]),
         implicit_capture=False, w_cut=0.25, w_surv=1.0,
         detector=None, n_batches=20, max_events=1_000_000, stack_cap=64,
-        importance=None, ww=None, collision_tally=False,
+        importance=None, ww=None, collision_tally=False, population_control=None,
     )
 
 
