@@ -222,6 +222,33 @@ def main():
         out["with_collision_estimator"] = {"histories_per_s": rate,
                                            "relative_to_track_length_only": rate / out["value"]}
         gc.close()
+    if not args.no_other_schedule:
+        # population control at census: the duct problem with 20 census steps
+        # under the event schedule, without and with splitting-roulette to one
+        # particle per source history at every census
+        rates = {}
+        for name, target in (("without", None), ("with_target_1", 1.0)):
+            pp = W.config2(n_census=20)
+            if target is not None:
+                pp["population_control"] = dict(target=target)
+            # population control holds one batch of histories resident
+            gq = mcdc.Problem(pp, mcdc.make_options(mcdc.SCHED_EVENT, event_chunk=N // 20))
+            gq.run(N, seed)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            gq.run(N, seed + 1)
+            torch.cuda.synchronize()
+            rates[name] = N / (time.perf_counter() - t0)
+            if target is not None:
+                c = gq.counters()
+                rates["pc_kills_per_history"] = c["pc_kills"] / (2 * N)
+                rates["pc_copies_per_history"] = c["pc_copies"] / (2 * N)
+            gq.close()
+        out["population_control_event_20_census"] = {
+            "histories_per_s_without": rates["without"],
+            "histories_per_s_with": rates["with_target_1"],
+            "pc_kills_per_history": rates["pc_kills_per_history"],
+            "pc_copies_per_history": rates["pc_copies_per_history"]}
     if not args.no_fom:
         out["fom"] = fom_comparison(mcdc, W)
     if not args.no_cpu_baseline:

@@ -84,6 +84,13 @@ typedef struct {
     int32_t col_tally;                 /* 1: also a collision-estimator tally on
                                           the mesh (w / Sigma_t per collision in
                                           the bin of the collision point)         */
+    int32_t pc_on;                     /* 1: population control at every
+                                          intermediate census (event schedule;
+                                          event_chunk >= histories per batch):
+                                          each batch's census bank is split /
+                                          rouletted to round(pc_target * batch
+                                          histories) particles of equal weight    */
+    double pc_target;                  /* census population per source history   */
     int32_t n_census;                  /* increasing census times, last = end     */
     const double *census;
     int32_t implicit_capture;          /* 0 analog; 1 implicit with weight cutoff */
@@ -128,6 +135,7 @@ typedef struct {
     uint64_t n_hist;
     int32_t status;                    /* sticky device error status             */
     uint64_t event_iterations;         /* event schedule: stage iterations launched */
+    uint64_t pc_kills, pc_copies;      /* population control: removed / added      */
 } mcdc_counters;
 
 typedef struct mcdc_problem *mcdc_handle;

@@ -60,6 +60,10 @@ int validate_desc(const mcdc_problem_desc *d) {
     if (d->n_batches < 1 || d->n_batches > 65535) return fail(MCDC_E_INVALID, "n_batches must lie in [1, 65535]");
     if (d->stack_cap < 0 || d->max_events < 1) return fail(MCDC_E_INVALID, "stack_cap/max_events");
     if (d->col_tally != 0 && d->col_tally != 1) return fail(MCDC_E_INVALID, "col_tally must be 0 or 1");
+    if (d->pc_on != 0 && d->pc_on != 1) return fail(MCDC_E_INVALID, "pc_on must be 0 or 1");
+    if (d->pc_on && !(d->pc_target > 0.0 && d->pc_target <= 64.0))
+        return fail(MCDC_E_INVALID, "pc_target must lie in (0, 64]");
+    if (d->pc_on && d->imp_on) return fail(MCDC_E_INVALID, "population control excludes the importance estimate");
     if (d->imp_on) {
         for (int a = 0; a < 4; ++a)
             if (d->imp_n[a] < 1) return fail(MCDC_E_INVALID, "imp_n must be >= 1");
@@ -209,6 +213,8 @@ void build_dev_problem(const mcdc_problem_desc *d, char *ws, const Layout &L, De
     }
     P.G_t = d->mesh_per_group ? d->G : 1;
     P.col_on = d->col_tally;
+    P.pc_on = d->pc_on;
+    P.pc_target = d->pc_target;
     P.implicit_capture = d->implicit_capture;
     P.w_cut = d->w_cut;
     P.w_surv = d->w_surv;
@@ -293,6 +299,8 @@ int mcdc_workspace_bytes(const mcdc_problem_desc *d, const mcdc_options *opt, si
     if (st) return st;
     Options o = resolve_options(opt);
     if ((st = check_options(o))) return st;
+    if (d->pc_on && o.schedule != MCDC_SCHED_EVENT)
+        return fail(MCDC_E_INVALID, "population control runs in the event schedule");
     if (!bytes) return fail(MCDC_E_INVALID, "null bytes");
     *bytes = make_layout(d, o).total;
     return MCDC_OK;
@@ -305,6 +313,8 @@ int mcdc_create_problem(const mcdc_problem_desc *d, const mcdc_options *opt, voi
     if (!out || !dev_ws) return fail(MCDC_E_INVALID, "null workspace or handle");
     Options o = resolve_options(opt);
     if ((st = check_options(o))) return st;
+    if (d->pc_on && o.schedule != MCDC_SCHED_EVENT)
+        return fail(MCDC_E_INVALID, "population control runs in the event schedule");
     Layout L = make_layout(d, o);
     if (bytes < L.total) return fail(MCDC_E_NOMEM, "workspace too small: need " + std::to_string(L.total));
     auto *h = new mcdc_problem();
@@ -463,12 +473,29 @@ int mcdc_run(mcdc_handle h, uint64_t n, uint64_t seed, void *stream) {
         // one pass over all histories of the run; each particle scores into
         // the slice of its history's batch; then every batch is closed out
         if (n == 0) return MCDC_OK;
-        A.h_begin = h0;
-        A.h_end = h0 + n;
         A.run_n = n;
         A.run_batches = B;
-        int st = event_run_range(h, A, s);
-        if (st) return st;
+        if (h->desc.pc_on) {
+            // population control synchronises the histories of one batch:
+            // each batch is one resident chunk, controlled on its own
+            if ((n + B - 1) / B > ev_resident_histories(h))
+                return fail(MCDC_E_INVALID, "population control needs event_chunk >= histories per batch");
+            for (uint64_t b = 0; b < B; ++b) {
+                const uint64_t lo = (b * n) / B, hi = ((b + 1) * n) / B;
+                if (hi == lo) continue;
+                A.h_begin = h0 + lo;
+                A.h_end = h0 + hi;
+                double m = floor(h->desc.pc_target * (double)(hi - lo) + 0.5);
+                A.pc_m = m < 1.0 ? 1.0 : m;
+                int st = event_run_range(h, A, s);
+                if (st) return st;
+            }
+        } else {
+            A.h_begin = h0;
+            A.h_end = h0 + n;
+            int st = event_run_range(h, A, s);
+            if (st) return st;
+        }
         for (uint64_t b = 0; b < B; ++b) {
             const uint64_t lo = (b * n) / B, hi = ((b + 1) * n) / B;
             if (hi == lo) continue;
@@ -555,6 +582,7 @@ void mcdc::fill_counters(const DevAcc &a, mcdc_counters *o) {
     o->splits = c[C_SPLIT]; o->rr_kills = c[C_RR_KILL]; o->rr_survivals = c[C_RR_SURVIVE];
     o->cutoff_kills = c[C_CUT_KILL]; o->cutoff_survivals = c[C_CUT_SURVIVE];
     o->detector_hits = c[C_DET_HIT]; o->particles = c[C_PARTICLE];
+    o->pc_kills = c[C_PC_KILL]; o->pc_copies = c[C_PC_COPY];
     o->w_source = a.wsum[W_SOURCE]; o->w_leak = a.wsum[W_LEAK]; o->w_absorb = a.wsum[W_ABSORB];
     o->w_time_end = a.wsum[W_TIME_END]; o->w_gain = a.wsum[W_GAIN]; o->w_loss = a.wsum[W_LOSS];
     o->path = a.wsum[W_PATH];

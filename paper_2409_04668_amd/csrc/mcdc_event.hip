@@ -1,47 +1,54 @@
-// Event-based schedule: particles live in an SoA bank in HBM and are moved
-// through the transport loop one event class at a time, each class a launch
-// over a compacted queue of bank indices:
-//   flight    (all live particles)  -> surface queue | collision queue |
-//                                        census queue | ended
-//   interact  (surface + collision queues, one launch) -> next active
-//             queue | ended; its last workgroup advances the queue roles
-// Queues are appended with one atomic per wavefront: __ballot of the
-// predicate, popcount for the wave's total, mbcnt for each lane's offset.
-// When the active queue drains, the census queue becomes the active queue
-// (the next census step); when both are empty the chunk of histories is done.
-// Queue roles live in device memory, so every launch of an iteration has fixed
-// arguments (graph-capturable); kernels with an empty input queue exit at once.
+// Event-based schedule: particles live in SoA banks in HBM and are moved
+// through the transport loop one event class at a time.  A stage reads its
+// input bank contiguously and copies every particle it keeps into the bank of
+// the next stage at a wave-reserved position, so reads and writes are
+// coalesced and no index queues are gathered through:
+//   flight    (active bank)      -> interaction bank (surface entries from the
+//                                   front, collision entries from the back) |
+//                                   census bank | ended
+//   interact  (interaction bank) -> next active bank (+ split daughters) |
+//                                   ended; its last workgroup advances the
+//                                   bank roles
+//   control   (census bank, only with population control at census)
+//                                -> next active bank
+// Positions come from one atomic per wavefront: __ballot of the predicate,
+// popcount for the wave's total, mbcnt for each lane's offset.  When the
+// active bank drains, the census bank becomes the active bank (the next census
+// step); when both are empty the chunk of histories is done.  Bank roles and
+// counts live in device memory, so every launch of an iteration has fixed
+// arguments; a kernel whose input is empty exits at once.
 #include "mcdc_runtime.hpp"
 #include "transport_stages.hpp"
 
 namespace mcdc {
 
-enum { Q_A = 0, Q_B = 1, Q_C = 2 };     // three physical active/census buffers
+// One bank: 9 FP64 fields (x y z ux uy uz t w dist) and 7 u32 fields
+// (g cell ci tag k seq slot), `cap` entries each.
+struct Bank {
+    double *d;
+    uint32_t *i;
+};
+
+enum { R_A = 0, R_B = 1, R_C = 2, R_X = 3 };   // three role banks, interaction bank
 
 struct EvCtl {
-    uint32_t n_act[3];                   // entries in the three active/census buffers
-    uint32_t n_surf, n_coll;
+    uint32_t n_act[3];                   // particles in the three role banks
+    uint32_t n_surf, n_coll;             // interaction bank: [0, n_surf), [cap - n_coll, cap)
     uint32_t cur, nxt, cen;              // roles: current active, next active, census
-    uint32_t bank_n;                     // bank entries in use
     uint32_t done;
-    uint32_t blocks_done;                // completion count of the interaction launch
-    uint32_t pad[5];
+    uint32_t blocks_done;                // last-workgroup hand-over within a launch
+    uint32_t pc_stage;                   // population control: 0 idle, 1 sum, 2 apply
+    unsigned long long pc_wq;            // census-bank weight in units of 2^-32
+    uint32_t pad[2];
 };
 
 struct EvBank {
-    double *d;                           // [9][cap]: x y z ux uy uz t w dist
-    uint32_t *i;                         // [7][cap]: g cell ci tag k seq slot
-    uint32_t *q;                         // [3][cap] active/census queues
-    uint32_t *qs, *qc;                   // [cap] surface, collision queues
+    Bank b[4];
     double *xh, *path;                   // [chunk] per-history
     uint32_t *events;                    // [chunk]
     EvCtl *ctl;
     uint32_t cap, chunk;
 };
-
-}  // namespace mcdc
-
-namespace mcdc {
 
 struct EventState {
     EvBank B;
@@ -49,42 +56,87 @@ struct EventState {
     int grid, block;
 };
 
-MCDC_DEV void bank_load(const EvBank &B, uint32_t j, Part &q, double &d, uint32_t &slot) {
-    const size_t c = B.cap;
-    q.x[0] = B.d[0 * c + j]; q.x[1] = B.d[1 * c + j]; q.x[2] = B.d[2 * c + j];
-    q.u[0] = B.d[3 * c + j]; q.u[1] = B.d[4 * c + j]; q.u[2] = B.d[5 * c + j];
-    q.t = B.d[6 * c + j]; q.w = B.d[7 * c + j]; d = B.d[8 * c + j];
-    q.g = (int32_t)B.i[0 * c + j]; q.cell = (int32_t)B.i[1 * c + j]; q.ci = (int32_t)B.i[2 * c + j];
-    q.tag = B.i[3 * c + j]; q.k = B.i[4 * c + j]; q.seq = B.i[5 * c + j]; slot = B.i[6 * c + j];
+MCDC_DEV void bank_load(const Bank &K, size_t c, uint32_t j, Part &q, double &d, uint32_t &slot) {
+    q.x[0] = K.d[0 * c + j]; q.x[1] = K.d[1 * c + j]; q.x[2] = K.d[2 * c + j];
+    q.u[0] = K.d[3 * c + j]; q.u[1] = K.d[4 * c + j]; q.u[2] = K.d[5 * c + j];
+    q.t = K.d[6 * c + j]; q.w = K.d[7 * c + j]; d = K.d[8 * c + j];
+    q.g = (int32_t)K.i[0 * c + j]; q.cell = (int32_t)K.i[1 * c + j]; q.ci = (int32_t)K.i[2 * c + j];
+    q.tag = K.i[3 * c + j]; q.k = K.i[4 * c + j]; q.seq = K.i[5 * c + j]; slot = K.i[6 * c + j];
     q.alive = true;
 }
 
-MCDC_DEV void bank_store(const EvBank &B, uint32_t j, const Part &q, double d, uint32_t slot) {
-    const size_t c = B.cap;
-    B.d[0 * c + j] = q.x[0]; B.d[1 * c + j] = q.x[1]; B.d[2 * c + j] = q.x[2];
-    B.d[3 * c + j] = q.u[0]; B.d[4 * c + j] = q.u[1]; B.d[5 * c + j] = q.u[2];
-    B.d[6 * c + j] = q.t; B.d[7 * c + j] = q.w; B.d[8 * c + j] = d;
-    B.i[0 * c + j] = (uint32_t)q.g; B.i[1 * c + j] = (uint32_t)q.cell; B.i[2 * c + j] = (uint32_t)q.ci;
-    B.i[3 * c + j] = q.tag; B.i[4 * c + j] = q.k; B.i[5 * c + j] = q.seq; B.i[6 * c + j] = slot;
+MCDC_DEV void bank_store(const Bank &K, size_t c, uint32_t j, const Part &q, double d, uint32_t slot) {
+    K.d[0 * c + j] = q.x[0]; K.d[1 * c + j] = q.x[1]; K.d[2 * c + j] = q.x[2];
+    K.d[3 * c + j] = q.u[0]; K.d[4 * c + j] = q.u[1]; K.d[5 * c + j] = q.u[2];
+    K.d[6 * c + j] = q.t; K.d[7 * c + j] = q.w; K.d[8 * c + j] = d;
+    K.i[0 * c + j] = (uint32_t)q.g; K.i[1 * c + j] = (uint32_t)q.cell; K.i[2 * c + j] = (uint32_t)q.ci;
+    K.i[3 * c + j] = q.tag; K.i[4 * c + j] = q.k; K.i[5 * c + j] = q.seq; K.i[6 * c + j] = slot;
 }
 
-// Wavefront-aggregated append: one atomic per wave on the queue tail.
-MCDC_DEV void wave_append(uint32_t *queue, uint32_t *count, uint32_t value, bool pred) {
+// Wavefront-aggregated reservation: the lanes with `pred` get consecutive
+// positions from one atomic per wave on *count; returns the lane's position.
+MCDC_DEV uint32_t wave_reserve(uint32_t *count, bool pred) {
     const uint64_t m = __ballot(pred);
-    if (m == 0) return;
+    if (m == 0) return 0;
     const int lane = (int)__lane_id();
     const int leader = __ffsll((long long)m) - 1;
     uint32_t base = 0;
     if (lane == leader) base = atomicAdd(count, (uint32_t)__popcll(m));
     base = __shfl(base, leader);
-    if (pred) {
-        const uint32_t off = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-        queue[base + off] = value;
+    return base + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                            __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Inclusive prefix sum over the 64 lanes of a wave (all lanes active).
+MCDC_DEV uint32_t wave_scan_incl(uint32_t x) {
+    const int lane = (int)__lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    return x;
+}
+
+// Copy a particle into bank K at a reserved position; past the capacity the
+// particle is dropped and the run reports a bank overflow.
+MCDC_DEV void bank_put(const RunArgs &A, const EvBank &B, const Bank &K, uint32_t pos, const Part &q,
+                       double d, uint32_t slot) {
+    if (pos >= B.cap) {
+        set_status(A, MCDC_E_BANK);
+        return;
+    }
+    bank_store(K, B.cap, pos, q, d, slot);
+}
+
+// Write the recorded copies of every lane of the wave into bank K: one atomic
+// per wave on *count, then each lane writes its nd copies (the parent state
+// with tag tag0 + i * golden, i = 1..nd, counter and sequence 0).
+MCDC_DEV void wave_write_copies(const RunArgs &A, const EvBank &B, const Bank &K, uint32_t *count,
+                                const Part &q, uint32_t slot, uint32_t nd, uint32_t tag0) {
+    const uint32_t incl = wave_scan_incl(nd);
+    const uint32_t total = __shfl(incl, 63);
+    if (total == 0) return;
+    uint32_t base = 0;
+    if (__lane_id() == 0) base = atomicAdd(count, total);
+    base = __shfl(base, 0);
+    const uint32_t off = incl - nd;
+    for (uint32_t i = 0; i < nd; ++i) {
+        const uint64_t j = (uint64_t)base + off + i;
+        if (j >= B.cap) {
+            set_status(A, MCDC_E_BANK);
+            break;
+        }
+        Part d = q;
+        d.tag = tag0 + (i + 1u) * 0x9E3779B9u;
+        d.k = 0;
+        d.seq = 0;
+        bank_store(K, B.cap, (uint32_t)j, d, 0.0, slot);
     }
 }
 
-// Per-history context of a banked particle.
+// Per-history context of a banked particle.  WW: 0 no weight windows,
+// 1 network at each check, 2 baked window map.
 template <int WW>
 struct EvCtx {
     static constexpr bool kWW = WW != 0;
@@ -102,24 +154,26 @@ struct EvCtx {
     }
     MCDC_DEV double *col_tally() const { return A.col + batch() * (uint64_t)P.nbins; }
     MCDC_DEV const float *mlp_params(const DevProblem &Pp) const { return Pp.ww_params; }
+    // several particles of one history can be in flight at once when they
+    // split (weight windows, population control): their sums are atomic
     MCDC_DEV bool count_flight() {
         uint32_t e;
-        if (WW) e = atomicAdd(&B.events[slot], 1u) + 1u;
+        if (WW || P.pc_on) e = atomicAdd(&B.events[slot], 1u) + 1u;
         else e = (B.events[slot] += 1u);
         return (int64_t)e <= P.max_events;
     }
     MCDC_DEV void add_score(double v) {
-        if (WW) unsafeAtomicAdd(&B.xh[slot], v);
+        if (WW || P.pc_on) unsafeAtomicAdd(&B.xh[slot], v);
         else B.xh[slot] += v;
     }
     MCDC_DEV void add_path(double v) {
         if (!A.xh_out) return;           // the per-history path is an output only
-        if (WW) unsafeAtomicAdd(&B.path[slot], v);
+        if (WW || P.pc_on) unsafeAtomicAdd(&B.path[slot], v);
         else B.path[slot] += v;
     }
     MCDC_DEV void imp_point(const DevProblem &, const Part &) {}
-    // daughters are only recorded here: the interaction kernel allocates
-    // bank entries and queue places for a whole wave at once
+    // split daughters are only recorded here: the interaction kernel writes
+    // them for a whole wave at once
     uint32_t split_n = 0, split_tag0 = 0;
     MCDC_DEV bool push_daughters(const Part &, uint32_t tag0, int n) {
         split_n = (uint32_t)n;
@@ -127,51 +181,6 @@ struct EvCtx {
         return true;
     }
 };
-
-// Inclusive prefix sum over the 64 lanes of a wave (all lanes active).
-MCDC_DEV uint32_t wave_scan_incl(uint32_t x) {
-    const int lane = (int)__lane_id();
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t y = __shfl_up(x, o);
-        if (lane >= o) x += y;
-    }
-    return x;
-}
-
-// Write the recorded daughters of every lane of the wave: one atomic per wave
-// on the bank size and one on the next active queue, then each lane writes
-// its n-1 daughters (the parent state with tag0 + i * golden, k = seq = 0)
-// at its offset.  Entries past the bank capacity are dropped with an error.
-MCDC_DEV void wave_write_daughters(const RunArgs &A, const EvBank &B, const Part &q, uint32_t slot,
-                                   uint32_t nd, uint32_t tag0) {
-    const uint32_t incl = wave_scan_incl(nd);
-    const uint32_t total = __shfl(incl, 63);
-    if (total == 0) return;
-    const int lane = (int)__lane_id();
-    const uint32_t nx = B.ctl->nxt;
-    uint32_t jb = 0, qb = 0;
-    if (lane == 0) {
-        jb = atomicAdd(&B.ctl->bank_n, total);
-        qb = atomicAdd(&B.ctl->n_act[nx], total);
-    }
-    jb = __shfl(jb, 0);
-    qb = __shfl(qb, 0);
-    const uint32_t off = incl - nd;
-    for (uint32_t i = 0; i < nd; ++i) {
-        const uint64_t j = (uint64_t)jb + off + i;
-        if (j >= B.cap) {
-            set_status(A, MCDC_E_BANK);
-            break;
-        }
-        Part d = q;
-        d.tag = tag0 + (i + 1u) * 0x9E3779B9u;
-        d.k = 0;
-        d.seq = 0;
-        bank_store(B, (uint32_t)j, d, 0.0, slot);
-        B.q[(size_t)nx * B.cap + qb + off + i] = (uint32_t)j;
-    }
-}
 
 template <bool WW>
 __global__ void __launch_bounds__(256) k_ev_source(DevProblem P, RunArgs A, EvBank B, uint32_t n) {
@@ -183,17 +192,17 @@ __global__ void __launch_bounds__(256) k_ev_source(DevProblem P, RunArgs A, EvBa
          s += gridDim.x * blockDim.x) {
         const bool valid = s < n;
         bool alive = false;
+        Part q;
         if (valid) {
             B.xh[s] = 0.0;
             B.path[s] = 0.0;
             B.events[s] = 0u;
             EvCtx<WW> C{P, A, B, s};
-            Part q;
             stage_source(P, A, S, C, q);
             alive = q.alive;
-            if (alive) bank_store(B, s, q, 0.0, s);
         }
-        wave_append(B.q + (size_t)cur * B.cap, &B.ctl->n_act[cur], s, valid && alive);
+        const uint32_t pos = wave_reserve(&B.ctl->n_act[cur], valid && alive);
+        if (valid && alive) bank_put(A, B, B.b[cur], pos, q, 0.0, s);
     }
     __syncthreads();
     shared_flush(S, A.acc);
@@ -205,31 +214,31 @@ __global__ void __launch_bounds__(256) k_ev_flight(DevProblem P, RunArgs A, EvBa
     shared_zero(S);
     __syncthreads();
     const uint32_t cur = B.ctl->cur, cen = B.ctl->cen;
-    const uint32_t n = B.ctl->n_act[cur];
-    const uint32_t *in = B.q + (size_t)cur * B.cap;
+    const uint32_t n = min(B.ctl->n_act[cur], B.cap);   // counts can pass cap on overflow
+    const Bank in = B.b[cur], X = B.b[R_X], CB = B.b[cen];
     uint32_t n_piece = 0, n_flight = 0;
     double path = 0.0;
     for (uint32_t j0 = blockIdx.x * blockDim.x; j0 < n; j0 += gridDim.x * blockDim.x) {
         const uint32_t jj = j0 + threadIdx.x;
         const bool valid = jj < n;
         int ev = -1;
-        uint32_t j = 0;
+        Part q;
+        double d = 0.0;
+        uint32_t slot = 0;
         if (valid) {
-            j = in[jj];
-            Part q;
-            double d;
-            uint32_t slot;
-            bank_load(B, j, q, d, slot);
+            bank_load(in, B.cap, jj, q, d, slot);
             EvCtx<WW> C{P, A, B, slot};
             GlobalTally tally{A.tally + C.batch() * (uint64_t)P.nbins};
             ev = stage_flight(P, A, S, tally, C, q, d, n_piece, path);
             if (ev >= 0) n_flight += 1;
-            if (q.alive) bank_store(B, j, q, d, slot);
-            else ev = -1;
+            if (!q.alive) ev = -1;
         }
-        wave_append(B.qs, &B.ctl->n_surf, j, ev == EV_SURFACE);
-        wave_append(B.qc, &B.ctl->n_coll, j, ev == EV_SCATTER);
-        wave_append(B.q + (size_t)cen * B.cap, &B.ctl->n_act[cen], j, ev == EV_CENSUS);
+        const uint32_t ps = wave_reserve(&B.ctl->n_surf, ev == EV_SURFACE);
+        const uint32_t pc = wave_reserve(&B.ctl->n_coll, ev == EV_SCATTER);
+        const uint32_t pn = wave_reserve(&B.ctl->n_act[cen], ev == EV_CENSUS);
+        if (ev == EV_SURFACE) bank_put(A, B, X, ps, q, d, slot);
+        else if (ev == EV_SCATTER) bank_put(A, B, X, B.cap - 1u - pc, q, d, slot);
+        else if (ev == EV_CENSUS) bank_put(A, B, CB, pn, q, d, slot);
     }
     atomicAdd(&S.cnt[C_FLIGHT], (unsigned long long)n_flight);
     atomicAdd(&S.cnt[C_PIECE], (unsigned long long)n_piece);
@@ -238,9 +247,11 @@ __global__ void __launch_bounds__(256) k_ev_flight(DevProblem P, RunArgs A, EvBa
     shared_flush(S, A.acc);
 }
 
-// Queue roles for the next iteration.  Reads the counters with atomics so
-// that the values other workgroups appended are seen.
-MCDC_DEV void ev_advance(EvCtl *c) {
+// Bank roles for the next iteration.  Reads the counts with atomics so that
+// what other workgroups reserved is seen.  With population control a census
+// switch first runs the control (the sum and apply launches of the same
+// iteration), which then rotates the roles.
+MCDC_DEV void ev_advance(EvCtl *c, bool pc) {
     const uint32_t cur = c->cur, nxt = c->nxt, cen = c->cen;
     const uint32_t n_nxt = atomicAdd(&c->n_act[nxt], 0u);
     const uint32_t n_cen = atomicAdd(&c->n_act[cen], 0u);
@@ -250,19 +261,40 @@ MCDC_DEV void ev_advance(EvCtl *c) {
     if (n_nxt > 0) {
         c->cur = nxt;
         c->nxt = cur;
-    } else if (n_cen > 0) {                  // next census step
-        c->cur = cen;
-        c->cen = nxt;
-        c->nxt = cur;
+    } else if (n_cen > 0) {
+        if (pc) {
+            c->pc_wq = 0ull;
+            c->pc_stage = 1;
+        } else {                         // next census step
+            c->cur = cen;
+            c->cen = nxt;
+            c->nxt = cur;
+        }
     } else {
         c->done = 1;
     }
 }
 
+// Is this workgroup the last of the launch to finish?  (after its last
+// global write; resets the count for the next launch)
+MCDC_DEV bool last_block(EvCtl *c, bool &s_last) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        s_last = atomicAdd(&c->blocks_done, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (s_last && threadIdx.x == 0) {
+        __threadfence();
+        c->blocks_done = 0;
+    }
+    return s_last;
+}
+
 // Surface and collision stages in one launch: entries [0, n_surf) of the
-// combined range come from the surface queue, the rest from the collision
-// queue.  The last workgroup to finish advances the queue roles.  WW: 0 none,
-// 1 network at each check, 2 baked window map.
+// combined range are the surface entries at the front of the interaction
+// bank, the rest the collision entries at its back.  WW: 0 none, 1 network
+// at each check, 2 baked window map.
 template <int WW>
 __global__ void __launch_bounds__(256) k_ev_interact(DevProblem P, RunArgs A, EvBank B) {
     __shared__ Shared S;
@@ -270,48 +302,137 @@ __global__ void __launch_bounds__(256) k_ev_interact(DevProblem P, RunArgs A, Ev
     shared_zero(S);
     __syncthreads();
     const uint32_t nxt = B.ctl->nxt;
-    const uint32_t ns = B.ctl->n_surf, nc = B.ctl->n_coll;
+    const uint32_t ns = min(B.ctl->n_surf, B.cap);
+    const uint32_t nc = min(B.ctl->n_coll, B.cap - ns);
     const uint32_t n = ns + nc;
+    const Bank X = B.b[R_X], out = B.b[nxt];
     for (uint32_t j0 = blockIdx.x * blockDim.x; j0 < n; j0 += gridDim.x * blockDim.x) {
         const uint32_t jj = j0 + threadIdx.x;
         const bool valid = jj < n;
         bool alive = false;
-        uint32_t j = 0;
-        uint32_t nd = 0, tag0 = 0, dslot = 0;     // recorded daughters of this lane
-        Part dq;
+        uint32_t nd = 0, tag0 = 0, slot = 0;
+        Part q;
+        double d = 0.0;
         if (valid) {
             const bool surf = jj < ns;
-            j = surf ? B.qs[jj] : B.qc[jj - ns];
-            Part q;
-            double d;
-            uint32_t slot;
-            bank_load(B, j, q, d, slot);
+            bank_load(X, B.cap, surf ? jj : B.cap - 1u - (jj - ns), q, d, slot);
             EvCtx<WW> C{P, A, B, slot};
             const bool due = surf ? stage_surface(P, A, S, C, q, d) : stage_collision(P, A, S, C, q, d);
             if (WW != 0 && due) ww_check(P, A, S, C, q);
             alive = q.alive;
-            if (alive) bank_store(B, j, q, d, slot);
             if (WW != 0 && C.split_n > 1) {
                 nd = C.split_n - 1;
                 tag0 = C.split_tag0;
-                dq = q;
-                dslot = slot;
             }
         }
-        if (WW != 0) wave_write_daughters(A, B, dq, dslot, nd, tag0);
-        wave_append(B.q + (size_t)nxt * B.cap, &B.ctl->n_act[nxt], j, valid && alive);
+        const uint32_t pos = wave_reserve(&B.ctl->n_act[nxt], alive);
+        if (alive) bank_put(A, B, out, pos, q, d, slot);
+        if (WW != 0) wave_write_copies(A, B, out, &B.ctl->n_act[nxt], q, slot, nd, tag0);
     }
     __syncthreads();
     shared_flush(S, A.acc);
-    if (threadIdx.x == 0) {
-        __threadfence();
-        s_last = atomicAdd(&B.ctl->blocks_done, 1u) == gridDim.x - 1;
+    if (last_block(B.ctl, s_last) && threadIdx.x == 0) ev_advance(B.ctl, P.pc_on != 0);
+}
+
+// Population control, step 1: the census bank's total weight, summed exactly
+// as integers floor(w * 2^32).
+__global__ void __launch_bounds__(256) k_ev_pc_sum(EvBank B) {
+    __shared__ unsigned long long s_sum;
+    __shared__ bool s_last;
+    if (B.ctl->pc_stage != 1) return;
+    if (threadIdx.x == 0) s_sum = 0ull;
+    __syncthreads();
+    const uint32_t cen = B.ctl->cen;
+    const uint32_t n = min(B.ctl->n_act[cen], B.cap);
+    const double *w = B.b[cen].d + 7 * (size_t)B.cap;
+    unsigned long long part = 0ull;
+    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x)
+        part += (unsigned long long)floor(w[j] * 4294967296.0);
+    if (part) atomicAdd(&s_sum, part);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_sum) atomicAdd(&B.ctl->pc_wq, s_sum);
+    if (last_block(B.ctl, s_last) && threadIdx.x == 0) B.ctl->pc_stage = 2;
+}
+
+// Population control, step 2: splitting-roulette of every census particle to
+// the target weight w_T = (sum * 2^-32) / M.  One draw xi from the particle's
+// stream: below w_T it survives iff xi * w_T < w, at weight w_T; otherwise it
+// becomes n = floor(w / w_T + xi) particles of weight w_T, the copies taking
+// stream tags from one further block.  Survivors and copies go to the next
+// active bank, which then becomes the active bank.
+__global__ void __launch_bounds__(256) k_ev_pc_apply(DevProblem P, RunArgs A, EvBank B) {
+    __shared__ Shared S;
+    __shared__ bool s_last;
+    if (B.ctl->pc_stage != 2) return;
+    shared_zero(S);
+    __syncthreads();
+    const uint32_t cen = B.ctl->cen, nxt = B.ctl->nxt;
+    const uint32_t n = min(B.ctl->n_act[cen], B.cap);
+    const double wt = ((double)B.ctl->pc_wq * 0x1p-32) / A.pc_m;
+    const bool on = wt > 0.0;              // a bank of negligible weight is left as it is
+    const Bank in = B.b[cen], out = B.b[nxt];
+    for (uint32_t j0 = blockIdx.x * blockDim.x; j0 < n; j0 += gridDim.x * blockDim.x) {
+        const uint32_t jj = j0 + threadIdx.x;
+        const bool valid = jj < n;
+        bool keep = false;
+        uint32_t nd = 0, tag0 = 0, slot = 0;
+        Part q;
+        double d = 0.0;
+        if (valid) {
+            bank_load(in, B.cap, jj, q, d, slot);
+            keep = true;
+            if (on) {
+                const uint64_t hist = A.h_begin + slot;
+                Rng r = make_rng(A.seed, hist, P.problem_id, q.tag, q.k);
+                const double xi = rng_uniform(r);
+                const double w = q.w;
+                if (w < wt) {
+                    q.k = r.k;
+                    if (xi * wt < w) {
+                        atomicAdd(&S.wsum[W_GAIN], wt - w);
+                        q.w = wt;
+                        trace_rec(A, hist, q, EV_PC_KEEP, 1.0);
+                    } else {
+                        atomicAdd(&S.wsum[W_LOSS], w);
+                        atomicAdd(&S.cnt[C_PC_KILL], 1ull);
+                        trace_rec(A, hist, q, EV_PC_KILL, 0.0);
+                        keep = false;
+                    }
+                } else {
+                    const double nf = floor(w / wt + xi);
+                    const double tot = nf * wt;
+                    if (tot > w) atomicAdd(&S.wsum[W_GAIN], tot - w);
+                    else atomicAdd(&S.wsum[W_LOSS], w - tot);
+                    const uint32_t nn = (uint32_t)nf;
+                    if (nn >= 2) {
+                        uint32_t blk[4];
+                        rng_block(r, blk);
+                        tag0 = blk[0];
+                        nd = nn - 1u;
+                        atomicAdd(&S.cnt[C_PC_COPY], (unsigned long long)nd);
+                        atomicAdd(&S.cnt[C_PARTICLE], (unsigned long long)nd);
+                    }
+                    q.k = r.k;
+                    q.w = wt;
+                    trace_rec(A, hist, q, EV_PC_KEEP, nf);
+                }
+            }
+        }
+        const uint32_t pos = wave_reserve(&B.ctl->n_act[nxt], keep);
+        if (keep) bank_put(A, B, out, pos, q, d, slot);
+        wave_write_copies(A, B, out, &B.ctl->n_act[nxt], q, slot, nd, tag0);
     }
     __syncthreads();
-    if (s_last && threadIdx.x == 0) {
-        __threadfence();
-        ev_advance(B.ctl);
-        B.ctl->blocks_done = 0;
+    shared_flush(S, A.acc);
+    if (last_block(B.ctl, s_last) && threadIdx.x == 0) {
+        EvCtl *c = B.ctl;
+        const uint32_t cur = c->cur;     // drained
+        c->n_act[cen] = 0;
+        c->cur = nxt;
+        c->nxt = cen;
+        c->cen = cur;
+        c->pc_stage = 0;
+        if (atomicAdd(&c->n_act[nxt], 0u) == 0u) c->done = 1;
     }
 }
 
@@ -339,16 +460,17 @@ __global__ void __launch_bounds__(256) k_ev_finish(RunArgs A, EvBank B, uint32_t
     }
 }
 
-__global__ void k_ev_reset(EvBank B, uint32_t n_hist) {
+__global__ void k_ev_reset(EvBank B) {
     EvCtl *c = B.ctl;
     for (int i = 0; i < 3; ++i) c->n_act[i] = 0;
     c->n_surf = c->n_coll = 0;
-    c->cur = Q_A;
-    c->nxt = Q_B;
-    c->cen = Q_C;
-    c->bank_n = n_hist;
+    c->cur = R_A;
+    c->nxt = R_B;
+    c->cen = R_C;
     c->done = 0;
     c->blocks_done = 0;
+    c->pc_stage = 0;
+    c->pc_wq = 0ull;
 }
 
 __global__ void k_ev_count_hist(DevAcc *acc, uint64_t n) { atomicAdd(&acc->cnt[C_HIST], (unsigned long long)n); }
@@ -362,22 +484,28 @@ static uint32_t ev_chunk(const mcdc_problem_desc *d, const Options &o) {
     return (uint32_t)c;
 }
 
+// Bank capacity: the live population, not the particles ever made (every
+// stage compacts): the resident histories, times 4 with weight windows, plus
+// room for the population-control target.
 static uint32_t ev_cap(const mcdc_problem_desc *d, const Options &o) {
     const uint64_t chunk = ev_chunk(d, o);
-    const uint64_t f = d->stack_cap > 0 ? 4 : 1;
+    uint64_t f = d->stack_cap > 0 ? 4 : 1;
+    if (d->pc_on) f += (uint64_t)ceil(d->pc_target) + 1;
     uint64_t cap = chunk * f;
     if (cap > 0xF0000000ull) cap = 0xF0000000ull;
     return (uint32_t)cap;
 }
 
+static size_t bank_bytes(size_t cap) { return al(9 * cap * sizeof(double)) + al(7 * cap * sizeof(uint32_t)); }
+
 size_t event_workspace_bytes(const mcdc_problem_desc *d, const Options &o) {
     if (o.schedule != MCDC_SCHED_EVENT) return 0;
     const size_t cap = ev_cap(d, o), chunk = ev_chunk(d, o);
-    size_t b = al(9 * cap * sizeof(double)) + al(7 * cap * sizeof(uint32_t)) +
-               al(3 * cap * sizeof(uint32_t)) + 2 * al(cap * sizeof(uint32_t)) +
-               2 * al(chunk * sizeof(double)) + al(chunk * sizeof(uint32_t)) + al(sizeof(EvCtl));
-    return b;
+    return 4 * bank_bytes(cap) + 2 * al(chunk * sizeof(double)) + al(chunk * sizeof(uint32_t)) +
+           al(sizeof(EvCtl));
 }
+
+uint64_t ev_resident_histories(const mcdc_problem *h) { return h->ev ? h->ev->B.chunk : 0; }
 
 int event_init(mcdc_problem *h) {
     if (h->desc.imp_on) return fail(MCDC_E_INVALID, "the importance estimate runs in the history schedule only");
@@ -387,11 +515,12 @@ int event_init(mcdc_problem *h) {
     EvBank &B = E->B;
     B.cap = (uint32_t)cap;
     B.chunk = (uint32_t)chunk;
-    B.d = (double *)p; p += al(9 * cap * sizeof(double));
-    B.i = (uint32_t *)p; p += al(7 * cap * sizeof(uint32_t));
-    B.q = (uint32_t *)p; p += al(3 * cap * sizeof(uint32_t));
-    B.qs = (uint32_t *)p; p += al(cap * sizeof(uint32_t));
-    B.qc = (uint32_t *)p; p += al(cap * sizeof(uint32_t));
+    for (int k = 0; k < 4; ++k) {
+        B.b[k].d = (double *)p;
+        p += al(9 * cap * sizeof(double));
+        B.b[k].i = (uint32_t *)p;
+        p += al(7 * cap * sizeof(uint32_t));
+    }
     B.xh = (double *)p; p += al(chunk * sizeof(double));
     B.path = (double *)p; p += al(chunk * sizeof(double));
     B.events = (uint32_t *)p; p += al(chunk * sizeof(uint32_t));
@@ -421,13 +550,14 @@ int event_run_range(mcdc_problem *h, const RunArgs &A0, hipStream_t s) {
     const DevProblem &P = h->P;
     const EvBank &B = E->B;
     const int grid = E->grid, block = E->block;
+    const bool pc = P.pc_on != 0;
     for (uint64_t c0 = A0.h_begin; c0 < A0.h_end; c0 += B.chunk) {
         const uint64_t c1 = c0 + B.chunk < A0.h_end ? c0 + B.chunk : A0.h_end;
         const uint32_t n = (uint32_t)(c1 - c0);
         RunArgs A = A0;
         A.h_begin = c0;
         A.h_end = c1;
-        hipLaunchKernelGGL(k_ev_reset, dim3(1), dim3(1), 0, s, B, n);
+        hipLaunchKernelGGL(k_ev_reset, dim3(1), dim3(1), 0, s, B);
         hipLaunchKernelGGL(k_ev_count_hist, dim3(1), dim3(1), 0, s, A.acc, (uint64_t)n);
         int sg = (int)((n + block - 1) / block);
         if (sg > grid) sg = grid;
@@ -445,6 +575,10 @@ int event_run_range(mcdc_problem *h, const RunArgs &A0, hipStream_t s) {
                 if (!ww) hipLaunchKernelGGL((k_ev_interact<0>), dim3(grid), dim3(block), 0, s, P, A, B);
                 else if (P.ww_map) hipLaunchKernelGGL((k_ev_interact<2>), dim3(grid), dim3(block), 0, s, P, A, B);
                 else hipLaunchKernelGGL((k_ev_interact<1>), dim3(grid), dim3(block), 0, s, P, A, B);
+                if (pc) {
+                    hipLaunchKernelGGL(k_ev_pc_sum, dim3(grid), dim3(block), 0, s, B);
+                    hipLaunchKernelGGL(k_ev_pc_apply, dim3(grid), dim3(block), 0, s, P, A, B);
+                }
             }
             hipError_t e = hipMemcpyAsync(E->host_done, &B.ctl->done, sizeof(uint32_t),
                                           hipMemcpyDeviceToHost, s);

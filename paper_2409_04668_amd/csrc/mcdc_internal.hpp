@@ -22,7 +22,7 @@ constexpr int kLdsTallyMaxBins = 7680;       // 60 KiB of FP64 LDS tile
 enum {
     C_HIST = 0, C_FLIGHT, C_PIECE, C_COLLISION, C_ABSORB, C_SURFACE, C_LEAK, C_CENSUS,
     C_TIME_END, C_SPLIT, C_RR_KILL, C_RR_SURVIVE, C_CUT_KILL, C_CUT_SURVIVE, C_DET_HIT,
-    C_PARTICLE, N_CNT
+    C_PARTICLE, C_PC_KILL, C_PC_COPY, N_CNT
 };
 enum { W_SOURCE = 0, W_LEAK, W_ABSORB, W_TIME_END, W_GAIN, W_LOSS, W_PATH, N_WSUM };
 
@@ -30,7 +30,7 @@ enum { W_SOURCE = 0, W_LEAK, W_ABSORB, W_TIME_END, W_GAIN, W_LOSS, W_PATH, N_WSU
 enum {
     EV_SOURCE = 0, EV_SCATTER = 1, EV_ABSORB = 2, EV_SURFACE = 3, EV_LEAK = 4, EV_CENSUS = 5,
     EV_TIME_END = 6, EV_SPLIT = 7, EV_RR_KILL = 8, EV_RR_SURVIVE = 9, EV_CUT_KILL = 10,
-    EV_CUT_SURVIVE = 11,
+    EV_CUT_SURVIVE = 11, EV_PC_KILL = 12, EV_PC_KEEP = 13,
 };
 
 struct DevAcc {
@@ -55,6 +55,8 @@ struct DevProblem {
     double mesh_lo[4], mesh_delta[4], mesh_idelta[4];
     int32_t mesh_n[4], mesh_bounded[3], G_t;
     int32_t col_on;                      // collision-estimator tally
+    int32_t pc_on;                       // population control at intermediate census
+    double pc_target;                    // census population per source history
     int32_t implicit_capture;
     double w_cut, w_surv;
     int32_t has_detector;
@@ -82,6 +84,7 @@ struct RunArgs {
     uint64_t h_begin, h_end, h_run0;
     uint64_t run_n;                      // histories of the whole run (event schedule)
     uint64_t run_batches;                // batches of the run (event schedule)
+    double pc_m;                         // population-control target size of this chunk
     double *tally;                       // current-batch accumulator [nbins]; event
                                          // schedule: [run_batches][nbins] slices
     double *col;                         // collision estimator, same layout as tally

@@ -61,6 +61,7 @@ void timing_end(mcdc_problem *h, hipStream_t s);
 size_t event_workspace_bytes(const mcdc_problem_desc *d, const Options &o);
 int event_init(mcdc_problem *h);
 int event_run_range(mcdc_problem *h, const RunArgs &A, hipStream_t s);
+uint64_t ev_resident_histories(const mcdc_problem *h);   // histories per resident chunk
 void event_destroy(mcdc_problem *h);
 
 // batched problems (mcdc_batch.hip)

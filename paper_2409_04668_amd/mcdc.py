@@ -51,7 +51,8 @@ class ProblemDesc(C.Structure):
         ("src_kind", C.c_int32), ("src_lo", D3), ("src_hi", D3), ("src_t0", C.c_double),
         ("src_t1", C.c_double), ("src_isotropic", C.c_int32), ("src_dir", D3),
         ("src_group", C.c_int32), ("mesh_lo", D4), ("mesh_hi", D4), ("mesh_n", I4),
-        ("mesh_per_group", C.c_int32), ("col_tally", C.c_int32),
+        ("mesh_per_group", C.c_int32), ("col_tally", C.c_int32), ("pc_on", C.c_int32),
+        ("pc_target", C.c_double),
         ("n_census", C.c_int32), ("census", PD),
         ("implicit_capture", C.c_int32), ("w_cut", C.c_double), ("w_surv", C.c_double),
         ("has_detector", C.c_int32), ("det_lo", D3), ("det_hi", D3), ("imp_on", C.c_int32),
@@ -80,7 +81,8 @@ class Counters(C.Structure):
                                            "w_gain", "w_loss", "path"]] +
                 [("leak", C.c_double * 6), ("det_sum", C.c_double), ("det_sumsq", C.c_double),
                  ("batches", C.c_int64), ("n_hist", C.c_uint64), ("status", C.c_int32),
-                 ("event_iterations", C.c_uint64)])
+                 ("event_iterations", C.c_uint64), ("pc_kills", C.c_uint64),
+                 ("pc_copies", C.c_uint64)])
 
     def as_dict(self):
         d = {n: getattr(self, n) for n, _ in self._fields_ if n != "leak"}
@@ -210,6 +212,9 @@ class _Desc:
         d.mesh_n = I4(*map(int, m["n"]))
         d.mesh_per_group = 1 if m["per_group"] else 0
         d.col_tally = 1 if prob.get("collision_tally") else 0
+        pc = prob.get("population_control")
+        d.pc_on = 1 if pc is not None else 0
+        d.pc_target = float(pc["target"]) if pc is not None else 0.0
         cen = arr(prob["census"], np.float64)
         d.n_census, d.census = cen.size, cen.ctypes.data_as(PD)
         d.implicit_capture = 1 if prob["implicit_capture"] else 0

@@ -9,7 +9,8 @@ INT_COUNTERS = [("hist", "histories"), ("flight", "flights"), ("piece", "pieces"
                 ("leak", "leaks"), ("census", "census_stops"), ("time_end", "time_ends"),
                 ("split", "splits"), ("rr_kill", "rr_kills"), ("rr_survive", "rr_survivals"),
                 ("cut_kill", "cutoff_kills"), ("cut_survive", "cutoff_survivals"),
-                ("det_hit", "detector_hits"), ("particle", "particles")]
+                ("det_hit", "detector_hits"), ("particle", "particles"),
+                ("pc_kill", "pc_kills"), ("pc_copy", "pc_copies")]
 W_COUNTERS = [("source", "w_source"), ("leak", "w_leak"), ("absorb", "w_absorb"),
               ("time_end", "w_time_end"), ("gain", "w_gain"), ("loss", "w_loss"),
               ("path", "path")]

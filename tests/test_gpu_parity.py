@@ -395,3 +395,97 @@ def test_collision_tally_agrees_with_track_length_on_gpu():
     z = np.abs(mt - mcol)[ok] / np.hypot(mt * rt, mcol * rc)[ok]
     assert np.mean(z < 3) > 0.95 and np.max(z) < 6
     gp.close()
+
+
+# ---------------------------------------------------------------------------
+# population control at census (event schedule)
+# ---------------------------------------------------------------------------
+
+def _pc_pair(p, n, seed, chunk=0, trace_cap=400000):
+    """Event-schedule run against the oracle: identical trajectories; the
+    per-history sums of a history whose particles were split are compared to
+    1e-12 (several particles add into them in another order)."""
+    from gpu_util import assert_counters, assert_traces_equal
+    gp, orc, tg, to, hg, ho = run_pair(p, n, seed, trace_cap=trace_cap, options=_ev(chunk))
+    assert_traces_equal(tg[0], to[0])
+    np.testing.assert_allclose(hg[0], ho[0], rtol=1e-12, atol=1e-300)
+    s, s2 = gp.raw()
+    assert_close_sums(s, orc.tally_sum, what="tally_sum")
+    assert_close_sums(s2, orc.tally_sumsq, what="tally_sumsq")
+    assert_counters(gp.counters(), orc)
+    return gp, orc
+
+
+def _void_pulse(target):
+    p = W._base(1)
+    p["outer_lo"] = np.full(3, -50.0)
+    p["outer_hi"] = np.full(3, 50.0)
+    p["sigma_t"] = np.array([[0.0]])
+    p["sigma_s"] = np.array([[[0.0]]])
+    p["mesh"] = dict(lo=np.array([-50.0, -50.0, -50.0, 0.0]), hi=np.array([50.0, 50.0, 50.0, 10.0]),
+                     n=np.array([2, 1, 1, 5], np.int32), per_group=False)
+    p["census"] = np.array([5.0, 10.0])
+    p["n_batches"] = 2
+    p["population_control"] = dict(target=target)
+    return p
+
+
+@pytest.mark.parametrize("target", [2.0, 0.3])
+def test_population_control_parity_void(target):
+    gp, orc = _pc_pair(_void_pulse(target), 1000, 141)
+    c = orc.counters
+    assert c["pc_copy"] > 0 if target > 1 else c["pc_kill"] > 0
+
+
+def test_population_control_parity_infinite_medium():
+    p = W.infinite_medium(1.0, [[0.9]], [1.0], half=5.0, t_end=8.0, nt=8)
+    p["census"] = np.linspace(1.0, 8.0, 8)
+    p["population_control"] = dict(target=1.5)
+    p["n_batches"] = 4
+    gp, orc = _pc_pair(p, 2000, 142)
+    # analog weights stay 1 and the census population falls below the target,
+    # so the control only splits
+    assert orc.counters["pc_copy"] > 100
+
+
+def test_population_control_parity_duct_with_weight_window_map():
+    p = W.config2(n_census=4)
+    p["mesh"]["n"] = np.array([6, 10, 6, 4], np.int32)
+    p["ww"] = dict(params=ramp_mlp(-1.5, noise_seed=5), hidden=64, logk=0.3, ratio=5.0, n_max=10,
+                   map=(12, 20, 12, 10))
+    p["stack_cap"] = 256
+    p["population_control"] = dict(target=0.7)
+    gp, orc = _pc_pair(p, 1500, 143)
+    assert orc.counters["pc_kill"] > 0 and orc.counters["split"] > 0
+
+
+def test_population_control_rejections():
+    mc = _mcdc()
+    p = _void_pulse(1.0)
+    with pytest.raises(mc.McdcError):
+        mc.Problem(p, mc.make_options(mc.SCHED_HISTORY))
+    gp = mc.Problem(p, _ev(100))                # batches of 500 histories do not fit
+    with pytest.raises(mc.McdcError):
+        gp.run(1000, 1)
+    gp.close()
+
+
+def test_population_control_unbiased_at_scale():
+    """2e6 histories, eight census steps, target 0.5 per history: mesh tally
+    of the controlled run agrees with the uncontrolled one."""
+    mc = _mcdc()
+    p = W.infinite_medium(1.0, [[0.8]], [1.0], half=20.0, t_end=8.0, nt=8)
+    p["census"] = np.linspace(1.0, 8.0, 8)
+    q = dict(p, population_control=dict(target=0.5))
+    n = 2_000_000
+    out = []
+    for prob, seed in ((p, 151), (q, 152)):
+        gp = mc.Problem(prob, _ev(1 << 20))
+        gp.run(n, seed)
+        out.append(gp.tallies(mc.TALLY_MESH))
+        c = gp.counters()
+        gp.close()
+    (ma, ra), (mp, rp) = out
+    z = np.abs(ma - mp) / np.hypot(ma * ra, mp * rp)
+    assert np.all(z < 4.5), z
+    assert c["pc_kills"] > 0
