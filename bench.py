@@ -90,7 +90,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(histories shard by id range across GPUs; see the design notes)", file=sys.stderr)
+              "(histories would shard by history-id range across GPUs, with one sum of the "
+              "batch tallies)", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -21,8 +21,8 @@
  *  - hash-based (counter-based) random numbers for replicable testing: Sec.
  *    "Monte Carlo Neutron Transport and MC/DC", list of novel developments.
  * Everything else (RNG algorithm, sampling formulas, estimator, tie rules,
- * weight windows) is a reading recorded in the design notes and restated in
- * the comments below.
+ * weight windows, population control) is a reading of this implementation,
+ * stated in the comments below.
  */
 #include "oracle.h"
 
