@@ -77,7 +77,7 @@ def main():
     ap.add_argument("--histories", type=int, default=100_000_000)
     ap.add_argument("--schedule", choices=["history", "event"], default="history")
     ap.add_argument("--waves-per-cu", type=int, default=0)
-    ap.add_argument("--cpu-sample", type=int, default=8_000_000)
+    ap.add_argument("--cpu-sample", type=int, default=20_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fom", action="store_true",
                     help="skip the analog vs learned-weight-window FOM comparison")
@@ -289,24 +289,37 @@ def fom_comparison(mcdc, W, target=0.01):
     """FOM = 1/(R^2 T) at `target` detector relative error on the duct
     problem: analog (history schedule) vs learned weight windows (importance
     from 20 x 1e6 analog histories, network trained on the GPU, baked onto a
-    2 cm x 10 s window map; event schedule, since a history's split chain runs
-    serially on one lane in the history schedule).  Each side: a pilot run
-    sets N for the target error, then N histories are timed.  Training and
-    baking are setup, reported beside it."""
+    2 cm x 10 s window map; schedule picked by the autotuner, which finds the
+    event schedule several times faster here because a history's split chain
+    runs serially on one lane in the history schedule).  Each side: a pilot
+    run sets N for the target error, then N histories are timed.  Training,
+    baking and tuning are setup, reported beside it."""
     from paper_2409_04668_amd import learned_ww as L
     p = W.config2()
     t0 = time.perf_counter()
     ww, info = L.build_ww(p, n_runs=20, n_per_run=1_000_000, map_dims=WW_MAP_DIMS)
     t_build = time.perf_counter() - t0
     pw = W.config4(ww)
+    # the autotuner picks the schedule for the weight-window problem from a
+    # short pilot; resident histories for the event schedule then follow the
+    # run length (up to 2^23)
+    from paper_2409_04668_amd import autotune
+    choice = autotune.tune_single(pw, pilot=1_000_000, waves=(16,), event_chunks=(1 << 20,),
+                                  use_cache=False)
+    wopt = dict(choice["options"])
+    if wopt["schedule"] == mcdc.SCHED_EVENT:
+        wopt["event_chunk"] = 1 << 23
     analog = L.fom_at_target(p, seed=31, target=target, pilot=20_000_000)
     learned = L.fom_at_target(pw, seed=41, target=target, pilot=4_000_000,
-                              options=mcdc.make_options(mcdc.SCHED_EVENT, event_chunk=1 << 23))
+                              options=mcdc.make_options(**wopt))
     z = abs(analog["mean"] - learned["mean"]) / (
         (analog["mean"] * analog["rel_err"]) ** 2 + (learned["mean"] * learned["rel_err"]) ** 2) ** 0.5
     return {"target_rel_err": target, "ratio": learned["fom"] / analog["fom"],
             "analog": dict(analog, schedule="history"),
-            "learned_ww": dict(learned, schedule="event", window_map=list(WW_MAP_DIMS)),
+            "learned_ww": dict(learned, window_map=list(WW_MAP_DIMS),
+                               schedule="event" if wopt["schedule"] == mcdc.SCHED_EVENT
+                               else "history", options=wopt,
+                               autotune_trials=choice["trials"]),
             "agreement_sigma": z, "training": dict(info, total_seconds=t_build),
             "fom_with_training_amortised": 1.0 / (learned["rel_err"] ** 2 *
                                                   (learned["seconds"] + t_build))}

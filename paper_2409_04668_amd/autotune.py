@@ -77,21 +77,31 @@ def _time_single(prob, opt, n, seed) -> float:
     return n / dt
 
 
-def tune_single(prob, pilot=2_000_000, waves=(8, 12, 16, 24, 32), event_chunks=(1 << 20, 1 << 22),
-                cache_path=DEFAULT_CACHE, use_cache=True, seed=12345):
-    """Returns {"options": dict for mcdc.make_options, "histories_per_s": ..., "trials": [...]}."""
+def tune_single(prob, pilot=2_000_000, waves=(8, 12, 16, 24, 32),
+                event_chunks=(1 << 20, 1 << 22, 1 << 23), cache_path=DEFAULT_CACHE,
+                use_cache=True, seed=12345):
+    """Returns {"options": dict for mcdc.make_options, "histories_per_s": ..., "trials": [...]}.
+    Population control runs only in the event schedule, with every batch of
+    the pilot resident (chunks below the batch size are skipped)."""
     key = "single:" + _device_name() + ":" + _hash_problem(prob) + f":{pilot}"
     cache = _load(cache_path) if use_cache else {}
     if key in cache:
         return cache[key]
     trials = []
-    for w in waves:
-        o = dict(schedule=mcdc.SCHED_HISTORY, waves_per_cu=w)
-        trials.append((o, _time_single(prob, mcdc.make_options(**o), pilot, seed)))
+    pc = prob.get("population_control") is not None
+    if not pc:
+        for w in waves:
+            o = dict(schedule=mcdc.SCHED_HISTORY, waves_per_cu=w)
+            trials.append((o, _time_single(prob, mcdc.make_options(**o), pilot, seed)))
     if prob.get("importance") is None:
+        batch = -(-pilot // int(prob["n_batches"]))
         for ch in event_chunks:
+            if pc and ch < batch:
+                continue
             o = dict(schedule=mcdc.SCHED_EVENT, event_chunk=ch)
             trials.append((o, _time_single(prob, mcdc.make_options(**o), pilot, seed)))
+    if not trials:
+        raise ValueError("no schedule can run this problem at this pilot size")
     best = max(trials, key=lambda t: t[1])
     res = {"options": best[0], "histories_per_s": best[1],
            "trials": [{"options": o, "histories_per_s": r} for o, r in trials]}

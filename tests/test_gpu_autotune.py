@@ -1,0 +1,68 @@
+"""GPU tests of the autotuner: the schedule it picks runs the problem to the
+same per-history results as any other schedule, population control is only
+tried in the event schedule, and the batched tuner returns a working shape."""
+import numpy as np
+import pytest
+
+from oracle import mlp as M
+from paper_2409_04668_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _ramp(slope):
+    prm = np.zeros(M.n_params(5, 64), np.float32)
+    prm[0] = 1.0                            # W1[0][0]
+    prm[64 * 5] = 1.0                       # b1[0]
+    prm[64 * 5 + 64] = 1.0                  # W2[0][0]
+    prm[64 * 5 + 64 + 64 * 64 + 64] = slope  # W3[0]
+    prm[-1] = -slope                        # b3
+    return prm
+
+
+def test_tuned_schedule_gives_the_same_histories():
+    from paper_2409_04668_amd import autotune, mcdc
+    p = W.config2()
+    p["mesh"]["n"] = np.array([6, 10, 6, 4], np.int32)
+    p["ww"] = dict(params=_ramp(-1.5), hidden=64, logk=0.3, ratio=5.0, n_max=10,
+                   map=(12, 20, 12, 10))
+    p["stack_cap"] = 256
+    res = autotune.tune_single(p, pilot=200_000, waves=(8, 16), event_chunks=(1 << 18,),
+                               use_cache=False)
+    assert len(res["trials"]) == 3 and res["histories_per_s"] > 0
+    n = 20_000
+    out = []
+    for opt in (mcdc.make_options(**res["options"]), mcdc.make_options(mcdc.SCHED_HISTORY)):
+        gp = mcdc.Problem(p, opt)
+        gp.set_history_scores(n)
+        gp.run(n, 5)
+        out.append((gp.history_scores(), gp.counters()))
+        gp.close()
+    np.testing.assert_allclose(out[0][0], out[1][0], rtol=1e-12, atol=1e-300)
+    for k in ("flights", "pieces", "splits", "rr_kills", "particles"):
+        assert out[0][1][k] == out[1][1][k], k
+
+
+def test_population_control_is_tuned_in_the_event_schedule_only():
+    from paper_2409_04668_amd import autotune, mcdc
+    p = W.infinite_medium(1.0, [[0.8]], [1.0], half=20.0, t_end=8.0, nt=8)
+    p["census"] = np.linspace(1.0, 8.0, 8)
+    p["population_control"] = dict(target=1.0)
+    res = autotune.tune_single(p, pilot=100_000, event_chunks=(1 << 12, 1 << 16),
+                               use_cache=False)
+    # batches of 5000 histories: the 4096 chunk cannot hold one
+    assert [t["options"]["event_chunk"] for t in res["trials"]] == [1 << 16]
+    assert res["options"]["schedule"] == mcdc.SCHED_EVENT
+
+
+def test_batch_tuner_returns_a_working_shape():
+    from paper_2409_04668_amd import autotune, mcdc
+    probs, n_hist = W.config5()
+    probs, n_hist = probs[:12], np.minimum(n_hist[:12], 20_000)
+    res = autotune.tune_batch(probs, n_hist, chunks=(512, 4096), waves=(8,), use_cache=False)
+    assert len(res["trials"]) == 2 and res["histories_per_s"] > 0
+    bp = mcdc.BatchProblem(probs, n_hist, mcdc.make_options(**res["options"]))
+    bp.run(3)
+    for i in range(len(probs)):
+        assert bp.counters(i)["histories"] == n_hist[i]
+    bp.close()
