@@ -204,7 +204,7 @@ def source_log_k(prob: dict, params, ymin, ymax, n=10000, seed=3):
 
 
 def build_ww(prob: dict, n_runs=20, n_per_run=1_000_000, seed0=W.ROOT_SEED + 1, steps=3000,
-             lr=3e-3, ratio=5.0, n_max=10, method="auto", map_dims=None):
+             lr=3e-3, ratio=5.0, n_max=10, method="auto", map_dims=None, grid=None):
     """Whole pipeline; returns (ww dict for the problem, info dict).  With
     ``map_dims`` = (nx, ny, nz, nt) the transport reads w_T from the network
     baked onto that cell-centre map instead of evaluating it at every check."""
@@ -212,9 +212,9 @@ def build_ww(prob: dict, n_runs=20, n_per_run=1_000_000, seed0=W.ROOT_SEED + 1, 
     if method == "auto":
         method = "reciprocal" if G == 1 and prob.get("detector") is not None else "forward"
     if method == "reciprocal":
-        I, t_imp, n4 = reciprocal_importance(prob, n_runs, n_per_run, seed0)
+        I, t_imp, n4 = reciprocal_importance(prob, n_runs, n_per_run, seed0, grid=grid)
     else:
-        I, t_imp, n4 = forward_importance(prob, n_runs, n_per_run, seed0)
+        I, t_imp, n4 = forward_importance(prob, n_runs, n_per_run, seed0, grid=grid)
     X, y, wt = training_set(I, n4, G)
     params, losses, t_train = gpu_train(X, y, wt, steps=steps, lr=lr)
     ymin, ymax = float(y.min()), float(y.max())
