@@ -260,13 +260,16 @@ def test_invalid_desc_rejected():
 
 
 def test_full_size_duct_sampled_histories():
-    """Config-2 at full size (1e8 histories, bench launch configuration):
-    sampled histories recomputed one by one by the oracle match bit for bit;
-    all track length is scored (conservation) and weight balances."""
+    """Config-2 at full size (1e8 histories, bench launch configuration: the
+    history schedule with the LDS hot tile the autotuner places): sampled
+    histories recomputed one by one by the oracle match bit for bit; all
+    track length is scored (conservation) and weight balances."""
+    from paper_2409_04668_amd import autotune
     mc = _mcdc()
     n = 100_000_000
     p = W.config2()
-    gp = mc.Problem(p)
+    tile, _ = autotune.plan_hot_tile(p, pilot=1_000_000)
+    gp = mc.Problem(p, mc.make_options(mc.SCHED_HISTORY, tile=tile))
     gp.set_history_scores(n)
     gp.run(n, seed=2026)
     hs = gp.history_scores()
@@ -285,6 +288,38 @@ def test_full_size_duct_sampled_histories():
     assert abs(s.sum() - c["path"]) <= 1e-9 * c["path"]
     assert c["w_source"] == c["w_leak"] + c["w_absorb"] + c["w_time_end"]
     assert c["leaks"] + c["absorptions"] + c["time_ends"] == n
+
+
+@pytest.mark.slow
+def test_full_size_learned_ww_event_sampled_histories():
+    """The learned weight-window configuration as the FOM comparison runs it
+    (trained network baked onto the 2 cm x 10 s map, event schedule with 2^23
+    resident histories) at 4e7 histories: blocks of histories recomputed by
+    the oracle agree per history (several particles add into a history's sums
+    in another order: 1e-12); weight balances over the whole run."""
+    from paper_2409_04668_amd import learned_ww as L
+    mc = _mcdc()
+    p = W.config2()
+    ww, _ = L.build_ww(p, n_runs=4, n_per_run=1_000_000, steps=600, map_dims=(30, 50, 30, 20))
+    pw = W.config4(ww)
+    n = 40_000_000
+    gp = mc.Problem(pw, mc.make_options(mc.SCHED_EVENT, event_chunk=1 << 23))
+    gp.set_history_scores(n)
+    gp.run(n, seed=2027)
+    hs = gp.history_scores()
+    c = gp.counters()
+    gp.close()
+    hit = int(np.nonzero(hs[:, 0] > 0)[0][0])
+    q = dict(pw)
+    q["n_batches"] = 1
+    for first in (0, hit, n - 40):
+        r = O.OracleRun(q)
+        _, ho = r.run(40, 2027, per_history=True, first_id=first)
+        np.testing.assert_allclose(hs[first:first + 40], ho, rtol=1e-12, atol=1e-300)
+    assert c["histories"] == n and c["splits"] > 0
+    lhs = c["w_source"] + c["w_gain"] - c["w_loss"]
+    rhs = c["w_leak"] + c["w_absorb"] + c["w_time_end"]
+    assert abs(lhs - rhs) <= 1e-9 * c["w_source"]
 
 
 # ---------------------------------------------------------------------------
