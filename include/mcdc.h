@@ -155,6 +155,31 @@ int mcdc_create_problem(const mcdc_problem_desc *d, const mcdc_options *opt, voi
  * feed the batch statistics.  Results accumulate across runs. */
 int mcdc_run(mcdc_handle h, uint64_t n_histories, uint64_t seed, void *stream);
 
+/* A run taken census step by census step (event schedule; all histories
+ * resident: n_histories <= event_chunk; with population control, n_batches
+ * must be 1).  mcdc_run_begin samples the sources and returns; each
+ * mcdc_run_step transports until the next census step begins, or to the end
+ * of the run (*done = 1, after which the results include the run, as after
+ * mcdc_run with the same arguments).  Between steps the whole state of the
+ * run lives in the caller-owned workspace and in the host record below, so a
+ * run is checkpointed by copying both, and resumed by copying them into a
+ * handle created from the same description and options (then
+ * mcdc_set_run_state) and stepping on.  The per-history outputs of
+ * mcdc_set_history_scores are written when the run ends.  Steps synchronise
+ * `stream`.  MCDC_E_STATE for a step without a run in progress. */
+typedef struct {
+    uint64_t magic;                    /* identifies the record layout           */
+    uint64_t workspace_bytes, bins;    /* of the handle that wrote it            */
+    uint64_t n_hist, batches, event_iterations;
+    uint64_t run_first, run_n, run_seed;
+    double pc_m;
+    int32_t in_run, steps;
+} mcdc_run_state;
+int mcdc_run_begin(mcdc_handle h, uint64_t n_histories, uint64_t seed, void *stream);
+int mcdc_run_step(mcdc_handle h, int32_t *done, void *stream);
+int mcdc_get_run_state(mcdc_handle h, mcdc_run_state *out);
+int mcdc_set_run_state(mcdc_handle h, const mcdc_run_state *in);
+
 /* Synchronise `stream` and copy results to the host: per-bin mean score per
  * source history divided by bin volume and time width (MCDC_TALLY_MESH,
  * n = bins; MCDC_TALLY_COLLISION the same from the collision estimator, for

@@ -439,6 +439,7 @@ static RunArgs base_args(mcdc_handle h, uint64_t seed) {
     A.imp_score = (double *)(h->ws + h->L.imp_score);
     A.imp_weight = (double *)(h->ws + h->L.imp_weight);
     A.xh_out = h->xh_out;
+    A.keep_path = h->xh_out != nullptr;
     A.trace = h->trace;
     A.trace_cap = h->trace_cap;
     A.trace_count = h->trace_count;
@@ -452,9 +453,34 @@ static RunArgs base_args(mcdc_handle h, uint64_t seed) {
     return A;
 }
 
+// Batch close-outs of an event-schedule run of n histories (per-batch slices).
+static int close_event_run(mcdc_handle h, uint64_t n, hipStream_t s) {
+    const uint64_t B = (uint64_t)h->desc.n_batches;
+    double *batch = (double *)(h->ws + h->L.tally_batch);
+    double *sum = (double *)(h->ws + h->L.tally_sum);
+    double *sumsq = (double *)(h->ws + h->L.tally_sumsq);
+    double *cbatch = (double *)(h->ws + h->L.col_batch);
+    double *csum = (double *)(h->ws + h->L.col_sum);
+    double *csumsq = (double *)(h->ws + h->L.col_sumsq);
+    for (uint64_t b = 0; b < B; ++b) {
+        const uint64_t lo = (b * n) / B, hi = ((b + 1) * n) / B;
+        if (hi == lo) continue;
+        hipError_t e = launch_closeout(batch + b * (uint64_t)h->nbins, sum, sumsq, h->nbins,
+                                       (double)(hi - lo), s);
+        if (e == hipSuccess && h->desc.col_tally)
+            e = launch_closeout(cbatch + b * (uint64_t)h->nbins, csum, csumsq, h->nbins,
+                                (double)(hi - lo), s);
+        if (e != hipSuccess) return hip_fail(e, "run launch");
+        h->batches += 1;
+    }
+    h->n_hist += n;
+    return MCDC_OK;
+}
+
 int mcdc_run(mcdc_handle h, uint64_t n, uint64_t seed, void *stream) {
     if (!h) return fail(MCDC_E_INVALID, "null handle");
     if (h->is_batch) return fail(MCDC_E_STATE, "batched handle: use mcdc_run_batch");
+    if (h->in_run) return fail(MCDC_E_STATE, "a census-stepped run is in progress");
     if (h->n_hist + n >= (1ull << 48)) return fail(MCDC_E_INVALID, "history ids exhausted (2^48)");
     hipStream_t s = (hipStream_t)stream;
     const uint64_t B = (uint64_t)h->desc.n_batches;
@@ -496,19 +522,7 @@ int mcdc_run(mcdc_handle h, uint64_t n, uint64_t seed, void *stream) {
             int st = event_run_range(h, A, s);
             if (st) return st;
         }
-        for (uint64_t b = 0; b < B; ++b) {
-            const uint64_t lo = (b * n) / B, hi = ((b + 1) * n) / B;
-            if (hi == lo) continue;
-            hipError_t e = launch_closeout(batch + b * (uint64_t)h->nbins, sum, sumsq, h->nbins,
-                                           (double)(hi - lo), s);
-            if (e == hipSuccess && col)
-                e = launch_closeout(cbatch + b * (uint64_t)h->nbins, csum, csumsq, h->nbins,
-                                    (double)(hi - lo), s);
-            if (e != hipSuccess) return hip_fail(e, "run launch");
-            h->batches += 1;
-        }
-        h->n_hist += n;
-        return MCDC_OK;
+        return close_event_run(h, n, s);
     }
     for (uint64_t b = 0; b < B; ++b) {
         const uint64_t lo = (b * n) / B, hi = ((b + 1) * n) / B;
@@ -525,6 +539,97 @@ int mcdc_run(mcdc_handle h, uint64_t n, uint64_t seed, void *stream) {
         h->batches += 1;
     }
     h->n_hist += n;
+    return MCDC_OK;
+}
+
+// ---- census-step control ----------------------------------------------------
+
+static const uint64_t kRunStateMagic = 0x6D636463'72756E31ull;   // "mcdcrun1"
+
+static RunArgs stepped_args(mcdc_handle h) {
+    RunArgs A = base_args(h, h->run_seed);
+    A.h_run0 = h->run_first;
+    A.h_begin = h->run_first;
+    A.h_end = h->run_first + h->run_n;
+    A.run_n = h->run_n;
+    A.run_batches = (uint64_t)h->desc.n_batches;
+    A.pc_m = h->run_pc_m;
+    A.keep_path = 1;                     // outputs may be asked for before the last step
+    return A;
+}
+
+int mcdc_run_begin(mcdc_handle h, uint64_t n, uint64_t seed, void *stream) {
+    if (!h) return fail(MCDC_E_INVALID, "null handle");
+    if (h->is_batch || h->opt.schedule != MCDC_SCHED_EVENT)
+        return fail(MCDC_E_STATE, "census-step control runs in the event schedule");
+    if (h->in_run) return fail(MCDC_E_STATE, "a census-stepped run is in progress");
+    if (n == 0) return fail(MCDC_E_INVALID, "empty run");
+    if (n > ev_resident_histories(h)) return fail(MCDC_E_INVALID, "census-step control needs n <= event_chunk");
+    if (h->desc.pc_on && h->desc.n_batches != 1)
+        return fail(MCDC_E_INVALID, "census-step control with population control needs n_batches = 1");
+    if (h->n_hist + n >= (1ull << 48)) return fail(MCDC_E_INVALID, "history ids exhausted (2^48)");
+    h->run_first = h->n_hist;
+    h->run_n = n;
+    h->run_seed = seed;
+    const double m = floor(h->desc.pc_target * (double)n + 0.5);
+    h->run_pc_m = m < 1.0 ? 1.0 : m;
+    h->run_steps = 0;
+    int st = event_begin(h, stepped_args(h), (hipStream_t)stream);
+    if (st) return st;
+    h->in_run = true;
+    return MCDC_OK;
+}
+
+int mcdc_run_step(mcdc_handle h, int32_t *done, void *stream) {
+    if (!h || !done) return fail(MCDC_E_INVALID, "null argument");
+    if (!h->in_run) return fail(MCDC_E_STATE, "no census-stepped run in progress");
+    hipStream_t s = (hipStream_t)stream;
+    bool fin = false;
+    int st = event_step(h, stepped_args(h), s, fin);
+    if (st) return st;
+    h->run_steps += 1;
+    *done = fin ? 1 : 0;
+    if (fin) {
+        h->in_run = false;
+        return close_event_run(h, h->run_n, s);
+    }
+    return MCDC_OK;
+}
+
+int mcdc_get_run_state(mcdc_handle h, mcdc_run_state *o) {
+    if (!h || !o) return fail(MCDC_E_INVALID, "null argument");
+    memset(o, 0, sizeof(*o));
+    o->magic = kRunStateMagic;
+    o->workspace_bytes = h->L.total;
+    o->bins = h->nbins;
+    o->n_hist = h->n_hist;
+    o->batches = (uint64_t)h->batches;
+    o->event_iterations = h->event_iterations;
+    o->run_first = h->run_first;
+    o->run_n = h->run_n;
+    o->run_seed = h->run_seed;
+    o->pc_m = h->run_pc_m;
+    o->in_run = h->in_run ? 1 : 0;
+    o->steps = h->run_steps;
+    return MCDC_OK;
+}
+
+int mcdc_set_run_state(mcdc_handle h, const mcdc_run_state *in) {
+    if (!h || !in) return fail(MCDC_E_INVALID, "null argument");
+    if (in->magic != kRunStateMagic) return fail(MCDC_E_INVALID, "not a run-state record");
+    if (in->workspace_bytes != h->L.total || in->bins != h->nbins)
+        return fail(MCDC_E_INVALID, "run state of a handle with another description or options");
+    if (in->in_run && (h->is_batch || h->opt.schedule != MCDC_SCHED_EVENT))
+        return fail(MCDC_E_STATE, "census-step control runs in the event schedule");
+    h->n_hist = in->n_hist;
+    h->batches = (int64_t)in->batches;
+    h->event_iterations = in->event_iterations;
+    h->run_first = in->run_first;
+    h->run_n = in->run_n;
+    h->run_seed = in->run_seed;
+    h->run_pc_m = in->pc_m;
+    h->in_run = in->in_run != 0;
+    h->run_steps = in->steps;
     return MCDC_OK;
 }
 
@@ -665,6 +770,7 @@ int mcdc_get_tallies(mcdc_handle h, int kind, double *mean, double *rel, size_t 
 
 int mcdc_reset_tallies(mcdc_handle h, void *stream) {
     if (!h) return fail(MCDC_E_INVALID, "null handle");
+    if (h->in_run) return fail(MCDC_E_STATE, "a census-stepped run is in progress");
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipStreamSynchronize(s);
     if (e == hipSuccess) e = hipMemset(h->ws + h->L.tally_batch, 0, h->L.ww_params - h->L.tally_batch);

@@ -36,11 +36,15 @@ struct EvCtl {
     uint32_t n_surf, n_coll;             // interaction bank: [0, n_surf), [cap - n_coll, cap)
     uint32_t cur, nxt, cen;              // roles: current active, next active, census
     uint32_t done;
+    uint32_t paused;                     // a census step began; launches are no-ops
+                                         // (read by the host together with `done`)
     uint32_t blocks_done;                // last-workgroup hand-over within a launch
     uint32_t pc_stage;                   // population control: 0 idle, 1 sum, 2 apply
     unsigned long long pc_wq;            // census-bank weight in units of 2^-32
-    uint32_t pad[2];
+    uint32_t pause_at_census;            // census-step control: stop at the next census step
 };
+static_assert(offsetof(EvCtl, paused) == offsetof(EvCtl, done) + sizeof(uint32_t),
+              "the host reads done and paused as one pair");
 
 struct EvBank {
     Bank b[4];
@@ -52,7 +56,7 @@ struct EvBank {
 
 struct EventState {
     EvBank B;
-    uint32_t *host_done;                 // pinned
+    uint32_t *host_done;                 // pinned: done, paused
     int grid, block;
 };
 
@@ -167,7 +171,7 @@ struct EvCtx {
         else B.xh[slot] += v;
     }
     MCDC_DEV void add_path(double v) {
-        if (!A.xh_out) return;           // the per-history path is an output only
+        if (!A.keep_path) return;        // the per-history path is an output only
         if (WW || P.pc_on) unsafeAtomicAdd(&B.path[slot], v);
         else B.path[slot] += v;
     }
@@ -211,6 +215,7 @@ __global__ void __launch_bounds__(256) k_ev_source(DevProblem P, RunArgs A, EvBa
 template <bool WW>
 __global__ void __launch_bounds__(256) k_ev_flight(DevProblem P, RunArgs A, EvBank B) {
     __shared__ Shared S;
+    if (B.ctl->paused) return;
     shared_zero(S);
     __syncthreads();
     const uint32_t cur = B.ctl->cur, cen = B.ctl->cen;
@@ -269,6 +274,7 @@ MCDC_DEV void ev_advance(EvCtl *c, bool pc) {
             c->cur = cen;
             c->cen = nxt;
             c->nxt = cur;
+            if (c->pause_at_census) c->paused = 1;
         }
     } else {
         c->done = 1;
@@ -299,6 +305,7 @@ template <int WW>
 __global__ void __launch_bounds__(256) k_ev_interact(DevProblem P, RunArgs A, EvBank B) {
     __shared__ Shared S;
     __shared__ bool s_last;
+    if (B.ctl->paused) return;
     shared_zero(S);
     __syncthreads();
     const uint32_t nxt = B.ctl->nxt;
@@ -433,6 +440,7 @@ __global__ void __launch_bounds__(256) k_ev_pc_apply(DevProblem P, RunArgs A, Ev
         c->cen = cur;
         c->pc_stage = 0;
         if (atomicAdd(&c->n_act[nxt], 0u) == 0u) c->done = 1;
+        else if (c->pause_at_census) c->paused = 1;
     }
 }
 
@@ -471,6 +479,13 @@ __global__ void k_ev_reset(EvBank B) {
     c->blocks_done = 0;
     c->pc_stage = 0;
     c->pc_wq = 0ull;
+    c->pause_at_census = 0;
+    c->paused = 0;
+}
+
+__global__ void k_ev_set_pause(EvBank B, uint32_t pause) {
+    B.ctl->pause_at_census = pause;
+    B.ctl->paused = 0;
 }
 
 __global__ void k_ev_count_hist(DevAcc *acc, uint64_t n) { atomicAdd(&acc->cnt[C_HIST], (unsigned long long)n); }
@@ -525,7 +540,7 @@ int event_init(mcdc_problem *h) {
     B.path = (double *)p; p += al(chunk * sizeof(double));
     B.events = (uint32_t *)p; p += al(chunk * sizeof(uint32_t));
     B.ctl = (EvCtl *)p;
-    hipError_t e = hipHostMalloc((void **)&E->host_done, sizeof(uint32_t), hipHostMallocDefault);
+    hipError_t e = hipHostMalloc((void **)&E->host_done, 2 * sizeof(uint32_t), hipHostMallocDefault);
     if (e != hipSuccess) {
         delete E;
         return hip_fail(e, "event_init");
@@ -543,14 +558,71 @@ void event_destroy(mcdc_problem *h) {
     h->ev = nullptr;
 }
 
+static void ev_launch_source(mcdc_problem *h, const RunArgs &A, hipStream_t s, uint32_t n) {
+    EventState *E = h->ev;
+    const EvBank &B = E->B;
+    int sg = (int)((n + E->block - 1) / E->block);
+    if (sg > E->grid) sg = E->grid;
+    hipLaunchKernelGGL(k_ev_count_hist, dim3(1), dim3(1), 0, s, A.acc, (uint64_t)n);
+    if (h->P.ww_on) hipLaunchKernelGGL((k_ev_source<true>), dim3(sg), dim3(E->block), 0, s, h->P, A, B, n);
+    else hipLaunchKernelGGL((k_ev_source<false>), dim3(sg), dim3(E->block), 0, s, h->P, A, B, n);
+}
+
+// Iterate the stages of the resident chunk until it ends (or, under
+// census-step control, a census step begins): K iterations per host check.
+static int ev_iterate(mcdc_problem *h, const RunArgs &A, hipStream_t s, bool &done) {
+    EventState *E = h->ev;
+    const DevProblem &P = h->P;
+    const EvBank &B = E->B;
+    const int grid = E->grid, block = E->block;
+    const bool ww = P.ww_on != 0, pc = P.pc_on != 0;
+    for (int iter = 0;; ++iter) {
+        const int K = 8;
+        h->event_iterations += K;
+        for (int k = 0; k < K; ++k) {
+            timing_begin(h, s);
+            if (ww) hipLaunchKernelGGL((k_ev_flight<true>), dim3(grid), dim3(block), 0, s, P, A, B);
+            else hipLaunchKernelGGL((k_ev_flight<false>), dim3(grid), dim3(block), 0, s, P, A, B);
+            timing_end(h, s);
+            if (!ww) hipLaunchKernelGGL((k_ev_interact<0>), dim3(grid), dim3(block), 0, s, P, A, B);
+            else if (P.ww_map) hipLaunchKernelGGL((k_ev_interact<2>), dim3(grid), dim3(block), 0, s, P, A, B);
+            else hipLaunchKernelGGL((k_ev_interact<1>), dim3(grid), dim3(block), 0, s, P, A, B);
+            if (pc) {
+                hipLaunchKernelGGL(k_ev_pc_sum, dim3(grid), dim3(block), 0, s, B);
+                hipLaunchKernelGGL(k_ev_pc_apply, dim3(grid), dim3(block), 0, s, P, A, B);
+            }
+        }
+        hipError_t e = hipMemcpyAsync(E->host_done, &B.ctl->done, 2 * sizeof(uint32_t),
+                                      hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "event loop");
+        if (E->host_done[0]) {
+            done = true;
+            return MCDC_OK;
+        }
+        if (E->host_done[1]) {
+            done = false;
+            return MCDC_OK;
+        }
+        if (iter > 1000000) return fail(MCDC_E_EVENT_CAP, "event loop did not drain");
+    }
+}
+
+static int ev_finish_chunk(mcdc_problem *h, const RunArgs &A, hipStream_t s, uint32_t n) {
+    EventState *E = h->ev;
+    const int fg = (int)((n + E->block - 1) / E->block) < E->grid ? (int)((n + E->block - 1) / E->block)
+                                                                : E->grid;
+    hipLaunchKernelGGL(k_ev_finish, dim3(fg), dim3(E->block), 0, s, A, E->B, n);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "event launch");
+    return MCDC_OK;
+}
+
 // Transport histories [A.h_begin, A.h_end) chunk by chunk.
 int event_run_range(mcdc_problem *h, const RunArgs &A0, hipStream_t s) {
     EventState *E = h->ev;
     if (!E) return fail(MCDC_E_STATE, "event schedule not initialised");
-    const DevProblem &P = h->P;
     const EvBank &B = E->B;
-    const int grid = E->grid, block = E->block;
-    const bool pc = P.pc_on != 0;
     for (uint64_t c0 = A0.h_begin; c0 < A0.h_end; c0 += B.chunk) {
         const uint64_t c1 = c0 + B.chunk < A0.h_end ? c0 + B.chunk : A0.h_end;
         const uint32_t n = (uint32_t)(c1 - c0);
@@ -558,40 +630,35 @@ int event_run_range(mcdc_problem *h, const RunArgs &A0, hipStream_t s) {
         A.h_begin = c0;
         A.h_end = c1;
         hipLaunchKernelGGL(k_ev_reset, dim3(1), dim3(1), 0, s, B);
-        hipLaunchKernelGGL(k_ev_count_hist, dim3(1), dim3(1), 0, s, A.acc, (uint64_t)n);
-        int sg = (int)((n + block - 1) / block);
-        if (sg > grid) sg = grid;
-        const bool ww = P.ww_on != 0;
-        if (ww) hipLaunchKernelGGL((k_ev_source<true>), dim3(sg), dim3(block), 0, s, P, A, B, n);
-        else hipLaunchKernelGGL((k_ev_source<false>), dim3(sg), dim3(block), 0, s, P, A, B, n);
-        for (int iter = 0;; ++iter) {
-            const int K = 8;
-            h->event_iterations += K;
-            for (int k = 0; k < K; ++k) {
-                timing_begin(h, s);
-                if (ww) hipLaunchKernelGGL((k_ev_flight<true>), dim3(grid), dim3(block), 0, s, P, A, B);
-                else hipLaunchKernelGGL((k_ev_flight<false>), dim3(grid), dim3(block), 0, s, P, A, B);
-                timing_end(h, s);
-                if (!ww) hipLaunchKernelGGL((k_ev_interact<0>), dim3(grid), dim3(block), 0, s, P, A, B);
-                else if (P.ww_map) hipLaunchKernelGGL((k_ev_interact<2>), dim3(grid), dim3(block), 0, s, P, A, B);
-                else hipLaunchKernelGGL((k_ev_interact<1>), dim3(grid), dim3(block), 0, s, P, A, B);
-                if (pc) {
-                    hipLaunchKernelGGL(k_ev_pc_sum, dim3(grid), dim3(block), 0, s, B);
-                    hipLaunchKernelGGL(k_ev_pc_apply, dim3(grid), dim3(block), 0, s, P, A, B);
-                }
-            }
-            hipError_t e = hipMemcpyAsync(E->host_done, &B.ctl->done, sizeof(uint32_t),
-                                          hipMemcpyDeviceToHost, s);
-            if (e == hipSuccess) e = hipStreamSynchronize(s);
-            if (e != hipSuccess) return hip_fail(e, "event loop");
-            if (*E->host_done) break;
-            if (iter > 1000000) return fail(MCDC_E_EVENT_CAP, "event loop did not drain");
-        }
-        const int fg = (int)((n + block - 1) / block) < grid ? (int)((n + block - 1) / block) : grid;
-        hipLaunchKernelGGL(k_ev_finish, dim3(fg), dim3(block), 0, s, A, B, n);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return hip_fail(e, "event launch");
+        ev_launch_source(h, A, s, n);
+        bool done = false;
+        int st = ev_iterate(h, A, s, done);
+        if (st) return st;
+        if ((st = ev_finish_chunk(h, A, s, n))) return st;
     }
+    return MCDC_OK;
+}
+
+// Census-step control: the run's histories form one resident chunk.
+int event_begin(mcdc_problem *h, const RunArgs &A, hipStream_t s) {
+    EventState *E = h->ev;
+    if (!E) return fail(MCDC_E_STATE, "event schedule not initialised");
+    const uint32_t n = (uint32_t)(A.h_end - A.h_begin);
+    hipLaunchKernelGGL(k_ev_reset, dim3(1), dim3(1), 0, s, E->B);
+    hipLaunchKernelGGL(k_ev_set_pause, dim3(1), dim3(1), 0, s, E->B, 1u);
+    ev_launch_source(h, A, s, n);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "run_begin");
+    return MCDC_OK;
+}
+
+int event_step(mcdc_problem *h, const RunArgs &A, hipStream_t s, bool &done) {
+    EventState *E = h->ev;
+    if (!E) return fail(MCDC_E_STATE, "event schedule not initialised");
+    hipLaunchKernelGGL(k_ev_set_pause, dim3(1), dim3(1), 0, s, E->B, 1u);
+    int st = ev_iterate(h, A, s, done);
+    if (st) return st;
+    if (done) return ev_finish_chunk(h, A, s, (uint32_t)(A.h_end - A.h_begin));
     return MCDC_OK;
 }
 

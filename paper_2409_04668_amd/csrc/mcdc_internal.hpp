@@ -91,6 +91,8 @@ struct RunArgs {
     DevAcc *acc;
     double *imp_score, *imp_weight;
     double *xh_out;
+    int32_t keep_path;                   // accumulate per-history path (an output only)
+    int32_t pad_keep;
     mcdc_trace_rec *trace;
     uint64_t trace_cap;
     unsigned long long *trace_count;

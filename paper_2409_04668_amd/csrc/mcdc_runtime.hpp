@@ -37,6 +37,11 @@ struct mcdc_problem {
     size_t nimp = 0;
     uint64_t n_hist = 0;
     uint64_t event_iterations = 0;
+    // a run taken census step by census step (event schedule)
+    bool in_run = false;
+    int32_t run_steps = 0;
+    uint64_t run_first = 0, run_n = 0, run_seed = 0;
+    double run_pc_m = 0.0;
     int64_t batches = 0;
     mcdc_trace_rec *trace = nullptr;
     uint64_t trace_cap = 0;
@@ -62,6 +67,9 @@ size_t event_workspace_bytes(const mcdc_problem_desc *d, const Options &o);
 int event_init(mcdc_problem *h);
 int event_run_range(mcdc_problem *h, const RunArgs &A, hipStream_t s);
 uint64_t ev_resident_histories(const mcdc_problem *h);   // histories per resident chunk
+// census-step control: begin (sources) and one step; `done` when the run ended
+int event_begin(mcdc_problem *h, const RunArgs &A, hipStream_t s);
+int event_step(mcdc_problem *h, const RunArgs &A, hipStream_t s, bool &done);
 void event_destroy(mcdc_problem *h);
 
 // batched problems (mcdc_batch.hip)

@@ -75,6 +75,13 @@ COUNTER_FIELDS = ["histories", "flights", "pieces", "collisions", "absorptions",
                   "cutoff_kills", "cutoff_survivals", "detector_hits", "particles"]
 
 
+class RunState(C.Structure):
+    _fields_ = [("magic", C.c_uint64), ("workspace_bytes", C.c_uint64), ("bins", C.c_uint64),
+                ("n_hist", C.c_uint64), ("batches", C.c_uint64), ("event_iterations", C.c_uint64),
+                ("run_first", C.c_uint64), ("run_n", C.c_uint64), ("run_seed", C.c_uint64),
+                ("pc_m", C.c_double), ("in_run", C.c_int32), ("steps", C.c_int32)]
+
+
 class Counters(C.Structure):
     _fields_ = ([(n, C.c_uint64) for n in COUNTER_FIELDS] +
                 [(n, C.c_double) for n in ["w_source", "w_leak", "w_absorb", "w_time_end",
@@ -112,6 +119,10 @@ _sig("mcdc_workspace_bytes", C.c_int, C.POINTER(ProblemDesc), C.POINTER(Options)
 _sig("mcdc_create_problem", C.c_int, C.POINTER(ProblemDesc), C.POINTER(Options), VP, C.c_size_t,
      C.POINTER(VP))
 _sig("mcdc_run", C.c_int, VP, C.c_uint64, C.c_uint64, VP)
+_sig("mcdc_run_begin", C.c_int, VP, C.c_uint64, C.c_uint64, VP)
+_sig("mcdc_run_step", C.c_int, VP, C.POINTER(C.c_int32), VP)
+_sig("mcdc_get_run_state", C.c_int, VP, VP)
+_sig("mcdc_set_run_state", C.c_int, VP, VP)
 _sig("mcdc_get_tallies", C.c_int, VP, C.c_int, PD, PD, C.c_size_t, VP)
 _sig("mcdc_get_raw", C.c_int, VP, PD, PD, C.c_size_t, VP)
 _sig("mcdc_get_raw_collision", C.c_int, VP, PD, PD, C.c_size_t, VP)
@@ -296,6 +307,24 @@ class Problem:
     # ---- running -------------------------------------------------------
     def run(self, n_hist: int, seed: int, stream=None):
         check(_lib.mcdc_run(self.h, int(n_hist), int(seed), _stream_ptr(stream)), "run")
+
+    # ---- census-step control (event schedule) --------------------------
+    def run_begin(self, n_hist: int, seed: int, stream=None):
+        check(_lib.mcdc_run_begin(self.h, int(n_hist), int(seed), _stream_ptr(stream)), "run_begin")
+
+    def run_step(self, stream=None) -> bool:
+        """Transport to the next census step; True when the run has ended."""
+        done = C.c_int32(0)
+        check(_lib.mcdc_run_step(self.h, C.byref(done), _stream_ptr(stream)), "run_step")
+        return bool(done.value)
+
+    def run_state(self) -> "RunState":
+        st = RunState()
+        check(_lib.mcdc_get_run_state(self.h, C.byref(st)), "get_run_state")
+        return st
+
+    def set_run_state(self, st: "RunState"):
+        check(_lib.mcdc_set_run_state(self.h, C.byref(st)), "set_run_state")
 
     def set_trace(self, cap: int):
         """Record every event of later runs (device buffer of ``cap`` records)."""

@@ -82,3 +82,8 @@ def test_failure_paths_without_gpu():
     # the weight-window map needs a handle
     dims = (ctypes.c_int32 * 4)(4, 4, 4, 4)
     assert mcdc._lib.mcdc_set_ww_map(None, dims, None, 0, None) == mcdc.E_INVALID
+    # census-step control needs a handle
+    done = ctypes.c_int32()
+    assert mcdc._lib.mcdc_run_step(None, ctypes.byref(done), None) == mcdc.E_INVALID
+    st = mcdc.RunState()
+    assert mcdc._lib.mcdc_get_run_state(None, ctypes.byref(st)) == mcdc.E_INVALID

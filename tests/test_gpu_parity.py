@@ -524,3 +524,135 @@ def test_population_control_unbiased_at_scale():
     z = np.abs(ma - mp) / np.hypot(ma * ra, mp * rp)
     assert np.all(z < 4.5), z
     assert c["pc_kills"] > 0
+
+
+# ---------------------------------------------------------------------------
+# edge cases: ragged and empty runs in the event schedule, maximum sizes
+# ---------------------------------------------------------------------------
+
+def test_ragged_and_empty_runs_event_schedule():
+    p = W.config1()
+    # fewer histories than batches, chunks of 4 histories, continuing ids
+    for n in (0, 1, 7):
+        full_parity(p, n, seed=113, trace_cap=1000, options=_ev(4))
+    full_parity(p, 333, seed=114, trace_cap=20000, options=_ev(100), runs=3)
+    # population control with batches of 3 and 4 histories
+    _pc_pair(_void_pulse(2.0), 7, 115, chunk=8)
+
+
+def test_largest_hot_tile_and_most_groups():
+    """The largest LDS tile (19456 bins) on the duct, and eight energy groups
+    (the most the library takes) with a per-group mesh."""
+    mc = _mcdc()
+    p = W.config2(n_census=2)
+    tile = ([0, 0, 0, 0, 0], [16, 19, 16, 4, 1])
+    assert int(np.prod(tile[1])) == mc.MAX_TILE_BINS
+    full_parity(p, 3000, seed=116, trace_cap=200000, options=mc.make_options(tile=tile))
+    q = W.config3()
+    G = 8
+    rng = np.random.default_rng(5)
+    st = rng.uniform(0.05, 0.5, size=(3, G))
+    ss = np.zeros((3, G, G))
+    for m in range(3):
+        for g in range(G):
+            wts = rng.uniform(0.0, 1.0, size=g + 1)
+            ss[m, g, :g + 1] = 0.7 * st[m, g] * wts / wts.sum()
+    q["sigma_t"], q["sigma_s"] = st, ss
+    q["speed"] = 10.0 ** (1.0 + np.arange(G) / 2.0)
+    q["source"]["group"] = G - 1
+    q["mesh"]["n"] = np.array([6, 10, 6, 4], np.int32)
+    full_parity(q, 300, seed=117, trace_cap=600000)
+    r = dict(q)
+    r["sigma_t"] = np.ones((3, G + 1))
+    r["sigma_s"] = np.zeros((3, G + 1, G + 1))
+    r["speed"] = np.ones(G + 1)
+    with pytest.raises(mc.McdcError):
+        mc.Problem(r)
+
+
+# ---------------------------------------------------------------------------
+# census-step control with checkpoint/resume (event schedule)
+# ---------------------------------------------------------------------------
+
+def _stepped_with_checkpoint(p, n, seed, opt, stop_after=2):
+    """Begin a run, take `stop_after` census steps, copy the workspace and the
+    run record into a fresh handle, and step that one to the end."""
+    mc = _mcdc()
+    ga = mc.Problem(p, opt)
+    ga.run_begin(n, seed)
+    for _ in range(stop_after):
+        assert not ga.run_step()
+    st = ga.run_state()
+    assert st.in_run == 1 and st.steps == stop_after
+    ws = ga.ws.clone()
+    ga.close()
+    gb = mc.Problem(p, opt)
+    assert gb.ws.numel() == ws.numel()
+    gb.ws.copy_(ws)
+    gb.set_run_state(st)
+    gb.set_history_scores(n)
+    steps = stop_after
+    while not gb.run_step():
+        steps += 1
+        assert steps < 100
+    return gb, steps + 1
+
+
+def test_census_steps_checkpoint_resume_matches_oracle():
+    p = W.config2(n_census=5)
+    p["mesh"]["n"] = np.array([12, 20, 12, 10], np.int32)
+    p["collision_tally"] = True
+    n, seed = 4000, 161
+    gb, steps = _stepped_with_checkpoint(p, n, seed, _ev(1 << 13))
+    assert 3 <= steps <= 6
+    orc = O.OracleRun(p)
+    _, ho = orc.run(n, seed, per_history=True)
+    assert np.array_equal(gb.history_scores(), ho)
+    s, s2 = gb.raw()
+    assert_close_sums(s, orc.tally_sum, what="tally_sum")
+    assert_close_sums(s2, orc.tally_sumsq, what="tally_sumsq")
+    c, c2 = gb.raw_collision()
+    assert_close_sums(c, orc.col_sum, what="col_sum")
+    from gpu_util import assert_counters
+    assert_counters(gb.counters(), orc)
+    gb.close()
+
+
+def test_census_steps_checkpoint_resume_with_population_control():
+    p = W.infinite_medium(1.0, [[0.9]], [1.0], half=5.0, t_end=8.0, nt=8)
+    p["census"] = np.linspace(1.0, 8.0, 8)
+    p["population_control"] = dict(target=1.5)
+    p["n_batches"] = 1
+    n, seed = 3000, 162
+    gb, steps = _stepped_with_checkpoint(p, n, seed, _ev(1 << 12), stop_after=3)
+    assert steps == 8
+    orc = O.OracleRun(p)
+    _, ho = orc.run(n, seed, per_history=True)
+    np.testing.assert_allclose(gb.history_scores(), ho, rtol=1e-12, atol=1e-300)
+    s, _ = gb.raw()
+    assert_close_sums(s, orc.tally_sum, what="tally_sum")
+    from gpu_util import assert_counters
+    assert_counters(gb.counters(), orc)
+    gb.close()
+
+
+def test_census_step_control_rejections():
+    mc = _mcdc()
+    p = W.config2(n_census=3)
+    gh = mc.Problem(p)                               # history schedule
+    with pytest.raises(mc.McdcError):
+        gh.run_begin(100, 1)
+    gh.close()
+    ge = mc.Problem(p, _ev(1000))
+    with pytest.raises(mc.McdcError):
+        ge.run_begin(5000, 1)                        # more than the resident histories
+    with pytest.raises(mc.McdcError):
+        ge.run_step()                                # no run in progress
+    ge.run_begin(500, 1)
+    with pytest.raises(mc.McdcError):
+        ge.run(10, 2)                                # a stepped run is in progress
+    while not ge.run_step():
+        pass
+    ge.run(10, 2)                                    # and afterwards plain runs work again
+    assert ge.counters()["histories"] == 510
+    ge.close()
