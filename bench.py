@@ -261,7 +261,10 @@ def bench_batch(args, torch, mcdc, W):
     """256 batched problems (1e4-1e6 histories each, 10 census steps): one
     pass = every problem's histories; histories/s over the whole batch."""
     probs, n_hist = W.config5()
-    bp = mcdc.BatchProblem(probs, n_hist)
+    # work-chunk size and occupancy from the autotuner (full passes, setup)
+    from paper_2409_04668_amd import autotune
+    tuned = autotune.tune_batch(probs, n_hist, use_cache=False)
+    bp = mcdc.BatchProblem(probs, n_hist, mcdc.make_options(**tuned["options"]))
     total = int(n_hist.sum())
     for i in range(args.warmup):
         bp.run(7 + i)
@@ -278,7 +281,8 @@ def bench_batch(args, torch, mcdc, W):
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * T / args.steps,
         "higher_is_better": True, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "256 box problems, 1-8 regions, 1-7 groups, 20^3 x 10 t-bins each",
-                   "histories_per_pass": total},
+                   "histories_per_pass": total, "autotuned_options": tuned["options"],
+                   "autotune_trials": tuned["trials"]},
         "pieces_per_history": pieces / (total * (args.steps + args.warmup))}), flush=True)
 
 
