@@ -98,12 +98,12 @@ struct BatchCtx {
 
 // LDS tile for one time slice of one problem; other bins go to HBM.
 struct TileTally {
-    double *lds;
-    double *glob;
+    lds_f64 *lds;
+    hbm_f64 *glob;
     uint32_t lo, hi;
     MCDC_DEV void add(uint32_t i, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, double v) const {
-        if (i >= lo && i < hi) atomicAdd(lds + (i - lo), v);
-        else unsafeAtomicAdd(glob + i, v);
+        if (i >= lo && i < hi) lds_add(lds + (i - lo), v);
+        else hbm_add(glob + i, v);
     }
 };
 
@@ -215,7 +215,7 @@ __global__ void __launch_bounds__(512) k_b_persistent(BDev D) {
         const uint32_t n = step == 0 ? BP.n_hist : D.nq[cur * D.n_prob + p];
         const uint32_t e0 = (ch - D.chunk_off[p]) * D.chunk;
         const uint32_t e1 = e0 + D.chunk < n ? e0 + D.chunk : n;
-        TileTally tally{s_tile, D.tally + BP.tally_off,
+        TileTally tally{(lds_f64 *)s_tile, (hbm_f64 *)(D.tally + BP.tally_off),
                         TILE && BP.slice ? step * BP.slice : 0u,
                         TILE && BP.slice ? (step + 1) * BP.slice : 0u};
         uint32_t n_flight = 0, n_piece = 0, n_new = 0;

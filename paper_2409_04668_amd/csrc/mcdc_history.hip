@@ -161,12 +161,12 @@ MCDC_DEV GlobalTally make_tally(GlobalTally *, const DevProblem &, const RunArgs
     return GlobalTally{A.tally};
 }
 MCDC_DEV LdsTally make_tally(LdsTally *, const DevProblem &, const RunArgs &, double *lds) {
-    return LdsTally{lds};
+    return LdsTally{(lds_f64 *)lds};
 }
 MCDC_DEV HotTileTally make_tally(HotTileTally *, const DevProblem &P, const RunArgs &A, double *lds) {
     HotTileTally t;
-    t.lds = lds;
-    t.glob = A.tally;
+    t.lds = (lds_f64 *)lds;
+    t.glob = (hbm_f64 *)A.tally;
     for (int a = 0; a < 5; ++a) {
         t.lo[a] = P.hot_lo[a];
         t.n[a] = P.hot_n[a];

@@ -271,25 +271,39 @@ struct GlobalTally {
         unsafeAtomicAdd(base + i, v);
     }
 };
+// LDS and HBM tally targets carry their address space in the pointer type, so
+// an update is a ds_add_f64 or a global_atomic_add_f64; through generic
+// pointers the two branches of a tile test fold into one flat atomic.
+typedef __attribute__((address_space(3))) double lds_f64;
+typedef __attribute__((address_space(1))) double hbm_f64;
+
+MCDC_DEV void lds_add(lds_f64 *p, double v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+MCDC_DEV void hbm_add(hbm_f64 *p, double v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 struct LdsTally {
-    double *base;
+    lds_f64 *base;
     MCDC_DEV void add(uint32_t i, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, double v) const {
-        atomicAdd(base + i, v);
+        lds_add(base + i, v);
     }
 };
 // A sub-box of the (g, t, z, y, x) mesh privatised in LDS (the bins that take
 // most of the updates); every other bin goes to HBM atomics.
 struct HotTileTally {
-    double *lds, *glob;
+    lds_f64 *lds;
+    hbm_f64 *glob;
     uint32_t lo[5], n[5];                    // x, y, z, t, g
     MCDC_DEV void add(uint32_t i, uint32_t g, uint32_t t, uint32_t z, uint32_t y, uint32_t x,
                       double v) const {
         const uint32_t dx = x - lo[0], dy = y - lo[1], dz = z - lo[2], dt = t - lo[3], dg = g - lo[4];
         if (dx < n[0] && dy < n[1] && dz < n[2] && dt < n[3] && dg < n[4]) {
             const uint32_t j = (((dg * n[3] + dt) * n[2] + dz) * n[1] + dy) * n[0] + dx;
-            atomicAdd(lds + j, v);
+            lds_add(lds + j, v);
         } else {
-            unsafeAtomicAdd(glob + i, v);
+            hbm_add(glob + i, v);
         }
     }
 };
