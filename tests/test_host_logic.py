@@ -30,3 +30,16 @@ def test_config_shapes():
     for p in probs[:20]:
         assert 1 <= p["sigma_t"].shape[1] <= 7 and p["mesh"]["n"][3] == len(p["census"]) == 10
         assert 0 <= len(p["box_mat"]) <= 7
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: any other --gpus exits with status 2 and a
+    message, before touching a device."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
