@@ -656,3 +656,95 @@ def test_census_step_control_rejections():
     ge.run(10, 2)                                    # and afterwards plain runs work again
     assert ge.counters()["histories"] == 510
     ge.close()
+
+
+# ---------------------------------------------------------------------------
+# weight windows with several energy groups (network input 4 + G)
+# ---------------------------------------------------------------------------
+
+def _ramp_mlp_g(in_dim, slope, group_bias, noise_seed=None):
+    """y = slope * xhat_x + group_bias[g] (exact in FP32 up to the noise)."""
+    H = 64
+    prm = np.zeros(M.n_params(in_dim, H), np.float32)
+    W1 = prm[:H * in_dim].reshape(H, in_dim)
+    W1[0, 0] = 1.0                          # unit 0 carries xhat_x + 1
+    for g, b in enumerate(group_bias):      # unit 1 + g carries the one-hot input of g
+        W1[1 + g, 4 + g] = 1.0
+    o = H * in_dim
+    prm[o + 0] = 1.0                        # b1[0]
+    o += H
+    W2 = prm[o:o + H * H].reshape(H, H)
+    W2[0, 0] = 1.0
+    for g in range(len(group_bias)):
+        W2[1 + g, 1 + g] = 1.0
+    o += H * H + H
+    prm[o + 0] = slope                      # W3
+    for g, b in enumerate(group_bias):
+        prm[o + 1 + g] = b
+    o += H
+    prm[o] = -slope                         # b3
+    if noise_seed is not None:
+        noise = M.init_params(in_dim, H, seed=noise_seed) * np.float32(0.01)
+        prm = prm + noise
+    return prm
+
+
+@pytest.mark.parametrize("use_map", [False, True])
+def test_weight_window_parity_multigroup(use_map):
+    p = W.config3(n_census=2)
+    p["mesh"]["n"] = np.array([6, 10, 6, 4], np.int32)
+    G = 7
+    ww = dict(params=_ramp_mlp_g(4 + G, -1.5, np.linspace(-1.0, 1.0, G), noise_seed=9), hidden=64,
+              logk=0.5, ratio=5.0, n_max=10)
+    if use_map:
+        ww["map"] = (12, 20, 12, 8)
+    p["ww"] = ww
+    p["stack_cap"] = 256
+    gp, orc = full_parity(p, 300, seed=171, trace_cap=800000)
+    assert orc.counters["split"] > 10 and orc.counters["rr_kill"] > 10
+    # the same histories under the event schedule
+    from gpu_util import assert_counters, assert_traces_equal, run_pair
+    ge, orc2, tg, to, hg, ho = run_pair(p, 300, 171, trace_cap=800000, options=_ev())
+    assert_traces_equal(tg[0], to[0])
+    np.testing.assert_allclose(hg[0], ho[0], rtol=1e-12, atol=1e-300)
+    assert_counters(ge.counters(), orc2)
+
+
+@pytest.mark.slow
+def test_learned_ww_multigroup_pipeline_stays_unbiased():
+    """Several groups: forward importance estimate, GPU training on 4 + G
+    inputs, baked map, event schedule; the detector mean agrees with the
+    analog run."""
+    import math
+    from paper_2409_04668_amd import learned_ww as L
+    mc = _mcdc()
+    # the duct problem in three groups (the 7-group data draw every region,
+    # the duct too, from the same ranges, and then nothing reaches the
+    # detector): shield and source Sigma_t near 0.1, a near-void duct,
+    # downscatter with c = 0.5, speeds 1, 2, 4 cm/s
+    p = W.config2()
+    G = 3
+    st = np.array([[0.10, 0.09, 0.11], [1e-4, 1e-4, 1e-4], [0.10, 0.08, 0.12]])
+    ss = np.zeros((3, G, G))
+    for m in range(3):
+        for g in range(G):
+            ss[m, g, :g + 1] = 0.5 * st[m, g] / (g + 1)
+    p["sigma_t"], p["sigma_s"] = st, ss
+    p["speed"] = np.array([1.0, 2.0, 4.0])
+    p["source"]["group"] = G - 1
+    p["mesh"] = dict(lo=np.array([0.0, 0.0, 0.0, 0.0]), hi=np.array([60.0, 100.0, 60.0, 200.0]),
+                     n=np.array([6, 10, 6, 4], np.int32), per_group=True)
+    ww, info = L.build_ww(p, n_runs=10, n_per_run=4_000_000, steps=800, map_dims=(12, 20, 12, 10))
+    assert info["method"] == "forward" and info["loss_last"] < info["loss_first"]
+    q = dict(p, ww=ww, stack_cap=256)
+    out = []
+    for prob, n, seed in ((p, 40_000_000, 181), (q, 8_000_000, 182)):
+        gp = mc.Problem(prob, _ev(1 << 22))
+        gp.run(n, seed)
+        m, r = gp.tallies(mc.TALLY_DETECTOR)
+        out.append((float(m[0]), float(r[0]) * float(m[0]), gp.counters()))
+        gp.close()
+    (ma, sa, _), (mw, sw, cw) = out
+    assert ma > 0 and mw > 0
+    assert abs(ma - mw) < 4 * math.hypot(sa, sw), out
+    assert cw["splits"] > 0
