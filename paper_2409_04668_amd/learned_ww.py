@@ -22,7 +22,9 @@ Then: the training set is one point per coarse cell with a positive estimate
 group one-hot; target = log importance); full-batch Adam on the GPU
 (mcdc_mlp_train); log K = log of the mean importance over source samples so
 that source particles start inside their windows; and the network output is
-clamped at run time to the range of its training targets.
+clamped at run time to the range of its training targets.  The transport then
+evaluates the network at every check, or (``map_dims``) reads w_T from the
+network baked once onto a regular cell-centre map (mcdc_set_ww_map).
 
 Weight windows change the variance, not the expected tallies; the analog run
 stays the reference for both the tallies and the figure of merit.
@@ -55,7 +57,7 @@ def _cell_inputs(n4, G: int):
 def reciprocal_importance(prob: dict, n_runs=20, n_per_run=1_000_000, seed0=W.ROOT_SEED + 1,
                           grid=None, options=None):
     """Importance I[t][z][y][x] on the coarse grid from runs with the source in
-    the detector (one group only).  Returns (I, seconds)."""
+    the detector (one group only).  Returns (I, seconds, grid cells n4)."""
     import torch
     if prob["sigma_t"].shape[1] != 1:
         raise ValueError("reciprocal importance needs one energy group")
@@ -99,7 +101,8 @@ def reciprocal_importance(prob: dict, n_runs=20, n_per_run=1_000_000, seed0=W.RO
 
 def forward_importance(prob: dict, n_runs: int, n_per_run: int, seed0: int, grid=None,
                        options=None):
-    """Forward estimate (any G): I[g][t][z][y][x] = score / weight per cell."""
+    """Forward estimate (any G): I[g][t][z][y][x] = score / weight per cell.
+    Returns (I, seconds, grid cells n4)."""
     import torch
     q = W.with_(prob, importance=grid or W.coarse_importance_grid(), ww=None,
                 implicit_capture=False)

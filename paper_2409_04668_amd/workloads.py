@@ -30,7 +30,8 @@ Problem dict schema (all lengths in cm, times in s):
 ``max_events``               flight cap per history
 ``stack_cap``                LIFO depth for split daughters per history
 ``importance``               None or dict(n[4]) coarse space-time grid
-``ww``                       None or dict(params float32[...], hidden, logk, ratio, n_max)
+``ww``                       None or dict(params float32[...], hidden, logk, ratio, n_max,
+                             ymin, ymax, map (nx, ny, nz, nt) or None)
 
 The slab of the one-group problem is an outer box with infinite y/z extent; a
 plane source on x=0 is then a point source at the origin (translation
