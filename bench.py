@@ -27,9 +27,15 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_PIECE = 16.0          # FP64 atomic read-modify-write: 8 B read + 8 B written
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_history_duct_1e8_pmc.txt")
-KERNEL_SOURCES = ["transport_device.hpp", "transport_stages.hpp", "mcdc_history.hip",
-                  "mcdc_internal.hpp"]
+KERNEL_SOURCES = ["transport_device.hpp", "transport_stages.hpp", "lane_stack.hpp",
+                  "mcdc_internal.hpp", "mcdc_history.hip", "mcdc_event.hip"]
+SCHED_NAMES = {1: "history", 2: "event", 3: "hybrid"}
+# the tracking kernel whose launches are timed under each schedule
+TIMED_KERNEL = {1: "k_history", 2: "k_ev_flight", 3: "k_ev_lead"}
+
+
+def pmc_summary(kernel: str) -> str:
+    return os.path.join(ROOT, "profiles", f"{kernel}_duct_1e8_pmc.txt")
 
 
 def kernel_hash() -> str:
@@ -40,13 +46,14 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per tracking launch from the committed rocprofv3 PMC summary,
-    or None if there is none or the kernel changed since it was taken."""
-    if not os.path.exists(PMC_SUMMARY):
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from its committed rocprofv3 PMC
+    summary, or None if there is none or the kernels changed since."""
+    path = pmc_summary(kernel)
+    if not os.path.exists(path):
         return None
     vals = {}
-    with open(PMC_SUMMARY) as f:
+    with open(path) as f:
         for line in f:
             if ":" in line:
                 k, v = line.split(":", 1)
@@ -69,13 +76,37 @@ def cpu_baseline(prob, n_sample, seed):
                        f"{r.last_seconds:.1f} s")
 
 
+def duct_options(args, mcdc, prob):
+    """Options of the duct runs: the LDS hot tile placed from a short analog
+    pilot, then (--schedule auto) the schedule the autotuner picks from
+    2e7-history trials of the history, event and hybrid schedules.  Setup,
+    not timed.  Returns (options dict, tuner result or None, tile, captured
+    fraction)."""
+    from paper_2409_04668_amd import autotune
+    tile, tile_frac = (None, 0.0) if args.no_tile else autotune.plan_hot_tile(prob, pilot=1_000_000)
+    tuned = None
+    if args.schedule == "auto":
+        tuned = autotune.tune_single(prob, pilot=20_000_000, waves=(16,), event_chunks=(1 << 24,),
+                                     tile=tile, use_cache=False)
+        oargs = dict(tuned["options"])
+    else:
+        sched = {"history": mcdc.SCHED_HISTORY, "event": mcdc.SCHED_EVENT,
+                 "hybrid": mcdc.SCHED_HYBRID}[args.schedule]
+        oargs = dict(schedule=sched, event_chunk=1 << 24)
+        if tile is not None and sched != mcdc.SCHED_EVENT:
+            oargs["tile"] = [[int(v) for v in tile[0]], [int(v) for v in tile[1]]]
+    if args.waves_per_cu:
+        oargs["waves_per_cu"] = args.waves_per_cu
+    return oargs, tuned, tile, tile_frac
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--histories", type=int, default=100_000_000)
-    ap.add_argument("--schedule", choices=["history", "event"], default="history")
+    ap.add_argument("--schedule", choices=["auto", "history", "event", "hybrid"], default="auto")
     ap.add_argument("--waves-per-cu", type=int, default=0)
     ap.add_argument("--cpu-sample", type=int, default=20_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -113,14 +144,10 @@ def main():
         return bench_fom(args, torch, mcdc, W)
 
     prob = W.config2()
-    sched = mcdc.SCHED_HISTORY if args.schedule == "history" else mcdc.SCHED_EVENT
-    tile, tile_frac = None, 0.0
-    if sched == mcdc.SCHED_HISTORY and not args.no_tile:
-        # the autotuner places the LDS hot tile from a short pilot run (setup,
-        # not timed)
-        from paper_2409_04668_amd import autotune
-        tile, tile_frac = autotune.plan_hot_tile(prob, pilot=1_000_000)
-    gp = mcdc.Problem(prob, mcdc.make_options(sched, waves_per_cu=args.waves_per_cu, tile=tile))
+    oargs, tuned, tile, tile_frac = duct_options(args, mcdc, prob)
+    sched = oargs["schedule"]
+    kernel = TIMED_KERNEL[sched]
+    gp = mcdc.Problem(prob, mcdc.make_options(**oargs))
     N = args.histories
     seed = 20260001
     for i in range(args.warmup):
@@ -144,7 +171,7 @@ def main():
     avg_launch_s = kms / 1e3 / max(launches, 1)
     bytes_per_launch = BYTES_PER_PIECE * pieces / max(launches, 1)
     achieved = bytes_per_launch / avg_launch_s / 1e9
-    traffic = measured_traffic()
+    traffic = measured_traffic(kernel)
     det_mean, det_rel = gp.tallies(mcdc.TALLY_DETECTOR)
     out = {
         "metric": "histories/s (analog, FP64 tallies) on the 3D duct problem",
@@ -161,14 +188,16 @@ def main():
         "data": "synthetic",
         "config": {"workload": "3D duct 60x100x60 cm, 1 group, 1 cm mesh x 20 t-bins "
                                "(7.2e6 FP64 bins), analog, 1e8 histories per step",
-                   "histories_per_step": N, "schedule": args.schedule,
+                   "histories_per_step": N, "schedule": SCHED_NAMES[sched],
+                   "options": oargs,
+                   "autotune_trials": tuned["trials"] if tuned else None,
                    "tally_bins": W.n_bins(prob),
                    "lds_hot_tile": None if tile is None else
                    {"lo_xyztg": [int(v) for v in tile[0]], "n_xyztg": [int(v) for v in tile[1]],
                     "pilot_track_length_fraction": tile_frac}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_history", "launches": launches,
+                     "kernel": kernel, "launches": launches,
                      "avg_launch_ms": 1e3 * avg_launch_s,
                      "algorithmic_bytes_per_launch": bytes_per_launch,
                      "atomic_updates_per_s": pieces / (kms / 1e3) if kms > 0 else None},
@@ -196,24 +225,28 @@ def main():
                             "workload": "Kobayashi dog-leg void duct, time dependent, 1 group",
                             "source": "Sec. Performance (GPU profiling paragraph)"}
     gp.close()
-    # the same step under the other schedule (event-based: staged kernels over
-    # compacted queues), one timed step after a warm-up, as a comparison
+    # the same step under the other schedules (tile where they take one),
+    # one timed step after a warm-up, as a comparison
     if not args.no_other_schedule:
-        other = "event" if args.schedule == "history" else "history"
-        osched = mcdc.SCHED_EVENT if other == "event" else mcdc.SCHED_HISTORY
-        go = mcdc.Problem(prob, mcdc.make_options(osched, event_chunk=1 << 24))
-        go.run(N, seed)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        go.run(N, seed + 1)
-        torch.cuda.synchronize()
-        out["other_schedule"] = {"schedule": other,
-                                 "histories_per_s": N / (time.perf_counter() - t0)}
-        go.close()
+        out["other_schedules"] = {}
+        for osched in (mcdc.SCHED_HISTORY, mcdc.SCHED_EVENT, mcdc.SCHED_HYBRID):
+            if osched == sched:
+                continue
+            o = dict(schedule=osched, event_chunk=1 << 24)
+            if tile is not None and osched != mcdc.SCHED_EVENT:
+                o["tile"] = tile
+            go = mcdc.Problem(prob, mcdc.make_options(**o))
+            go.run(N, seed)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            go.run(N, seed + 1)
+            torch.cuda.synchronize()
+            out["other_schedules"][SCHED_NAMES[osched]] = N / (time.perf_counter() - t0)
+            go.close()
     if not args.no_other_schedule:
         # the same step with the collision estimator as a second mesh tally
         pc = dict(prob, collision_tally=True)
-        gc = mcdc.Problem(pc, mcdc.make_options(sched, waves_per_cu=args.waves_per_cu, tile=tile))
+        gc = mcdc.Problem(pc, mcdc.make_options(**oargs))
         gc.run(N, seed)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -225,7 +258,7 @@ def main():
         gc.close()
     if not args.no_other_schedule:
         # population control at census: the duct problem with 20 census steps
-        # under the event schedule, without and with splitting-roulette to one
+        # under the hybrid schedule, without and with splitting-roulette to one
         # particle per source history at every census
         rates = {}
         for name, target in (("without", None), ("with_target_1", 1.0)):
@@ -233,7 +266,7 @@ def main():
             if target is not None:
                 pp["population_control"] = dict(target=target)
             # population control holds one batch of histories resident
-            gq = mcdc.Problem(pp, mcdc.make_options(mcdc.SCHED_EVENT, event_chunk=N // 20))
+            gq = mcdc.Problem(pp, mcdc.make_options(mcdc.SCHED_HYBRID, event_chunk=N // 20))
             gq.run(N, seed)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -245,13 +278,13 @@ def main():
                 rates["pc_kills_per_history"] = c["pc_kills"] / (2 * N)
                 rates["pc_copies_per_history"] = c["pc_copies"] / (2 * N)
             gq.close()
-        out["population_control_event_20_census"] = {
+        out["population_control_hybrid_20_census"] = {
             "histories_per_s_without": rates["without"],
             "histories_per_s_with": rates["with_target_1"],
             "pc_kills_per_history": rates["pc_kills_per_history"],
             "pc_copies_per_history": rates["pc_copies_per_history"]}
     if not args.no_fom:
-        out["fom"] = fom_comparison(mcdc, W)
+        out["fom"] = fom_comparison(mcdc, W, oargs, tile)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_sample, seed)
     print(json.dumps(out), flush=True)
@@ -289,15 +322,17 @@ def bench_batch(args, torch, mcdc, W):
 WW_MAP_DIMS = (30, 50, 30, 20)      # 2 cm cells x 10 s: network baked per cell centre
 
 
-def fom_comparison(mcdc, W, target=0.01):
+def fom_comparison(mcdc, W, analog_options, tile, target=0.01):
     """FOM = 1/(R^2 T) at `target` detector relative error on the duct
-    problem: analog (history schedule) vs learned weight windows (importance
-    from 20 x 1e6 analog histories, network trained on the GPU, baked onto a
-    2 cm x 10 s window map; schedule picked by the autotuner, which finds the
-    event schedule several times faster here because a history's split chain
-    runs serially on one lane in the history schedule).  Each side: a pilot
-    run sets N for the target error, then N histories are timed.  Training,
-    baking and tuning are setup, reported beside it."""
+    problem: analog (the options of the main duct step) vs learned weight
+    windows (importance from 20 x 1e6 analog histories, network trained on
+    the GPU, baked onto a 2 cm x 10 s window map; schedule picked by the
+    autotuner among the history schedule, where a history's split chain runs
+    serially on one work-item, and the event and hybrid schedules, which
+    spread long chains over the grid; the analog hot tile where the schedule
+    takes one).  Each side: a pilot run sets N for the target error, then N
+    histories are timed.  Training, baking and tuning are setup, reported
+    beside it."""
     from paper_2409_04668_amd import learned_ww as L
     p = W.config2()
     t0 = time.perf_counter()
@@ -308,21 +343,22 @@ def fom_comparison(mcdc, W, target=0.01):
     # short pilot; resident histories for the event schedule then follow the
     # run length (up to 2^23)
     from paper_2409_04668_amd import autotune
-    choice = autotune.tune_single(pw, pilot=1_000_000, waves=(16,), event_chunks=(1 << 20,),
-                                  use_cache=False)
+    choice = autotune.tune_single(pw, pilot=4_000_000, waves=(16,), event_chunks=(1 << 22,),
+                                  tile=tile, use_cache=False)
     wopt = dict(choice["options"])
-    if wopt["schedule"] == mcdc.SCHED_EVENT:
-        wopt["event_chunk"] = 1 << 23
-    analog = L.fom_at_target(p, seed=31, target=target, pilot=20_000_000)
+    if wopt["schedule"] in (mcdc.SCHED_EVENT, mcdc.SCHED_HYBRID):
+        wopt["event_chunk"] = 1 << 24
+    analog = L.fom_at_target(p, seed=31, target=target, pilot=20_000_000,
+                             options=mcdc.make_options(**analog_options))
     learned = L.fom_at_target(pw, seed=41, target=target, pilot=4_000_000,
                               options=mcdc.make_options(**wopt))
     z = abs(analog["mean"] - learned["mean"]) / (
         (analog["mean"] * analog["rel_err"]) ** 2 + (learned["mean"] * learned["rel_err"]) ** 2) ** 0.5
     return {"target_rel_err": target, "ratio": learned["fom"] / analog["fom"],
-            "analog": dict(analog, schedule="history"),
+            "analog": dict(analog, schedule=SCHED_NAMES[analog_options["schedule"]],
+                           options=analog_options),
             "learned_ww": dict(learned, window_map=list(WW_MAP_DIMS),
-                               schedule="event" if wopt["schedule"] == mcdc.SCHED_EVENT
-                               else "history", options=wopt,
+                               schedule=SCHED_NAMES[wopt["schedule"]], options=wopt,
                                autotune_trials=choice["trials"]),
             "agreement_sigma": z, "training": dict(info, total_seconds=t_build),
             "fom_with_training_amortised": 1.0 / (learned["rel_err"] ** 2 *
@@ -331,7 +367,8 @@ def fom_comparison(mcdc, W, target=0.01):
 
 def bench_fom(args, torch, mcdc, W):
     """FOM at 1% detector relative error, analog vs learned weight windows."""
-    f = fom_comparison(mcdc, W)
+    oargs, _, tile, _ = duct_options(args, mcdc, W.config2())
+    f = fom_comparison(mcdc, W, oargs, tile)
     print(json.dumps({
         "metric": "FOM 1/(R^2 T) at 1% detector relative error, analog vs learned weight windows",
         "value": f["ratio"], "unit": "FOM ratio (learned / analog)", **f,

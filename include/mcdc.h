@@ -49,7 +49,14 @@ typedef enum {
 
 enum { MCDC_VACUUM = 0, MCDC_REFLECTIVE = 1 };
 enum { MCDC_SRC_POINT = 0, MCDC_SRC_BOX = 1 };
-enum { MCDC_SCHED_AUTO = 0, MCDC_SCHED_HISTORY = 1, MCDC_SCHED_EVENT = 2 };
+/* Schedules.  HISTORY: one work-item follows a history and its split
+ * daughters to the end.  EVENT: particles live in banks and move through the
+ * transport loop one event class per launch.  HYBRID: one work-item follows
+ * each history until its first weight-window split (or, with population
+ * control or census-step control, its first census); the particles it then
+ * holds go to the event banks and finish there.  HYBRID uses the EVENT
+ * schedule's workspace and supports everything it does. */
+enum { MCDC_SCHED_AUTO = 0, MCDC_SCHED_HISTORY = 1, MCDC_SCHED_EVENT = 2, MCDC_SCHED_HYBRID = 3 };
 enum { MCDC_TALLY_MESH = 0, MCDC_TALLY_DETECTOR = 1, MCDC_TALLY_LEAKAGE = 2,
        MCDC_TALLY_COLLISION = 3 };
 
@@ -101,7 +108,9 @@ typedef struct {
     int32_t imp_n[4];                  /* its x,y,z,t cells                        */
     int32_t n_batches;                 /* batches per run for mesh statistics     */
     int64_t max_events;                /* flights per history before an error     */
-    int32_t stack_cap;                 /* split daughters held per history        */
+    int32_t stack_cap;                 /* split daughters held per history (history
+                                          schedule: more is MCDC_E_STACK; hybrid
+                                          lead stage: more go to the event banks) */
     uint32_t problem_id;               /* part of every RNG counter               */
 } mcdc_problem_desc;
 
@@ -296,7 +305,9 @@ int mcdc_get_batch_counters(mcdc_handle h, size_t p, mcdc_counters *out, void *s
 int mcdc_get_batch_history_path(mcdc_handle h, size_t p, double *out, size_t n, void *stream);
 
 /* Kernel timing: with `on` = 1, later runs record a pair of HIP events on the
- * run's stream around every tracking-kernel launch; mcdc_kernel_time
+ * run's stream around every launch of the schedule's tracking kernel (history
+ * schedule: the history kernel; event schedule: the flight stage; hybrid
+ * schedule: the lead stage); mcdc_kernel_time
  * synchronises them and returns the number of launches recorded since the last
  * call and their summed duration in milliseconds (then forgets them). */
 int mcdc_set_kernel_timing(mcdc_handle h, int on);

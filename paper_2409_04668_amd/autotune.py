@@ -1,8 +1,8 @@
 """Autotuner: picks the schedule and launch shape by timing short pilot runs.
 
-Single problems: history-based vs event-based schedule, persistent-grid
-occupancy target (waves per CU) and, for event mode, the chunk of resident
-histories.  Batched problems: work-queue chunk size and occupancy.  Results are
+Single problems: history-based, event-based or hybrid schedule,
+persistent-grid occupancy target (waves per CU) and, for the event and hybrid
+schedules, the chunk of resident histories.  Batched problems: work-queue chunk size and occupancy.  Results are
 cached in a JSON file keyed by a hash of the problem data and the device name,
 so a later run of the same workload skips the search.
 
@@ -78,28 +78,38 @@ def _time_single(prob, opt, n, seed) -> float:
 
 
 def tune_single(prob, pilot=2_000_000, waves=(8, 12, 16, 24, 32),
-                event_chunks=(1 << 20, 1 << 22, 1 << 23), cache_path=DEFAULT_CACHE,
+                event_chunks=(1 << 20, 1 << 22, 1 << 23), tile=None, cache_path=DEFAULT_CACHE,
                 use_cache=True, seed=12345):
     """Returns {"options": dict for mcdc.make_options, "histories_per_s": ..., "trials": [...]}.
-    Population control runs only in the event schedule, with every batch of
-    the pilot resident (chunks below the batch size are skipped)."""
-    key = "single:" + _device_name() + ":" + _hash_problem(prob) + f":{pilot}"
+    Tries the history schedule at each occupancy and the event and hybrid
+    schedules at each chunk size.  `tile` = (lo[5], n[5]), e.g. from
+    plan_hot_tile: the LDS hot tile of the history schedule and of the hybrid
+    schedule's lead stage.  Population control runs only in the event and
+    hybrid schedules, with every batch of the pilot resident (chunks below the
+    batch size are skipped)."""
+    tj = None if tile is None else [[int(v) for v in tile[0]], [int(v) for v in tile[1]]]
+    key = "single:" + _device_name() + ":" + _hash_problem(prob) + f":{pilot}:{tj}"
     cache = _load(cache_path) if use_cache else {}
     if key in cache:
         return cache[key]
     trials = []
     pc = prob.get("population_control") is not None
+
+    def trial(**o):
+        if tj is not None and o["schedule"] != mcdc.SCHED_EVENT:
+            o["tile"] = tj
+        trials.append((o, _time_single(prob, mcdc.make_options(**o), pilot, seed)))
+
     if not pc:
         for w in waves:
-            o = dict(schedule=mcdc.SCHED_HISTORY, waves_per_cu=w)
-            trials.append((o, _time_single(prob, mcdc.make_options(**o), pilot, seed)))
+            trial(schedule=mcdc.SCHED_HISTORY, waves_per_cu=w)
     if prob.get("importance") is None:
         batch = -(-pilot // int(prob["n_batches"]))
         for ch in event_chunks:
             if pc and ch < batch:
                 continue
-            o = dict(schedule=mcdc.SCHED_EVENT, event_chunk=ch)
-            trials.append((o, _time_single(prob, mcdc.make_options(**o), pilot, seed)))
+            for sched in (mcdc.SCHED_EVENT, mcdc.SCHED_HYBRID):
+                trial(schedule=sched, event_chunk=ch)
     if not trials:
         raise ValueError("no schedule can run this problem at this pilot size")
     best = max(trials, key=lambda t: t[1])

@@ -93,6 +93,7 @@ Options resolve_options(const mcdc_options *o) {
     r.lds_tally = 1;
     r.event_chunk = 1 << 22;
     r.tile_bins = 0;
+    r.lead = false;
     for (int a = 0; a < 5; ++a) r.tile_lo[a] = r.tile_n[a] = 0;
     if (o) {
         if (o->schedule) r.schedule = o->schedule;
@@ -111,8 +112,12 @@ Options resolve_options(const mcdc_options *o) {
         if (on) r.tile_bins = bins > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)bins;
     }
     if (r.schedule == MCDC_SCHED_AUTO) r.schedule = MCDC_SCHED_HISTORY;
+    // the hybrid schedule is the event schedule with a lead stage
+    r.lead = r.schedule == MCDC_SCHED_HYBRID;
+    if (r.lead) r.schedule = MCDC_SCHED_EVENT;
     // the hot tile runs one 1024-work-item workgroup per CU-share of LDS
-    if (r.tile_bins && r.schedule == MCDC_SCHED_HISTORY) r.block = 1024;
+    // (history schedule, and the lead stage of the hybrid schedule)
+    if (r.tile_bins && (r.schedule == MCDC_SCHED_HISTORY || r.lead)) r.block = 1024;
     else r.tile_bins = 0;
     r.grid = history_grid(r.block, r.waves_per_cu);
     r.n_lanes = (uint64_t)r.grid * r.block;

@@ -17,6 +17,15 @@
 // step); when both are empty the chunk of histories is done.  Bank roles and
 // counts live in device memory, so every launch of an iteration has fixed
 // arguments; a kernel whose input is empty exits at once.
+//
+// Hybrid schedule: a lead stage replaces the source stage.  One work-item
+// follows each history through its flights in registers, as the history
+// schedule does, until the history ends, splits at a weight window, or (with
+// population control or census-step control) reaches a census; only then do
+// its particles go to the banks.  Histories that never split never touch the
+// banks; the split chains, which would serialise on one work-item, are spread
+// over the grid by the event stages.
+#include "lane_stack.hpp"
 #include "mcdc_runtime.hpp"
 #include "transport_stages.hpp"
 
@@ -209,6 +218,208 @@ __global__ void __launch_bounds__(256) k_ev_source(DevProblem P, RunArgs A, EvBa
         if (valid && alive) bank_put(A, B, B.b[cur], pos, q, 0.0, s);
     }
     __syncthreads();
+    shared_flush(S, A.acc);
+}
+
+// Lead-stage flights per history (its particles together) before the rest of
+// the history is handed to the event stages: short histories finish in the
+// lead, long split chains are spread over the grid instead of holding one
+// work-item.
+#ifndef MCDC_LEAD_FLIGHTS
+#define MCDC_LEAD_FLIGHTS 16
+#endif
+
+// Context of a history in the lead stage: one work-item owns the history (its
+// banked particles, if any, move only after the lead stage), so its sums stay
+// in registers and are stored to the per-history arrays when the lead ends.
+// Split daughters go onto the work-item's stack while it has room, else into
+// the active bank.
+template <int WW>
+struct LeadCtx {
+    static constexpr bool kWW = WW != 0;
+    static constexpr bool kWWMap = WW == 2;
+    const DevProblem &P;
+    const RunArgs &A;
+    const EvBank &B;
+    uint64_t lane;
+    uint32_t cur;
+    uint32_t slot;
+    double xh, path;
+    uint32_t events;
+    int sp;
+    MCDC_DEV uint64_t hist() const { return A.h_begin + slot; }
+    MCDC_DEV uint64_t batch() const {
+        const uint64_t r = A.h_begin + slot - A.h_run0;
+        return ((r + 1) * A.run_batches - 1) / A.run_n;
+    }
+    MCDC_DEV double *col_tally() const { return A.col + batch() * (uint64_t)P.nbins; }
+    MCDC_DEV const float *mlp_params(const DevProblem &Pp) const { return Pp.ww_params; }
+    MCDC_DEV bool count_flight() {
+        events += 1u;
+        return (int64_t)events <= P.max_events;
+    }
+    MCDC_DEV void add_score(double v) { xh += v; }
+    MCDC_DEV void add_path(double v) {
+        if (A.keep_path) path += v;
+    }
+    MCDC_DEV void imp_point(const DevProblem &, const Part &) {}
+    // copy a particle ready for its next flight into the active bank
+    MCDC_DEV void to_bank(const Part &q, uint32_t pos) const {
+        bank_put(A, B, B.b[cur], pos, q, 0.0, slot);
+    }
+    // daughters i = 1..n-1 (tag tag0 + i * golden, counter and sequence 0)
+    MCDC_DEV bool push_daughters(const Part &q, uint32_t tag0, int n) {
+        const int room = P.stack_cap - sp;
+        const int spill = n - 1 > room ? n - 1 - room : 0;
+        const uint32_t base = spill ? atomicAdd(&B.ctl->n_act[cur], (uint32_t)spill) : 0u;
+        for (int i = 1; i < n; ++i) {
+            Part d = q;
+            d.tag = tag0 + (uint32_t)i * 0x9E3779B9u;
+            d.k = 0;
+            d.seq = 0;
+            if (i <= room) {
+                stack_push(A, lane, P.stack_cap, sp, d);
+                sp += 1;
+            } else {
+                to_bank(d, base + (uint32_t)(i - 1 - room));
+            }
+        }
+        return true;
+    }
+};
+
+// Tally target of the lead stage: HBM atomics into the history's batch slice,
+// or (LDS == 2) a hot tile in LDS for the workgroup's batch with the rest of
+// the mesh, and every other batch, in HBM.
+template <int LDS>
+struct LeadTally {
+    GlobalTally t;
+    MCDC_DEV void init(const DevProblem &, double *) {}
+    MCDC_DEV void select(const DevProblem &P, const RunArgs &A, uint64_t b, uint64_t) {
+        t.base = A.tally + b * (uint64_t)P.nbins;
+    }
+};
+template <>
+struct LeadTally<2> {
+    HotTileTally t;
+    MCDC_DEV void init(const DevProblem &P, double *lds) {
+        t.lds = (lds_f64 *)lds;
+        for (int a = 0; a < 5; ++a) {
+            t.lo[a] = P.hot_lo[a];
+            t.n[a] = P.hot_n[a];
+        }
+    }
+    // the tile holds batch b_tile only: an empty x extent sends every update
+    // of another batch to HBM
+    MCDC_DEV void select(const DevProblem &P, const RunArgs &A, uint64_t b, uint64_t b_tile) {
+        t.glob = (hbm_f64 *)(A.tally + b * (uint64_t)P.nbins);
+        t.n[0] = b == b_tile ? P.hot_n[0] : 0u;
+    }
+};
+
+MCDC_DEV uint64_t batch_of(const RunArgs &A, uint32_t slot) {
+    const uint64_t r = A.h_begin + slot - A.h_run0;
+    return ((r + 1) * A.run_batches - 1) / A.run_n;
+}
+
+// Lead stage (hybrid schedule).  Workgroup w takes the contiguous slots
+// [w n / G, (w+1) n / G) (so its LDS tile, if any, sees one batch apart from
+// at most one boundary); its work-items take the next slot from a counter in
+// LDS and run one flight per loop turn, as the history schedule does: the
+// particle, then the daughters on the stack, then the next slot.  After
+// MCDC_LEAD_FLIGHTS flights of one history its particle and stacked daughters
+// go into the active bank; with population control or census-step control a
+// particle that reaches a census goes into the census bank.  The event stages
+// finish what was banked.  LDS: 0 tally in HBM, 2 hot tile in LDS.
+template <int LDS, int WW>
+__global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_ev_lead(DevProblem P, RunArgs A, EvBank B,
+                                                                  uint32_t n) {
+    extern __shared__ double s_tile[];
+    __shared__ Shared S;
+    __shared__ uint32_t s_next;
+    shared_zero(S);
+    const uint32_t r0 = (uint32_t)((uint64_t)blockIdx.x * n / gridDim.x);
+    const uint32_t r1 = (uint32_t)((uint64_t)(blockIdx.x + 1) * n / gridDim.x);
+    if (threadIdx.x == 0) s_next = r0;
+    if (LDS == 2)
+        for (uint32_t i = threadIdx.x; i < P.hot_bins; i += blockDim.x) s_tile[i] = 0.0;
+    __syncthreads();
+    const uint64_t b_tile = batch_of(A, r0);
+    const uint32_t cur = B.ctl->cur, cen = B.ctl->cen;
+    const bool stop_at_census = P.pc_on || B.ctl->pause_at_census;
+    const uint64_t lane = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t n_flight = 0, n_piece = 0, lead_flights = 0;
+    double path = 0.0;
+    LeadCtx<WW> C{P, A, B, lane, cur, 0u, 0.0, 0.0, 0u, 0};
+    LeadTally<LDS> tally;
+    tally.init(P, s_tile);
+    Part q;
+    q.alive = false;
+    bool in_hist = false;
+    for (;;) {
+        if (!q.alive) {
+            if (WW != 0 && C.sp > 0) {
+                C.sp -= 1;
+                stack_pop(A, lane, P.stack_cap, C.sp, q);
+            } else {
+                if (in_hist) {
+                    B.xh[C.slot] = C.xh;
+                    B.path[C.slot] = C.path;
+                    B.events[C.slot] = C.events;
+                    in_hist = false;
+                }
+                const uint32_t s = atomicAdd(&s_next, 1u);
+                if (s >= r1) break;
+                C.slot = s;
+                C.xh = 0.0;
+                C.path = 0.0;
+                C.events = 0u;
+                C.sp = 0;
+                lead_flights = 0;
+                in_hist = true;
+                tally.select(P, A, batch_of(A, s), b_tile);
+                stage_source(P, A, S, C, q);
+                if (!q.alive) continue;
+            }
+        }
+        if (WW != 0 && lead_flights >= MCDC_LEAD_FLIGHTS) {
+            // hand the rest of the history over: this particle and the stack
+            const uint32_t base = atomicAdd(&B.ctl->n_act[cur], (uint32_t)C.sp + 1u);
+            C.to_bank(q, base);
+            for (int i = 0; i < C.sp; ++i) {
+                Part r;
+                stack_pop(A, lane, P.stack_cap, i, r);
+                C.to_bank(r, base + 1u + (uint32_t)i);
+            }
+            C.sp = 0;
+            q.alive = false;
+            continue;
+        }
+        lead_flights += 1;
+        double d = 0.0;
+        const int ev = stage_flight(P, A, S, tally.t, C, q, d, n_piece, path);
+        if (ev >= 0) n_flight += 1;
+        if (!q.alive) {
+            if (ev < 0) C.sp = 0;           // event cap: the history is abandoned
+            continue;
+        }
+        bool due = false;
+        if (ev == EV_SURFACE) {
+            due = stage_surface(P, A, S, C, q, d);
+        } else if (ev == EV_SCATTER) {
+            due = stage_collision(P, A, S, C, q, d);
+        } else if (ev == EV_CENSUS && stop_at_census) {
+            bank_put(A, B, B.b[cen], atomicAdd(&B.ctl->n_act[cen], 1u), q, d, C.slot);
+            q.alive = false;
+            continue;
+        }
+        if (WW != 0 && due) ww_check(P, A, S, C, q);
+    }
+    atomicAdd(&S.cnt[C_FLIGHT], (unsigned long long)n_flight);
+    atomicAdd(&S.cnt[C_PIECE], (unsigned long long)n_piece);
+    atomicAdd(&S.wsum[W_PATH], path);
+    __syncthreads();
+    if (LDS == 2 && r0 < r1) hot_tile_flush(P, s_tile, A.tally + b_tile * (uint64_t)P.nbins);
     shared_flush(S, A.acc);
 }
 
@@ -564,6 +775,37 @@ static void ev_launch_source(mcdc_problem *h, const RunArgs &A, hipStream_t s, u
     int sg = (int)((n + E->block - 1) / E->block);
     if (sg > E->grid) sg = E->grid;
     hipLaunchKernelGGL(k_ev_count_hist, dim3(1), dim3(1), 0, s, A.acc, (uint64_t)n);
+    if (h->opt.lead) {
+        // the lead grid is the history schedule's (block, grid): work-item i
+        // owns stack lane i, and A.n_lanes = grid * block lanes exist
+        const DevProblem &P = h->P;
+        const int lb = h->opt.block;
+        int lg = (int)((n + lb - 1) / lb);
+        if (lg > h->opt.grid) lg = h->opt.grid;
+        if (lg < 1) lg = 1;
+        const int ww = P.ww_on ? (P.ww_map ? 2 : 1) : 0;
+        const size_t shm = P.hot_bins ? (size_t)P.hot_bins * sizeof(double) : 0;
+#define MCDC_LEAD(L, W)                                                                        \
+    do {                                                                                       \
+        if (shm > 65536)                                                                       \
+            (void)hipFuncSetAttribute((const void *)k_ev_lead<L, W>,                           \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);   \
+        hipLaunchKernelGGL((k_ev_lead<L, W>), dim3(lg), dim3(lb), shm, s, P, A, B, n);         \
+    } while (0)
+        timing_begin(h, s);
+        if (P.hot_bins) {
+            if (ww == 2) MCDC_LEAD(2, 2);
+            else if (ww == 1) MCDC_LEAD(2, 1);
+            else MCDC_LEAD(2, 0);
+        } else {
+            if (ww == 2) MCDC_LEAD(0, 2);
+            else if (ww == 1) MCDC_LEAD(0, 1);
+            else MCDC_LEAD(0, 0);
+        }
+#undef MCDC_LEAD
+        timing_end(h, s);
+        return;
+    }
     if (h->P.ww_on) hipLaunchKernelGGL((k_ev_source<true>), dim3(sg), dim3(E->block), 0, s, h->P, A, B, n);
     else hipLaunchKernelGGL((k_ev_source<false>), dim3(sg), dim3(E->block), 0, s, h->P, A, B, n);
 }
@@ -575,15 +817,16 @@ static int ev_iterate(mcdc_problem *h, const RunArgs &A, hipStream_t s, bool &do
     const DevProblem &P = h->P;
     const EvBank &B = E->B;
     const int grid = E->grid, block = E->block;
-    const bool ww = P.ww_on != 0, pc = P.pc_on != 0;
+    const bool ww = P.ww_on != 0, pc = P.pc_on != 0, lead = h->opt.lead;
     for (int iter = 0;; ++iter) {
         const int K = 8;
         h->event_iterations += K;
         for (int k = 0; k < K; ++k) {
-            timing_begin(h, s);
+            // timed stage: the flight stage (the lead stage in the hybrid schedule)
+            if (!lead) timing_begin(h, s);
             if (ww) hipLaunchKernelGGL((k_ev_flight<true>), dim3(grid), dim3(block), 0, s, P, A, B);
             else hipLaunchKernelGGL((k_ev_flight<false>), dim3(grid), dim3(block), 0, s, P, A, B);
-            timing_end(h, s);
+            if (!lead) timing_end(h, s);
             if (!ww) hipLaunchKernelGGL((k_ev_interact<0>), dim3(grid), dim3(block), 0, s, P, A, B);
             else if (P.ww_map) hipLaunchKernelGGL((k_ev_interact<2>), dim3(grid), dim3(block), 0, s, P, A, B);
             else hipLaunchKernelGGL((k_ev_interact<1>), dim3(grid), dim3(block), 0, s, P, A, B);

@@ -8,50 +8,10 @@
 // Tallies: track-length pieces go to FP64 atomics, either straight into the
 // batch accumulator in HBM or, when the whole mesh fits, into an LDS tile per
 // workgroup that is flushed with one global atomic per touched bin at the end.
+#include "lane_stack.hpp"
 #include "transport_stages.hpp"
 
 namespace mcdc {
-
-// Daughter stack in HBM, SoA [field][depth][lane]: each field access of a
-// wave is one contiguous 512-byte transaction.
-MCDC_DEV void stack_push(const RunArgs &A, uint64_t lane, int cap, int depth, const Part &q) {
-    const uint64_t L = A.n_lanes;
-    const uint64_t o = (uint64_t)depth * L + lane;
-    const uint64_t F = (uint64_t)cap * L;
-    A.stk_d[0 * F + o] = q.x[0];
-    A.stk_d[1 * F + o] = q.x[1];
-    A.stk_d[2 * F + o] = q.x[2];
-    A.stk_d[3 * F + o] = q.u[0];
-    A.stk_d[4 * F + o] = q.u[1];
-    A.stk_d[5 * F + o] = q.u[2];
-    A.stk_d[6 * F + o] = q.t;
-    A.stk_d[7 * F + o] = q.w;
-    A.stk_i[0 * F + o] = q.g;
-    A.stk_i[1 * F + o] = q.cell;
-    A.stk_i[2 * F + o] = q.ci;
-    A.stk_i[3 * F + o] = (int32_t)q.tag;
-}
-
-MCDC_DEV void stack_pop(const RunArgs &A, uint64_t lane, int cap, int depth, Part &q) {
-    const uint64_t L = A.n_lanes;
-    const uint64_t o = (uint64_t)depth * L + lane;
-    const uint64_t F = (uint64_t)cap * L;
-    q.x[0] = A.stk_d[0 * F + o];
-    q.x[1] = A.stk_d[1 * F + o];
-    q.x[2] = A.stk_d[2 * F + o];
-    q.u[0] = A.stk_d[3 * F + o];
-    q.u[1] = A.stk_d[4 * F + o];
-    q.u[2] = A.stk_d[5 * F + o];
-    q.t = A.stk_d[6 * F + o];
-    q.w = A.stk_d[7 * F + o];
-    q.g = A.stk_i[0 * F + o];
-    q.cell = A.stk_i[1 * F + o];
-    q.ci = A.stk_i[2 * F + o];
-    q.tag = (uint32_t)A.stk_i[3 * F + o];
-    q.k = 0;
-    q.seq = 0;
-    q.alive = true;
-}
 
 // Per-work-item history context (registers).  WW: 0 no weight windows,
 // 1 network evaluated at each check, 2 baked window map.
@@ -262,21 +222,7 @@ __global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_history(DevProblem P,
             if (v != 0.0) unsafeAtomicAdd(&A.tally[i], v);
         }
     } else if (LDS == 2) {
-        // tile bin j -> mesh bin: walk the tile in x-fastest order
-        const uint32_t nx = P.hot_n[0], ny = P.hot_n[1], nz = P.hot_n[2], nt = P.hot_n[3];
-        const uint32_t mx = P.mesh_n[0], my = P.mesh_n[1], mz = P.mesh_n[2], mt = P.mesh_n[3];
-        for (uint32_t j = threadIdx.x; j < P.hot_bins; j += blockDim.x) {
-            const double v = s_tile[j];
-            if (v == 0.0) continue;
-            uint32_t r = j;
-            const uint32_t x = r % nx + P.hot_lo[0]; r /= nx;
-            const uint32_t y = r % ny + P.hot_lo[1]; r /= ny;
-            const uint32_t z = r % nz + P.hot_lo[2]; r /= nz;
-            const uint32_t t = r % nt + P.hot_lo[3]; r /= nt;
-            const uint32_t g = r + P.hot_lo[4];
-            const uint32_t b = (((g * mt + t) * mz + z) * my + y) * mx + x;
-            unsafeAtomicAdd(&A.tally[b], v);
-        }
+        hot_tile_flush(P, s_tile, A.tally);
     }
     shared_flush(S, A.acc);
 }

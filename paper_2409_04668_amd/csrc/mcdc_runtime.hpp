@@ -15,6 +15,7 @@ namespace mcdc {
 
 struct Options {
     int schedule, block, waves_per_cu, lds_tally;
+    bool lead;                           // event schedule with the history-style lead stage
     int64_t event_chunk;
     int32_t tile_lo[5], tile_n[5];
     uint32_t tile_bins;                  // 0: no hot tile

@@ -308,6 +308,25 @@ struct HotTileTally {
     }
 };
 
+// Add a workgroup's hot tile (LDS, x fastest over the tile box) into the mesh
+// tally at `out`: one HBM atomic per touched bin.
+MCDC_DEV void hot_tile_flush(const DevProblem &P, const double *tile, double *out) {
+    const uint32_t nx = P.hot_n[0], ny = P.hot_n[1], nz = P.hot_n[2], nt = P.hot_n[3];
+    const uint32_t mx = P.mesh_n[0], my = P.mesh_n[1], mz = P.mesh_n[2], mt = P.mesh_n[3];
+    for (uint32_t j = threadIdx.x; j < P.hot_bins; j += blockDim.x) {
+        const double v = tile[j];
+        if (v == 0.0) continue;
+        uint32_t r = j;
+        const uint32_t x = r % nx + P.hot_lo[0]; r /= nx;
+        const uint32_t y = r % ny + P.hot_lo[1]; r /= ny;
+        const uint32_t z = r % nz + P.hot_lo[2]; r /= nz;
+        const uint32_t t = r % nt + P.hot_lo[3]; r /= nt;
+        const uint32_t g = r + P.hot_lo[4];
+        const uint32_t b = (((g * mt + t) * mz + z) * my + y) * mx + x;
+        unsafeAtomicAdd(&out[b], v);
+    }
+}
+
 // Track-length scoring of the segment p + s u, s in [0,d], from time t0 at
 // speed v: the segment is cut at every mesh plane and time edge it crosses
 // (edges lo + k*delta; crossing distances recomputed from the segment start;

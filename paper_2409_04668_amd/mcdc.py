@@ -29,7 +29,7 @@ _lib = C.CDLL(LIB_PATH)
 
 OK = 0
 E_INVALID, E_NOMEM, E_HIP, E_EVENT_CAP, E_CANCELLED, E_STATE, E_STACK, E_BANK = -1, -2, -3, -4, -5, -6, -7, -8
-SCHED_AUTO, SCHED_HISTORY, SCHED_EVENT = 0, 1, 2
+SCHED_AUTO, SCHED_HISTORY, SCHED_EVENT, SCHED_HYBRID = 0, 1, 2, 3
 TALLY_MESH, TALLY_DETECTOR, TALLY_LEAKAGE, TALLY_COLLISION = 0, 1, 2, 3
 MAX_G = 8
 HIDDEN = 64

@@ -1,6 +1,6 @@
 """GPU tests of the autotuner: the schedule it picks runs the problem to the
 same per-history results as any other schedule, population control is only
-tried in the event schedule, and the batched tuner returns a working shape."""
+tried in the event and hybrid schedules, and the batched tuner returns a working shape."""
 import numpy as np
 import pytest
 
@@ -29,7 +29,7 @@ def test_tuned_schedule_gives_the_same_histories():
     p["stack_cap"] = 256
     res = autotune.tune_single(p, pilot=200_000, waves=(8, 16), event_chunks=(1 << 18,),
                                use_cache=False)
-    assert len(res["trials"]) == 3 and res["histories_per_s"] > 0
+    assert len(res["trials"]) == 4 and res["histories_per_s"] > 0
     n = 20_000
     out = []
     for opt in (mcdc.make_options(**res["options"]), mcdc.make_options(mcdc.SCHED_HISTORY)):
@@ -43,7 +43,7 @@ def test_tuned_schedule_gives_the_same_histories():
         assert out[0][1][k] == out[1][1][k], k
 
 
-def test_population_control_is_tuned_in_the_event_schedule_only():
+def test_population_control_is_tuned_in_the_banked_schedules_only():
     from paper_2409_04668_amd import autotune, mcdc
     p = W.infinite_medium(1.0, [[0.8]], [1.0], half=20.0, t_end=8.0, nt=8)
     p["census"] = np.linspace(1.0, 8.0, 8)
@@ -51,8 +51,8 @@ def test_population_control_is_tuned_in_the_event_schedule_only():
     res = autotune.tune_single(p, pilot=100_000, event_chunks=(1 << 12, 1 << 16),
                                use_cache=False)
     # batches of 5000 histories: the 4096 chunk cannot hold one
-    assert [t["options"]["event_chunk"] for t in res["trials"]] == [1 << 16]
-    assert res["options"]["schedule"] == mcdc.SCHED_EVENT
+    assert [t["options"]["event_chunk"] for t in res["trials"]] == [1 << 16] * 2
+    assert res["options"]["schedule"] in (mcdc.SCHED_EVENT, mcdc.SCHED_HYBRID)
 
 
 def test_batch_tuner_returns_a_working_shape():
@@ -66,3 +66,22 @@ def test_batch_tuner_returns_a_working_shape():
     for i in range(len(probs)):
         assert bp.counters(i)["histories"] == n_hist[i]
     bp.close()
+
+
+def test_tuner_gives_the_tile_to_the_history_and_hybrid_trials():
+    from paper_2409_04668_amd import autotune, mcdc
+    p = W.config2(n_census=3)
+    tile = ([2, 3, 1, 0, 0], [10, 12, 9, 6, 1])
+    res = autotune.tune_single(p, pilot=200_000, waves=(16,), event_chunks=(1 << 18,), tile=tile,
+                               use_cache=False)
+    scheds = [t["options"]["schedule"] for t in res["trials"]]
+    assert scheds == [mcdc.SCHED_HISTORY, mcdc.SCHED_EVENT, mcdc.SCHED_HYBRID]
+    for t in res["trials"]:
+        has = "tile" in t["options"]
+        assert has == (t["options"]["schedule"] != mcdc.SCHED_EVENT)
+        if has:
+            assert t["options"]["tile"] == [list(tile[0]), list(tile[1])]
+    gp = mcdc.Problem(p, mcdc.make_options(**res["options"]))
+    gp.run(10_000, 3)
+    assert gp.counters()["histories"] == 10_000
+    gp.close()
