@@ -2,112 +2,225 @@
 // Adam, trained full-batch on importance estimates that the transport itself
 // produced.  Parameter layout: W1[64][in], b1[64], W2[64][64], b2[64], W3[64], b3.
 //
-// One training step is three launches:
-//   k_mlp_point   one work-item per point: forward pass, loss term, and the
-//                 per-point backward quantities dL/dout, dL/dz2 (64), dL/dz1 (64),
-//                 stored with h1, h2 in a caller-provided scratch buffer;
-//   k_mlp_partial each work-item owns one parameter and sums its gradient over
-//                 a contiguous chunk of points (fixed order: reproducible);
-//   k_mlp_adam    sums the chunk partials in chunk order and applies Adam.
+// One training step is two launches:
+//   k_mlp_step  one workgroup per 64 consecutive points: forward pass, loss,
+//               backward pass and the gradient summed over its points (in
+//               point order) into partial[workgroup][param];
+//   k_mlp_adam  sums the workgroup partials in workgroup order (so a step is
+//               reproducible bit for bit) and applies Adam.
+// Inference (k_mlp_point) is one work-item per point.
 #include "mcdc_runtime.hpp"
 
 namespace mcdc {
 
-constexpr int kMlpChunks = 32;
+constexpr int kPts = 64;                  // points per workgroup of a training step
+constexpr int kLd = kH + 1;               // padded per-point row in LDS (no bank conflicts)
 
 __host__ __device__ inline int mlp_np(int in_dim) { return kH * in_dim + kH + kH * kH + kH + kH + 1; }
 
 struct MlpScratch {
-    float *h1, *h2, *dz1, *dz2, *dout;     // [n][64] x4, [n]
-    float *partial;                        // [kMlpChunks][np]
+    float *partial;                        // [workgroups][np]
     float *wsum;                           // [1]
+    int groups;                            // workgroups of a step: ceil(n / kPts)
 };
 
+static int mlp_groups(size_t n) { return (int)((n + kPts - 1) / kPts); }
+
 static size_t mlp_scratch_floats(size_t n, int in_dim) {
-    return 4 * n * kH + n + (size_t)kMlpChunks * mlp_np(in_dim) + 64;
+    return (size_t)mlp_groups(n) * mlp_np(in_dim) + 64;
 }
 
 static MlpScratch carve(float *base, size_t n, int in_dim) {
     MlpScratch s;
-    s.h1 = base;
-    s.h2 = s.h1 + n * kH;
-    s.dz1 = s.h2 + n * kH;
-    s.dz2 = s.dz1 + n * kH;
-    s.dout = s.dz2 + n * kH;
-    s.partial = s.dout + n;
-    s.wsum = s.partial + (size_t)kMlpChunks * mlp_np(in_dim);
+    s.partial = base;
+    s.groups = mlp_groups(n);
+    s.wsum = s.partial + (size_t)s.groups * mlp_np(in_dim);
     return s;
 }
 
-// Forward (and, when y != nullptr, the per-point backward quantities).
-template <bool BWD>
+// Parameters are read-only and the same for every lane of a wave: they are
+// read through the constant address space (uniform scalar loads into SGPRs).
+typedef const __attribute__((address_space(4))) float cparam_t;
+
+// Forward pass, one work-item per point.
 __global__ void __launch_bounds__(256) k_mlp_point(const float *__restrict__ prm, int in_dim,
-                                                   const float *__restrict__ X,
-                                                   const float *__restrict__ y,
-                                                   const float *__restrict__ wt, size_t n,
-                                                   float *__restrict__ out, MlpScratch S,
-                                                   float *__restrict__ loss) {
-    extern __shared__ float s_prm[];
-    const int np = mlp_np(in_dim);
-    for (int i = threadIdx.x; i < np; i += blockDim.x) s_prm[i] = prm[i];
-    __syncthreads();
-    const float *W1 = s_prm;
-    const float *b1 = W1 + kH * in_dim;
-    const float *W2 = b1 + kH;
-    const float *b2 = W2 + kH * kH;
-    const float *W3 = b2 + kH;
+                                                   const float *__restrict__ X, size_t n,
+                                                   float *__restrict__ out) {
+    cparam_t *W1 = (cparam_t *)(uintptr_t)prm;
+    cparam_t *b1 = W1 + kH * in_dim;
+    cparam_t *W2 = b1 + kH;
+    cparam_t *b2 = W2 + kH * kH;
+    cparam_t *W3 = b2 + kH;
     const float b3 = W3[kH];
     const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    float lterm = 0.0f;
-    if (p < n) {
-        float x[4 + kMaxG];
+    if (p >= n) return;
+    float x[4 + kMaxG];
 #pragma unroll
-        for (int k = 0; k < 4 + kMaxG; ++k) x[k] = k < in_dim ? X[p * in_dim + k] : 0.0f;
-        float h1[kH];
+    for (int k = 0; k < 4 + kMaxG; ++k) x[k] = k < in_dim ? X[p * in_dim + k] : 0.0f;
+    float h1[kH];
 #pragma unroll
-        for (int j = 0; j < kH; ++j) {
-            float acc = b1[j];
+    for (int j = 0; j < kH; ++j) {
+        float acc = b1[j];
 #pragma unroll
-            for (int k = 0; k < 4 + kMaxG; ++k)
-                if (k < in_dim) acc = acc + W1[j * in_dim + k] * x[k];
-            h1[j] = acc > 0.0f ? acc : 0.0f;
-        }
-        float o = b3;
-        for (int j = 0; j < kH; ++j) {
-            float acc = b2[j];
-#pragma unroll
-            for (int i = 0; i < kH; ++i) acc = acc + W2[j * kH + i] * h1[i];
-            const float h2 = acc > 0.0f ? acc : 0.0f;
-            if (BWD) S.h2[p * kH + j] = h2;
-            o = o + W3[j] * h2;
-        }
-        if (out) out[p] = o;
-        if (BWD) {
-#pragma unroll
-            for (int i = 0; i < kH; ++i) S.h1[p * kH + i] = h1[i];
-            const float inv = 1.0f / S.wsum[0];
-            const float r = o - y[p];
-            lterm = wt[p] * r * r * inv;
-            const float dout = 2.0f * wt[p] * r * inv;
-            S.dout[p] = dout;
-            float dh1[kH];
-#pragma unroll
-            for (int i = 0; i < kH; ++i) dh1[i] = 0.0f;
-            for (int j = 0; j < kH; ++j) {
-                const float h2 = S.h2[p * kH + j];
-                const float dz2 = h2 > 0.0f ? dout * W3[j] : 0.0f;
-                S.dz2[p * kH + j] = dz2;
-#pragma unroll
-                for (int i = 0; i < kH; ++i) dh1[i] = dh1[i] + dz2 * W2[j * kH + i];
-            }
-#pragma unroll
-            for (int i = 0; i < kH; ++i) S.dz1[p * kH + i] = h1[i] > 0.0f ? dh1[i] : 0.0f;
-        }
+        for (int k = 0; k < 4 + kMaxG; ++k)
+            if (k < in_dim) acc = acc + W1[j * in_dim + k] * x[k];
+        h1[j] = acc > 0.0f ? acc : 0.0f;
     }
-    if (BWD && loss) {
-        // wave reduction, then one atomic per wave
+    float o = b3;
+    for (int j = 0; j < kH; ++j) {
+        float acc = b2[j];
+#pragma unroll
+        for (int i = 0; i < kH; ++i) acc = acc + W2[j * kH + i] * h1[i];
+        const float h2 = acc > 0.0f ? acc : 0.0f;
+        o = o + W3[j] * h2;
+    }
+    out[p] = o;
+}
+
+// One training step's gradient for points [64 b, 64 b + 64): 512 work-items,
+// lane l of every wave is point 64 b + l, and wave w owns hidden units
+// [8 w, 8 w + 8) of both layers.  Per-point activations and backward
+// quantities live in LDS; parameters come through scalar loads.  Points past
+// n contribute nothing (their dL/dout is zero).
+constexpr int kStepThreads = 512;
+constexpr int kUnits = kH / (kStepThreads / 64);   // hidden units per wave
+constexpr size_t mlp_step_lds_floats(int in_dim) {
+    return (size_t)kPts * in_dim + 4 * kPts * kLd + (kStepThreads / 64) * kPts + kPts;
+}
+
+__global__ void __launch_bounds__(kStepThreads) k_mlp_step(const float *__restrict__ prm, int in_dim,
+                                                           const float *__restrict__ X,
+                                                           const float *__restrict__ y,
+                                                           const float *__restrict__ wt, size_t n,
+                                                           MlpScratch S, float *__restrict__ loss) {
+    constexpr int kWaves = kStepThreads / 64;
+    extern __shared__ float sm[];
+    float *s_x = sm;                                 // [64][in_dim]
+    float *s_h1 = s_x + kPts * in_dim;               // [64][kLd]
+    float *s_h2 = s_h1 + kPts * kLd;
+    float *s_dz1 = s_h2 + kPts * kLd;
+    float *s_dz2 = s_dz1 + kPts * kLd;
+    float *s_op = s_dz2 + kPts * kLd;                // [waves][64] output partials
+    float *s_dout = s_op + kWaves * kPts;            // [64]
+    cparam_t *W1 = (cparam_t *)(uintptr_t)prm;
+    cparam_t *b1 = W1 + kH * in_dim;
+    cparam_t *W2 = b1 + kH;
+    cparam_t *b2 = W2 + kH * kH;
+    cparam_t *W3 = b2 + kH;
+    const float b3 = W3[kH];
+    const int np = mlp_np(in_dim);
+    const int tid = threadIdx.x, l = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int u0 = kUnits * w;
+    const size_t p0 = (size_t)blockIdx.x * kPts;
+    for (int i = tid; i < kPts * in_dim; i += kStepThreads) {
+        const size_t pi = p0 + (size_t)(i / in_dim);
+        s_x[i] = pi < n ? X[p0 * in_dim + i] : 0.0f;
+    }
+    __syncthreads();
+    const size_t p = p0 + l;
+    // layer 1: this wave's units of point l
+    for (int u = 0; u < kUnits; ++u) {
+        const int i = u0 + u;
+        float acc = b1[i];
+        for (int k = 0; k < in_dim; ++k) acc = acc + W1[i * in_dim + k] * s_x[l * in_dim + k];
+        s_h1[l * kLd + i] = acc > 0.0f ? acc : 0.0f;
+    }
+    __syncthreads();
+    // layer 2 (this wave's units) and its share of the output
+    float a2[kUnits];
+#pragma unroll
+    for (int u = 0; u < kUnits; ++u) a2[u] = b2[u0 + u];
+    for (int i = 0; i < kH; ++i) {
+        const float h = s_h1[l * kLd + i];
+#pragma unroll
+        for (int u = 0; u < kUnits; ++u) a2[u] = a2[u] + W2[(u0 + u) * kH + i] * h;
+    }
+    float op = 0.0f;
+#pragma unroll
+    for (int u = 0; u < kUnits; ++u) {
+        const float h2 = a2[u] > 0.0f ? a2[u] : 0.0f;
+        s_h2[l * kLd + u0 + u] = h2;
+        op = op + W3[u0 + u] * h2;
+    }
+    s_op[w * kPts + l] = op;
+    __syncthreads();
+    // output (wave partials added in wave order), loss term and dL/dout
+    float o = b3;
+    for (int v = 0; v < kWaves; ++v) o = o + s_op[v * kPts + l];
+    float lterm = 0.0f, dout = 0.0f;
+    if (p < n) {
+        const float inv = 1.0f / S.wsum[0];
+        const float r = o - y[p];
+        lterm = wt[p] * r * r * inv;
+        dout = 2.0f * wt[p] * r * inv;
+    }
+    if (w == 0) s_dout[l] = dout;
+#pragma unroll
+    for (int u = 0; u < kUnits; ++u) {
+        const int j = u0 + u;
+        s_dz2[l * kLd + j] = s_h2[l * kLd + j] > 0.0f ? dout * W3[j] : 0.0f;
+    }
+    __syncthreads();
+    // dL/dz1 for this wave's units
+    float a1[kUnits];
+#pragma unroll
+    for (int u = 0; u < kUnits; ++u) a1[u] = 0.0f;
+    for (int j = 0; j < kH; ++j) {
+        const float dz = s_dz2[l * kLd + j];
+#pragma unroll
+        for (int u = 0; u < kUnits; ++u) a1[u] = a1[u] + dz * W2[j * kH + u0 + u];
+    }
+#pragma unroll
+    for (int u = 0; u < kUnits; ++u) {
+        const int i = u0 + u;
+        s_dz1[l * kLd + i] = s_h1[l * kLd + i] > 0.0f ? a1[u] : 0.0f;
+    }
+    __syncthreads();
+    // the workgroup's gradient, each parameter summed over its 64 points in
+    // point order.  W2[j][i]: work-item (i = lane, wave w) takes rows
+    // j = w, w + 8, ..., sharing each h1 read among them.
+    float *part = S.partial + (size_t)blockIdx.x * np;
+    const int ob1 = kH * in_dim, oW2 = ob1 + kH, ob2 = oW2 + kH * kH, oW3 = ob2 + kH, ob3 = oW3 + kH;
+    {
+        constexpr int kRows = kH / kWaves;
+        float g2[kRows];
+#pragma unroll
+        for (int k = 0; k < kRows; ++k) g2[k] = 0.0f;
+        for (int r = 0; r < kPts; ++r) {
+            const float h = s_h1[r * kLd + l];
+#pragma unroll
+            for (int k = 0; k < kRows; ++k) g2[k] = g2[k] + s_dz2[r * kLd + w + kWaves * k] * h;
+        }
+#pragma unroll
+        for (int k = 0; k < kRows; ++k) part[oW2 + (w + kWaves * k) * kH + l] = g2[k];
+    }
+    // every other parameter: W1, b1 (indices below oW2) and b2, W3, b3 (from ob2)
+    const int n_small = oW2 + (np - ob2);
+    for (int t = tid; t < n_small; t += kStepThreads) {
+        const int q = t < oW2 ? t : ob2 + (t - oW2);
+        float acc = 0.0f;
+        if (q < ob1) {
+            const int i = q / in_dim, k = q % in_dim;
+            for (int r = 0; r < kPts; ++r) acc = acc + s_dz1[r * kLd + i] * s_x[r * in_dim + k];
+        } else if (q < oW2) {
+            const int i = q - ob1;
+            for (int r = 0; r < kPts; ++r) acc = acc + s_dz1[r * kLd + i];
+        } else if (q < oW3) {
+            const int j = q - ob2;
+            for (int r = 0; r < kPts; ++r) acc = acc + s_dz2[r * kLd + j];
+        } else if (q < ob3) {
+            const int j = q - oW3;
+            for (int r = 0; r < kPts; ++r) acc = acc + s_dout[r] * s_h2[r * kLd + j];
+        } else {
+            for (int r = 0; r < kPts; ++r) acc = acc + s_dout[r];
+        }
+        part[q] = acc;
+    }
+    if (loss && w == 0) {
+        // wave reduction, then one atomic per workgroup
         for (int off = 32; off > 0; off >>= 1) lterm += __shfl_xor(lterm, off);
-        if ((threadIdx.x & 63) == 0 && lterm != 0.0f) atomicAdd(loss, lterm);
+        if (l == 0 && lterm != 0.0f) atomicAdd(loss, lterm);
     }
 }
 
@@ -124,49 +237,25 @@ __global__ void k_mlp_wsum(const float *__restrict__ wt, size_t n, float *__rest
     if (threadIdx.x == 0) wsum[0] = red[0];
 }
 
-// partial[c][q] = sum over points of chunk c of dL/dparam_q (point order)
-__global__ void __launch_bounds__(256) k_mlp_partial(int in_dim, const float *__restrict__ X,
-                                                     size_t n, MlpScratch S) {
-    const int np = mlp_np(in_dim);
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    const int c = blockIdx.y;
-    if (q >= np) return;
-    const size_t per = (n + kMlpChunks - 1) / kMlpChunks;
-    const size_t p0 = (size_t)c * per;
-    const size_t p1 = p0 + per < n ? p0 + per : n;
-    float acc = 0.0f;
-    const int oW1 = 0, ob1 = kH * in_dim, oW2 = ob1 + kH, ob2 = oW2 + kH * kH, oW3 = ob2 + kH,
-              ob3 = oW3 + kH;
-    if (q < ob1) {
-        const int i = q / in_dim, k = q % in_dim;
-        for (size_t p = p0; p < p1; ++p) acc += S.dz1[p * kH + i] * X[p * in_dim + k];
-    } else if (q < oW2) {
-        const int i = q - ob1;
-        for (size_t p = p0; p < p1; ++p) acc += S.dz1[p * kH + i];
-    } else if (q < ob2) {
-        const int j = (q - oW2) / kH, i = (q - oW2) % kH;
-        for (size_t p = p0; p < p1; ++p) acc += S.dz2[p * kH + j] * S.h1[p * kH + i];
-    } else if (q < oW3) {
-        const int j = q - ob2;
-        for (size_t p = p0; p < p1; ++p) acc += S.dz2[p * kH + j];
-    } else if (q < ob3) {
-        const int j = q - oW3;
-        for (size_t p = p0; p < p1; ++p) acc += S.dout[p] * S.h2[p * kH + j];
-    } else {
-        for (size_t p = p0; p < p1; ++p) acc += S.dout[p];
-    }
-    (void)oW1;
-    S.partial[(size_t)c * np + q] = acc;
-}
-
-// gradient = sum of chunk partials (chunk order); optional Adam update
+// gradient = sum of the workgroup partials (workgroup order); optional Adam
+// update
 __global__ void k_mlp_adam(int np, MlpScratch S, float *__restrict__ grad, float *__restrict__ prm,
                            float *__restrict__ m, float *__restrict__ v, float lr, float b1,
                            float b2, float eps, float c1, float c2, int do_adam) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= np) return;
-    float g = 0.0f;
-    for (int c = 0; c < kMlpChunks; ++c) g += S.partial[(size_t)c * np + q];
+    // eight interleaved running sums (independent loads in flight), added
+    // in a fixed order at the end
+    float a[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a[k] = 0.0f;
+    int c = 0;
+    for (; c + 8 <= S.groups; c += 8) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) a[k] += S.partial[(size_t)(c + k) * np + q];
+    }
+    for (int k = 0; c < S.groups; ++c, ++k) a[k] += S.partial[(size_t)c * np + q];
+    const float g = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
     if (grad) grad[q] = g;
     if (do_adam) {
         const float mq = b1 * m[q] + (1.0f - b1) * g;
@@ -188,13 +277,12 @@ static int mlp_check(int in_dim, size_t n) {
 
 static hipError_t step_grad(const float *prm, int in_dim, const float *X, const float *y,
                             const float *wt, size_t n, MlpScratch S, float *loss, hipStream_t s) {
-    const int np = mlp_np(in_dim);
-    const int block = 256;
-    const int grid = (int)((n + block - 1) / block);
-    hipLaunchKernelGGL((k_mlp_point<true>), dim3(grid), dim3(block), np * sizeof(float), s, prm,
-                       in_dim, X, y, wt, n, (float *)nullptr, S, loss);
-    hipLaunchKernelGGL(k_mlp_partial, dim3((np + block - 1) / block, kMlpChunks), dim3(block), 0, s,
-                       in_dim, X, n, S);
+    const size_t shm = mlp_step_lds_floats(in_dim) * sizeof(float);   // up to 71 KiB
+    if (shm > 65536)
+        (void)hipFuncSetAttribute((const void *)k_mlp_step, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)shm);
+    hipLaunchKernelGGL(k_mlp_step, dim3(S.groups), dim3(kStepThreads), shm, s, prm, in_dim, X, y, wt,
+                       n, S, loss);
     return hipGetLastError();
 }
 
@@ -214,10 +302,8 @@ int mcdc_mlp_forward(const float *prm, int32_t in_dim, const float *X, size_t n,
     if (st) return st;
     if (!prm || !X || !out) return fail(MCDC_E_INVALID, "null buffer");
     const int block = 256;
-    MlpScratch S{};
-    hipLaunchKernelGGL((k_mlp_point<false>), dim3((n + block - 1) / block), dim3(block),
-                       mlp_np(in_dim) * sizeof(float), (hipStream_t)stream, prm, in_dim, X,
-                       (const float *)nullptr, (const float *)nullptr, n, out, S, (float *)nullptr);
+    hipLaunchKernelGGL(k_mlp_point, dim3((n + block - 1) / block), dim3(block), 0,
+                       (hipStream_t)stream, prm, in_dim, X, n, out);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? MCDC_OK : hip_fail(e, "mlp_forward");
 }

@@ -31,28 +31,42 @@ def test_mlp_forward_matches_oracle():
     assert np.max(np.abs(got - ref)) <= 2e-5 * (np.max(np.abs(ref)) + 1)
 
 
-def test_mlp_gradient_matches_oracle():
-    import ctypes as C
+def _gpu_grad(p, X, y, wt, in_dim):
     import torch
     from paper_2409_04668_amd import mcdc
-    p = M.init_params(IN, H, seed=3)
-    X, y, wt = _data(2500, 4)          # several chunks and a ragged tail
     dev = torch.device("cuda:0")
     tp = torch.from_numpy(p).to(dev)
-    tX, ty, tw = (torch.from_numpy(a).to(dev) for a in (X, y, wt))
+    tX, ty, tw = (torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (X, y, wt))
     tg = torch.zeros_like(tp)
     tl = torch.zeros(1, dtype=torch.float32, device=dev)
-    scr = torch.empty(int(mcdc._lib.mcdc_mlp_scratch_bytes(IN, len(X))), dtype=torch.uint8, device=dev)
-    mcdc.check(mcdc._lib.mcdc_mlp_grad(mcdc._ptr(tp), IN, mcdc._ptr(tX), mcdc._ptr(ty),
+    scr = torch.empty(int(mcdc._lib.mcdc_mlp_scratch_bytes(in_dim, len(X))), dtype=torch.uint8,
+                      device=dev)
+    mcdc.check(mcdc._lib.mcdc_mlp_grad(mcdc._ptr(tp), in_dim, mcdc._ptr(tX), mcdc._ptr(ty),
                                        mcdc._ptr(tw), len(X), mcdc._ptr(tg), mcdc._ptr(tl),
                                        mcdc._ptr(scr), mcdc._stream_ptr()), "grad")
-    g = tg.cpu().numpy().astype(np.float64)
+    return tg.cpu().numpy(), tl.item()
+
+
+@pytest.mark.parametrize("in_dim,n", [(IN, 2500), (IN, 64), (IN, 1), (12, 3001)])
+def test_mlp_gradient_matches_oracle(in_dim, n):
+    """Several 64-point workgroups and a ragged last one, exactly one, a single
+    point, and the widest input (4 + 8 groups)."""
+    p = M.init_params(in_dim, H, seed=3)
+    X, y, wt = _data(n, 4)
+    if in_dim > IN:
+        rng = np.random.default_rng(9)
+        X = np.concatenate([X[:, :4], rng.uniform(0, 1, (n, in_dim - 4))], axis=1).astype(np.float32)
+    g, lo = _gpu_grad(p, X, y, wt, in_dim)
+    g = g.astype(np.float64)
     ref = M.grad(p.astype(np.float64), X.astype(np.float64), y.astype(np.float64),
-                 wt.astype(np.float64), IN, H)
-    lref = M.loss(p.astype(np.float64), X, y, wt, IN, H)
-    assert abs(tl.item() - lref) <= 1e-4 * lref
+                 wt.astype(np.float64), in_dim, H)
+    lref = M.loss(p.astype(np.float64), X, y, wt, in_dim, H)
+    assert abs(lo - lref) <= 1e-4 * lref
     assert np.linalg.norm(g - ref) <= 1e-4 * np.linalg.norm(ref)
     assert np.max(np.abs(g - ref)) <= 1e-4 * np.max(np.abs(ref))
+    # the gradient sums run in a fixed order: a second call is bit-identical
+    g2, _ = _gpu_grad(p, X, y, wt, in_dim)
+    assert np.array_equal(g2.astype(np.float64), g)
 
 
 def test_mlp_adam_training_matches_oracle_and_decreases_loss():
