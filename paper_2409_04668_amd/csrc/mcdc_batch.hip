@@ -77,13 +77,13 @@ struct BatchCtx {
     static constexpr bool kWW = false;
     static constexpr bool kWWMap = false;
     MCDC_DEV double *col_tally() const { return nullptr; }
-    const DevProblem &P;
+    CP &P;
     const RunArgs &A;
     const BDev &D;
     uint64_t hist_id;
     uint64_t slot;
     MCDC_DEV uint64_t hist() const { return hist_id; }
-    MCDC_DEV const float *mlp_params(const DevProblem &Pp) const { return Pp.ww_params; }
+    MCDC_DEV const float *mlp_params(CP &Pp) const { return Pp.ww_params; }
     // one particle per history (no weight windows in batched runs): the
     // history's flight count lives in the particle's bank slot
     MCDC_DEV bool count_flight() {
@@ -92,7 +92,7 @@ struct BatchCtx {
     }
     MCDC_DEV void add_score(double) {}
     MCDC_DEV void add_path(double v) { D.bd[8 * D.cap + slot] += v; }
-    MCDC_DEV void imp_point(const DevProblem &, const Part &) {}
+    MCDC_DEV void imp_point(CP &, const Part &) {}
     MCDC_DEV bool push_daughters(const Part &, uint32_t, int) { return false; }
 };
 
@@ -190,7 +190,8 @@ __global__ void __launch_bounds__(512) k_b_persistent(BDev D) {
         }
         const int p = __builtin_amdgcn_readfirstlane((int)lo);
         const BProb &BP = D.probs[p];
-        const DevProblem &P = BP.P;
+        // the problem array is not written during the launch
+        CP &P = *(CP *)(uintptr_t)&BP.P;
         if (p != tile_p) {
             if (tile_p >= 0) {
                 __syncthreads();

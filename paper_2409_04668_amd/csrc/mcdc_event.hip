@@ -154,7 +154,7 @@ template <int WW>
 struct EvCtx {
     static constexpr bool kWW = WW != 0;
     static constexpr bool kWWMap = WW == 2;
-    const DevProblem &P;
+    CP &P;
     const RunArgs &A;
     const EvBank &B;
     uint32_t slot;
@@ -166,7 +166,7 @@ struct EvCtx {
         return ((r + 1) * A.run_batches - 1) / A.run_n;
     }
     MCDC_DEV double *col_tally() const { return A.col + batch() * (uint64_t)P.nbins; }
-    MCDC_DEV const float *mlp_params(const DevProblem &Pp) const { return Pp.ww_params; }
+    MCDC_DEV const float *mlp_params(CP &Pp) const { return Pp.ww_params; }
     // several particles of one history can be in flight at once when they
     // split (weight windows, population control): their sums are atomic
     MCDC_DEV bool count_flight() {
@@ -184,7 +184,7 @@ struct EvCtx {
         if (WW || P.pc_on) unsafeAtomicAdd(&B.path[slot], v);
         else B.path[slot] += v;
     }
-    MCDC_DEV void imp_point(const DevProblem &, const Part &) {}
+    MCDC_DEV void imp_point(CP &, const Part &) {}
     // split daughters are only recorded here: the interaction kernel writes
     // them for a whole wave at once
     uint32_t split_n = 0, split_tag0 = 0;
@@ -196,7 +196,8 @@ struct EvCtx {
 };
 
 template <bool WW>
-__global__ void __launch_bounds__(256) k_ev_source(DevProblem P, RunArgs A, EvBank B, uint32_t n) {
+__global__ void __launch_bounds__(256) k_ev_source(DevProblem, RunArgs A, EvBank B, uint32_t n) {
+    CP &P = kernel_problem();
     __shared__ Shared S;
     shared_zero(S);
     __syncthreads();
@@ -238,7 +239,7 @@ template <int WW>
 struct LeadCtx {
     static constexpr bool kWW = WW != 0;
     static constexpr bool kWWMap = WW == 2;
-    const DevProblem &P;
+    CP &P;
     const RunArgs &A;
     const EvBank &B;
     uint64_t lane;
@@ -253,7 +254,7 @@ struct LeadCtx {
         return ((r + 1) * A.run_batches - 1) / A.run_n;
     }
     MCDC_DEV double *col_tally() const { return A.col + batch() * (uint64_t)P.nbins; }
-    MCDC_DEV const float *mlp_params(const DevProblem &Pp) const { return Pp.ww_params; }
+    MCDC_DEV const float *mlp_params(CP &Pp) const { return Pp.ww_params; }
     MCDC_DEV bool count_flight() {
         events += 1u;
         return (int64_t)events <= P.max_events;
@@ -262,7 +263,7 @@ struct LeadCtx {
     MCDC_DEV void add_path(double v) {
         if (A.keep_path) path += v;
     }
-    MCDC_DEV void imp_point(const DevProblem &, const Part &) {}
+    MCDC_DEV void imp_point(CP &, const Part &) {}
     // copy a particle ready for its next flight into the active bank
     MCDC_DEV void to_bank(const Part &q, uint32_t pos) const {
         bank_put(A, B, B.b[cur], pos, q, 0.0, slot);
@@ -294,15 +295,15 @@ struct LeadCtx {
 template <int LDS>
 struct LeadTally {
     GlobalTally t;
-    MCDC_DEV void init(const DevProblem &, double *) {}
-    MCDC_DEV void select(const DevProblem &P, const RunArgs &A, uint64_t b, uint64_t) {
+    MCDC_DEV void init(CP &, double *) {}
+    MCDC_DEV void select(CP &P, const RunArgs &A, uint64_t b, uint64_t) {
         t.base = A.tally + b * (uint64_t)P.nbins;
     }
 };
 template <>
 struct LeadTally<2> {
     HotTileTally t;
-    MCDC_DEV void init(const DevProblem &P, double *lds) {
+    MCDC_DEV void init(CP &P, double *lds) {
         t.lds = (lds_f64 *)lds;
         for (int a = 0; a < 5; ++a) {
             t.lo[a] = P.hot_lo[a];
@@ -311,7 +312,7 @@ struct LeadTally<2> {
     }
     // the tile holds batch b_tile only: an empty x extent sends every update
     // of another batch to HBM
-    MCDC_DEV void select(const DevProblem &P, const RunArgs &A, uint64_t b, uint64_t b_tile) {
+    MCDC_DEV void select(CP &P, const RunArgs &A, uint64_t b, uint64_t b_tile) {
         t.glob = (hbm_f64 *)(A.tally + b * (uint64_t)P.nbins);
         t.n[0] = b == b_tile ? P.hot_n[0] : 0u;
     }
@@ -332,8 +333,9 @@ MCDC_DEV uint64_t batch_of(const RunArgs &A, uint32_t slot) {
 // particle that reaches a census goes into the census bank.  The event stages
 // finish what was banked.  LDS: 0 tally in HBM, 2 hot tile in LDS.
 template <int LDS, int WW>
-__global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_ev_lead(DevProblem P, RunArgs A, EvBank B,
+__global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_ev_lead(DevProblem, RunArgs A, EvBank B,
                                                                   uint32_t n) {
+    CP &P = kernel_problem();
     extern __shared__ double s_tile[];
     __shared__ Shared S;
     __shared__ uint32_t s_next;
@@ -357,10 +359,11 @@ __global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_ev_lead(DevProblem P,
     q.alive = false;
     bool in_hist = false;
     for (;;) {
+        CP &PL = problem_reload(P);
         if (!q.alive) {
             if (WW != 0 && C.sp > 0) {
                 C.sp -= 1;
-                stack_pop(A, lane, P.stack_cap, C.sp, q);
+                stack_pop(A, lane, PL.stack_cap, C.sp, q);
             } else {
                 if (in_hist) {
                     B.xh[C.slot] = C.xh;
@@ -377,8 +380,8 @@ __global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_ev_lead(DevProblem P,
                 C.sp = 0;
                 lead_flights = 0;
                 in_hist = true;
-                tally.select(P, A, batch_of(A, s), b_tile);
-                stage_source(P, A, S, C, q);
+                tally.select(PL, A, batch_of(A, s), b_tile);
+                stage_source(PL, A, S, C, q);
                 if (!q.alive) continue;
             }
         }
@@ -388,7 +391,7 @@ __global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_ev_lead(DevProblem P,
             C.to_bank(q, base);
             for (int i = 0; i < C.sp; ++i) {
                 Part r;
-                stack_pop(A, lane, P.stack_cap, i, r);
+                stack_pop(A, lane, PL.stack_cap, i, r);
                 C.to_bank(r, base + 1u + (uint32_t)i);
             }
             C.sp = 0;
@@ -397,7 +400,7 @@ __global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_ev_lead(DevProblem P,
         }
         lead_flights += 1;
         double d = 0.0;
-        const int ev = stage_flight(P, A, S, tally.t, C, q, d, n_piece, path);
+        const int ev = stage_flight(PL, A, S, tally.t, C, q, d, n_piece, path);
         if (ev >= 0) n_flight += 1;
         if (!q.alive) {
             if (ev < 0) C.sp = 0;           // event cap: the history is abandoned
@@ -405,15 +408,15 @@ __global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_ev_lead(DevProblem P,
         }
         bool due = false;
         if (ev == EV_SURFACE) {
-            due = stage_surface(P, A, S, C, q, d);
+            due = stage_surface(PL, A, S, C, q, d);
         } else if (ev == EV_SCATTER) {
-            due = stage_collision(P, A, S, C, q, d);
+            due = stage_collision(PL, A, S, C, q, d);
         } else if (ev == EV_CENSUS && stop_at_census) {
             bank_put(A, B, B.b[cen], atomicAdd(&B.ctl->n_act[cen], 1u), q, d, C.slot);
             q.alive = false;
             continue;
         }
-        if (WW != 0 && due) ww_check(P, A, S, C, q);
+        if (WW != 0 && due) ww_check(PL, A, S, C, q);
     }
     atomicAdd(&S.cnt[C_FLIGHT], (unsigned long long)n_flight);
     atomicAdd(&S.cnt[C_PIECE], (unsigned long long)n_piece);
@@ -424,7 +427,8 @@ __global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_ev_lead(DevProblem P,
 }
 
 template <bool WW>
-__global__ void __launch_bounds__(256) k_ev_flight(DevProblem P, RunArgs A, EvBank B) {
+__global__ void __launch_bounds__(256) k_ev_flight(DevProblem, RunArgs A, EvBank B) {
+    CP &P = kernel_problem();
     __shared__ Shared S;
     if (B.ctl->paused) return;
     shared_zero(S);
@@ -435,6 +439,7 @@ __global__ void __launch_bounds__(256) k_ev_flight(DevProblem P, RunArgs A, EvBa
     uint32_t n_piece = 0, n_flight = 0;
     double path = 0.0;
     for (uint32_t j0 = blockIdx.x * blockDim.x; j0 < n; j0 += gridDim.x * blockDim.x) {
+        CP &PL = problem_reload(P);
         const uint32_t jj = j0 + threadIdx.x;
         const bool valid = jj < n;
         int ev = -1;
@@ -443,9 +448,9 @@ __global__ void __launch_bounds__(256) k_ev_flight(DevProblem P, RunArgs A, EvBa
         uint32_t slot = 0;
         if (valid) {
             bank_load(in, B.cap, jj, q, d, slot);
-            EvCtx<WW> C{P, A, B, slot};
-            GlobalTally tally{A.tally + C.batch() * (uint64_t)P.nbins};
-            ev = stage_flight(P, A, S, tally, C, q, d, n_piece, path);
+            EvCtx<WW> C{PL, A, B, slot};
+            GlobalTally tally{A.tally + C.batch() * (uint64_t)PL.nbins};
+            ev = stage_flight(PL, A, S, tally, C, q, d, n_piece, path);
             if (ev >= 0) n_flight += 1;
             if (!q.alive) ev = -1;
         }
@@ -513,7 +518,8 @@ MCDC_DEV bool last_block(EvCtl *c, bool &s_last) {
 // bank, the rest the collision entries at its back.  WW: 0 none, 1 network
 // at each check, 2 baked window map.
 template <int WW>
-__global__ void __launch_bounds__(256) k_ev_interact(DevProblem P, RunArgs A, EvBank B) {
+__global__ void __launch_bounds__(256) k_ev_interact(DevProblem, RunArgs A, EvBank B) {
+    CP &P = kernel_problem();
     __shared__ Shared S;
     __shared__ bool s_last;
     if (B.ctl->paused) return;
@@ -525,6 +531,7 @@ __global__ void __launch_bounds__(256) k_ev_interact(DevProblem P, RunArgs A, Ev
     const uint32_t n = ns + nc;
     const Bank X = B.b[R_X], out = B.b[nxt];
     for (uint32_t j0 = blockIdx.x * blockDim.x; j0 < n; j0 += gridDim.x * blockDim.x) {
+        CP &PL = problem_reload(P);
         const uint32_t jj = j0 + threadIdx.x;
         const bool valid = jj < n;
         bool alive = false;
@@ -534,9 +541,9 @@ __global__ void __launch_bounds__(256) k_ev_interact(DevProblem P, RunArgs A, Ev
         if (valid) {
             const bool surf = jj < ns;
             bank_load(X, B.cap, surf ? jj : B.cap - 1u - (jj - ns), q, d, slot);
-            EvCtx<WW> C{P, A, B, slot};
-            const bool due = surf ? stage_surface(P, A, S, C, q, d) : stage_collision(P, A, S, C, q, d);
-            if (WW != 0 && due) ww_check(P, A, S, C, q);
+            EvCtx<WW> C{PL, A, B, slot};
+            const bool due = surf ? stage_surface(PL, A, S, C, q, d) : stage_collision(PL, A, S, C, q, d);
+            if (WW != 0 && due) ww_check(PL, A, S, C, q);
             alive = q.alive;
             if (WW != 0 && C.split_n > 1) {
                 nd = C.split_n - 1;
@@ -578,7 +585,8 @@ __global__ void __launch_bounds__(256) k_ev_pc_sum(EvBank B) {
 // becomes n = floor(w / w_T + xi) particles of weight w_T, the copies taking
 // stream tags from one further block.  Survivors and copies go to the next
 // active bank, which then becomes the active bank.
-__global__ void __launch_bounds__(256) k_ev_pc_apply(DevProblem P, RunArgs A, EvBank B) {
+__global__ void __launch_bounds__(256) k_ev_pc_apply(DevProblem, RunArgs A, EvBank B) {
+    CP &P = kernel_problem();
     __shared__ Shared S;
     __shared__ bool s_last;
     if (B.ctl->pc_stage != 2) return;

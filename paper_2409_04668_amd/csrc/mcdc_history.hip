@@ -19,7 +19,7 @@ template <int WW, bool IMP>
 struct HistCtx {
     static constexpr bool kWW = WW != 0;
     static constexpr bool kWWMap = WW == 2;
-    const DevProblem &P;
+    CP &P;
     const RunArgs &A;
     uint64_t lane;
     uint64_t id;
@@ -29,7 +29,7 @@ struct HistCtx {
 
     MCDC_DEV uint64_t hist() const { return id; }
     MCDC_DEV double *col_tally() const { return A.col; }
-    MCDC_DEV const float *mlp_params(const DevProblem &Pp) const { return Pp.ww_params; }
+    MCDC_DEV const float *mlp_params(CP &Pp) const { return Pp.ww_params; }
     MCDC_DEV bool count_flight() {
         events += 1;
         return events <= P.max_events;
@@ -53,7 +53,7 @@ struct HistCtx {
     }
     // forward importance estimate: record the score so far at each flight
     // start, per distinct coarse cell (at most kImpList cells per history)
-    MCDC_DEV void imp_point(const DevProblem &Pp, const Part &q) {
+    MCDC_DEV void imp_point(CP &Pp, const Part &q) {
         if (!IMP) return;
         int ix[4];
 #pragma unroll
@@ -117,13 +117,13 @@ struct TallyFor<1> { using type = LdsTally; };
 template <>
 struct TallyFor<2> { using type = HotTileTally; };
 
-MCDC_DEV GlobalTally make_tally(GlobalTally *, const DevProblem &, const RunArgs &A, double *) {
+MCDC_DEV GlobalTally make_tally(GlobalTally *, CP &, const RunArgs &A, double *) {
     return GlobalTally{A.tally};
 }
-MCDC_DEV LdsTally make_tally(LdsTally *, const DevProblem &, const RunArgs &, double *lds) {
+MCDC_DEV LdsTally make_tally(LdsTally *, CP &, const RunArgs &, double *lds) {
     return LdsTally{(lds_f64 *)lds};
 }
-MCDC_DEV HotTileTally make_tally(HotTileTally *, const DevProblem &P, const RunArgs &A, double *lds) {
+MCDC_DEV HotTileTally make_tally(HotTileTally *, CP &P, const RunArgs &A, double *lds) {
     HotTileTally t;
     t.lds = (lds_f64 *)lds;
     t.glob = (hbm_f64 *)A.tally;
@@ -135,7 +135,8 @@ MCDC_DEV HotTileTally make_tally(HotTileTally *, const DevProblem &P, const RunA
 }
 
 template <int LDS, int WW, bool IMP>
-__global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_history(DevProblem P, RunArgs A) {
+__global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_history(DevProblem, RunArgs A) {
+    CP &P = kernel_problem();
     extern __shared__ double s_tile[];
     __shared__ Shared S;
     shared_zero(S);
@@ -157,6 +158,7 @@ __global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_history(DevProblem P,
 
     bool ww_due = false;                    // a weight-window check waits for this lane
     for (;;) {
+        CP &PL = problem_reload(P);
         if (WW == 1) {
             // Weight-window checks run batched: a lane that needs one waits
             // (its particle does not move) until at least half of the wave's
@@ -165,7 +167,7 @@ __global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_history(DevProblem P,
             const uint64_t due = __ballot(ww_due);
             if (due && 2 * __popcll(due) >= __popcll(__ballot(true))) {
                 if (ww_due) {
-                    ww_check(P, A, S, H, q);
+                    ww_check(PL, A, S, H, q);
                     ww_due = false;
                 }
                 continue;
@@ -175,7 +177,7 @@ __global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_history(DevProblem P,
         if (!q.alive) {
             if (WW && H.sp > 0) {
                 H.sp -= 1;
-                stack_pop(A, lane, P.stack_cap, H.sp, q);
+                stack_pop(A, lane, PL.stack_cap, H.sp, q);
             } else {
                 if (in_hist) {
                     finish_history(A, S, H);
@@ -191,21 +193,21 @@ __global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_history(DevProblem P,
                 H.n_imp = 0;
                 in_hist = true;
                 n_hist += 1;
-                stage_source(P, A, S, H, q);
+                stage_source(PL, A, S, H, q);
                 if (!q.alive) continue;
             }
         }
         double d;
-        const int ev = stage_flight(P, A, S, tally, H, q, d, n_piece, path);
+        const int ev = stage_flight(PL, A, S, tally, H, q, d, n_piece, path);
         if (ev == EV_SURFACE) {
-            ww_due = stage_surface(P, A, S, H, q, d);
+            ww_due = stage_surface(PL, A, S, H, q, d);
         } else if (ev == EV_SCATTER) {
-            ww_due = stage_collision(P, A, S, H, q, d);
+            ww_due = stage_collision(PL, A, S, H, q, d);
         } else if (ev < 0) {
             H.sp = 0;                       // event cap: the history is abandoned
         }
         if (WW == 2 && ww_due) {            // a map read is cheap: check at once
-            ww_check(P, A, S, H, q);
+            ww_check(PL, A, S, H, q);
             ww_due = false;
         }
         if (ev >= 0) n_flight += 1;

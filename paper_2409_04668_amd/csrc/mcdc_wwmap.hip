@@ -11,9 +11,10 @@ namespace mcdc {
 
 // One thread per map cell, layout [g][t][z][y][x]; cell-centre inputs
 // 2 (i + 1/2) / n - 1 per axis, rounded to float once.
-__global__ void __launch_bounds__(256) k_ww_bake(DevProblem P, const float *__restrict__ prm,
+__global__ void __launch_bounds__(256) k_ww_bake(DevProblem, const float *__restrict__ prm,
                                                  int32_t nx, int32_t ny, int32_t nz, int32_t nt,
                                                  uint64_t cells, double *__restrict__ out) {
+    CP &P = kernel_problem();
     const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= cells) return;
     uint64_t r = c;

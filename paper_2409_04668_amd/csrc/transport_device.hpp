@@ -21,6 +21,26 @@ namespace mcdc {
 
 #define MCDC_DEV __device__ __forceinline__
 
+// The problem description as the kernels read it: in the constant address
+// space, so that its fields (the same for every lane) come through uniform
+// scalar loads.  Every kernel that takes the description by value takes it
+// as its first argument, at offset 0 of the kernel-argument segment, and
+// reads it there.
+typedef const __attribute__((address_space(4))) DevProblem CP;
+
+MCDC_DEV CP &kernel_problem() { return *(CP *)__builtin_amdgcn_kernarg_segment_ptr(); }
+
+// An opaque copy of the description's address, taken once per turn of a
+// long transport loop: the compiler then loads each field where it is used
+// (scalar-cache hits) instead of hoisting every field out of the loop into
+// SGPRs, which overflow and spill to VGPR lanes (one v_readlane per 32 bits
+// at every use).
+MCDC_DEV CP &problem_reload(CP &P) {
+    CP *p = &P;
+    asm volatile("" : "+s"(p));
+    return *p;
+}
+
 constexpr double kInf = __builtin_huge_val();
 
 // ---------------------------------------------------------------------------
@@ -174,12 +194,14 @@ MCDC_DEV bool axis_in(double lo, double hi, double p, double u) {
     return false;
 }
 
-MCDC_DEV bool box_in(const double lo[3], const double hi[3], const double p[3], const double u[3]) {
+typedef const __attribute__((address_space(4))) double cdouble_t;   // a field of CP
+
+MCDC_DEV bool box_in(cdouble_t *lo, cdouble_t *hi, const double p[3], const double u[3]) {
     return axis_in(lo[0], hi[0], p[0], u[0]) && axis_in(lo[1], hi[1], p[1], u[1]) &&
            axis_in(lo[2], hi[2], p[2], u[2]);
 }
 
-MCDC_DEV int locate(const DevProblem &P, const double p[3], const double u[3]) {
+MCDC_DEV int locate(CP &P, const double p[3], const double u[3]) {
     for (int b = 0; b < P.n_boxes; ++b)
         if (box_in(P.box_lo[b], P.box_hi[b], p, u)) return b;
     return -1;
@@ -188,7 +210,7 @@ MCDC_DEV int locate(const DevProblem &P, const double p[3], const double u[3]) {
 // Next surface along u: outer-box exit, then per box its exit (inside) or
 // slab-test entry (0 <= entry < exit).  First strict minimum wins in the order
 // outer box, boxes ascending, axes x,y,z; negative exits clamp to 0.
-MCDC_DEV double dist_surface(const DevProblem &P, const double p[3], const double u[3],
+MCDC_DEV double dist_surface(CP &P, const double p[3], const double u[3],
                              const double iu[3], int &axis, double &plane) {
     double best = kInf;
     int bax = -1;
@@ -202,8 +224,8 @@ MCDC_DEV double dist_surface(const DevProblem &P, const double p[3], const doubl
         if (s < best) { best = s; bax = a; bpl = pl; }
     }
     for (int b = 0; b < P.n_boxes; ++b) {
-        const double *lo = P.box_lo[b];
-        const double *hi = P.box_hi[b];
+        cdouble_t *lo = P.box_lo[b];
+        cdouble_t *hi = P.box_hi[b];
         if (box_in(lo, hi, p, u)) {
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
@@ -241,7 +263,7 @@ MCDC_DEV double dist_surface(const DevProblem &P, const double p[3], const doubl
 }
 
 // Part of [0,d] inside the detector box.
-MCDC_DEV double detector_len(const DevProblem &P, const double p[3], const double u[3],
+MCDC_DEV double detector_len(CP &P, const double p[3], const double u[3],
                              const double iu[3], double d) {
     double si = 0.0, so = d;
 #pragma unroll
@@ -310,7 +332,7 @@ struct HotTileTally {
 
 // Add a workgroup's hot tile (LDS, x fastest over the tile box) into the mesh
 // tally at `out`: one HBM atomic per touched bin.
-MCDC_DEV void hot_tile_flush(const DevProblem &P, const double *tile, double *out) {
+MCDC_DEV void hot_tile_flush(CP &P, const double *tile, double *out) {
     const uint32_t nx = P.hot_n[0], ny = P.hot_n[1], nz = P.hot_n[2], nt = P.hot_n[3];
     const uint32_t mx = P.mesh_n[0], my = P.mesh_n[1], mz = P.mesh_n[2], mt = P.mesh_n[3];
     for (uint32_t j = threadIdx.x; j < P.hot_bins; j += blockDim.x) {
@@ -333,7 +355,7 @@ MCDC_DEV void hot_tile_flush(const DevProblem &P, const double *tile, double *ou
 // all axes at the minimum advance together); each in-mesh piece of positive
 // length adds w * length to tally[g][it][iz][iy][ix].  Returns the pieces.
 template <class T>
-MCDC_DEV uint32_t score_mesh(const DevProblem &P, const double p[3], const double u[3],
+MCDC_DEV uint32_t score_mesh(CP &P, const double p[3], const double u[3],
                              const double iu[3], double t0, double v, double d, double w, int g,
                              const T &tally) {
     if (!(d > 0.0)) return 0;
@@ -479,7 +501,7 @@ MCDC_DEV float mlp_infer(const float *__restrict__ gprm, int in_dim, const float
 // Mesh bin holding a point (x, y, z, t) in group g, for the collision
 // estimator: per axis floor((p - lo) / delta); -1 outside the mesh (an
 // unbounded axis is one bin).
-MCDC_DEV int64_t mesh_point_bin(const DevProblem &P, const double p[3], double t, int g) {
+MCDC_DEV int64_t mesh_point_bin(CP &P, const double p[3], double t, int g) {
     int64_t c = P.G_t > 1 ? g : 0;
 #pragma unroll
     for (int a = 3; a >= 0; --a) {
@@ -498,7 +520,7 @@ MCDC_DEV int64_t mesh_point_bin(const DevProblem &P, const double p[3], double t
 // Map cell of a point for the weight-window map: per axis floor(s n) of the
 // fraction s of the outer box (of the last census time), clamped to [0, n-1];
 // layout [g][t][z][y][x].
-MCDC_DEV int64_t ww_map_cell(const DevProblem &P, const Part &q) {
+MCDC_DEV int64_t ww_map_cell(CP &P, const Part &q) {
     int64_t c = q.g;
 #pragma unroll
     for (int a = 3; a >= 0; --a) {
@@ -514,7 +536,7 @@ MCDC_DEV int64_t ww_map_cell(const DevProblem &P, const Part &q) {
 // Window target from the network: output y at the normalised point (2 s - 1
 // per axis, group one-hot), clamped to its training-target range, and
 // w_T = exp(log K - y).
-MCDC_DEV double ww_net_target(const DevProblem &P, const float *prm, const float xt[4], int g) {
+MCDC_DEV double ww_net_target(CP &P, const float *prm, const float xt[4], int g) {
     float in[4 + kMaxG];
 #pragma unroll
     for (int a = 0; a < 4; ++a) in[a] = xt[a];

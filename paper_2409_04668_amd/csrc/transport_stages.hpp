@@ -56,7 +56,7 @@ MCDC_DEV void trace_rec(const RunArgs &A, uint64_t hist, Part &q, int type, doub
 MCDC_DEV void set_status(const RunArgs &A, int st) { atomicMin(&A.acc->status, st); }
 
 // outer boundary after a surface crossing; returns the leak face or -1
-MCDC_DEV int boundary(const DevProblem &P, Part &q) {
+MCDC_DEV int boundary(CP &P, Part &q) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         if (axis_in(P.outer_lo[a], P.outer_hi[a], q.x[a], q.u[a])) continue;
@@ -89,7 +89,7 @@ MCDC_DEV void leak(Shared &S, Part &q, int face) {
 // roulette below it, nothing (and no draw) inside.  w_T comes from the
 // network at the particle's point, or from the map cell that holds it.
 template <class Ctx>
-MCDC_DEV void ww_check(const DevProblem &P, const RunArgs &A, Shared &S, Ctx &C, Part &q) {
+MCDC_DEV void ww_check(CP &P, const RunArgs &A, Shared &S, Ctx &C, Part &q) {
     double wt;
     if (Ctx::kWWMap) {
         wt = P.ww_map[ww_map_cell(P, q)];
@@ -140,7 +140,7 @@ MCDC_DEV void ww_check(const DevProblem &P, const RunArgs &A, Shared &S, Ctx &C,
 // group, unit weight, cell; leaks at once when born on the outer boundary
 // moving out.
 template <class Ctx>
-MCDC_DEV void stage_source(const DevProblem &P, const RunArgs &A, Shared &S, Ctx &C, Part &q) {
+MCDC_DEV void stage_source(CP &P, const RunArgs &A, Shared &S, Ctx &C, Part &q) {
     q.tag = 0;
     q.k = 0;
     q.seq = 0;
@@ -193,7 +193,7 @@ MCDC_DEV void stage_source(const DevProblem &P, const RunArgs &A, Shared &S, Ctx
 // EV_TIME_END or -1 (particle ended), EV_SURFACE or EV_SCATTER (the surface or
 // collision stage comes next; `d` is the flight length).
 template <class T, class Ctx>
-MCDC_DEV int stage_flight(const DevProblem &P, const RunArgs &A, Shared &S, const T &tally, Ctx &C,
+MCDC_DEV int stage_flight(CP &P, const RunArgs &A, Shared &S, const T &tally, Ctx &C,
                           Part &q, double &d, uint32_t &n_piece, double &path) {
     if (!C.count_flight()) {
         set_status(A, MCDC_E_EVENT_CAP);
@@ -267,7 +267,7 @@ MCDC_DEV int stage_flight(const DevProblem &P, const RunArgs &A, Shared &S, cons
 // when a weight-window check is due (the caller runs ww_check before the
 // particle moves again, possibly batched with other lanes).
 template <class Ctx>
-MCDC_DEV bool stage_surface(const DevProblem &P, const RunArgs &A, Shared &S, Ctx &C, Part &q,
+MCDC_DEV bool stage_surface(CP &P, const RunArgs &A, Shared &S, Ctx &C, Part &q,
                             double d) {
     atomicAdd(&S.cnt[C_SURFACE], 1ull);
     const int face = boundary(P, q);
@@ -285,7 +285,7 @@ MCDC_DEV bool stage_surface(const DevProblem &P, const RunArgs &A, Shared &S, Ct
 // the outgoing group (cumulative row) and an isotropic direction.  Returns
 // true when a weight-window check is due.
 template <class Ctx>
-MCDC_DEV bool stage_collision(const DevProblem &P, const RunArgs &A, Shared &S, Ctx &C, Part &q,
+MCDC_DEV bool stage_collision(CP &P, const RunArgs &A, Shared &S, Ctx &C, Part &q,
                               double d) {
     atomicAdd(&S.cnt[C_COLLISION], 1ull);
     const int mat = q.cell >= 0 ? P.box_mat[q.cell] : P.background_mat;
