@@ -377,6 +377,46 @@ static int64_t o_point_bin(const o_mesh *M, const double p[3], double t, int g)
     return c;
 }
 
+/* Surface-current tally (a reading; the paper names tallies but defines no
+ * surface estimator): the plane x[a] = c of one axis.  A flight p + s u,
+ * s in (0, d], crosses it at s* = (c - p[a]) * (1 / u[a]) when 0 < s* <= d,
+ * and adds its weight w to the bin of the crossing: side (0 when u[a] > 0,
+ * 1 when u[a] < 0), group (per-group meshes), the time bin of t + s* / v and
+ * the mesh bins of the two other axes at p + s* u (the lower axis fastest);
+ * a crossing outside the mesh is not scored.  A flight that ends on the plane
+ * counts there; the next one, starting on it, does not.  The number of
+ * surface bins is 2 G_t nt n_b1 n_b2.  Returns 1 when it scored. */
+static int o_score_surface(const o_mesh *M, int a, double c, const double p[3],
+                           const double u[3], const double iu[3], double t0, double v,
+                           double d, double w, int g, double *out)
+{
+    if (u[a] == 0.0) return 0;
+    double sx = (c - p[a]) * iu[a];
+    if (!(sx > 0.0 && sx <= d)) return 0;
+    int b1 = a == 0 ? 1 : 0, b2 = a == 2 ? 1 : 2;
+    int64_t i1 = 0, i2 = 0, it;
+    if (M->bounded[b1]) {
+        double f = floor((p[b1] + u[b1] * sx - M->lo[b1]) * M->idelta[b1]);
+        if (f < 0.0 || f >= (double)M->n[b1]) return 0;
+        i1 = (int64_t)f;
+    }
+    if (M->bounded[b2]) {
+        double f = floor((p[b2] + u[b2] * sx - M->lo[b2]) * M->idelta[b2]);
+        if (f < 0.0 || f >= (double)M->n[b2]) return 0;
+        i2 = (int64_t)f;
+    }
+    {
+        double f = floor((t0 + sx / v - M->lo[3]) * M->idelta[3]);
+        if (f < 0.0 || f >= (double)M->n[3]) return 0;
+        it = (int64_t)f;
+    }
+    int64_t side = u[a] > 0.0 ? 0 : 1;
+    int64_t gg = M->G_t > 1 ? g : 0;
+    int64_t bin = (((side * M->G_t + gg) * M->n[3] + it) * M->n[b2] + i2) * M->n[b1] + i1;
+    out[bin] += w;
+    return 1;
+}
+
 /* returns pieces scored; tally may be NULL (count only) */
 static int64_t o_score_mesh(const o_mesh *M, const double p[3], const double u[3],
                             const double iu[3], double t0, double v, double d, double w,
@@ -809,6 +849,10 @@ static void o_flight(o_ctx *C, o_part *q)
     }
     R->wsum[ORC_W_PATH] += q->w * d;
     C->path_h += q->w * d;
+    if (P->surf_on)
+        R->cnt[ORC_C_SURF_CROSS] += (uint64_t)o_score_surface(&C->M, P->surf_axis, P->surf_pos, q->p,
+                                                              q->u, iu, q->t, v, d, q->w, q->g,
+                                                              R->surf_batch);
 
     /* move (Fig. 2) */
     q->p[0] = q->p[0] + q->u[0] * d;
@@ -1180,6 +1224,8 @@ static int o_validate(const orc_problem *P)
         return ORC_E_INVALID;
     if (P->imp_on && (P->ww_on || P->implicit_capture)) return ORC_E_INVALID;
     if (P->pc_on && (P->imp_on || !(P->pc_target > 0.0))) return ORC_E_INVALID;
+    if (P->surf_on && (P->surf_axis < 0 || P->surf_axis > 2 || !isfinite(P->surf_pos)))
+        return ORC_E_INVALID;
     if (P->ww_on) {
         int pos = 0, zero = 0;
         for (int a = 0; a < 4; ++a) {
@@ -1199,6 +1245,7 @@ int orc_run(const orc_problem *P, uint64_t seed, uint64_t hist0, uint64_t n_hist
     int st = o_validate(P);
     if (st != ORC_OK) return st;
     if (P->col_tally && (!R->col_batch || !R->col_sum || !R->col_sumsq)) return ORC_E_INVALID;
+    if (P->surf_on && (!R->surf_batch || !R->surf_sum || !R->surf_sumsq)) return ORC_E_INVALID;
     o_ctx C;
     memset(&C, 0, sizeof(C));
     C.P = P;
@@ -1242,6 +1289,18 @@ int orc_run(const orc_problem *P, uint64_t seed, uint64_t hist0, uint64_t n_hist
                     R->col_sum[i] += cb;
                     R->col_sumsq[i] += cb * cb / nb;
                     R->col_batch[i] = 0.0;
+                }
+            }
+        }
+        if (P->surf_on) {
+            int a = P->surf_axis, b1 = a == 0 ? 1 : 0, b2 = a == 2 ? 1 : 2;
+            size_t ns = (size_t)2 * C.M.G_t * P->mesh_n[3] * P->mesh_n[b1] * P->mesh_n[b2];
+            for (size_t i = 0; i < ns; ++i) {
+                double sb = R->surf_batch[i];
+                if (sb != 0.0) {
+                    R->surf_sum[i] += sb;
+                    R->surf_sumsq[i] += sb * sb / nb;
+                    R->surf_batch[i] = 0.0;
                 }
             }
         }

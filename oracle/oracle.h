@@ -51,7 +51,7 @@ enum {
     ORC_C_HIST = 0, ORC_C_FLIGHT, ORC_C_PIECE, ORC_C_COLLISION, ORC_C_ABSORB,
     ORC_C_SURFACE, ORC_C_LEAK, ORC_C_CENSUS, ORC_C_TIME_END, ORC_C_SPLIT,
     ORC_C_RR_KILL, ORC_C_RR_SURVIVE, ORC_C_CUT_KILL, ORC_C_CUT_SURVIVE,
-    ORC_C_DET_HIT, ORC_C_PARTICLE, ORC_C_PC_KILL, ORC_C_PC_COPY, ORC_NCOUNT
+    ORC_C_DET_HIT, ORC_C_PARTICLE, ORC_C_PC_KILL, ORC_C_PC_COPY, ORC_C_SURF_CROSS, ORC_NCOUNT
 };
 /* weight sums */
 enum {
@@ -94,6 +94,10 @@ typedef struct {
                                          network, (nx, ny, nz, nt) cells; 0: network
                                          evaluated at every check */
     int32_t col_tally;                /* also a collision-estimator mesh tally */
+    int32_t surf_on;                  /* also a surface-current tally on the plane
+                                         x[surf_axis] = surf_pos                 */
+    int32_t surf_axis;
+    double surf_pos;
     int32_t pc_on;                    /* population control at every intermediate
                                          census: a batch's histories advance census
                                          step by census step together */
@@ -117,6 +121,7 @@ typedef struct {
     double *tally_sum;        /* [nbins] sum over batches of S_b              */
     double *tally_sumsq;      /* [nbins] sum over batches of S_b^2 / N_b      */
     double *col_batch, *col_sum, *col_sumsq;  /* collision estimator, same layout */
+    double *surf_batch, *surf_sum, *surf_sumsq;  /* surface current, [2][G_t][nt][n_b2][n_b1] */
     double det[2];            /* sum x_h, sum x_h^2 over histories            */
     double leak[6];
     double wsum[ORC_NWSUM];

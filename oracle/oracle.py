@@ -21,11 +21,11 @@ LIB_PATH = os.path.join(HERE, "liboracle.so")
 CFLAGS = ["-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
           "-Wall", "-Wno-unused-function"]
 
-NCOUNT = 18
+NCOUNT = 19
 NWSUM = 7
 COUNTER_NAMES = ["hist", "flight", "piece", "collision", "absorb", "surface", "leak",
                  "census", "time_end", "split", "rr_kill", "rr_survive", "cut_kill",
-                 "cut_survive", "det_hit", "particle", "pc_kill", "pc_copy"]
+                 "cut_survive", "det_hit", "particle", "pc_kill", "pc_copy", "surf_cross"]
 WSUM_NAMES = ["source", "leak", "absorb", "time_end", "gain", "loss", "path"]
 
 EV = dict(source=0, scatter=1, absorb=2, surface=3, leak=4, census=5, time_end=6, split=7,
@@ -68,7 +68,8 @@ class OrcProblem(C.Structure):
         ("ww_on", C.c_int32), ("ww_hidden", C.c_int32), ("ww_nmax", C.c_int32),
         ("ww_params", PF), ("ww_ymin", C.c_float), ("ww_ymax", C.c_float),
         ("ww_logk", C.c_double), ("ww_ratio", C.c_double), ("ww_map_n", I4),
-        ("col_tally", C.c_int32), ("pc_on", C.c_int32), ("pc_target", C.c_double),
+        ("col_tally", C.c_int32), ("surf_on", C.c_int32), ("surf_axis", C.c_int32),
+        ("surf_pos", C.c_double), ("pc_on", C.c_int32), ("pc_target", C.c_double),
         ("n_batches", C.c_int32), ("max_events", C.c_int64), ("stack_cap", C.c_int32),
         ("problem_id", C.c_uint32),
     ]
@@ -92,6 +93,7 @@ assert TRACE_DTYPE.itemsize == C.sizeof(OrcTraceRec)
 class OrcResult(C.Structure):
     _fields_ = [("tally_batch", PD), ("tally_sum", PD), ("tally_sumsq", PD),
                 ("col_batch", PD), ("col_sum", PD), ("col_sumsq", PD),
+                ("surf_batch", PD), ("surf_sum", PD), ("surf_sumsq", PD),
                 ("det", C.c_double * 2), ("leak", C.c_double * 6), ("wsum", C.c_double * NWSUM),
                 ("cnt", C.c_uint64 * NCOUNT), ("imp_score", PD), ("imp_weight", PD),
                 ("hist_xh", PD), ("trace", C.POINTER(OrcTraceRec)), ("trace_cap", C.c_int64),
@@ -206,6 +208,11 @@ class _Problem:
             if ww.get("map") is not None:
                 s.ww_map_n = I4(*[int(v) for v in ww["map"]])
         s.col_tally = 1 if prob.get("collision_tally") else 0
+        sf = prob.get("surface_tally")
+        s.surf_on = 1 if sf is not None else 0
+        if sf is not None:
+            s.surf_axis = int(sf["axis"])
+            s.surf_pos = float(sf["pos"])
         pc = prob.get("population_control")
         s.pc_on = 1 if pc is not None else 0
         s.pc_target = float(pc["target"]) if pc is not None else 0.0
@@ -216,6 +223,11 @@ class _Problem:
         self.s = s
         mn = [int(v) for v in m["n"]]
         self.nbins = (G if m["per_group"] else 1) * mn[0] * mn[1] * mn[2] * mn[3]
+        self.n_surf = 0
+        if sf is not None:
+            a = int(sf["axis"])
+            b1, b2 = (1, 2) if a == 0 else ((0, 2) if a == 1 else (0, 1))
+            self.n_surf = 2 * (G if m["per_group"] else 1) * mn[3] * mn[b1] * mn[b2]
         self.n_imp = G * int(np.prod(imp["n"])) if imp is not None else 0
 
 
@@ -246,6 +258,13 @@ class OracleRun:
             self.col_sumsq = np.zeros(nb)
             self.R.col_batch, self.R.col_sum, self.R.col_sumsq = (
                 _pd(self.col_batch), _pd(self.col_sum), _pd(self.col_sumsq))
+        if self.P.n_surf:
+            ns = self.P.n_surf
+            self.surf_batch = np.zeros(ns)
+            self.surf_sum = np.zeros(ns)
+            self.surf_sumsq = np.zeros(ns)
+            self.R.surf_batch, self.R.surf_sum, self.R.surf_sumsq = (
+                _pd(self.surf_batch), _pd(self.surf_sum), _pd(self.surf_sumsq))
         if self.P.n_imp:
             self.R.imp_score, self.R.imp_weight = _pd(self.imp_score), _pd(self.imp_weight)
         self.n_hist = 0
@@ -304,11 +323,14 @@ class OracleRun:
     def mesh_stats(self, estimator: str = "track"):
         """Per-bin mean score per source particle and its standard error from
         batch means (weighted form for unequal batches); estimator "track"
-        (track length) or "collision"."""
+        (track length), "collision", or "surface" (surface-current bins
+        [side][group][t][b2][b1], side 0 crossing in +axis direction)."""
         N = float(self.n_hist)
         B = int(self.R.batches_done)
-        s1, s2 = ((self.tally_sum, self.tally_sumsq) if estimator == "track"
-                  else (self.col_sum, self.col_sumsq))
+        s1, s2 = {"track": (self.tally_sum, self.tally_sumsq),
+                  "collision": (getattr(self, "col_sum", None), getattr(self, "col_sumsq", None)),
+                  "surface": (getattr(self, "surf_sum", None),
+                              getattr(self, "surf_sumsq", None))}[estimator]
         mean = s1 / N
         if B < 2:
             return mean, np.full_like(mean, np.nan)

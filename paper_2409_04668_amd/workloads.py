@@ -25,6 +25,9 @@ Problem dict schema (all lengths in cm, times in s):
 ``detector``                 None or dict(lo[3], hi[3])
 ``n_batches``                batches for the mesh-tally statistics
 ``collision_tally``          bool; also score the collision estimator w/Sigma_t on the mesh
+``surface_tally``            None or dict(axis, pos): also a surface-current tally on the
+                             plane x[axis] = pos, binned by side of crossing, group (per-group
+                             meshes), the mesh's time bins and its bins on the other two axes
 ``population_control``       None or dict(target): splitting-roulette of every intermediate
                              census bank to `target` particles per source history
 ``max_events``               flight cap per history
@@ -64,7 +67,8 @@ def _base(G: int = 1) -> dict:
         census=np.array([1.0]),
         implicit_capture=False, w_cut=0.25, w_surv=1.0,
         detector=None, n_batches=20, max_events=1_000_000, stack_cap=64,
-        importance=None, ww=None, collision_tally=False, population_control=None,
+        importance=None, ww=None, collision_tally=False, surface_tally=None,
+        population_control=None,
     )
 
 
