@@ -58,7 +58,7 @@ enum { MCDC_SRC_POINT = 0, MCDC_SRC_BOX = 1 };
  * schedule's workspace and supports everything it does. */
 enum { MCDC_SCHED_AUTO = 0, MCDC_SCHED_HISTORY = 1, MCDC_SCHED_EVENT = 2, MCDC_SCHED_HYBRID = 3 };
 enum { MCDC_TALLY_MESH = 0, MCDC_TALLY_DETECTOR = 1, MCDC_TALLY_LEAKAGE = 2,
-       MCDC_TALLY_COLLISION = 3 };
+       MCDC_TALLY_COLLISION = 3, MCDC_TALLY_SURFACE = 4 };
 
 #define MCDC_MAX_BOXES 16
 #define MCDC_MAX_MAT 16
@@ -91,6 +91,15 @@ typedef struct {
     int32_t col_tally;                 /* 1: also a collision-estimator tally on
                                           the mesh (w / Sigma_t per collision in
                                           the bin of the collision point)         */
+    int32_t surf_on;                   /* 1: also a surface-current tally on the
+                                          plane x[surf_axis] = surf_pos: every
+                                          flight crossing it adds its weight to
+                                          the bin [side][g][t][b2][b1] of the
+                                          crossing (side 0: moving toward +axis;
+                                          g as the mesh; t and the other two axes
+                                          b1 < b2 binned as the mesh)             */
+    int32_t surf_axis;                 /* 0 x, 1 y, 2 z                           */
+    double surf_pos;
     int32_t pc_on;                     /* 1: population control at every
                                           intermediate census (event schedule;
                                           event_chunk >= histories per batch):
@@ -145,6 +154,7 @@ typedef struct {
     int32_t status;                    /* sticky device error status             */
     uint64_t event_iterations;         /* event schedule: stage iterations launched */
     uint64_t pc_kills, pc_copies;      /* population control: removed / added      */
+    uint64_t surf_crossings;           /* scored surface-tally crossings          */
 } mcdc_counters;
 
 typedef struct mcdc_problem *mcdc_handle;
@@ -192,7 +202,10 @@ int mcdc_set_run_state(mcdc_handle h, const mcdc_run_state *in);
 /* Synchronise `stream` and copy results to the host: per-bin mean score per
  * source history divided by bin volume and time width (MCDC_TALLY_MESH,
  * n = bins; MCDC_TALLY_COLLISION the same from the collision estimator, for
- * problems created with col_tally), the detector mean track length per
+ * problems created with col_tally), per surface bin the mean crossing weight
+ * per source history divided by the bin's area and time width
+ * (MCDC_TALLY_SURFACE, n = mcdc_surface_bins; problems created with
+ * surf_on), the detector mean track length per
  * history (n = 1), or the leaked weight per face per history (n = 6);
  * rel_err may be NULL.  Returns the sticky device error status if a run
  * failed. */
@@ -207,6 +220,11 @@ int mcdc_get_raw(mcdc_handle h, double *tally_sum, double *tally_sumsq, size_t n
  * created with col_tally; MCDC_E_STATE otherwise). */
 int mcdc_get_raw_collision(mcdc_handle h, double *col_sum, double *col_sumsq, size_t n,
                            void *stream);
+/* The same for the surface-current tally (problems created with surf_on;
+ * MCDC_E_STATE otherwise); n = mcdc_surface_bins = 2 * G_t * nt * n_b1 * n_b2. */
+int mcdc_get_raw_surface(mcdc_handle h, double *surf_sum, double *surf_sumsq, size_t n,
+                         void *stream);
+int mcdc_surface_bins(mcdc_handle h, size_t *n);
 int mcdc_get_counters(mcdc_handle h, mcdc_counters *out, void *stream);
 int mcdc_reset_tallies(mcdc_handle h, void *stream);
 int mcdc_tally_bins(mcdc_handle h, size_t *n);

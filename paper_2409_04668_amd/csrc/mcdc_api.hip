@@ -60,6 +60,9 @@ int validate_desc(const mcdc_problem_desc *d) {
     if (d->n_batches < 1 || d->n_batches > 65535) return fail(MCDC_E_INVALID, "n_batches must lie in [1, 65535]");
     if (d->stack_cap < 0 || d->max_events < 1) return fail(MCDC_E_INVALID, "stack_cap/max_events");
     if (d->col_tally != 0 && d->col_tally != 1) return fail(MCDC_E_INVALID, "col_tally must be 0 or 1");
+    if (d->surf_on != 0 && d->surf_on != 1) return fail(MCDC_E_INVALID, "surf_on must be 0 or 1");
+    if (d->surf_on && (d->surf_axis < 0 || d->surf_axis > 2 || !isfinite(d->surf_pos)))
+        return fail(MCDC_E_INVALID, "surf_axis must be 0..2 and surf_pos finite");
     if (d->pc_on != 0 && d->pc_on != 1) return fail(MCDC_E_INVALID, "pc_on must be 0 or 1");
     if (d->pc_on && !(d->pc_target > 0.0 && d->pc_target <= 64.0))
         return fail(MCDC_E_INVALID, "pc_target must lie in (0, 64]");
@@ -74,6 +77,14 @@ int validate_desc(const mcdc_problem_desc *d) {
             if (isinf(d->outer_lo[a]) || isinf(d->outer_hi[a]))
                 return fail(MCDC_E_INVALID, "weight windows / importance need a finite outer box");
     return MCDC_OK;
+}
+
+// surface-current bins: 2 sides x groups of the mesh x time bins x the mesh
+// bins of the two in-plane axes
+static size_t desc_nsurf(const mcdc_problem_desc *d) {
+    if (!d->surf_on) return 0;
+    const int a = d->surf_axis, b1 = a == 0 ? 1 : 0, b2 = a == 2 ? 1 : 2;
+    return (size_t)2 * (d->mesh_per_group ? d->G : 1) * d->mesh_n[3] * d->mesh_n[b1] * d->mesh_n[b2];
 }
 
 uint32_t desc_nbins(const mcdc_problem_desc *d) {
@@ -152,6 +163,10 @@ Layout make_layout(const mcdc_problem_desc *d, const Options &o) {
     L.col_batch = off; off = align_up(off + nslices * nc * sizeof(double));
     L.col_sum = off; off = align_up(off + nc * sizeof(double));
     L.col_sumsq = off; off = align_up(off + nc * sizeof(double));
+    const size_t nsf = desc_nsurf(d);                // surface current, per batch slice
+    L.surf_batch = off; off = align_up(off + nslices * nsf * sizeof(double));
+    L.surf_sum = off; off = align_up(off + nsf * sizeof(double));
+    L.surf_sumsq = off; off = align_up(off + nsf * sizeof(double));
     L.acc = off; off = align_up(off + sizeof(DevAcc));
     const size_t ni = desc_nimp(d);
     L.imp_score = off; off = align_up(off + ni * sizeof(double));
@@ -218,6 +233,19 @@ void build_dev_problem(const mcdc_problem_desc *d, char *ws, const Layout &L, De
     }
     P.G_t = d->mesh_per_group ? d->G : 1;
     P.col_on = d->col_tally;
+    P.surf_on = d->surf_on;
+    if (d->surf_on) {
+        const int a = d->surf_axis, b[2] = {a == 0 ? 1 : 0, a == 2 ? 1 : 2};
+        P.surf_axis = a;
+        P.surf_pos = d->surf_pos;
+        for (int k = 0; k < 2; ++k) {
+            P.surf_lo[k] = P.mesh_lo[b[k]];
+            P.surf_id[k] = P.mesh_idelta[b[k]];
+            P.surf_n[k] = P.mesh_n[b[k]];
+            P.surf_bd[k] = P.mesh_bounded[b[k]];
+        }
+        P.surf_nbins = (uint32_t)desc_nsurf(d);
+    }
     P.pc_on = d->pc_on;
     P.pc_target = d->pc_target;
     P.implicit_capture = d->implicit_capture;
@@ -440,6 +468,7 @@ static RunArgs base_args(mcdc_handle h, uint64_t seed) {
     A.seed = seed;
     A.tally = (double *)(h->ws + h->L.tally_batch);
     A.col = h->desc.col_tally ? (double *)(h->ws + h->L.col_batch) : nullptr;
+    A.surf = h->desc.surf_on ? (double *)(h->ws + h->L.surf_batch) : nullptr;
     A.acc = (DevAcc *)(h->ws + h->L.acc);
     A.imp_score = (double *)(h->ws + h->L.imp_score);
     A.imp_weight = (double *)(h->ws + h->L.imp_weight);
@@ -467,6 +496,9 @@ static int close_event_run(mcdc_handle h, uint64_t n, hipStream_t s) {
     double *cbatch = (double *)(h->ws + h->L.col_batch);
     double *csum = (double *)(h->ws + h->L.col_sum);
     double *csumsq = (double *)(h->ws + h->L.col_sumsq);
+    double *sbatch = (double *)(h->ws + h->L.surf_batch);
+    double *ssum = (double *)(h->ws + h->L.surf_sum);
+    double *ssumsq = (double *)(h->ws + h->L.surf_sumsq);
     for (uint64_t b = 0; b < B; ++b) {
         const uint64_t lo = (b * n) / B, hi = ((b + 1) * n) / B;
         if (hi == lo) continue;
@@ -475,6 +507,9 @@ static int close_event_run(mcdc_handle h, uint64_t n, hipStream_t s) {
         if (e == hipSuccess && h->desc.col_tally)
             e = launch_closeout(cbatch + b * (uint64_t)h->nbins, csum, csumsq, h->nbins,
                                 (double)(hi - lo), s);
+        if (e == hipSuccess && h->desc.surf_on)
+            e = launch_closeout(sbatch + b * (uint64_t)h->P.surf_nbins, ssum, ssumsq,
+                                h->P.surf_nbins, (double)(hi - lo), s);
         if (e != hipSuccess) return hip_fail(e, "run launch");
         h->batches += 1;
     }
@@ -499,6 +534,9 @@ int mcdc_run(mcdc_handle h, uint64_t n, uint64_t seed, void *stream) {
     double *csum = (double *)(h->ws + h->L.col_sum);
     double *csumsq = (double *)(h->ws + h->L.col_sumsq);
     const bool col = h->desc.col_tally != 0;
+    double *sbatch = (double *)(h->ws + h->L.surf_batch);
+    double *ssum = (double *)(h->ws + h->L.surf_sum);
+    double *ssumsq = (double *)(h->ws + h->L.surf_sumsq);
     const bool lds = h->opt.lds_tally && h->nbins <= (uint32_t)kLdsTallyMaxBins;
     if (h->opt.schedule == MCDC_SCHED_EVENT) {
         // one pass over all histories of the run; each particle scores into
@@ -540,6 +578,8 @@ int mcdc_run(mcdc_handle h, uint64_t n, uint64_t seed, void *stream) {
         if (e == hipSuccess) e = launch_closeout(batch, sum, sumsq, h->nbins, (double)(hi - lo), s);
         if (e == hipSuccess && col)
             e = launch_closeout(cbatch, csum, csumsq, h->nbins, (double)(hi - lo), s);
+        if (e == hipSuccess && h->desc.surf_on)
+            e = launch_closeout(sbatch, ssum, ssumsq, h->P.surf_nbins, (double)(hi - lo), s);
         if (e != hipSuccess) return hip_fail(e, "run launch");
         h->batches += 1;
     }
@@ -682,6 +722,28 @@ int mcdc_get_raw_collision(mcdc_handle h, double *csum, double *csumsq, size_t n
     return MCDC_OK;
 }
 
+int mcdc_surface_bins(mcdc_handle h, size_t *n) {
+    if (!h || !n) return fail(MCDC_E_INVALID, "null argument");
+    *n = h->is_batch ? 0 : desc_nsurf(&h->desc);
+    return MCDC_OK;
+}
+
+int mcdc_get_raw_surface(mcdc_handle h, double *ssum, double *ssumsq, size_t n, void *stream) {
+    if (!h) return fail(MCDC_E_INVALID, "null handle");
+    if (h->is_batch || !h->desc.surf_on)
+        return fail(MCDC_E_STATE, "problem created without the surface-current tally");
+    if (n != desc_nsurf(&h->desc)) return fail(MCDC_E_INVALID, "wrong surface bin count");
+    DevAcc acc;
+    int st = read_acc(h, acc, (hipStream_t)stream);
+    if (st) return st;
+    hipError_t e = hipSuccess;
+    if (ssum) e = hipMemcpy(ssum, h->ws + h->L.surf_sum, n * sizeof(double), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && ssumsq)
+        e = hipMemcpy(ssumsq, h->ws + h->L.surf_sumsq, n * sizeof(double), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "get_raw_surface");
+    return MCDC_OK;
+}
+
 }  // extern "C"
 
 void mcdc::fill_counters(const DevAcc &a, mcdc_counters *o) {
@@ -693,6 +755,7 @@ void mcdc::fill_counters(const DevAcc &a, mcdc_counters *o) {
     o->cutoff_kills = c[C_CUT_KILL]; o->cutoff_survivals = c[C_CUT_SURVIVE];
     o->detector_hits = c[C_DET_HIT]; o->particles = c[C_PARTICLE];
     o->pc_kills = c[C_PC_KILL]; o->pc_copies = c[C_PC_COPY];
+    o->surf_crossings = c[C_SURF];
     o->w_source = a.wsum[W_SOURCE]; o->w_leak = a.wsum[W_LEAK]; o->w_absorb = a.wsum[W_ABSORB];
     o->w_time_end = a.wsum[W_TIME_END]; o->w_gain = a.wsum[W_GAIN]; o->w_loss = a.wsum[W_LOSS];
     o->path = a.wsum[W_PATH];
@@ -743,20 +806,26 @@ int mcdc_get_tallies(mcdc_handle h, int kind, double *mean, double *rel, size_t 
         }
         return MCDC_OK;
     }
-    if (kind != MCDC_TALLY_MESH && kind != MCDC_TALLY_COLLISION)
+    if (kind != MCDC_TALLY_MESH && kind != MCDC_TALLY_COLLISION && kind != MCDC_TALLY_SURFACE)
         return fail(MCDC_E_INVALID, "unknown tally kind");
     if (kind == MCDC_TALLY_COLLISION && !h->desc.col_tally)
         return fail(MCDC_E_STATE, "problem created without the collision estimator");
-    if (n != h->nbins) return fail(MCDC_E_INVALID, "wrong bin count");
-    const size_t o1 = kind == MCDC_TALLY_MESH ? h->L.tally_sum : h->L.col_sum;
-    const size_t o2 = kind == MCDC_TALLY_MESH ? h->L.tally_sumsq : h->L.col_sumsq;
+    if (kind == MCDC_TALLY_SURFACE && !h->desc.surf_on)
+        return fail(MCDC_E_STATE, "problem created without the surface-current tally");
+    const bool surf = kind == MCDC_TALLY_SURFACE;
+    if (n != (surf ? desc_nsurf(&h->desc) : (size_t)h->nbins)) return fail(MCDC_E_INVALID, "wrong bin count");
+    const size_t o1 = surf ? h->L.surf_sum : (kind == MCDC_TALLY_MESH ? h->L.tally_sum : h->L.col_sum);
+    const size_t o2 = surf ? h->L.surf_sumsq : (kind == MCDC_TALLY_MESH ? h->L.tally_sumsq : h->L.col_sumsq);
     std::vector<double> s(n), s2(n);
     hipError_t e = hipMemcpy(s.data(), h->ws + o1, n * sizeof(double), hipMemcpyDeviceToHost);
     if (e == hipSuccess) e = hipMemcpy(s2.data(), h->ws + o2, n * sizeof(double), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "get_tallies");
+    // mesh bins: divided by volume and time width; surface bins: by the bin's
+    // area on the plane and time width
     double vol = 1.0;
     for (int a = 0; a < 4; ++a)
-        if (a == 3 || h->P.mesh_bounded[a]) vol *= h->P.mesh_delta[a];
+        if ((a == 3 || h->P.mesh_bounded[a]) && !(surf && a == h->desc.surf_axis))
+            vol *= h->P.mesh_delta[a];
     const double B = (double)h->batches;
     for (size_t i = 0; i < n; ++i) {
         const double m = s[i] / N;

@@ -77,6 +77,7 @@ struct BatchCtx {
     static constexpr bool kWW = false;
     static constexpr bool kWWMap = false;
     MCDC_DEV double *col_tally() const { return nullptr; }
+    MCDC_DEV double *surf_tally() const { return nullptr; }
     CP &P;
     const RunArgs &A;
     const BDev &D;
@@ -356,6 +357,7 @@ static int bvalidate(const mcdc_problem_desc *ds, size_t n, const uint64_t *nh) 
         if (ds[p].imp_on || ds[p].stack_cap > 0) return fail(MCDC_E_INVALID, "batched problems run analog/implicit transport without weight windows");
         if (ds[p].has_detector) return fail(MCDC_E_INVALID, "batched problems have no detector tally");
         if (ds[p].col_tally) return fail(MCDC_E_INVALID, "batched problems have no collision-estimator tally");
+        if (ds[p].surf_on) return fail(MCDC_E_INVALID, "batched problems have no surface-current tally");
         if (ds[p].pc_on) return fail(MCDC_E_INVALID, "batched problems run without population control");
         if (nh[p] > 0xFFFFFFF0ull) return fail(MCDC_E_INVALID, "too many histories in one problem");
         cap += nh[p];

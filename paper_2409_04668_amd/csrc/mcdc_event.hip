@@ -166,6 +166,7 @@ struct EvCtx {
         return ((r + 1) * A.run_batches - 1) / A.run_n;
     }
     MCDC_DEV double *col_tally() const { return A.col + batch() * (uint64_t)P.nbins; }
+    MCDC_DEV double *surf_tally() const { return A.surf + batch() * (uint64_t)P.surf_nbins; }
     MCDC_DEV const float *mlp_params(CP &Pp) const { return Pp.ww_params; }
     // several particles of one history can be in flight at once when they
     // split (weight windows, population control): their sums are atomic
@@ -254,6 +255,7 @@ struct LeadCtx {
         return ((r + 1) * A.run_batches - 1) / A.run_n;
     }
     MCDC_DEV double *col_tally() const { return A.col + batch() * (uint64_t)P.nbins; }
+    MCDC_DEV double *surf_tally() const { return A.surf + batch() * (uint64_t)P.surf_nbins; }
     MCDC_DEV const float *mlp_params(CP &Pp) const { return Pp.ww_params; }
     MCDC_DEV bool count_flight() {
         events += 1u;

@@ -29,6 +29,7 @@ struct HistCtx {
 
     MCDC_DEV uint64_t hist() const { return id; }
     MCDC_DEV double *col_tally() const { return A.col; }
+    MCDC_DEV double *surf_tally() const { return A.surf; }
     MCDC_DEV const float *mlp_params(CP &Pp) const { return Pp.ww_params; }
     MCDC_DEV bool count_flight() {
         events += 1;

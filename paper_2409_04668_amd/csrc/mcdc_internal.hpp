@@ -22,7 +22,7 @@ constexpr int kLdsTallyMaxBins = 7680;       // 60 KiB of FP64 LDS tile
 enum {
     C_HIST = 0, C_FLIGHT, C_PIECE, C_COLLISION, C_ABSORB, C_SURFACE, C_LEAK, C_CENSUS,
     C_TIME_END, C_SPLIT, C_RR_KILL, C_RR_SURVIVE, C_CUT_KILL, C_CUT_SURVIVE, C_DET_HIT,
-    C_PARTICLE, C_PC_KILL, C_PC_COPY, N_CNT
+    C_PARTICLE, C_PC_KILL, C_PC_COPY, C_SURF, N_CNT
 };
 enum { W_SOURCE = 0, W_LEAK, W_ABSORB, W_TIME_END, W_GAIN, W_LOSS, W_PATH, N_WSUM };
 
@@ -55,6 +55,11 @@ struct DevProblem {
     double mesh_lo[4], mesh_delta[4], mesh_idelta[4];
     int32_t mesh_n[4], mesh_bounded[3], G_t;
     int32_t col_on;                      // collision-estimator tally
+    int32_t surf_on, surf_axis;          // surface-current tally on x[axis] = pos
+    double surf_pos;
+    double surf_lo[2], surf_id[2];       // mesh lo and 1/delta of the in-plane axes b1 < b2
+    int32_t surf_n[2], surf_bd[2];       // their bins and boundedness
+    uint32_t surf_nbins;                 // 2 * G_t * nt * n_b1 * n_b2
     int32_t pc_on;                       // population control at intermediate census
     double pc_target;                    // census population per source history
     int32_t implicit_capture;
@@ -88,6 +93,7 @@ struct RunArgs {
     double *tally;                       // current-batch accumulator [nbins]; event
                                          // schedule: [run_batches][nbins] slices
     double *col;                         // collision estimator, same layout as tally
+    double *surf;                        // surface current; event schedule: per batch
     DevAcc *acc;
     double *imp_score, *imp_weight;
     double *xh_out;
@@ -104,7 +110,8 @@ struct RunArgs {
 };
 
 struct Layout {                          // workspace carving (byte offsets)
-    size_t tables, tally_batch, tally_sum, tally_sumsq, col_batch, col_sum, col_sumsq, acc,
+    size_t tables, tally_batch, tally_sum, tally_sumsq, col_batch, col_sum, col_sumsq,
+        surf_batch, surf_sum, surf_sumsq, acc,
         imp_score, imp_weight, ww_params,
         stk_d, stk_i, imp_list, event, total;
 };

@@ -498,6 +498,46 @@ MCDC_DEV float mlp_infer(const float *__restrict__ gprm, int in_dim, const float
     return out;
 }
 
+// Surface-current tally on the plane x[a] = c (a = P.surf_axis, c =
+// P.surf_pos): a flight p + s u, s in (0, d], crosses it at
+// s* = (c - p[a]) * iu[a] when 0 < s* <= d and adds its weight w to the bin
+// [side][g][t][b2][b1] of the crossing: side 0 when u[a] > 0, the group as
+// the mesh, the time bin of t0 + s*/v and the mesh bins of the two other axes
+// (b1 < b2) at p + s* u.  A crossing outside the mesh is not scored; a flight
+// that starts on the plane does not cross it.  Returns 1 when it scored.
+MCDC_DEV uint32_t score_surface(CP &P, const double p[3], const double u[3], const double iu[3],
+                                double t0, double v, double d, double w, int g, double *out) {
+    const int a = P.surf_axis;
+    const double ua = a == 0 ? u[0] : (a == 1 ? u[1] : u[2]);
+    if (ua == 0.0) return 0;
+    const double pa = a == 0 ? p[0] : (a == 1 ? p[1] : p[2]);
+    const double iua = a == 0 ? iu[0] : (a == 1 ? iu[1] : iu[2]);
+    const double sx = (P.surf_pos - pa) * iua;
+    if (!(sx > 0.0 && sx <= d)) return 0;
+    // in-plane axes b1 < b2
+    const double p1 = a == 0 ? p[1] : p[0], u1 = a == 0 ? u[1] : u[0];
+    const double p2 = a == 2 ? p[1] : p[2], u2 = a == 2 ? u[1] : u[2];
+    int32_t i1 = 0, i2 = 0;
+    if (P.surf_bd[0]) {
+        const double f = floor((p1 + u1 * sx - P.surf_lo[0]) * P.surf_id[0]);
+        if (f < 0.0 || f >= (double)P.surf_n[0]) return 0;
+        i1 = (int32_t)f;
+    }
+    if (P.surf_bd[1]) {
+        const double f = floor((p2 + u2 * sx - P.surf_lo[1]) * P.surf_id[1]);
+        if (f < 0.0 || f >= (double)P.surf_n[1]) return 0;
+        i2 = (int32_t)f;
+    }
+    const double ft = floor((t0 + sx / v - P.mesh_lo[3]) * P.mesh_idelta[3]);
+    if (ft < 0.0 || ft >= (double)P.mesh_n[3]) return 0;
+    const uint32_t side = ua > 0.0 ? 0u : 1u;
+    const uint32_t gg = P.G_t > 1 ? (uint32_t)g : 0u;
+    const uint32_t bin = (((side * (uint32_t)P.G_t + gg) * (uint32_t)P.mesh_n[3] + (uint32_t)ft) *
+                              (uint32_t)P.surf_n[1] + (uint32_t)i2) * (uint32_t)P.surf_n[0] + (uint32_t)i1;
+    unsafeAtomicAdd(out + bin, w);
+    return 1;
+}
+
 // Mesh bin holding a point (x, y, z, t) in group g, for the collision
 // estimator: per axis floor((p - lo) / delta); -1 outside the mesh (an
 // unbounded axis is one bin).

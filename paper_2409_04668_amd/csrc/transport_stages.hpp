@@ -234,6 +234,8 @@ MCDC_DEV int stage_flight(CP &P, const RunArgs &A, Shared &S, const T &tally, Ct
     const double wd = q.w * d;
     path += wd;
     C.add_path(wd);
+    if (P.surf_on && score_surface(P, q.x, q.u, iu, q.t, v, d, q.w, q.g, C.surf_tally()))
+        atomicAdd(&S.cnt[C_SURF], 1ull);
 
     q.x[0] = q.x[0] + q.u[0] * d;
     q.x[1] = q.x[1] + q.u[1] * d;

@@ -30,7 +30,7 @@ _lib = C.CDLL(LIB_PATH)
 OK = 0
 E_INVALID, E_NOMEM, E_HIP, E_EVENT_CAP, E_CANCELLED, E_STATE, E_STACK, E_BANK = -1, -2, -3, -4, -5, -6, -7, -8
 SCHED_AUTO, SCHED_HISTORY, SCHED_EVENT, SCHED_HYBRID = 0, 1, 2, 3
-TALLY_MESH, TALLY_DETECTOR, TALLY_LEAKAGE, TALLY_COLLISION = 0, 1, 2, 3
+TALLY_MESH, TALLY_DETECTOR, TALLY_LEAKAGE, TALLY_COLLISION, TALLY_SURFACE = 0, 1, 2, 3, 4
 MAX_G = 8
 HIDDEN = 64
 
@@ -51,7 +51,8 @@ class ProblemDesc(C.Structure):
         ("src_kind", C.c_int32), ("src_lo", D3), ("src_hi", D3), ("src_t0", C.c_double),
         ("src_t1", C.c_double), ("src_isotropic", C.c_int32), ("src_dir", D3),
         ("src_group", C.c_int32), ("mesh_lo", D4), ("mesh_hi", D4), ("mesh_n", I4),
-        ("mesh_per_group", C.c_int32), ("col_tally", C.c_int32), ("pc_on", C.c_int32),
+        ("mesh_per_group", C.c_int32), ("col_tally", C.c_int32), ("surf_on", C.c_int32),
+        ("surf_axis", C.c_int32), ("surf_pos", C.c_double), ("pc_on", C.c_int32),
         ("pc_target", C.c_double),
         ("n_census", C.c_int32), ("census", PD),
         ("implicit_capture", C.c_int32), ("w_cut", C.c_double), ("w_surv", C.c_double),
@@ -89,7 +90,7 @@ class Counters(C.Structure):
                 [("leak", C.c_double * 6), ("det_sum", C.c_double), ("det_sumsq", C.c_double),
                  ("batches", C.c_int64), ("n_hist", C.c_uint64), ("status", C.c_int32),
                  ("event_iterations", C.c_uint64), ("pc_kills", C.c_uint64),
-                 ("pc_copies", C.c_uint64)])
+                 ("pc_copies", C.c_uint64), ("surf_crossings", C.c_uint64)])
 
     def as_dict(self):
         d = {n: getattr(self, n) for n, _ in self._fields_ if n != "leak"}
@@ -126,6 +127,8 @@ _sig("mcdc_set_run_state", C.c_int, VP, VP)
 _sig("mcdc_get_tallies", C.c_int, VP, C.c_int, PD, PD, C.c_size_t, VP)
 _sig("mcdc_get_raw", C.c_int, VP, PD, PD, C.c_size_t, VP)
 _sig("mcdc_get_raw_collision", C.c_int, VP, PD, PD, C.c_size_t, VP)
+_sig("mcdc_get_raw_surface", C.c_int, VP, PD, PD, C.c_size_t, VP)
+_sig("mcdc_surface_bins", C.c_int, VP, C.POINTER(C.c_size_t))
 _sig("mcdc_get_counters", C.c_int, VP, C.POINTER(Counters), VP)
 _sig("mcdc_reset_tallies", C.c_int, VP, VP)
 _sig("mcdc_tally_bins", C.c_int, VP, C.POINTER(C.c_size_t))
@@ -223,6 +226,11 @@ class _Desc:
         d.mesh_n = I4(*map(int, m["n"]))
         d.mesh_per_group = 1 if m["per_group"] else 0
         d.col_tally = 1 if prob.get("collision_tally") else 0
+        sf = prob.get("surface_tally")
+        d.surf_on = 1 if sf is not None else 0
+        if sf is not None:
+            d.surf_axis = int(sf["axis"])
+            d.surf_pos = float(sf["pos"])
         pc = prob.get("population_control")
         d.pc_on = 1 if pc is not None else 0
         d.pc_target = float(pc["target"]) if pc is not None else 0.0
@@ -401,9 +409,24 @@ class Problem:
                                           self.nbins, _stream_ptr(stream)), "get_raw_collision")
         return s, s2
 
+    def surface_bins(self) -> int:
+        n = C.c_size_t()
+        check(_lib.mcdc_surface_bins(self.h, C.byref(n)), "surface_bins")
+        return int(n.value)
+
+    def raw_surface(self, stream=None):
+        """Surface-current sums [side][g][t][b2][b1] (side 0: crossing toward
+        +axis) and batch sums of squares."""
+        n = self.surface_bins()
+        s = np.zeros(n)
+        s2 = np.zeros(n)
+        check(_lib.mcdc_get_raw_surface(self.h, s.ctypes.data_as(PD), s2.ctypes.data_as(PD), n,
+                                        _stream_ptr(stream)), "get_raw_surface")
+        return s, s2
+
     def tallies(self, kind=TALLY_MESH, stream=None):
         n = {TALLY_MESH: self.nbins, TALLY_DETECTOR: 1, TALLY_LEAKAGE: 6,
-             TALLY_COLLISION: self.nbins}[kind]
+             TALLY_COLLISION: self.nbins}[kind] if kind != TALLY_SURFACE else self.surface_bins()
         m = np.zeros(n)
         r = np.zeros(n)
         check(_lib.mcdc_get_tallies(self.h, kind, m.ctypes.data_as(PD), r.ctypes.data_as(PD), n,

@@ -10,7 +10,8 @@ INT_COUNTERS = [("hist", "histories"), ("flight", "flights"), ("piece", "pieces"
                 ("split", "splits"), ("rr_kill", "rr_kills"), ("rr_survive", "rr_survivals"),
                 ("cut_kill", "cutoff_kills"), ("cut_survive", "cutoff_survivals"),
                 ("det_hit", "detector_hits"), ("particle", "particles"),
-                ("pc_kill", "pc_kills"), ("pc_copy", "pc_copies")]
+                ("pc_kill", "pc_kills"), ("pc_copy", "pc_copies"),
+                ("surf_cross", "surf_crossings")]
 W_COUNTERS = [("source", "w_source"), ("leak", "w_leak"), ("absorb", "w_absorb"),
               ("time_end", "w_time_end"), ("gain", "w_gain"), ("loss", "w_loss"),
               ("path", "path")]
@@ -94,5 +95,9 @@ def full_parity(prob, n, seed, trace_cap=0, options=None, runs=1):
         c, c2 = gp.raw_collision()
         assert_close_sums(c, orc.col_sum, what="col_sum")
         assert_close_sums(c2, orc.col_sumsq, what="col_sumsq")
+    if prob.get("surface_tally") is not None:
+        c, c2 = gp.raw_surface()
+        assert_close_sums(c, orc.surf_sum, what="surf_sum")
+        assert_close_sums(c2, orc.surf_sumsq, what="surf_sumsq")
     assert_counters(gp.counters(), orc)
     return gp, orc

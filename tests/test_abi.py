@@ -87,3 +87,27 @@ def test_failure_paths_without_gpu():
     assert mcdc._lib.mcdc_run_step(None, ctypes.byref(done), None) == mcdc.E_INVALID
     st = mcdc.RunState()
     assert mcdc._lib.mcdc_get_run_state(None, ctypes.byref(st)) == mcdc.E_INVALID
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libmcdc.so not built")
+def test_surface_tally_description_is_validated_on_cpu():
+    import numpy as np
+    from paper_2409_04668_amd import mcdc, workloads as W
+    n = ctypes.c_size_t()
+    p = W.config2()
+    p["surface_tally"] = dict(axis=1, pos=40.0)
+    d = mcdc._Desc(p)
+    assert mcdc._lib.mcdc_workspace_bytes(ctypes.byref(d.d), ctypes.byref(mcdc.make_options()),
+                                          ctypes.byref(n)) == 0
+    plain = ctypes.c_size_t()
+    d0 = mcdc._Desc(W.config2())
+    assert mcdc._lib.mcdc_workspace_bytes(ctypes.byref(d0.d), ctypes.byref(mcdc.make_options()),
+                                          ctypes.byref(plain)) == 0
+    # three more arrays of 2 sides x 20 t x 60 x 60 bins (x, z in the plane y = 40)
+    assert n.value - plain.value >= 3 * 8 * 2 * 20 * 60 * 60
+    for bad in (dict(axis=3, pos=1.0), dict(axis=0, pos=float("nan"))):
+        p["surface_tally"] = bad
+        d = mcdc._Desc(p)
+        assert mcdc._lib.mcdc_workspace_bytes(ctypes.byref(d.d), ctypes.byref(mcdc.make_options()),
+                                              ctypes.byref(n)) == mcdc.E_INVALID
+    assert np.isfinite(plain.value)
