@@ -256,6 +256,20 @@ def main():
         out["with_collision_estimator"] = {"histories_per_s": rate,
                                            "relative_to_track_length_only": rate / out["value"]}
         gc.close()
+        # the same step with a surface-current tally on the plane y = 45 cm
+        # (crossings of the first leg, binned on the x-z mesh and in time)
+        ps = dict(prob, surface_tally=dict(axis=1, pos=45.0))
+        gs = mcdc.Problem(ps, mcdc.make_options(**oargs))
+        gs.run(N, seed)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gs.run(N, seed + 1)
+        torch.cuda.synchronize()
+        rate = N / (time.perf_counter() - t0)
+        out["with_surface_current_tally"] = {"histories_per_s": rate,
+                                             "relative_to_track_length_only": rate / out["value"],
+                                             "crossings_per_history": gs.counters()["surf_crossings"] / (2 * N)}
+        gs.close()
     if not args.no_other_schedule:
         # population control at census: the duct problem with 20 census steps
         # under the hybrid schedule, without and with splitting-roulette to one

@@ -228,7 +228,7 @@ __global__ void __launch_bounds__(256) k_ev_source(DevProblem, RunArgs A, EvBank
 // lead, long split chains are spread over the grid instead of holding one
 // work-item.
 #ifndef MCDC_LEAD_FLIGHTS
-#define MCDC_LEAD_FLIGHTS 16
+#define MCDC_LEAD_FLIGHTS 64
 #endif
 
 // Context of a history in the lead stage: one work-item owns the history (its
