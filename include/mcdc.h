@@ -101,8 +101,9 @@ typedef struct {
     int32_t surf_axis;                 /* 0 x, 1 y, 2 z                           */
     double surf_pos;
     int32_t pc_on;                     /* 1: population control at every
-                                          intermediate census (event schedule;
-                                          event_chunk >= histories per batch):
+                                          intermediate census (event or hybrid
+                                          schedule; event_chunk >= histories per
+                                          batch):
                                           each batch's census bank is split /
                                           rouletted to round(pc_target * batch
                                           histories) particles of equal weight    */
@@ -152,7 +153,8 @@ typedef struct {
     int64_t batches;
     uint64_t n_hist;
     int32_t status;                    /* sticky device error status             */
-    uint64_t event_iterations;         /* event schedule: stage iterations launched */
+    uint64_t event_iterations;         /* event and hybrid schedules: stage
+                                          iterations launched                     */
     uint64_t pc_kills, pc_copies;      /* population control: removed / added      */
     uint64_t surf_crossings;           /* scored surface-tally crossings          */
 } mcdc_counters;
@@ -174,7 +176,7 @@ int mcdc_create_problem(const mcdc_problem_desc *d, const mcdc_options *opt, voi
  * feed the batch statistics.  Results accumulate across runs. */
 int mcdc_run(mcdc_handle h, uint64_t n_histories, uint64_t seed, void *stream);
 
-/* A run taken census step by census step (event schedule; all histories
+/* A run taken census step by census step (event or hybrid schedule; all histories
  * resident: n_histories <= event_chunk; with population control, n_batches
  * must be 1).  mcdc_run_begin samples the sources and returns; each
  * mcdc_run_step transports until the next census step begins, or to the end

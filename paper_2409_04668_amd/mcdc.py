@@ -316,7 +316,7 @@ class Problem:
     def run(self, n_hist: int, seed: int, stream=None):
         check(_lib.mcdc_run(self.h, int(n_hist), int(seed), _stream_ptr(stream)), "run")
 
-    # ---- census-step control (event schedule) --------------------------
+    # ---- census-step control (event or hybrid schedule) ----------------
     def run_begin(self, n_hist: int, seed: int, stream=None):
         check(_lib.mcdc_run_begin(self.h, int(n_hist), int(seed), _stream_ptr(stream)), "run_begin")
 
