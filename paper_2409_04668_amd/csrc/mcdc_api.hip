@@ -380,6 +380,24 @@ int mcdc_create_problem(const mcdc_problem_desc *d, const mcdc_options *opt, voi
         delete h;
         return hip_fail(e, "create_problem upload");
     }
+    {
+        // the kernels find the description at the start of their argument
+        // segment: check that once (scratch word: the accumulator's padding)
+        int *flag = &((DevAcc *)(h->ws + L.acc))->pad;
+        int ok = 0;
+        e = launch_problem_check(h->P, flag, 0);
+        if (e == hipSuccess) e = hipMemcpy(&ok, flag, sizeof(int), hipMemcpyDeviceToHost);
+        if (e == hipSuccess) e = hipMemset(flag, 0, sizeof(int));
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e != hipSuccess) {
+            delete h;
+            return hip_fail(e, "create_problem check");
+        }
+        if (!ok) {
+            delete h;
+            return fail(MCDC_E_HIP, "kernel argument layout differs from the problem description");
+        }
+    }
     if (o.schedule == MCDC_SCHED_EVENT && (st = event_init(h))) {
         delete h;
         return st;

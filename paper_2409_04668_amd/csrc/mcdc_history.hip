@@ -230,6 +230,22 @@ __global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_history(DevProblem, R
     shared_flush(S, A.acc);
 }
 
+// The kernels read the problem description through kernel_problem(), the
+// address of their first argument in the kernel-argument segment.  This
+// kernel reads a few fields by name and through that address: *out = 1 when
+// they agree (checked once per handle).
+__global__ void k_problem_check(DevProblem P, int *out) {
+    CP &K = kernel_problem();
+    *out = (K.problem_id == P.problem_id && K.nbins == P.nbins && K.n_census == P.n_census &&
+            K.G == P.G && K.mesh_n[3] == P.mesh_n[3] && K.max_events == P.max_events &&
+            K.hot_bins == P.hot_bins) ? 1 : 0;
+}
+
+hipError_t launch_problem_check(const DevProblem &P, int *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_problem_check, dim3(1), dim3(1), 0, s, P, out);
+    return hipGetLastError();
+}
+
 // Batch close-out: per bin, sum += S_b, sumsq += S_b^2 / N_b, S_b = 0.
 __global__ void k_closeout(double *__restrict__ batch, double *__restrict__ sum,
                            double *__restrict__ sumsq, uint32_t n, double nb) {

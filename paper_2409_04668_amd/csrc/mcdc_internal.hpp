@@ -121,6 +121,7 @@ hipError_t launch_history(const DevProblem &P, const RunArgs &A, int grid, int b
                           bool lds_tally, hipStream_t s);
 hipError_t launch_closeout(double *batch, double *sum, double *sumsq, uint32_t n, double nb,
                            hipStream_t s);
+hipError_t launch_problem_check(const DevProblem &P, int *out, hipStream_t s);
 int history_grid(int block, int waves_per_cu);
 
 }  // namespace mcdc
