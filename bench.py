@@ -46,9 +46,10 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str):
+def measured_traffic(kernel: str, histories_per_launch: float):
     """HBM bytes per launch of `kernel` from its committed rocprofv3 PMC
-    summary, or None if there is none or the kernels changed since."""
+    summary, or None if there is none, the kernels changed since, or its
+    launches held another number of histories."""
     path = pmc_summary(kernel)
     if not os.path.exists(path):
         return None
@@ -59,6 +60,12 @@ def measured_traffic(kernel: str):
                 k, v = line.split(":", 1)
                 vals[k.strip()] = v.strip()
     if vals.get("kernel_sha") != kernel_hash():
+        return None
+    try:
+        h = float(vals["histories_per_launch"])
+    except (KeyError, ValueError):
+        return None
+    if abs(h - histories_per_launch) > 1e-3 * histories_per_launch:
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
@@ -86,13 +93,13 @@ def duct_options(args, mcdc, prob):
     tile, tile_frac = (None, 0.0) if args.no_tile else autotune.plan_hot_tile(prob, pilot=1_000_000)
     tuned = None
     if args.schedule == "auto":
-        tuned = autotune.tune_single(prob, pilot=20_000_000, waves=(16,), event_chunks=(1 << 24,),
+        tuned = autotune.tune_single(prob, pilot=20_000_000, waves=(16,), event_chunks=(1 << 25,),
                                      tile=tile, use_cache=False)
         oargs = dict(tuned["options"])
     else:
         sched = {"history": mcdc.SCHED_HISTORY, "event": mcdc.SCHED_EVENT,
                  "hybrid": mcdc.SCHED_HYBRID}[args.schedule]
-        oargs = dict(schedule=sched, event_chunk=1 << 24)
+        oargs = dict(schedule=sched, event_chunk=1 << 25)
         if tile is not None and sched != mcdc.SCHED_EVENT:
             oargs["tile"] = [[int(v) for v in tile[0]], [int(v) for v in tile[1]]]
     if args.waves_per_cu:
@@ -171,7 +178,7 @@ def main():
     avg_launch_s = kms / 1e3 / max(launches, 1)
     bytes_per_launch = BYTES_PER_PIECE * pieces / max(launches, 1)
     achieved = bytes_per_launch / avg_launch_s / 1e9
-    traffic = measured_traffic(kernel)
+    traffic = measured_traffic(kernel, n_done / max(launches, 1))
     det_mean, det_rel = gp.tallies(mcdc.TALLY_DETECTOR)
     out = {
         "metric": "histories/s (analog, FP64 tallies) on the 3D duct problem",
@@ -232,7 +239,7 @@ def main():
         for osched in (mcdc.SCHED_HISTORY, mcdc.SCHED_EVENT, mcdc.SCHED_HYBRID):
             if osched == sched:
                 continue
-            o = dict(schedule=osched, event_chunk=1 << 24)
+            o = dict(schedule=osched, event_chunk=1 << 25)
             if tile is not None and osched != mcdc.SCHED_EVENT:
                 o["tile"] = tile
             go = mcdc.Problem(prob, mcdc.make_options(**o))
@@ -361,7 +368,7 @@ def fom_comparison(mcdc, W, analog_options, tile, target=0.01):
                                   tile=tile, use_cache=False)
     wopt = dict(choice["options"])
     if wopt["schedule"] in (mcdc.SCHED_EVENT, mcdc.SCHED_HYBRID):
-        wopt["event_chunk"] = 1 << 24
+        wopt["event_chunk"] = 1 << 25
     analog = L.fom_at_target(p, seed=31, target=target, pilot=20_000_000,
                              options=mcdc.make_options(**analog_options))
     learned = L.fom_at_target(pw, seed=41, target=target, pilot=4_000_000,

@@ -262,7 +262,7 @@ def test_hybrid_planned_tile_at_scale_matches_history_schedule():
 def test_full_size_duct_hybrid_tile_sampled_histories():
     """The duct problem at full size (1e8 histories) in the launch
     configuration the benchmark's autotuner picks on this GPU: the hybrid
-    schedule, 2^24 resident histories, the LDS hot tile from the analog pilot.
+    schedule, 2^25 resident histories, the LDS hot tile from the analog pilot.
     Sampled histories recomputed one by one by the oracle match bit for bit;
     all track length is scored and weight balances."""
     from paper_2409_04668_amd import autotune
@@ -270,13 +270,13 @@ def test_full_size_duct_hybrid_tile_sampled_histories():
     n = 100_000_000
     p = W.config2()
     tile, _ = autotune.plan_hot_tile(p, pilot=1_000_000)
-    gp = mc.Problem(p, _hy_tile(tile, chunk=1 << 24))
+    gp = mc.Problem(p, _hy_tile(tile, chunk=1 << 25))
     gp.set_history_scores(n)
     gp.run(n, seed=2028)
     hs = gp.history_scores()
     rng = np.random.default_rng(1)
     # histories at chunk and workgroup-range edges, random ones, detector hits
-    ids = np.unique(np.concatenate([[0, 1, (1 << 24) - 1, 1 << 24, n - 1], rng.integers(0, n, 40),
+    ids = np.unique(np.concatenate([[0, 1, (1 << 25) - 1, 1 << 25, n - 1], rng.integers(0, n, 40),
                                     np.nonzero(hs[:, 0] > 0)[0][:20]]))
     q = dict(p)
     q["n_batches"] = 1

@@ -304,7 +304,7 @@ def test_full_size_learned_ww_sampled_histories(learned_duct_ww, schedule):
     """The learned weight-window configuration as the FOM comparison runs it
     (trained network baked onto the 2 cm x 10 s map) at 4e7 histories, under
     the event schedule (2^23 resident histories) and under the hybrid
-    schedule the autotuner picks on this GPU (2^24 resident histories, the
+    schedule the autotuner picks on this GPU (2^25 resident histories, the
     analog run's LDS hot tile): blocks of histories recomputed by the oracle
     agree per history (several particles add into a history's sums in
     another order: 1e-12); weight balances over the whole run."""
@@ -316,7 +316,7 @@ def test_full_size_learned_ww_sampled_histories(learned_duct_ww, schedule):
         opt = mc.make_options(mc.SCHED_EVENT, event_chunk=1 << 23)
     else:
         tile, _ = autotune.plan_hot_tile(W.config2(), pilot=1_000_000)
-        opt = mc.make_options(mc.SCHED_HYBRID, event_chunk=1 << 24, tile=tile)
+        opt = mc.make_options(mc.SCHED_HYBRID, event_chunk=1 << 25, tile=tile)
     gp = mc.Problem(pw, opt)
     gp.set_history_scores(n)
     gp.run(n, seed=2027)
@@ -326,7 +326,7 @@ def test_full_size_learned_ww_sampled_histories(learned_duct_ww, schedule):
     hit = int(np.nonzero(hs[:, 0] > 0)[0][0])
     q = dict(pw)
     q["n_batches"] = 1
-    for first in (0, hit, (1 << 24) - 20, n - 40):
+    for first in (0, hit, (1 << 25) - 20, n - 40):
         r = O.OracleRun(q)
         _, ho = r.run(40, 2027, per_history=True, first_id=first)
         np.testing.assert_allclose(hs[first:first + 40], ho, rtol=1e-12, atol=1e-300)
