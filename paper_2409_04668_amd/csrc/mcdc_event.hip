@@ -19,12 +19,13 @@
 // arguments; a kernel whose input is empty exits at once.
 //
 // Hybrid schedule: a lead stage replaces the source stage.  One work-item
-// follows each history through its flights in registers, as the history
-// schedule does, until the history ends, splits at a weight window, or (with
-// population control or census-step control) reaches a census; only then do
-// its particles go to the banks.  Histories that never split never touch the
-// banks; the split chains, which would serialise on one work-item, are spread
-// over the grid by the event stages.
+// follows each history in registers, as the history schedule does, with its
+// split daughters on a per-work-item stack, until the history ends or has
+// taken MCDC_LEAD_FLIGHTS flights (or, with population control or
+// census-step control, a particle reaches a census); what is left then goes
+// to the banks.  Short histories never touch the banks; long split chains,
+// which would serialise on one work-item, are spread over the grid by the
+// event stages.
 #include "lane_stack.hpp"
 #include "mcdc_runtime.hpp"
 #include "transport_stages.hpp"

@@ -42,7 +42,9 @@ struct DevAcc {
     int pad;
 };
 
-// Problem tables as seen by the kernels (passed by value; < 2 KiB).
+// Problem tables as seen by the kernels: every kernel takes them by value as
+// its first argument (< 2 KiB) and reads them where the kernel-argument
+// segment holds them.
 struct DevProblem {
     double outer_lo[3], outer_hi[3];
     double box_lo[kMaxBoxes][3], box_hi[kMaxBoxes][3];

@@ -1,10 +1,11 @@
 // The transport loop split into stages: source, flight (distances, event
 // selection, scoring, move, census), surface crossing, collision, weight-window
-// check.  The history-based kernel calls them back to back for one particle;
-// the event-based kernels call each stage over a compacted queue of particles.
-// A context object supplies what belongs to the particle's history (its id for
-// the random streams, its detector score, its flight count, where split
-// daughters go), so both schedules share one definition of the arithmetic.
+// check.  The history-based kernel and the hybrid lead stage call them back
+// to back for one particle; the event-based kernels call each stage over a
+// compacted bank of particles.  A context object supplies what belongs to the
+// particle's history (its id for the random streams, its detector score, its
+// flight count, where split daughters go, its tally slices), so every schedule
+// shares one definition of the arithmetic.
 #pragma once
 
 #include "transport_device.hpp"
