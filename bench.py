@@ -278,6 +278,24 @@ def main():
                                              "crossings_per_history": gs.counters()["surf_crossings"] / (2 * N)}
         gs.close()
     if not args.no_other_schedule:
+        # the 7-group duct (5.04e7 tally bins), hybrid schedule with its own
+        # planned tile, one timed step of the same size after a warm-up
+        from paper_2409_04668_amd import autotune
+        p7 = W.config3()
+        tile7, frac7 = autotune.plan_hot_tile(p7, pilot=1_000_000)
+        g7 = mcdc.Problem(p7, mcdc.make_options(mcdc.SCHED_HYBRID, event_chunk=1 << 25,
+                                                tile=tile7))
+        g7.run(N, seed)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g7.run(N, seed + 1)
+        torch.cuda.synchronize()
+        out["multigroup_duct_7_groups"] = {
+            "histories_per_s": N / (time.perf_counter() - t0), "tally_bins": W.n_bins(p7),
+            "schedule": "hybrid", "tile_track_length_fraction": frac7,
+            "flights_per_history": g7.counters()["flights"] / (2 * N)}
+        g7.close()
+    if not args.no_other_schedule:
         # population control at census: the duct problem with 20 census steps
         # under the hybrid schedule, without and with splitting-roulette to one
         # particle per source history at every census

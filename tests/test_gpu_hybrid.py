@@ -291,3 +291,35 @@ def test_full_size_duct_hybrid_tile_sampled_histories():
     assert abs(s.sum() - c["path"]) <= 1e-9 * c["path"]
     assert c["w_source"] == c["w_leak"] + c["w_absorb"] + c["w_time_end"]
     assert c["leaks"] + c["absorptions"] + c["time_ends"] == n
+
+
+def test_full_size_multigroup_duct_hybrid_sampled_histories():
+    """The 7-group duct at full size (1e8 histories, 60x100x60 x 20 t x 7 groups
+    = 5.04e7 bins, per-batch slices), hybrid schedule with the tile the
+    autotuner plans for it: sampled histories recomputed one by one by the
+    oracle match bit for bit; all track length is scored and weight balances."""
+    from paper_2409_04668_amd import autotune
+    mc = _mcdc()
+    n = 100_000_000
+    p = W.config3()
+    tile, frac = autotune.plan_hot_tile(p, pilot=1_000_000)
+    assert tile is not None and frac > 0.0
+    gp = mc.Problem(p, _hy_tile(tile, chunk=1 << 25))
+    gp.set_history_scores(n)
+    gp.run(n, seed=2029)
+    hs = gp.history_scores()
+    c = gp.counters()
+    s, _ = gp.raw()
+    gp.close()
+    rng = np.random.default_rng(2)
+    ids = np.unique(np.concatenate([[0, (1 << 25) - 1, 1 << 25, n - 1], rng.integers(0, n, 24),
+                                    np.nonzero(hs[:, 0] > 0)[0][:8]]))
+    q = dict(p)
+    q["n_batches"] = 1
+    for i in ids:
+        r = O.OracleRun(q)
+        _, ho = r.run(1, 2029, per_history=True, first_id=int(i))
+        assert np.array_equal(ho[0], hs[i]), (i, ho[0], hs[i])
+    assert c["histories"] == n and c["particles"] == n
+    assert abs(s.sum() - c["path"]) <= 1e-9 * c["path"]
+    assert c["w_source"] == c["w_leak"] + c["w_absorb"] + c["w_time_end"]
