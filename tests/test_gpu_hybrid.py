@@ -323,3 +323,14 @@ def test_full_size_multigroup_duct_hybrid_sampled_histories():
     assert c["histories"] == n and c["particles"] == n
     assert abs(s.sum() - c["path"]) <= 1e-9 * c["path"]
     assert c["w_source"] == c["w_leak"] + c["w_absorb"] + c["w_time_end"]
+
+
+@pytest.mark.parametrize("sched", ["history", "hybrid", "event"])
+def test_full_size_slab_every_history(sched):
+    """The slab problem at its full size (1e5 histories, 100 x-bins x 20
+    t-bins): every history's (detector score, path) bit for bit, tallies and
+    batch sums of squares to 1e-10, counters exact, under each schedule."""
+    mc = _mcdc()
+    opt = mc.make_options({"history": mc.SCHED_HISTORY, "hybrid": mc.SCHED_HYBRID,
+                           "event": mc.SCHED_EVENT}[sched])
+    full_parity(W.config1(), 100_000, seed=2030, options=opt)
