@@ -505,32 +505,22 @@ static RunArgs base_args(mcdc_handle h, uint64_t seed) {
     return A;
 }
 
-// Batch close-outs of an event-schedule run of n histories (per-batch slices).
+// Batch close-outs of an event- or hybrid-schedule run of n histories: every
+// per-batch slice in one launch per tally.
 static int close_event_run(mcdc_handle h, uint64_t n, hipStream_t s) {
-    const uint64_t B = (uint64_t)h->desc.n_batches;
-    double *batch = (double *)(h->ws + h->L.tally_batch);
-    double *sum = (double *)(h->ws + h->L.tally_sum);
-    double *sumsq = (double *)(h->ws + h->L.tally_sumsq);
-    double *cbatch = (double *)(h->ws + h->L.col_batch);
-    double *csum = (double *)(h->ws + h->L.col_sum);
-    double *csumsq = (double *)(h->ws + h->L.col_sumsq);
-    double *sbatch = (double *)(h->ws + h->L.surf_batch);
-    double *ssum = (double *)(h->ws + h->L.surf_sum);
-    double *ssumsq = (double *)(h->ws + h->L.surf_sumsq);
-    for (uint64_t b = 0; b < B; ++b) {
-        const uint64_t lo = (b * n) / B, hi = ((b + 1) * n) / B;
-        if (hi == lo) continue;
-        hipError_t e = launch_closeout(batch + b * (uint64_t)h->nbins, sum, sumsq, h->nbins,
-                                       (double)(hi - lo), s);
-        if (e == hipSuccess && h->desc.col_tally)
-            e = launch_closeout(cbatch + b * (uint64_t)h->nbins, csum, csumsq, h->nbins,
-                                (double)(hi - lo), s);
-        if (e == hipSuccess && h->desc.surf_on)
-            e = launch_closeout(sbatch + b * (uint64_t)h->P.surf_nbins, ssum, ssumsq,
-                                h->P.surf_nbins, (double)(hi - lo), s);
-        if (e != hipSuccess) return hip_fail(e, "run launch");
-        h->batches += 1;
-    }
+    const uint32_t B = (uint32_t)h->desc.n_batches;
+    hipError_t e = launch_closeout_run((double *)(h->ws + h->L.tally_batch),
+                                       (double *)(h->ws + h->L.tally_sum),
+                                       (double *)(h->ws + h->L.tally_sumsq), h->nbins, B, n, s);
+    if (e == hipSuccess && h->desc.col_tally)
+        e = launch_closeout_run((double *)(h->ws + h->L.col_batch), (double *)(h->ws + h->L.col_sum),
+                                (double *)(h->ws + h->L.col_sumsq), h->nbins, B, n, s);
+    if (e == hipSuccess && h->desc.surf_on)
+        e = launch_closeout_run((double *)(h->ws + h->L.surf_batch), (double *)(h->ws + h->L.surf_sum),
+                                (double *)(h->ws + h->L.surf_sumsq), h->P.surf_nbins, B, n, s);
+    if (e != hipSuccess) return hip_fail(e, "run launch");
+    for (uint64_t b = 0; b < B; ++b)
+        if (((b + 1) * n) / B != (b * n) / B) h->batches += 1;
     h->n_hist += n;
     return MCDC_OK;
 }

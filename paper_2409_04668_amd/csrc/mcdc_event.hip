@@ -830,7 +830,9 @@ static int ev_iterate(mcdc_problem *h, const RunArgs &A, hipStream_t s, bool &do
     const int grid = E->grid, block = E->block;
     const bool ww = P.ww_on != 0, pc = P.pc_on != 0, lead = h->opt.lead;
     for (int iter = 0;; ++iter) {
-        const int K = 8;
+        // after a lead stage the banks are often empty: check after one
+        // iteration first, then every eight
+        const int K = lead && iter == 0 ? 1 : 8;
         h->event_iterations += K;
         for (int k = 0; k < K; ++k) {
             // timed stage: the flight stage (the lead stage in the hybrid schedule)

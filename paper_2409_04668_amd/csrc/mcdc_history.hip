@@ -230,6 +230,44 @@ __global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_history(DevProblem, R
     shared_flush(S, A.acc);
 }
 
+// Close-out of every batch slice of a run of n histories in B batches at
+// once: per bin, for b = 0, 1, ..., B-1, sum += S_b, sumsq += S_b^2 / N_b,
+// S_b = 0, with N_b the histories of batch b (empty batches skipped): the
+// additions, in the same order, of B single-slice close-outs.
+__global__ void k_closeout_run(double *__restrict__ batch, double *__restrict__ sum,
+                               double *__restrict__ sumsq, uint32_t n, uint32_t B,
+                               uint64_t n_hist) {
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        double s = sum[i], s2 = sumsq[i];
+        bool touched = false;
+        for (uint32_t b = 0; b < B; ++b) {
+            const uint64_t lo = (b * n_hist) / B, hi = ((b + 1) * n_hist) / B;
+            double *slot = batch + (uint64_t)b * n + i;
+            const double sb = *slot;
+            if (sb == 0.0 || hi == lo) continue;
+            s = s + sb;
+            s2 = s2 + sb * sb / (double)(hi - lo);
+            *slot = 0.0;
+            touched = true;
+        }
+        if (touched) {
+            sum[i] = s;
+            sumsq[i] = s2;
+        }
+    }
+}
+
+hipError_t launch_closeout_run(double *batch, double *sum, double *sumsq, uint32_t n, uint32_t B,
+                               uint64_t n_hist, hipStream_t s) {
+    const int block = 256;
+    int grid = (int)((n + block - 1) / block);
+    if (grid > 65536) grid = 65536;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(k_closeout_run, dim3(grid), dim3(block), 0, s, batch, sum, sumsq, n, B, n_hist);
+    return hipGetLastError();
+}
+
 // The kernels read the problem description through kernel_problem(), the
 // address of their first argument in the kernel-argument segment.  This
 // kernel reads a few fields by name and through that address: *out = 1 when

@@ -124,6 +124,8 @@ hipError_t launch_history(const DevProblem &P, const RunArgs &A, int grid, int b
 hipError_t launch_closeout(double *batch, double *sum, double *sumsq, uint32_t n, double nb,
                            hipStream_t s);
 hipError_t launch_problem_check(const DevProblem &P, int *out, hipStream_t s);
+hipError_t launch_closeout_run(double *batch, double *sum, double *sumsq, uint32_t n, uint32_t B,
+                               uint64_t n_hist, hipStream_t s);
 int history_grid(int block, int waves_per_cu);
 
 }  // namespace mcdc
