@@ -352,8 +352,11 @@ __global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_ev_lead(DevProblem, R
     const uint64_t b_tile = batch_of(A, r0);
     const uint32_t cur = B.ctl->cur, cen = B.ctl->cen;
     const bool stop_at_census = P.pc_on || B.ctl->pause_at_census;
+    // analog histories that cannot stop at a census never reach the banks:
+    // the lead stage closes their statistics itself (lead_finalizes)
+    const bool finalize = WW == 0 && !stop_at_census;
     const uint64_t lane = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t n_flight = 0, n_piece = 0, lead_flights = 0;
+    uint32_t n_flight = 0, n_piece = 0, lead_flights = 0, n_hit = 0;
     double path = 0.0;
     LeadCtx<WW> C{P, A, B, lane, cur, 0u, 0.0, 0.0, 0u, 0};
     LeadTally<LDS> tally;
@@ -369,9 +372,24 @@ __global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_ev_lead(DevProblem, R
                 stack_pop(A, lane, PL.stack_cap, C.sp, q);
             } else {
                 if (in_hist) {
-                    B.xh[C.slot] = C.xh;
-                    B.path[C.slot] = C.path;
-                    B.events[C.slot] = C.events;
+                    if (finalize) {
+                        // nothing of the history was banked: its statistics
+                        // are final (what the finish kernel does otherwise)
+                        if (C.xh != 0.0) {
+                            unsafeAtomicAdd(&A.acc->det[0], C.xh);
+                            unsafeAtomicAdd(&A.acc->det[1], C.xh * C.xh);
+                        }
+                        if (C.xh > 0.0) n_hit += 1;
+                        if (A.xh_out) {
+                            const uint64_t o = A.h_begin + C.slot - A.h_run0;
+                            A.xh_out[2 * o] = C.xh;
+                            A.xh_out[2 * o + 1] = C.path;
+                        }
+                    } else {
+                        B.xh[C.slot] = C.xh;
+                        B.path[C.slot] = C.path;
+                        B.events[C.slot] = C.events;
+                    }
                     in_hist = false;
                 }
                 const uint32_t s = atomicAdd(&s_next, 1u);
@@ -423,6 +441,7 @@ __global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_ev_lead(DevProblem, R
     }
     atomicAdd(&S.cnt[C_FLIGHT], (unsigned long long)n_flight);
     atomicAdd(&S.cnt[C_PIECE], (unsigned long long)n_piece);
+    if (n_hit) atomicAdd(&S.cnt[C_DET_HIT], (unsigned long long)n_hit);
     atomicAdd(&S.wsum[W_PATH], path);
     __syncthreads();
     if (LDS == 2 && r0 < r1) hot_tile_flush(P, s_tile, A.tally + b_tile * (uint64_t)P.nbins);
@@ -864,6 +883,13 @@ static int ev_iterate(mcdc_problem *h, const RunArgs &A, hipStream_t s, bool &do
     }
 }
 
+// Does the lead stage close the statistics of every history itself?  (The
+// same condition as `finalize` in k_ev_lead, for a run without census-step
+// control.)
+static bool lead_finalizes(const mcdc_problem *h) {
+    return h->opt.lead && !h->P.ww_on && !h->P.pc_on;
+}
+
 static int ev_finish_chunk(mcdc_problem *h, const RunArgs &A, hipStream_t s, uint32_t n) {
     EventState *E = h->ev;
     const int fg = (int)((n + E->block - 1) / E->block) < E->grid ? (int)((n + E->block - 1) / E->block)
@@ -890,7 +916,7 @@ int event_run_range(mcdc_problem *h, const RunArgs &A0, hipStream_t s) {
         bool done = false;
         int st = ev_iterate(h, A, s, done);
         if (st) return st;
-        if ((st = ev_finish_chunk(h, A, s, n))) return st;
+        if (!lead_finalizes(h) && (st = ev_finish_chunk(h, A, s, n))) return st;
     }
     return MCDC_OK;
 }
