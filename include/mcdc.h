@@ -130,13 +130,16 @@ typedef struct {
     int32_t block;                     /* work-items per workgroup (multiple of 64) */
     int32_t waves_per_cu;              /* persistent-grid occupancy target        */
     int32_t lds_tally;                 /* 1 allow, 0 forbid an LDS tally tile     */
-    int64_t event_chunk;               /* event mode: histories resident at once;
+    int64_t event_chunk;               /* event and hybrid schedules: histories
+                                          resident at once (at most 2^26);
                                           batched runs: entries per work chunk    */
-    /* History schedule: a sub-box of the tally mesh held in LDS per workgroup
-     * (bins [tile_lo, tile_lo + tile_n) along x, y, z, t, group), flushed to
-     * HBM at the end of each launch; all tile_n > 0 enables it (at most
-     * MCDC_MAX_TILE_BINS bins; workgroups of 1024 work-items).  Place it where
-     * most track-length pieces fall (e.g. from a pilot run's tally). */
+    /* History schedule and the hybrid schedule's lead stage: a sub-box of the
+     * tally mesh held in LDS per workgroup (bins [tile_lo, tile_lo + tile_n)
+     * along x, y, z, t, group), flushed to HBM at the end of each launch (the
+     * lead stage: for the batch of the workgroup's history range); all
+     * tile_n > 0 enables it (at most MCDC_MAX_TILE_BINS bins; workgroups of
+     * 1024 work-items).  Place it where most track-length pieces fall (e.g.
+     * from a pilot run's tally). */
     int32_t tile_lo[5], tile_n[5];
 } mcdc_options;
 
