@@ -73,6 +73,29 @@ def measured_traffic(kernel: str, histories_per_launch: float):
         return None
 
 
+def measured_valu(kernel: str):
+    """VALU issue figures of `kernel` from its committed SQ-counter summary
+    (None if there is none or the kernels changed since)."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_duct_1e8_sq.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_sha") != kernel_hash():
+        return None
+    try:
+        return {"simd_valu_busy_fraction": float(vals["simd_valu_busy_fraction"]),
+                "active_lanes_per_valu_instruction": float(vals["active_lanes_per_valu_instruction"].split()[0]),
+                "lane_throughput_fraction": float(vals["lane_throughput_fraction"]),
+                "source": os.path.relpath(path, ROOT)}
+    except (KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(prob, n_sample, seed):
     from oracle import oracle as O
     O.build(force=False)
@@ -207,7 +230,8 @@ def main():
                      "kernel": kernel, "launches": launches,
                      "avg_launch_ms": 1e3 * avg_launch_s,
                      "algorithmic_bytes_per_launch": bytes_per_launch,
-                     "atomic_updates_per_s": pieces / (kms / 1e3) if kms > 0 else None},
+                     "atomic_updates_per_s": pieces / (kms / 1e3) if kms > 0 else None,
+                     "valu_issue": measured_valu(kernel)},
         "pieces_per_history": pieces / n_done,
         "flights_per_history": (c1["flights"] - c0["flights"]) / n_done,
         "detector": {"mean": float(det_mean[0]), "rel_err": float(det_rel[0])},
