@@ -43,3 +43,38 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_committed_profiles_match_the_kernel_sources():
+    """The PMC and SQ summaries the benchmark reads carry the hash of the
+    kernel sources they were taken with and the histories per launch; they
+    match the current sources, and a changed launch size is refused."""
+    import bench
+    t = bench.measured_traffic("k_ev_lead", 1e8 / 3)
+    assert t is not None and 1e9 < t < 2e10
+    assert bench.measured_traffic("k_ev_lead", 1e8 / 6) is None
+    assert bench.measured_traffic("k_history", 5e6) is not None
+    v = bench.measured_valu("k_ev_lead")
+    assert v is not None and 0 < v["lane_throughput_fraction"] <= v["simd_valu_busy_fraction"] <= 1
+
+
+def test_tuner_trial_options_carry_the_tile_only_where_it_is_used(monkeypatch):
+    """tune_single's trial list on the host (timings stubbed): the history and
+    hybrid trials take the tile, the event trials do not, and population
+    control skips the history schedule and chunks below a batch."""
+    from paper_2409_04668_amd import autotune, mcdc
+    monkeypatch.setattr(autotune, "_time_single", lambda prob, opt, n, seed: float(opt.schedule))
+    monkeypatch.setattr(autotune, "_device_name", lambda: "test")
+    tile = ([1, 2, 3, 0, 0], [4, 5, 6, 2, 1])
+    res = autotune.tune_single(W.config2(), pilot=1000, waves=(8, 16), event_chunks=(1 << 10,),
+                               tile=tile, use_cache=False)
+    opts = [t["options"] for t in res["trials"]]
+    assert [o["schedule"] for o in opts] == [mcdc.SCHED_HISTORY] * 2 + [mcdc.SCHED_EVENT,
+                                                                       mcdc.SCHED_HYBRID]
+    for o in opts:
+        assert ("tile" in o) == (o["schedule"] != mcdc.SCHED_EVENT)
+    assert res["options"]["schedule"] == mcdc.SCHED_HYBRID      # the stub's largest rate
+    p = W.config2()
+    p["population_control"] = dict(target=1.0)
+    res = autotune.tune_single(p, pilot=100_000, event_chunks=(1 << 10, 1 << 16), use_cache=False)
+    assert [t["options"]["event_chunk"] for t in res["trials"]] == [1 << 16, 1 << 16]
