@@ -562,6 +562,8 @@ typedef struct {
     double imp_cnt[16], imp_xsum[16];
     double ww_lo[4], ww_inv[4];
     double *ww_map;           /* window map (NULL: network at every check) */
+    int wwg_on;               /* weight-window grid planes */
+    double wwg_d[3], wwg_id[3];
     int census_hit;           /* the last flight stopped at an intermediate census */
 } o_ctx;
 
@@ -803,8 +805,47 @@ static void o_imp_point(o_ctx *C, const o_part *q)
     }
 }
 
-/* One flight of particle q: the three candidate distances (census, surface,
- * collision), the event with the tie order census < surface < collision,
+/* Weight-window grid (a reading: besides collisions and surface crossings,
+ * the windows are checked where a flight reaches a plane of a regular grid
+ * over the outer box).  Interior planes lo + k (hi - lo) / n, k = 1..n-1, per
+ * axis.  Distance along u to the next plane ahead of p: moving up,
+ * k = floor((p - lo) / delta) + 1; moving down, the plane at or below p, one
+ * lower when p lies on it; then one further while the distance
+ * (plane - p) * (1 / u) is not positive, so a particle standing on a plane
+ * moves off it.  The first strict minimum in axis order x, y, z wins;
+ * returns +inf when no interior plane lies ahead. */
+static double o_dist_wwplane(const o_ctx *C, const double p[3], const double u[3],
+                             const double iu[3], int *axis, double *plane)
+{
+    const orc_problem *P = C->P;
+    double best = O_INF;
+    int bax = -1;
+    double bpl = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        if (u[a] == 0.0) continue;
+        const double lo = P->outer_lo[a], dl = C->wwg_d[a];
+        const double q = (p[a] - lo) * C->wwg_id[a];
+        const double f = floor(q);
+        double k = u[a] > 0.0 ? f + 1.0 : (q == f ? f - 1.0 : f);
+        const double step = u[a] > 0.0 ? 1.0 : -1.0;
+        double pl = lo + k * dl;
+        double s = (pl - p[a]) * iu[a];
+        for (int it = 0; it < 4 && !(s > 0.0); ++it) {
+            k = k + step;
+            pl = lo + k * dl;
+            s = (pl - p[a]) * iu[a];
+        }
+        if (!(s > 0.0) || k < 1.0 || k > (double)(P->ww_grid_n[a] - 1)) continue;
+        if (s < best) { best = s; bax = a; bpl = pl; }
+    }
+    *axis = bax;
+    *plane = bpl;
+    return best;
+}
+
+/* One flight of particle q: the candidate distances (census, surface, the
+ * next weight-window grid plane when windows and a grid are on, collision),
+ * the event with the tie order census < surface < grid plane < collision,
  * track-length scoring of the flight, the move of Fig. 2, and the event. */
 static void o_flight(o_ctx *C, o_part *q)
 {
@@ -834,10 +875,18 @@ static void o_flight(o_ctx *C, o_part *q)
     }
     q->k = st.k;
 
+    /* weight-window grid plane (only with windows and a grid) */
+    int wax = -1;
+    double wpl = 0.0;
+    double d_w = O_INF;
+    if (C->wwg_on) d_w = o_dist_wwplane(C, q->p, q->u, iu, &wax, &wpl);
+
+    /* ties: census, then surface, then grid plane, then collision */
     int ev;
     double d;
-    if (d_t <= d_s && d_t <= d_c) { ev = ORC_EV_CENSUS; d = d_t; }
-    else if (d_s <= d_c) { ev = ORC_EV_SURFACE; d = d_s; }
+    if (d_t <= d_s && d_t <= d_w && d_t <= d_c) { ev = ORC_EV_CENSUS; d = d_t; }
+    else if (d_s <= d_w && d_s <= d_c) { ev = ORC_EV_SURFACE; d = d_s; }
+    else if (wax >= 0 && d_w <= d_c) { ev = ORC_EV_WW_PLANE; d = d_w; }
     else { ev = ORC_EV_SCATTER; d = d_c; }
 
     /* track-length scoring of [0, d] */
@@ -875,6 +924,14 @@ static void o_flight(o_ctx *C, o_part *q)
         return;
     }
     q->t = q->t + d / v;
+
+    if (ev == ORC_EV_WW_PLANE) {
+        q->p[wax] = wpl;                 /* on the plane exactly */
+        R->cnt[ORC_C_WW_PLANE] += 1;
+        o_trace(C, q, ORC_EV_WW_PLANE, d);
+        o_ww(C, q);
+        return;
+    }
 
     if (ev == ORC_EV_SURFACE) {
         q->p[sax] = spl;
@@ -1226,6 +1283,15 @@ static int o_validate(const orc_problem *P)
     if (P->pc_on && (P->imp_on || !(P->pc_target > 0.0))) return ORC_E_INVALID;
     if (P->surf_on && (P->surf_axis < 0 || P->surf_axis > 2 || !isfinite(P->surf_pos)))
         return ORC_E_INVALID;
+    {
+        int gpos = 0, gzero = 0;
+        for (int a = 0; a < 3; ++a) {
+            if (P->ww_grid_n[a] > 0 && P->ww_grid_n[a] <= 65536) ++gpos;
+            if (P->ww_grid_n[a] == 0) ++gzero;
+        }
+        if (!(gpos == 3 || gzero == 3)) return ORC_E_INVALID;
+        if (gpos == 3 && !P->ww_on) return ORC_E_INVALID;
+    }
     if (P->ww_on) {
         int pos = 0, zero = 0;
         for (int a = 0; a < 4; ++a) {
@@ -1255,6 +1321,11 @@ int orc_run(const orc_problem *P, uint64_t seed, uint64_t hist0, uint64_t n_hist
     C.status = ORC_OK;
     C.stack = (o_part *)malloc(sizeof(o_part) * (size_t)(P->stack_cap > 0 ? P->stack_cap : 1));
     o_ww_norm(P, C.ww_lo, C.ww_inv);
+    C.wwg_on = P->ww_on && P->ww_grid_n[0] > 0;
+    for (int a = 0; a < 3 && C.wwg_on; ++a) {
+        C.wwg_d[a] = (P->outer_hi[a] - P->outer_lo[a]) / (double)P->ww_grid_n[a];
+        C.wwg_id[a] = 1.0 / C.wwg_d[a];
+    }
     if (o_has_map(P)) {
         size_t cells = (size_t)P->G * P->ww_map_n[0] * P->ww_map_n[1] * P->ww_map_n[2] *
                        P->ww_map_n[3];

@@ -44,6 +44,7 @@ enum {
     ORC_EV_CUTOFF_SURVIVE = 11,
     ORC_EV_PC_KILL = 12,          /* population control at a census: removed        */
     ORC_EV_PC_KEEP = 13,          /* population control: kept as aux copies        */
+    ORC_EV_WW_PLANE = 14,         /* a flight reached a weight-window grid plane   */
 };
 
 /* counters */
@@ -51,7 +52,7 @@ enum {
     ORC_C_HIST = 0, ORC_C_FLIGHT, ORC_C_PIECE, ORC_C_COLLISION, ORC_C_ABSORB,
     ORC_C_SURFACE, ORC_C_LEAK, ORC_C_CENSUS, ORC_C_TIME_END, ORC_C_SPLIT,
     ORC_C_RR_KILL, ORC_C_RR_SURVIVE, ORC_C_CUT_KILL, ORC_C_CUT_SURVIVE,
-    ORC_C_DET_HIT, ORC_C_PARTICLE, ORC_C_PC_KILL, ORC_C_PC_COPY, ORC_C_SURF_CROSS, ORC_NCOUNT
+    ORC_C_DET_HIT, ORC_C_PARTICLE, ORC_C_PC_KILL, ORC_C_PC_COPY, ORC_C_SURF_CROSS, ORC_C_WW_PLANE, ORC_NCOUNT
 };
 /* weight sums */
 enum {
@@ -93,6 +94,9 @@ typedef struct {
     int32_t ww_map_n[4];              /* all > 0: targets from a cell-centre map of the
                                          network, (nx, ny, nz, nt) cells; 0: network
                                          evaluated at every check */
+    int32_t ww_grid_n[3];             /* all > 0: the windows are also checked where a
+                                         flight reaches an interior plane of an
+                                         (nx, ny, nz) grid over the outer box; 0: off */
     int32_t col_tally;                /* also a collision-estimator mesh tally */
     int32_t surf_on;                  /* also a surface-current tally on the plane
                                          x[surf_axis] = surf_pos                 */

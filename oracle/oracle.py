@@ -21,16 +21,17 @@ LIB_PATH = os.path.join(HERE, "liboracle.so")
 CFLAGS = ["-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
           "-Wall", "-Wno-unused-function"]
 
-NCOUNT = 19
+NCOUNT = 20
 NWSUM = 7
 COUNTER_NAMES = ["hist", "flight", "piece", "collision", "absorb", "surface", "leak",
                  "census", "time_end", "split", "rr_kill", "rr_survive", "cut_kill",
-                 "cut_survive", "det_hit", "particle", "pc_kill", "pc_copy", "surf_cross"]
+                 "cut_survive", "det_hit", "particle", "pc_kill", "pc_copy", "surf_cross",
+                 "ww_plane"]
 WSUM_NAMES = ["source", "leak", "absorb", "time_end", "gain", "loss", "path"]
 
 EV = dict(source=0, scatter=1, absorb=2, surface=3, leak=4, census=5, time_end=6, split=7,
           roulette_kill=8, roulette_survive=9, cutoff_kill=10, cutoff_survive=11, pc_kill=12,
-          pc_keep=13)
+          pc_keep=13, ww_plane=14)
 
 
 def build(force: bool = True) -> str:
@@ -68,6 +69,7 @@ class OrcProblem(C.Structure):
         ("ww_on", C.c_int32), ("ww_hidden", C.c_int32), ("ww_nmax", C.c_int32),
         ("ww_params", PF), ("ww_ymin", C.c_float), ("ww_ymax", C.c_float),
         ("ww_logk", C.c_double), ("ww_ratio", C.c_double), ("ww_map_n", I4),
+        ("ww_grid_n", C.c_int32 * 3),
         ("col_tally", C.c_int32), ("surf_on", C.c_int32), ("surf_axis", C.c_int32),
         ("surf_pos", C.c_double), ("pc_on", C.c_int32), ("pc_target", C.c_double),
         ("n_batches", C.c_int32), ("max_events", C.c_int64), ("stack_cap", C.c_int32),
@@ -207,6 +209,8 @@ class _Problem:
             s.ww_ymax = float(ww.get("ymax", 3.0e38))
             if ww.get("map") is not None:
                 s.ww_map_n = I4(*[int(v) for v in ww["map"]])
+            if ww.get("grid") is not None:
+                s.ww_grid_n = (C.c_int32 * 3)(*[int(v) for v in ww["grid"]])
         s.col_tally = 1 if prob.get("collision_tally") else 0
         sf = prob.get("surface_tally")
         s.surf_on = 1 if sf is not None else 0
