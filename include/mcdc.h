@@ -160,6 +160,7 @@ typedef struct {
                                           iterations launched                     */
     uint64_t pc_kills, pc_copies;      /* population control: removed / added      */
     uint64_t surf_crossings;           /* scored surface-tally crossings          */
+    uint64_t ww_plane_stops;           /* flights ended on a window grid plane    */
 } mcdc_counters;
 
 typedef struct mcdc_problem *mcdc_handle;
@@ -275,6 +276,15 @@ int mcdc_set_ww_mlp(mcdc_handle h, const float *params, size_t n_params, double 
  * MCDC_E_NOMEM when capacity (in doubles) is too small. */
 int mcdc_set_ww_map(mcdc_handle h, const int32_t n[4], double *dev_map, size_t capacity,
                     void *stream);
+
+/* Weight-window grid planes (a reading: the paper places no window checks):
+ * besides after collisions and surface crossings, the windows are checked
+ * where a flight reaches an interior plane of a regular n[0] x n[1] x n[2]
+ * grid over the outer box (planes lo + k (hi - lo) / n, k = 1..n-1 per axis;
+ * the flight stops on the plane; ties: census, surface, plane, collision).
+ * n == NULL or all zero turns the planes off.  Each n[a] lies in [1, 65536].
+ * MCDC_E_STATE without a network. */
+int mcdc_set_ww_grid(mcdc_handle h, const int32_t n[3]);
 
 /* Coarse importance estimate accumulated by runs with imp_on: host copies of
  * score[c] and weight[c] for G * imp_n[0..3] cells (x fastest, then y, z, t, g). */

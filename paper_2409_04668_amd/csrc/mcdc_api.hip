@@ -460,6 +460,7 @@ int mcdc_set_ww_mlp(mcdc_handle h, const float *params, size_t n, double logk, d
     if (!params) {
         h->P.ww_on = 0;
         h->P.ww_map = nullptr;
+        h->P.ww_grid_on = 0;
         return MCDC_OK;
     }
     if (h->desc.stack_cap < 1) return fail(MCDC_E_STATE, "problem was created with stack_cap = 0");
@@ -477,6 +478,25 @@ int mcdc_set_ww_mlp(mcdc_handle h, const float *params, size_t n, double logk, d
     h->P.ww_nmax = n_max;
     h->P.ww_ymin = ymin;
     h->P.ww_ymax = ymax;
+    return MCDC_OK;
+}
+
+int mcdc_set_ww_grid(mcdc_handle h, const int32_t n[3]) {
+    if (!h) return fail(MCDC_E_INVALID, "null handle");
+    if (h->is_batch) return fail(MCDC_E_STATE, "batched handle has no weight windows");
+    if (!n || (n[0] == 0 && n[1] == 0 && n[2] == 0)) {
+        h->P.ww_grid_on = 0;
+        return MCDC_OK;
+    }
+    if (!h->P.ww_on) return fail(MCDC_E_STATE, "set the network with mcdc_set_ww_mlp first");
+    for (int a = 0; a < 3; ++a)
+        if (n[a] < 1 || n[a] > (1 << 16)) return fail(MCDC_E_INVALID, "grid planes: n must lie in [1, 65536]");
+    for (int a = 0; a < 3; ++a) {
+        h->P.ww_grid_n[a] = n[a];
+        h->P.ww_grid_d[a] = (h->desc.outer_hi[a] - h->desc.outer_lo[a]) / (double)n[a];
+        h->P.ww_grid_id[a] = 1.0 / h->P.ww_grid_d[a];
+    }
+    h->P.ww_grid_on = 1;
     return MCDC_OK;
 }
 
@@ -764,6 +784,7 @@ void mcdc::fill_counters(const DevAcc &a, mcdc_counters *o) {
     o->detector_hits = c[C_DET_HIT]; o->particles = c[C_PARTICLE];
     o->pc_kills = c[C_PC_KILL]; o->pc_copies = c[C_PC_COPY];
     o->surf_crossings = c[C_SURF];
+    o->ww_plane_stops = c[C_WW_PLANE];
     o->w_source = a.wsum[W_SOURCE]; o->w_leak = a.wsum[W_LEAK]; o->w_absorb = a.wsum[W_ABSORB];
     o->w_time_end = a.wsum[W_TIME_END]; o->w_gain = a.wsum[W_GAIN]; o->w_loss = a.wsum[W_LOSS];
     o->path = a.wsum[W_PATH];

@@ -40,6 +40,7 @@ struct Bank {
 };
 
 enum { R_A = 0, R_B = 1, R_C = 2, R_X = 3 };   // three role banks, interaction bank
+constexpr uint32_t kPlaneMark = 0x80000000u;     // interaction entry: a grid-plane stop
 
 struct EvCtl {
     uint32_t n_act[3];                   // particles in the three role banks
@@ -432,6 +433,8 @@ __global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_ev_lead(DevProblem, R
             due = stage_surface(PL, A, S, C, q, d);
         } else if (ev == EV_SCATTER) {
             due = stage_collision(PL, A, S, C, q, d);
+        } else if (ev == EV_WW_PLANE) {
+            due = true;
         } else if (ev == EV_CENSUS && stop_at_census) {
             bank_put(A, B, B.b[cen], atomicAdd(&B.ctl->n_act[cen], 1u), q, d, C.slot);
             q.alive = false;
@@ -476,10 +479,13 @@ __global__ void __launch_bounds__(256) k_ev_flight(DevProblem, RunArgs A, EvBank
             if (ev >= 0) n_flight += 1;
             if (!q.alive) ev = -1;
         }
-        const uint32_t ps = wave_reserve(&B.ctl->n_surf, ev == EV_SURFACE);
+        // grid-plane stops go to the front of the interaction bank with the
+        // surfaces, marked in the slot's top bit (slots are below 2^26)
+        const bool front = ev == EV_SURFACE || ev == EV_WW_PLANE;
+        const uint32_t ps = wave_reserve(&B.ctl->n_surf, front);
         const uint32_t pc = wave_reserve(&B.ctl->n_coll, ev == EV_SCATTER);
         const uint32_t pn = wave_reserve(&B.ctl->n_act[cen], ev == EV_CENSUS);
-        if (ev == EV_SURFACE) bank_put(A, B, X, ps, q, d, slot);
+        if (front) bank_put(A, B, X, ps, q, d, ev == EV_WW_PLANE ? slot | kPlaneMark : slot);
         else if (ev == EV_SCATTER) bank_put(A, B, X, B.cap - 1u - pc, q, d, slot);
         else if (ev == EV_CENSUS) bank_put(A, B, CB, pn, q, d, slot);
     }
@@ -563,8 +569,12 @@ __global__ void __launch_bounds__(256) k_ev_interact(DevProblem, RunArgs A, EvBa
         if (valid) {
             const bool surf = jj < ns;
             bank_load(X, B.cap, surf ? jj : B.cap - 1u - (jj - ns), q, d, slot);
+            const bool plane = surf && (slot & kPlaneMark) != 0u;   // grid-plane stop
+            slot &= ~kPlaneMark;
             EvCtx<WW> C{PL, A, B, slot};
-            const bool due = surf ? stage_surface(PL, A, S, C, q, d) : stage_collision(PL, A, S, C, q, d);
+            const bool due = plane ? true
+                                   : (surf ? stage_surface(PL, A, S, C, q, d)
+                                           : stage_collision(PL, A, S, C, q, d));
             if (WW != 0 && due) ww_check(PL, A, S, C, q);
             alive = q.alive;
             if (WW != 0 && C.split_n > 1) {

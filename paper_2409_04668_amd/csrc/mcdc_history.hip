@@ -204,6 +204,8 @@ __global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_history(DevProblem, R
             ww_due = stage_surface(PL, A, S, H, q, d);
         } else if (ev == EV_SCATTER) {
             ww_due = stage_collision(PL, A, S, H, q, d);
+        } else if (ev == EV_WW_PLANE) {
+            ww_due = true;
         } else if (ev < 0) {
             H.sp = 0;                       // event cap: the history is abandoned
         }

@@ -22,7 +22,7 @@ constexpr int kLdsTallyMaxBins = 7680;       // 60 KiB of FP64 LDS tile
 enum {
     C_HIST = 0, C_FLIGHT, C_PIECE, C_COLLISION, C_ABSORB, C_SURFACE, C_LEAK, C_CENSUS,
     C_TIME_END, C_SPLIT, C_RR_KILL, C_RR_SURVIVE, C_CUT_KILL, C_CUT_SURVIVE, C_DET_HIT,
-    C_PARTICLE, C_PC_KILL, C_PC_COPY, C_SURF, N_CNT
+    C_PARTICLE, C_PC_KILL, C_PC_COPY, C_SURF, C_WW_PLANE, N_CNT
 };
 enum { W_SOURCE = 0, W_LEAK, W_ABSORB, W_TIME_END, W_GAIN, W_LOSS, W_PATH, N_WSUM };
 
@@ -30,7 +30,7 @@ enum { W_SOURCE = 0, W_LEAK, W_ABSORB, W_TIME_END, W_GAIN, W_LOSS, W_PATH, N_WSU
 enum {
     EV_SOURCE = 0, EV_SCATTER = 1, EV_ABSORB = 2, EV_SURFACE = 3, EV_LEAK = 4, EV_CENSUS = 5,
     EV_TIME_END = 6, EV_SPLIT = 7, EV_RR_KILL = 8, EV_RR_SURVIVE = 9, EV_CUT_KILL = 10,
-    EV_CUT_SURVIVE = 11, EV_PC_KILL = 12, EV_PC_KEEP = 13,
+    EV_CUT_SURVIVE = 11, EV_PC_KILL = 12, EV_PC_KEEP = 13, EV_WW_PLANE = 14,
 };
 
 struct DevAcc {
@@ -77,6 +77,8 @@ struct DevProblem {
     double ww_logk, ww_ratio, ww_lo[4], ww_inv[4];
     const double *ww_map;                // device w_T per map cell, or null (network per check)
     int32_t ww_map_n[4];
+    int32_t ww_grid_on, ww_grid_n[3];    // window checks also on the interior planes of a
+    double ww_grid_d[3], ww_grid_id[3];  // regular grid over the outer box (delta, 1/delta)
     int64_t max_events;
     int32_t stack_cap;
     uint32_t problem_id;

@@ -498,6 +498,40 @@ MCDC_DEV float mlp_infer(const float *__restrict__ gprm, int in_dim, const float
     return out;
 }
 
+// Weight-window grid planes: the interior planes lo + k delta (k = 1..n-1) of
+// a regular grid over the outer box, per axis.  Distance along u to the next
+// one ahead of p: moving up k = floor((p - lo) / delta) + 1, moving down the
+// plane at or below p (one lower when p is on it); then one further while
+// (plane - p) * iu is not positive, so a particle on a plane moves off it.
+// First strict minimum in axis order; +inf (axis -1) when none lies ahead.
+MCDC_DEV double dist_ww_plane(CP &P, const double p[3], const double u[3], const double iu[3],
+                              int &axis, double &plane) {
+    double best = kInf;
+    int bax = -1;
+    double bpl = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (u[a] == 0.0) continue;
+        const double lo = P.outer_lo[a], dl = P.ww_grid_d[a];
+        const double q = (p[a] - lo) * P.ww_grid_id[a];
+        const double f = floor(q);
+        const bool up = u[a] > 0.0;
+        double k = up ? f + 1.0 : (q == f ? f - 1.0 : f);
+        double pl = lo + k * dl;
+        double s = (pl - p[a]) * iu[a];
+        for (int it = 0; it < 4 && !(s > 0.0); ++it) {
+            k = up ? k + 1.0 : k - 1.0;
+            pl = lo + k * dl;
+            s = (pl - p[a]) * iu[a];
+        }
+        if (!(s > 0.0) || k < 1.0 || k > (double)(P.ww_grid_n[a] - 1)) continue;
+        if (s < best) { best = s; bax = a; bpl = pl; }
+    }
+    axis = bax;
+    plane = bpl;
+    return best;
+}
+
 // Surface-current tally on the plane x[a] = c (a = P.surf_axis, c =
 // P.surf_pos): a flight p + s u, s in (0, d], crosses it at
 // s* = (c - p[a]) * iu[a] when 0 < s* <= d and adds its weight w to the bin

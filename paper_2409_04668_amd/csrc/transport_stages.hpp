@@ -188,11 +188,13 @@ MCDC_DEV void stage_source(CP &P, const RunArgs &A, Shared &S, Ctx &C, Part &q) 
     trace_rec(A, C.hist(), q, EV_SOURCE, 0.0);
 }
 
-// Flight: census, surface and collision distances; the event (ties: census,
-// then surface, then collision); track-length scoring; the move of Fig. 2;
-// census and end-of-time handling.  Returns EV_CENSUS (particle continues),
-// EV_TIME_END or -1 (particle ended), EV_SURFACE or EV_SCATTER (the surface or
-// collision stage comes next; `d` is the flight length).
+// Flight: census, surface, weight-window grid plane (windows with a grid) and
+// collision distances; the event (ties: census, then surface, then grid
+// plane, then collision); track-length scoring; the move of Fig. 2; census and
+// end-of-time handling.  Returns EV_CENSUS (particle continues), EV_TIME_END or
+// -1 (particle ended), EV_SURFACE or EV_SCATTER (the surface or collision
+// stage comes next), EV_WW_PLANE (the window check comes next); `d` is the
+// flight length.
 template <class T, class Ctx>
 MCDC_DEV int stage_flight(CP &P, const RunArgs &A, Shared &S, const T &tally, Ctx &C,
                           Part &q, double &d, uint32_t &n_piece, double &path) {
@@ -222,9 +224,16 @@ MCDC_DEV int stage_flight(CP &P, const RunArgs &A, Shared &S, const T &tally, Ct
     }
     q.k = r.k;
 
+    // weight-window grid plane (windows with a grid only)
+    int wax = -1;
+    double wpl = 0.0, d_w = kInf;
+    if (Ctx::kWW && P.ww_grid_on) d_w = dist_ww_plane(P, q.x, q.u, iu, wax, wpl);
+
+    // ties: census, surface, grid plane, collision
     int ev;
-    if (d_t <= d_s && d_t <= d_c) { ev = EV_CENSUS; d = d_t; }
-    else if (d_s <= d_c) { ev = EV_SURFACE; d = d_s; }
+    if (d_t <= d_s && d_t <= d_w && d_t <= d_c) { ev = EV_CENSUS; d = d_t; }
+    else if (d_s <= d_w && d_s <= d_c) { ev = EV_SURFACE; d = d_s; }
+    else if (wax >= 0 && d_w <= d_c) { ev = EV_WW_PLANE; d = d_w; }
     else { ev = EV_SCATTER; d = d_c; }
 
     n_piece += score_mesh(P, q.x, q.u, iu, q.t, v, d, q.w, q.g, tally);
@@ -257,6 +266,16 @@ MCDC_DEV int stage_flight(CP &P, const RunArgs &A, Shared &S, const T &tally, Ct
         return EV_CENSUS;
     }
     q.t = q.t + d / v;
+    if (Ctx::kWW && ev == EV_WW_PLANE) {
+        // on the plane exactly (select, no dynamic index); the window check
+        // comes next
+        if (wax == 0) q.x[0] = wpl;
+        else if (wax == 1) q.x[1] = wpl;
+        else q.x[2] = wpl;
+        atomicAdd(&S.cnt[C_WW_PLANE], 1ull);
+        trace_rec(A, C.hist(), q, EV_WW_PLANE, d);
+        return EV_WW_PLANE;
+    }
     if (ev == EV_SURFACE) {
         // snap the crossing coordinate onto the plane (select, no dynamic index)
         if (sax == 0) q.x[0] = spl;

@@ -207,10 +207,13 @@ def source_log_k(prob: dict, params, ymin, ymax, n=10000, seed=3):
 
 
 def build_ww(prob: dict, n_runs=20, n_per_run=1_000_000, seed0=W.ROOT_SEED + 1, steps=3000,
-             lr=3e-3, ratio=5.0, n_max=10, method="auto", map_dims=None, grid=None):
+             lr=3e-3, ratio=5.0, n_max=10, method="auto", map_dims=None, grid=None,
+             grid_planes=None):
     """Whole pipeline; returns (ww dict for the problem, info dict).  With
     ``map_dims`` = (nx, ny, nz, nt) the transport reads w_T from the network
-    baked onto that cell-centre map instead of evaluating it at every check."""
+    baked onto that cell-centre map instead of evaluating it at every check;
+    with ``grid_planes`` = (nx, ny, nz) the windows are also checked on the
+    interior planes of that grid over the outer box."""
     G = prob["sigma_t"].shape[1]
     if method == "auto":
         method = "reciprocal" if G == 1 and prob.get("detector") is not None else "forward"
@@ -223,7 +226,8 @@ def build_ww(prob: dict, n_runs=20, n_per_run=1_000_000, seed0=W.ROOT_SEED + 1, 
     ymin, ymax = float(y.min()), float(y.max())
     logk = source_log_k(prob, params, ymin, ymax)
     ww = dict(params=params, hidden=mcdc.HIDDEN, logk=logk, ratio=ratio, n_max=n_max,
-              ymin=ymin, ymax=ymax, map=None if map_dims is None else tuple(map_dims))
+              ymin=ymin, ymax=ymax, map=None if map_dims is None else tuple(map_dims),
+              grid=None if grid_planes is None else tuple(grid_planes))
     info = dict(method=method, importance_seconds=t_imp, train_seconds=t_train,
                 n_points=int(X.shape[0]), loss_first=float(losses[0]), loss_last=float(losses[-1]),
                 target_var=float(np.var(y)), logk=logk, ymin=ymin, ymax=ymax)

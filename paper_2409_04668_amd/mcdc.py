@@ -90,7 +90,8 @@ class Counters(C.Structure):
                 [("leak", C.c_double * 6), ("det_sum", C.c_double), ("det_sumsq", C.c_double),
                  ("batches", C.c_int64), ("n_hist", C.c_uint64), ("status", C.c_int32),
                  ("event_iterations", C.c_uint64), ("pc_kills", C.c_uint64),
-                 ("pc_copies", C.c_uint64), ("surf_crossings", C.c_uint64)])
+                 ("pc_copies", C.c_uint64), ("surf_crossings", C.c_uint64),
+                 ("ww_plane_stops", C.c_uint64)])
 
     def as_dict(self):
         d = {n: getattr(self, n) for n, _ in self._fields_ if n != "leak"}
@@ -137,6 +138,7 @@ _sig("mcdc_set_history_scores", C.c_int, VP, VP)
 _sig("mcdc_set_ww_mlp", C.c_int, VP, C.POINTER(C.c_float), C.c_size_t, C.c_double, C.c_double,
      C.c_int32, C.c_float, C.c_float)
 _sig("mcdc_set_ww_map", C.c_int, VP, C.POINTER(C.c_int32), VP, C.c_size_t, VP)
+_sig("mcdc_set_ww_grid", C.c_int, VP, C.POINTER(C.c_int32))
 _sig("mcdc_get_importance", C.c_int, VP, PD, PD, C.c_size_t, VP)
 _sig("mcdc_mlp_param_count", C.c_size_t, C.c_int32)
 _sig("mcdc_mlp_forward", C.c_int, VP, C.c_int32, VP, C.c_size_t, VP, VP)
@@ -300,6 +302,8 @@ class Problem:
                         ww.get("ymin", -3.0e38), ww.get("ymax", 3.0e38))
             if ww.get("map") is not None:
                 self.set_ww_map(ww["map"])
+            if ww.get("grid") is not None:
+                self.set_ww_grid(ww["grid"])
 
     def close(self):
         if self.h:
@@ -388,6 +392,15 @@ class Problem:
         check(_lib.mcdc_set_ww_map(self.h, n, _ptr(buf), cells, _stream_ptr(stream)),
               "set_ww_map")
         self._ww_map = buf
+
+    def set_ww_grid(self, n):
+        """Window checks also on the interior planes of an n[0] x n[1] x n[2]
+        grid over the outer box (None turns them off)."""
+        if n is None:
+            check(_lib.mcdc_set_ww_grid(self.h, None), "set_ww_grid")
+            return
+        arr = (C.c_int32 * 3)(*[int(v) for v in n])
+        check(_lib.mcdc_set_ww_grid(self.h, arr), "set_ww_grid")
 
     def ww_map(self):
         """The baked window targets w_T as a host array [g][t][z][y][x]."""

@@ -11,7 +11,7 @@ INT_COUNTERS = [("hist", "histories"), ("flight", "flights"), ("piece", "pieces"
                 ("cut_kill", "cutoff_kills"), ("cut_survive", "cutoff_survivals"),
                 ("det_hit", "detector_hits"), ("particle", "particles"),
                 ("pc_kill", "pc_kills"), ("pc_copy", "pc_copies"),
-                ("surf_cross", "surf_crossings")]
+                ("surf_cross", "surf_crossings"), ("ww_plane", "ww_plane_stops")]
 W_COUNTERS = [("source", "w_source"), ("leak", "w_leak"), ("absorb", "w_absorb"),
               ("time_end", "w_time_end"), ("gain", "w_gain"), ("loss", "w_loss"),
               ("path", "path")]
