@@ -399,6 +399,17 @@ MCDC_DEV uint32_t score_mesh(CP &P, const double p[3], const double u[3],
     const uint32_t n0 = P.mesh_n[0], n1 = P.mesh_n[1], n2 = P.mesh_n[2], n3 = P.mesh_n[3];
     const uint32_t gt = (uint32_t)(P.G_t > 1 ? g : 0);
     const uint32_t gbase = gt * n3;
+    // Per-axis step and edge offset: moving up, the next edge above cell i is
+    // edge i + 1; moving down, the edge below cell i is edge i.  The advance
+    // below computes every axis's candidate and keeps it by select, so lanes
+    // with different direction signs or tie patterns run the same
+    // instructions (the values are those of advancing axis by axis).
+    int step[3], off[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        step[a] = u[a] > 0.0 ? 1 : -1;
+        off[a] = u[a] > 0.0 ? 1 : 0;
+    }
     uint32_t pieces = 0;
     double sp = 0.0;
     for (;;) {
@@ -422,27 +433,22 @@ MCDC_DEV uint32_t score_mesh(CP &P, const double p[3], const double u[3],
         bool done = false;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            if (s[a] != sn) continue;
-            if (u[a] > 0.0) {
-                idx[a] += 1;
-                if (idx[a] >= P.mesh_n[a]) { done = true; continue; }
-                const double e = P.mesh_lo[a] + (double)(idx[a] + 1) * P.mesh_delta[a];
-                s[a] = (e - p[a]) * iu[a];
-            } else {
-                idx[a] -= 1;
-                if (idx[a] < 0) { done = true; continue; }
-                const double e = P.mesh_lo[a] + (double)idx[a] * P.mesh_delta[a];
-                s[a] = (e - p[a]) * iu[a];
-            }
+            const bool adv = s[a] == sn;
+            const int ni = idx[a] + step[a];
+            const double e = P.mesh_lo[a] + (double)(ni + off[a]) * P.mesh_delta[a];
+            const double sa = (e - p[a]) * iu[a];
+            done = done || (adv && (uint32_t)ni >= (uint32_t)P.mesh_n[a]);
+            idx[a] = adv ? ni : idx[a];
+            s[a] = adv ? sa : s[a];
         }
-        if (s[3] == sn) {
-            idx[3] += 1;
-            if (idx[3] >= P.mesh_n[3]) {
-                done = true;
-            } else {
-                const double e = P.mesh_lo[3] + (double)(idx[3] + 1) * P.mesh_delta[3];
-                s[3] = (e - t0) * v;
-            }
+        {
+            const bool adv = s[3] == sn;
+            const int ni = idx[3] + 1;
+            const double e = P.mesh_lo[3] + (double)(ni + 1) * P.mesh_delta[3];
+            const double sa = (e - t0) * v;
+            done = done || (adv && ni >= P.mesh_n[3]);
+            idx[3] = adv ? ni : idx[3];
+            s[3] = adv ? sa : s[3];
         }
         if (done) break;
         sp = sn;
