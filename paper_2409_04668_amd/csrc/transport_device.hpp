@@ -188,10 +188,7 @@ struct Part {
 // inside iff lo < p < hi, or p == lo with u >= 0, or p == hi with u < 0.
 // ---------------------------------------------------------------------------
 MCDC_DEV bool axis_in(double lo, double hi, double p, double u) {
-    if (lo < p && p < hi) return true;
-    if (p == lo) return u >= 0.0;
-    if (p == hi) return u < 0.0;
-    return false;
+    return (lo < p && p < hi) || (p == lo && u >= 0.0) || (p == hi && p != lo && u < 0.0);
 }
 
 typedef const __attribute__((address_space(4))) double cdouble_t;   // a field of CP
@@ -201,10 +198,15 @@ MCDC_DEV bool box_in(cdouble_t *lo, cdouble_t *hi, const double p[3], const doub
            axis_in(lo[2], hi[2], p[2], u[2]);
 }
 
+// The first box containing the point (every box is tested, so the lanes of a
+// wave leave the loop together), or -1 for the background.
 MCDC_DEV int locate(CP &P, const double p[3], const double u[3]) {
-    for (int b = 0; b < P.n_boxes; ++b)
-        if (box_in(P.box_lo[b], P.box_hi[b], p, u)) return b;
-    return -1;
+    int cell = -1;
+    for (int b = 0; b < P.n_boxes; ++b) {
+        const bool in = box_in(P.box_lo[b], P.box_hi[b], p, u);
+        cell = (cell < 0 && in) ? b : cell;
+    }
+    return cell;
 }
 
 // Next surface along u: outer-box exit, then per box its exit (inside) or
@@ -223,39 +225,43 @@ MCDC_DEV double dist_surface(CP &P, const double p[3], const double u[3],
         if (!(s > 0.0)) s = 0.0;
         if (s < best) { best = s; bax = a; bpl = pl; }
     }
+    // Per box, the slab distances to its two faces on each axis serve both
+    // cases: inside, the far face is the exit; outside, the near faces give
+    // the entry.  Both candidates are formed and kept by select, so lanes
+    // inside and outside a box run the same instructions.
     for (int b = 0; b < P.n_boxes; ++b) {
         cdouble_t *lo = P.box_lo[b];
         cdouble_t *hi = P.box_hi[b];
-        if (box_in(lo, hi, p, u)) {
+        const bool inside = box_in(lo, hi, p, u);
+        double tn = -kInf, tf = kInf, tpl = 0.0;
+        int ta = -1;
+        bool miss = false;
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                if (u[a] == 0.0) continue;
-                const double pl = u[a] > 0.0 ? hi[a] : lo[a];
-                double s = (pl - p[a]) * iu[a];
-                if (!(s > 0.0)) s = 0.0;
-                if (s < best) { best = s; bax = a; bpl = pl; }
-            }
-        } else {
-            double tn = -kInf, tf = kInf, tpl = 0.0;
-            int ta = -1;
-            bool miss = false;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                if (u[a] == 0.0) {
-                    if (!axis_in(lo[a], hi[a], p[a], 0.0)) miss = true;
-                    continue;
-                }
-                const double s1 = (lo[a] - p[a]) * iu[a];
-                const double s2 = (hi[a] - p[a]) * iu[a];
-                const double nr = u[a] > 0.0 ? s1 : s2;
-                const double fr = u[a] > 0.0 ? s2 : s1;
-                if (nr > tn) { tn = nr; ta = a; tpl = u[a] > 0.0 ? lo[a] : hi[a]; }
-                if (fr < tf) tf = fr;
-            }
-            if (!miss && ta >= 0 && tn < tf && tn >= 0.0 && tn < best) {
-                best = tn; bax = ta; bpl = tpl;
-            }
+        for (int a = 0; a < 3; ++a) {
+            const bool up = u[a] > 0.0;
+            const double s1 = (lo[a] - p[a]) * iu[a];
+            const double s2 = (hi[a] - p[a]) * iu[a];
+            const double nr = up ? s1 : s2;
+            const double fr = up ? s2 : s1;
+            const bool moving = u[a] != 0.0;
+            // inside: exit through the far face (negative distances clamp to 0)
+            const double se = fr > 0.0 ? fr : 0.0;
+            const bool take = inside && moving && se < best;
+            best = take ? se : best;
+            bax = take ? a : bax;
+            bpl = take ? (up ? hi[a] : lo[a]) : bpl;
+            // outside: slab test
+            miss = miss || (!moving && !axis_in(lo[a], hi[a], p[a], 0.0));
+            const bool nearer = moving && nr > tn;
+            tn = nearer ? nr : tn;
+            ta = nearer ? a : ta;
+            tpl = nearer ? (up ? lo[a] : hi[a]) : tpl;
+            tf = (moving && fr < tf) ? fr : tf;
         }
+        const bool enter = !inside && !miss && ta >= 0 && tn < tf && tn >= 0.0 && tn < best;
+        best = enter ? tn : best;
+        bax = enter ? ta : bax;
+        bpl = enter ? tpl : bpl;
     }
     axis = bax;
     plane = bpl;
