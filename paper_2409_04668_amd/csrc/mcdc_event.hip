@@ -309,16 +309,14 @@ struct LeadTally<2> {
     HotTileTally t;
     MCDC_DEV void init(CP &P, double *lds) {
         t.lds = (lds_f64 *)lds;
-        for (int a = 0; a < 5; ++a) {
-            t.lo[a] = P.hot_lo[a];
-            t.n[a] = P.hot_n[a];
-        }
+        t.prob = &P;
+        t.n0 = P.hot_n[0];
     }
     // the tile holds batch b_tile only: an empty x extent sends every update
     // of another batch to HBM
     MCDC_DEV void select(CP &P, const RunArgs &A, uint64_t b, uint64_t b_tile) {
         t.glob = (hbm_f64 *)(A.tally + b * (uint64_t)P.nbins);
-        t.n[0] = b == b_tile ? P.hot_n[0] : 0u;
+        t.n0 = b == b_tile ? P.hot_n[0] : 0u;
     }
 };
 

@@ -128,10 +128,8 @@ MCDC_DEV HotTileTally make_tally(HotTileTally *, CP &P, const RunArgs &A, double
     HotTileTally t;
     t.lds = (lds_f64 *)lds;
     t.glob = (hbm_f64 *)A.tally;
-    for (int a = 0; a < 5; ++a) {
-        t.lo[a] = P.hot_lo[a];
-        t.n[a] = P.hot_n[a];
-    }
+    t.prob = &P;
+    t.n0 = P.hot_n[0];
     return t;
 }
 

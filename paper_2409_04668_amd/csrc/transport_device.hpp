@@ -319,16 +319,24 @@ struct LdsTally {
     }
 };
 // A sub-box of the (g, t, z, y, x) mesh privatised in LDS (the bins that take
-// most of the updates); every other bin goes to HBM atomics.
+// most of the updates); every other bin goes to HBM atomics.  The box's
+// corner and extents are read from the problem description at each update
+// (scalar loads) rather than held in SGPRs for the whole kernel; `n0` is the
+// x extent, zero while the workgroup scores a batch the tile does not hold.
 struct HotTileTally {
     lds_f64 *lds;
     hbm_f64 *glob;
-    uint32_t lo[5], n[5];                    // x, y, z, t, g
+    CP *prob;
+    uint32_t n0;
     MCDC_DEV void add(uint32_t i, uint32_t g, uint32_t t, uint32_t z, uint32_t y, uint32_t x,
                       double v) const {
-        const uint32_t dx = x - lo[0], dy = y - lo[1], dz = z - lo[2], dt = t - lo[3], dg = g - lo[4];
-        if (dx < n[0] && dy < n[1] && dz < n[2] && dt < n[3] && dg < n[4]) {
-            const uint32_t j = (((dg * n[3] + dt) * n[2] + dz) * n[1] + dy) * n[0] + dx;
+        CP &Q = problem_reload(*prob);
+        const uint32_t dx = x - Q.hot_lo[0], dy = y - Q.hot_lo[1], dz = z - Q.hot_lo[2],
+                       dt = t - Q.hot_lo[3], dg = g - Q.hot_lo[4];
+        const uint32_t n1 = Q.hot_n[1], n2 = Q.hot_n[2], n3 = Q.hot_n[3];
+        const bool hot = (dx < n0) & (dy < n1) & (dz < n2) & (dt < n3) & (dg < Q.hot_n[4]);
+        if (hot) {
+            const uint32_t j = (((dg * n3 + dt) * n2 + dz) * n1 + dy) * n0 + dx;
             lds_add(lds + j, v);
         } else {
             hbm_add(glob + i, v);
