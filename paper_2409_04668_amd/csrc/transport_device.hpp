@@ -331,11 +331,15 @@ struct HotTileTally {
     MCDC_DEV void add(uint32_t i, uint32_t g, uint32_t t, uint32_t z, uint32_t y, uint32_t x,
                       double v) const {
         CP &Q = problem_reload(*prob);
-        const uint32_t dx = x - Q.hot_lo[0], dy = y - Q.hot_lo[1], dz = z - Q.hot_lo[2],
-                       dt = t - Q.hot_lo[3], dg = g - Q.hot_lo[4];
-        const uint32_t n1 = Q.hot_n[1], n2 = Q.hot_n[2], n3 = Q.hot_n[3];
-        const bool hot = (dx < n0) & (dy < n1) & (dz < n2) & (dt < n3) & (dg < Q.hot_n[4]);
-        if (hot) {
+        uint32_t l0 = Q.hot_lo[0], l1 = Q.hot_lo[1], l2 = Q.hot_lo[2], l3 = Q.hot_lo[3],
+                 l4 = Q.hot_lo[4], n1 = Q.hot_n[1], n2 = Q.hot_n[2], n3 = Q.hot_n[3],
+                 n4 = Q.hot_n[4];
+        // all nine fields loaded before the test (no load sinks into one of
+        // its branches), so the test is one compare per axis and mask ANDs
+        asm volatile("" : "+s"(l0), "+s"(l1), "+s"(l2), "+s"(l3), "+s"(l4), "+s"(n1), "+s"(n2),
+                          "+s"(n3), "+s"(n4));
+        const uint32_t dx = x - l0, dy = y - l1, dz = z - l2, dt = t - l3, dg = g - l4;
+        if (dx < n0 && dy < n1 && dz < n2 && dt < n3 && dg < n4) {
             const uint32_t j = (((dg * n3 + dt) * n2 + dz) * n1 + dy) * n0 + dx;
             lds_add(lds + j, v);
         } else {
