@@ -431,10 +431,11 @@ MCDC_DEV uint32_t score_mesh(CP &P, const double p[3], const double u[3],
     uint32_t pieces = 0;
     double sp = 0.0;
     for (;;) {
-        double sn = d;
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-            if (s[a] < sn) sn = s[a];
+        // the nearest of d and the four next-edge distances (no NaN occurs;
+        // +0 and -0, the only values min may order either way, compare equal
+        // in every later test and give the same differences)
+        const double sn = __builtin_fmin(__builtin_fmin(d, s[0]),
+                                         __builtin_fmin(__builtin_fmin(s[1], s[2]), s[3]));
         if (sn > sp) {
             const bool in = (uint32_t)idx[0] < n0 && (uint32_t)idx[1] < n1 &&
                             (uint32_t)idx[2] < n2 && (uint32_t)idx[3] < n3;
