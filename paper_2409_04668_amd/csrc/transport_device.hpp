@@ -379,9 +379,19 @@ MCDC_DEV uint32_t score_mesh(CP &P, const double p[3], const double u[3],
     if (!(d > 0.0)) return 0;
     int idx[4];
     double s[4];
+    // The walk ends at d or where it leaves the mesh, whichever comes first:
+    // the last edge of a bounded axis in the direction of travel (edge n
+    // moving up, edge 0 moving down) and the last time edge, each at the
+    // distance the walk itself would compute for that edge.
+    double dd = d;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         if (!P.mesh_bounded[a]) { idx[a] = 0; s[a] = kInf; continue; }
+        if (u[a] != 0.0) {
+            const int k = u[a] > 0.0 ? P.mesh_n[a] : 0;
+            const double se = (P.mesh_lo[a] + (double)k * P.mesh_delta[a] - p[a]) * iu[a];
+            if (se < dd) dd = se;
+        }
         const double q = (p[a] - P.mesh_lo[a]) * P.mesh_idelta[a];
         double fq = floor(q);
         if (fq < -1.0) fq = -1.0;
@@ -413,6 +423,8 @@ MCDC_DEV uint32_t score_mesh(CP &P, const double p[3], const double u[3],
         idx[3] = i;
         const double e = P.mesh_lo[3] + (double)(i + 1) * P.mesh_delta[3];
         s[3] = (e - t0) * v;
+        const double se = (P.mesh_lo[3] + (double)P.mesh_n[3] * P.mesh_delta[3] - t0) * v;
+        if (se < dd) dd = se;
     }
     const uint32_t n0 = P.mesh_n[0], n1 = P.mesh_n[1], n2 = P.mesh_n[2], n3 = P.mesh_n[3];
     const uint32_t gt = (uint32_t)(P.G_t > 1 ? g : 0);
@@ -431,10 +443,10 @@ MCDC_DEV uint32_t score_mesh(CP &P, const double p[3], const double u[3],
     uint32_t pieces = 0;
     double sp = 0.0;
     for (;;) {
-        // the nearest of d and the four next-edge distances (no NaN occurs;
-        // +0 and -0, the only values min may order either way, compare equal
-        // in every later test and give the same differences)
-        const double sn = __builtin_fmin(__builtin_fmin(d, s[0]),
+        // the nearest of the walk's end and the four next-edge distances (no
+        // NaN occurs; +0 and -0, the only values min may order either way,
+        // compare equal in every later test and give the same differences)
+        const double sn = __builtin_fmin(__builtin_fmin(dd, s[0]),
                                          __builtin_fmin(__builtin_fmin(s[1], s[2]), s[3]));
         if (sn > sp) {
             const bool in = (uint32_t)idx[0] < n0 && (uint32_t)idx[1] < n1 &&
@@ -448,15 +460,13 @@ MCDC_DEV uint32_t score_mesh(CP &P, const double p[3], const double u[3],
                 pieces += 1;
             }
         }
-        if (sn >= d) break;
-        bool done = false;
+        if (sn >= dd) break;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             const bool adv = s[a] == sn;
             const int ni = idx[a] + step[a];
             const double e = P.mesh_lo[a] + (double)(ni + off[a]) * P.mesh_delta[a];
             const double sa = (e - p[a]) * iu[a];
-            done = done || (adv && (uint32_t)ni >= (uint32_t)P.mesh_n[a]);
             idx[a] = adv ? ni : idx[a];
             s[a] = adv ? sa : s[a];
         }
@@ -465,11 +475,9 @@ MCDC_DEV uint32_t score_mesh(CP &P, const double p[3], const double u[3],
             const int ni = idx[3] + 1;
             const double e = P.mesh_lo[3] + (double)(ni + 1) * P.mesh_delta[3];
             const double sa = (e - t0) * v;
-            done = done || (adv && ni >= P.mesh_n[3]);
             idx[3] = adv ? ni : idx[3];
             s[3] = adv ? sa : s[3];
         }
-        if (done) break;
         sp = sn;
     }
     return pieces;
