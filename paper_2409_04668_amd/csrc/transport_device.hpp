@@ -368,6 +368,14 @@ MCDC_DEV void hot_tile_flush(CP &P, const double *tile, double *out) {
     }
 }
 
+// Minimum of two doubles that are never NaN: one v_min_f64, without the
+// quieting of signalling NaNs the compiler adds in front of fmin.
+MCDC_DEV double min_f64(double a, double b) {
+    double r;
+    asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
 // Track-length scoring of the segment p + s u, s in [0,d], from time t0 at
 // speed v: the segment is cut at every mesh plane and time edge it crosses
 // (edges lo + k*delta; crossing distances recomputed from the segment start;
@@ -447,8 +455,7 @@ MCDC_DEV uint32_t score_mesh(CP &P, const double p[3], const double u[3],
         // the nearest of the walk's end and the four next-edge distances (no
         // NaN occurs; +0 and -0, the only values min may order either way,
         // compare equal in every later test and give the same differences)
-        const double sn = __builtin_fmin(__builtin_fmin(dd, s[0]),
-                                         __builtin_fmin(__builtin_fmin(s[1], s[2]), s[3]));
+        const double sn = min_f64(min_f64(dd, s[0]), min_f64(min_f64(s[1], s[2]), s[3]));
         if (sn > sp) {
             const bool in = (uint32_t)idx[0] < n0 && (uint32_t)idx[1] < n1 &&
                             (uint32_t)idx[2] < n2 && (uint32_t)idx[3] < n3;
