@@ -381,7 +381,7 @@ MCDC_DEV double min_f64(double a, double b) {
 // (edges lo + k*delta; crossing distances recomputed from the segment start;
 // all axes at the minimum advance together); each in-mesh piece of positive
 // length adds w * length to tally[g][it][iz][iy][ix].  Returns the pieces.
-template <class T>
+template <bool kEntry, class T>
 MCDC_DEV uint32_t score_mesh(CP &P, const double p[3], const double u[3],
                              const double iu[3], double t0, double v, double d, double w, int g,
                              const T &tally) {
@@ -436,6 +436,20 @@ MCDC_DEV uint32_t score_mesh(CP &P, const double p[3], const double u[3],
         if (se < dd) dd = se;
     }
     const uint32_t n0 = P.mesh_n[0], n1 = P.mesh_n[1], n2 = P.mesh_n[2], n3 = P.mesh_n[3];
+    // A segment that starts outside the mesh on some axes enters it where it
+    // crosses the entry edge of the last of them (that axis's first crossing,
+    // already in s); every piece that starts at or beyond that distance lies
+    // inside the mesh (the walk ends where it leaves), and none before it.
+    // With kEntry the in-mesh test is that one comparison; without it (for
+    // kernels already at their register limit) the four index tests.
+    double s_in = -kInf;
+    if constexpr (kEntry) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            if (P.mesh_bounded[a] && (idx[a] < 0 || idx[a] >= P.mesh_n[a]) && s[a] > s_in)
+                s_in = s[a];
+        if (idx[3] < 0 && s[3] > s_in) s_in = s[3];
+    }
     const uint32_t gt = (uint32_t)(P.G_t > 1 ? g : 0);
     const uint32_t gbase = gt * n3;
     // Per-axis step and edge offset: moving up, the next edge above cell i is
@@ -457,8 +471,12 @@ MCDC_DEV uint32_t score_mesh(CP &P, const double p[3], const double u[3],
         // compare equal in every later test and give the same differences)
         const double sn = min_f64(min_f64(dd, s[0]), min_f64(min_f64(s[1], s[2]), s[3]));
         if (sn > sp) {
-            const bool in = (uint32_t)idx[0] < n0 && (uint32_t)idx[1] < n1 &&
-                            (uint32_t)idx[2] < n2 && (uint32_t)idx[3] < n3;
+            bool in;
+            if constexpr (kEntry)
+                in = sp >= s_in;
+            else
+                in = (uint32_t)idx[0] < n0 && (uint32_t)idx[1] < n1 && (uint32_t)idx[2] < n2 &&
+                     (uint32_t)idx[3] < n3;
             if (in) {
                 const uint32_t b =
                     (((gbase + (uint32_t)idx[3]) * n2 + (uint32_t)idx[2]) * n1 + (uint32_t)idx[1]) *

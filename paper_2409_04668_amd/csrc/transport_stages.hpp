@@ -236,7 +236,7 @@ MCDC_DEV int stage_flight(CP &P, const RunArgs &A, Shared &S, const T &tally, Ct
     else if (wax >= 0 && d_w <= d_c) { ev = EV_WW_PLANE; d = d_w; }
     else { ev = EV_SCATTER; d = d_c; }
 
-    n_piece += score_mesh(P, q.x, q.u, iu, q.t, v, d, q.w, q.g, tally);
+    n_piece += score_mesh<!Ctx::kWW>(P, q.x, q.u, iu, q.t, v, d, q.w, q.g, tally);
     if (P.has_detector) {
         const double l = detector_len(P, q.x, q.u, iu, d);
         if (l > 0.0) C.add_score(q.w * l);
