@@ -76,6 +76,9 @@ struct BatchState {
 struct BatchCtx {
     static constexpr bool kWW = false;
     static constexpr bool kWWMap = false;
+    // the persistent batch kernel sits at its register limit: the mesh walk
+    // keeps the four index tests instead of carrying an entry distance
+    static constexpr bool kTightRegs = true;
     MCDC_DEV double *col_tally() const { return nullptr; }
     MCDC_DEV double *surf_tally() const { return nullptr; }
     CP &P;

@@ -188,6 +188,13 @@ MCDC_DEV void stage_source(CP &P, const RunArgs &A, Shared &S, Ctx &C, Part &q) 
     trace_rec(A, C.hist(), q, EV_SOURCE, 0.0);
 }
 
+// Contexts whose kernels sit at their register limit declare kTightRegs.
+template <class C, class = void>
+struct tight_regs : std::false_type {};
+template <class C>
+struct tight_regs<C, std::void_t<decltype(C::kTightRegs)>>
+    : std::integral_constant<bool, C::kTightRegs> {};
+
 // Flight: census, surface, weight-window grid plane (windows with a grid) and
 // collision distances; the event (ties: census, then surface, then grid
 // plane, then collision); track-length scoring; the move of Fig. 2; census and
@@ -236,7 +243,8 @@ MCDC_DEV int stage_flight(CP &P, const RunArgs &A, Shared &S, const T &tally, Ct
     else if (wax >= 0 && d_w <= d_c) { ev = EV_WW_PLANE; d = d_w; }
     else { ev = EV_SCATTER; d = d_c; }
 
-    n_piece += score_mesh<!Ctx::kWW>(P, q.x, q.u, iu, q.t, v, d, q.w, q.g, tally);
+    n_piece += score_mesh<!Ctx::kWW && !tight_regs<Ctx>::value>(P, q.x, q.u, iu, q.t, v, d, q.w,
+                                                                 q.g, tally);
     if (P.has_detector) {
         const double l = detector_len(P, q.x, q.u, iu, d);
         if (l > 0.0) C.add_score(q.w * l);
