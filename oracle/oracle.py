@@ -342,12 +342,53 @@ class OracleRun:
         return mean, np.sqrt(np.maximum(var, 0.0))
 
     def detector_stats(self):
-        """Mean detector score per history and its standard error."""
+        """Mean detector score per history and its standard error (the sample
+        variance of the per-history scores over N - 1, divided by N)."""
         N = float(self.n_hist)
         s1, s2 = self.detector
         m = s1 / N
-        var = (s2 / N - m * m) / (N - 1.0) if N > 1 else float("nan")
+        if N < 2:
+            return m, float("nan")
+        var = (s2 / N - m * m) / (N - 1.0)
         return m, float(np.sqrt(max(var, 0.0)))
+
+    def report(self, kind: str):
+        """The run's output: tallies with their statistical error (the paper's
+        problem statement and the finalization step of Sec. "MC/DC on CPUs").
+
+        kind "mesh" / "collision": per bin, the mean score per source history
+        divided by the bin's volume and time width (the space- and
+        time-averaged flux); "surface": the mean crossing weight per source
+        history divided by the bin's area on the plane and its time width;
+        "detector": the mean track length per history in the detector box;
+        "leakage": the weight leaked per face per history.  Returns (mean,
+        rel) with rel = standard error / mean: 0 where the mean is 0, NaN with
+        fewer than two batches (mesh kinds) or histories (detector), and NaN
+        for leakage, which keeps no second moment."""
+        N = float(self.n_hist)
+        if kind == "detector":
+            m, se = self.detector_stats()
+            if np.isnan(se):
+                return np.array([m]), np.array([np.nan])
+            return np.array([m]), np.array([se / m if m > 0.0 else 0.0])
+        if kind == "leakage":
+            return self.leak / N, np.full(6, np.nan)
+        est = {"mesh": "track", "collision": "collision", "surface": "surface"}[kind]
+        mean, se = self.mesh_stats(est)
+        msh = self.prob["mesh"]
+        lo = np.asarray(msh["lo"], float)
+        hi = np.asarray(msh["hi"], float)
+        nn = np.asarray(msh["n"])
+        skip = int(self.prob["surface_tally"]["axis"]) if kind == "surface" else -1
+        size = 1.0
+        for a in range(4):
+            if a == skip or (a < 3 and np.isinf(lo[a]) and np.isinf(hi[a])):
+                continue                      # an unbounded axis is not cut
+            size *= (hi[a] - lo[a]) / float(nn[a])
+        rel = np.where(mean > 0.0, se / np.where(mean > 0.0, mean, 1.0), 0.0)
+        if int(self.R.batches_done) < 2:
+            rel = np.full_like(mean, np.nan)
+        return mean / size, rel
 
 
 def run(prob: dict, n_hist: int, seed: int, **kw) -> OracleRun:
