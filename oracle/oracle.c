@@ -19,7 +19,11 @@
  *  - tally accumulation by a plain add on the CPU, an atomic add on the GPU:
  *    Fig. 3;
  *  - hash-based (counter-based) random numbers for replicable testing: Sec.
- *    "Monte Carlo Neutron Transport and MC/DC", list of novel developments.
+ *    "Monte Carlo Neutron Transport and MC/DC", list of novel developments;
+ *  - the k-eigenvalue mode beside the time-dependent one, fission as a
+ *    physical event that ends a history, and the generation of daughter
+ *    particles from fission in the kernel set: Sec. "Monte Carlo Neutron
+ *    Transport and MC/DC" (feature list) and Sec. "MC/DC on CPUs".
  * Everything else (RNG algorithm, sampling formulas, estimator, tie rules,
  * weight windows, population control) is a reading of this implementation,
  * stated in the comments below.
@@ -565,7 +569,26 @@ typedef struct {
     int wwg_on;               /* weight-window grid planes */
     double wwg_d[3], wwg_id[3];
     int census_hit;           /* the last flight stopped at an intermediate census */
+    /* k-eigenvalue mode (NULL fis: fixed-source run, no fission) */
+    struct o_sites *fis;      /* sites produced in this generation, in history order */
+    double k_norm;            /* site production is divided by this */
+    double kcol;              /* sum of w nuSigma_f / Sigma_t over collisions */
 } o_ctx;
+
+/* Fission sites of one generation: position and outgoing group. */
+typedef struct { double p[3]; int g; } o_site;
+typedef struct o_sites { o_site *s; size_t n, cap; } o_sites;
+
+static void o_site_push(o_sites *b, const double p[3], int g)
+{
+    if (b->n == b->cap) {
+        b->cap = b->cap ? 2 * b->cap : 1024;
+        b->s = (o_site *)realloc(b->s, b->cap * sizeof(o_site));
+    }
+    for (int a = 0; a < 3; ++a) b->s[b->n].p[a] = p[a];
+    b->s[b->n].g = g;
+    b->n += 1;
+}
 
 static void o_trace(o_ctx *C, o_part *q, int type, double aux)
 {
@@ -960,6 +983,44 @@ static void o_flight(o_ctx *C, o_part *q)
     double sig_s = 0.0;
     for (int h = 0; h < P->G; ++h) sig_s = sig_s + ss_row[h];
     st = o_part_stream(C, q);
+    /* k-eigenvalue mode: fission sites for the next generation.  The
+     * expected number of fission neutrons from this collision, w nuSigma_f /
+     * Sigma_t, is the collision estimate of the multiplication; divided by
+     * the generation's normalisation k_norm it is the expected number of
+     * sites, n = floor(w nuSigma_f / Sigma_t / k_norm + xi) of them (one
+     * draw), each at the collision point with an outgoing group drawn from
+     * the material's fission spectrum (first g' with xi sum(chi) below the
+     * ascending cumulative chi; one draw per site when G > 1).  Fission is
+     * part of the absorption, so the collision then goes on as before. */
+    if (C->fis) {
+        const double nusf = P->nu_sigma_f[mat * P->G + q->g];
+        if (nusf > 0.0) {
+            const double prod = q->w * nusf / sig_t;
+            C->kcol += prod;
+            const double xi = o_draw(&st);
+            const int64_t n = (int64_t)floor(prod / C->k_norm + xi);
+            const double *chi = P->chi + (size_t)mat * P->G;
+            double chi_sum = 0.0;
+            for (int h = 0; h < P->G; ++h) chi_sum = chi_sum + chi[h];
+            for (int64_t i = 0; i < n; ++i) {
+                int gs = 0;
+                if (P->G > 1) {
+                    const double target = o_draw(&st) * chi_sum;
+                    double cum = 0.0;
+                    int gn = -1, last = 0;
+                    for (int h = 0; h < P->G; ++h) {
+                        cum = cum + chi[h];
+                        if (chi[h] > 0.0) last = h;
+                        if (gn < 0 && target < cum) gn = h;
+                    }
+                    gs = gn >= 0 ? gn : last;
+                }
+                o_site_push(C->fis, q->p, gs);
+            }
+            q->k = st.k;
+            if (n > 0) o_trace(C, q, ORC_EV_FISSION, (double)n);
+        }
+    }
     if (!P->implicit_capture) {
         double xi = o_draw(&st);
         q->k = st.k;
@@ -1306,10 +1367,56 @@ static int o_validate(const orc_problem *P)
     return ORC_OK;
 }
 
+/* 1 when any material has nuSigma_f > 0 */
+static int o_fissile(const orc_problem *P)
+{
+    if (!P->nu_sigma_f) return 0;
+    for (int i = 0; i < P->n_mat * P->G; ++i)
+        if (P->nu_sigma_f[i] > 0.0) return 1;
+    return 0;
+}
+
+/* Batch close-out: per bin, sum += S_b, sumsq += S_b^2 / N_b, S_b = 0, for
+ * every mesh-type tally of the problem. */
+static void o_closeout(o_ctx *C, size_t nbins, double nb)
+{
+    const orc_problem *P = C->P;
+    orc_result *R = C->R;
+    for (size_t i = 0; i < nbins; ++i) {
+        double sb = R->tally_batch[i];
+        if (sb != 0.0) {
+            R->tally_sum[i] += sb;
+            R->tally_sumsq[i] += sb * sb / nb;
+            R->tally_batch[i] = 0.0;
+        }
+        if (P->col_tally) {
+            double cb = R->col_batch[i];
+            if (cb != 0.0) {
+                R->col_sum[i] += cb;
+                R->col_sumsq[i] += cb * cb / nb;
+                R->col_batch[i] = 0.0;
+            }
+        }
+    }
+    if (P->surf_on) {
+        int a = P->surf_axis, b1 = a == 0 ? 1 : 0, b2 = a == 2 ? 1 : 2;
+        size_t ns = (size_t)2 * C->M.G_t * P->mesh_n[3] * P->mesh_n[b1] * P->mesh_n[b2];
+        for (size_t i = 0; i < ns; ++i) {
+            double sb = R->surf_batch[i];
+            if (sb != 0.0) {
+                R->surf_sum[i] += sb;
+                R->surf_sumsq[i] += sb * sb / nb;
+                R->surf_batch[i] = 0.0;
+            }
+        }
+    }
+}
+
 int orc_run(const orc_problem *P, uint64_t seed, uint64_t hist0, uint64_t n_hist, orc_result *R)
 {
     int st = o_validate(P);
     if (st != ORC_OK) return st;
+    if (o_fissile(P)) return ORC_E_INVALID;     /* fission runs in k-eigenvalue mode */
     if (P->col_tally && (!R->col_batch || !R->col_sum || !R->col_sumsq)) return ORC_E_INVALID;
     if (P->surf_on && (!R->surf_batch || !R->surf_sum || !R->surf_sumsq)) return ORC_E_INVALID;
     o_ctx C;
@@ -1346,39 +1453,176 @@ int orc_run(const orc_problem *P, uint64_t seed, uint64_t hist0, uint64_t n_hist
                 if (st != ORC_OK) { free(C.stack); free(C.ww_map); return st; }
             }
         }
-        double nb = (double)(hi - lo);
-        for (size_t i = 0; i < nbins; ++i) {
-            double sb = R->tally_batch[i];
-            if (sb != 0.0) {
-                R->tally_sum[i] += sb;
-                R->tally_sumsq[i] += sb * sb / nb;
-                R->tally_batch[i] = 0.0;
-            }
-            if (P->col_tally) {
-                double cb = R->col_batch[i];
-                if (cb != 0.0) {
-                    R->col_sum[i] += cb;
-                    R->col_sumsq[i] += cb * cb / nb;
-                    R->col_batch[i] = 0.0;
-                }
-            }
-        }
-        if (P->surf_on) {
-            int a = P->surf_axis, b1 = a == 0 ? 1 : 0, b2 = a == 2 ? 1 : 2;
-            size_t ns = (size_t)2 * C.M.G_t * P->mesh_n[3] * P->mesh_n[b1] * P->mesh_n[b2];
-            for (size_t i = 0; i < ns; ++i) {
-                double sb = R->surf_batch[i];
-                if (sb != 0.0) {
-                    R->surf_sum[i] += sb;
-                    R->surf_sumsq[i] += sb * sb / nb;
-                    R->surf_batch[i] = 0.0;
-                }
-            }
-        }
+        o_closeout(&C, nbins, (double)(hi - lo));
         R->batches_done += 1;
     }
     R->hist_done += n_hist;
     free(C.stack);
     free(C.ww_map);
     return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* k-eigenvalue mode: power iteration on the fission source.                 */
+/* ------------------------------------------------------------------------ */
+
+/* Source particle of a generation after the first: born at a fission site
+ * of the previous generation (its position and group), at t = 0 (the mode is
+ * steady state), with unit weight and an isotropic direction drawn from the
+ * history's own stream; then the same checks as a fixed source. */
+static void o_source_site(o_ctx *C, o_part *q, const o_site *site)
+{
+    const orc_problem *P = C->P;
+    memset(q, 0, sizeof(*q));
+    o_stream st = o_part_stream(C, q);
+    for (int a = 0; a < 3; ++a) q->p[a] = site->p[a];
+    q->t = 0.0;
+    o_direction(&st, q->u);
+    q->g = site->g;
+    q->w = 1.0;
+    q->k = st.k;
+    q->alive = 1;
+    q->ci = 0;
+    while (q->ci < P->n_census && !(P->census[q->ci] > q->t)) q->ci += 1;
+    C->R->cnt[ORC_C_PARTICLE] += 1;
+    C->R->wsum[ORC_W_SOURCE] += q->w;
+    q->cell = o_locate(P, q->p, q->u);
+    if (q->ci >= P->n_census) {
+        C->R->wsum[ORC_W_TIME_END] += q->w;
+        C->R->cnt[ORC_C_TIME_END] += 1;
+        q->alive = 0;
+        o_trace(C, q, ORC_EV_TIME_END, 0.0);
+        return;
+    }
+    for (int a = 0; a < 3; ++a) {
+        if (!o_axis_in(P->outer_lo[a], P->outer_hi[a], q->p[a], q->u[a])) {
+            o_leak(C, q, 2 * a + (q->p[a] >= P->outer_hi[a] ? 1 : 0));
+            o_trace(C, q, ORC_EV_LEAK, 0.0);
+            return;
+        }
+    }
+    o_trace(C, q, ORC_EV_SOURCE, 0.0);
+}
+
+/* One history of a generation; its detector score counts only when the
+ * generation scores (an active one). */
+static int o_keff_history(o_ctx *C, uint64_t h, uint64_t slot, const o_site *site, int score)
+{
+    orc_result *R = C->R;
+    C->hist = h;
+    C->xh = 0.0;
+    C->path_h = 0.0;
+    C->events = 0;
+    C->sp = 0;
+    R->cnt[ORC_C_HIST] += 1;
+    o_part q;
+    if (site) o_source_site(C, &q, site);
+    else o_source(C, &q);
+    while (q.alive && C->status == ORC_OK) o_flight(C, &q);
+    if (C->status != ORC_OK) return C->status;
+    if (score) {
+        R->det[0] += C->xh;
+        R->det[1] += C->xh * C->xh;
+        if (C->xh > 0.0) R->cnt[ORC_C_DET_HIT] += 1;
+    }
+    if (R->hist_xh) {
+        R->hist_xh[2 * slot] = C->xh;
+        R->hist_xh[2 * slot + 1] = C->path_h;
+    }
+    return ORC_OK;
+}
+
+/* Stream tag of the draw that places a generation's comb ("keff" in ASCII). */
+#define O_COMB_TAG 0x6B656666u
+
+/* Generation g (ids g M .. g M + M - 1): the first takes the problem's
+ * source, later ones the combed sites of the one before.  After the
+ * generation: k_col = (sum of w nuSigma_f / Sigma_t) / M; S sites; the
+ * site-count estimate k_site = k_norm S / M becomes the next k_norm, so the
+ * expected population stays near M; the next source is M sites taken from
+ * the S in production order by a comb with one random offset xi (drawn from
+ * the stream of the next generation's first history id with tag "keff"):
+ * site floor((j + xi) S / M) for j = 0..M-1 (at most S - 1), each of unit
+ * weight.  An active generation closes out as one tally batch of M
+ * histories; an inactive one discards what it scored. */
+int orc_run_keff(const orc_problem *P, uint64_t seed, orc_keff *K, orc_result *R)
+{
+    int st = o_validate(P);
+    if (st != ORC_OK) return st;
+    if (!o_fissile(P) || !P->chi || K->M < 1 || K->M > ((uint64_t)1 << 32) || K->n_inactive < 0 ||
+        K->n_active < 1 || !(K->k0 > 0.0) || P->ww_on || P->pc_on || P->imp_on)
+        return ORC_E_INVALID;
+    for (int m = 0; m < P->n_mat; ++m) {
+        double sum = 0.0, sf = 0.0;
+        for (int g = 0; g < P->G; ++g) {
+            if (P->chi[m * P->G + g] < 0.0 || P->nu_sigma_f[m * P->G + g] < 0.0) return ORC_E_INVALID;
+            sum += P->chi[m * P->G + g];
+            sf += P->nu_sigma_f[m * P->G + g];
+        }
+        if (sf > 0.0 && !(sum > 0.0)) return ORC_E_INVALID;
+    }
+    if (P->col_tally && (!R->col_batch || !R->col_sum || !R->col_sumsq)) return ORC_E_INVALID;
+    if (P->surf_on && (!R->surf_batch || !R->surf_sum || !R->surf_sumsq)) return ORC_E_INVALID;
+    o_ctx C;
+    memset(&C, 0, sizeof(C));
+    C.P = P;
+    C.M = o_mesh_make(P);
+    C.R = R;
+    C.seed = seed;
+    C.status = ORC_OK;
+    C.stack = (o_part *)malloc(sizeof(o_part));
+    o_sites sites = {0};
+    C.fis = &sites;
+    C.k_norm = K->k0;
+    const uint64_t M = K->M;
+    o_site *src = NULL;
+    size_t nbins = (size_t)C.M.G_t * P->mesh_n[0] * P->mesh_n[1] * P->mesh_n[2] * P->mesh_n[3];
+    const int n_gen = K->n_inactive + K->n_active;
+    for (int g = 0; g < n_gen && st == ORC_OK; ++g) {
+        const int score = g >= K->n_inactive;
+        sites.n = 0;
+        C.kcol = 0.0;
+        for (uint64_t j = 0; j < M; ++j) {
+            st = o_keff_history(&C, (uint64_t)g * M + j, (uint64_t)g * M + j, src ? &src[j] : NULL,
+                                score);
+            if (st != ORC_OK) break;
+        }
+        if (st != ORC_OK) break;
+        const uint64_t S = sites.n;
+        K->k_col[g] = C.kcol / (double)M;
+        K->k_site[g] = C.k_norm * (double)S / (double)M;
+        K->n_sites[g] = S;
+        if (score) {
+            o_closeout(&C, nbins, (double)M);
+            R->batches_done += 1;
+            R->hist_done += M;
+        } else {
+            memset(R->tally_batch, 0, nbins * sizeof(double));
+            if (P->col_tally) memset(R->col_batch, 0, nbins * sizeof(double));
+            if (P->surf_on) {
+                int a = P->surf_axis, b1 = a == 0 ? 1 : 0, b2 = a == 2 ? 1 : 2;
+                size_t ns = (size_t)2 * C.M.G_t * P->mesh_n[3] * P->mesh_n[b1] * P->mesh_n[b2];
+                memset(R->surf_batch, 0, ns * sizeof(double));
+            }
+        }
+        if (S == 0) { st = ORC_E_EXTINCT; break; }
+        o_stream cs = o_stream_make(seed, (uint64_t)(g + 1) * M, P->problem_id, O_COMB_TAG);
+        const double xi = o_draw(&cs);
+        if (!src) src = (o_site *)malloc(M * sizeof(o_site));
+        for (uint64_t j = 0; j < M; ++j) {
+            uint64_t idx = (uint64_t)floor(((double)j + xi) * (double)S / (double)M);
+            if (idx > S - 1) idx = S - 1;
+            src[j] = sites.s[idx];
+        }
+        C.k_norm = K->k_site[g];
+    }
+    if (st == ORC_OK && K->src_out)
+        for (uint64_t j = 0; j < M; ++j) {
+            for (int a = 0; a < 3; ++a) K->src_out[4 * j + a] = src[j].p[a];
+            K->src_out[4 * j + 3] = (double)src[j].g;
+        }
+    free(sites.s);
+    free(src);
+    free(C.stack);
+    return st;
 }

@@ -1,6 +1,7 @@
 /*
  * CPU oracle for the fixed-source, time-dependent Monte Carlo transport loop
- * (scatter + absorb, no fission).
+ * (scatter + absorb), and for the k-eigenvalue mode (fission source iterated
+ * over generations).
  *
  * TEST INFRASTRUCTURE ONLY.  Nothing in the product library includes, links
  * or calls this code; only the tests, the smoke check and the CPU-baseline leg
@@ -26,6 +27,7 @@ enum {
     ORC_E_INVALID = -1,
     ORC_E_EVENT_CAP = -4,
     ORC_E_STACK = -7,
+    ORC_E_EXTINCT = -9,           /* k-eigenvalue: a generation produced no site */
 };
 
 /* trace record types */
@@ -45,6 +47,7 @@ enum {
     ORC_EV_PC_KILL = 12,          /* population control at a census: removed        */
     ORC_EV_PC_KEEP = 13,          /* population control: kept as aux copies        */
     ORC_EV_WW_PLANE = 14,         /* a flight reached a weight-window grid plane   */
+    ORC_EV_FISSION = 15,          /* fission sites produced at a collision (aux = n) */
 };
 
 /* counters */
@@ -110,6 +113,8 @@ typedef struct {
     int64_t max_events;
     int32_t stack_cap;
     uint32_t problem_id;
+    const double *nu_sigma_f;         /* [n_mat][G] nu * Sigma_f, or NULL (no fission) */
+    const double *chi;                /* [n_mat][G] fission spectrum (outgoing group)   */
 } orc_problem;
 
 typedef struct {
@@ -141,6 +146,24 @@ typedef struct {
 
 int orc_run(const orc_problem *P, uint64_t seed, uint64_t hist0, uint64_t n_hist,
             orc_result *R);
+
+/* k-eigenvalue mode: power iteration on the fission source, n_inactive +
+ * n_active generations of M histories (history id g * M + j for slot j of
+ * generation g).  Per generation g: k_col[g] = sum over collisions of
+ * w nuSigma_f / Sigma_t, divided by M; n_sites[g] = fission sites produced;
+ * k_site[g] = k_norm * n_sites / M, where k_norm (k0 for the first
+ * generation, then the previous k_site) divides the site production.  Only
+ * the active generations score tallies, each one batch of M histories.
+ * src_out (may be NULL): [M][4] (x, y, z, group) of the last combed source. */
+typedef struct {
+    uint64_t M;
+    int32_t n_inactive, n_active;
+    double k0;
+    double *k_col, *k_site;   /* [n_inactive + n_active] */
+    uint64_t *n_sites;        /* [n_inactive + n_active] */
+    double *src_out;
+} orc_keff;
+int orc_run_keff(const orc_problem *P, uint64_t seed, orc_keff *K, orc_result *R);
 
 /* primitives exposed for the pin tests */
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);

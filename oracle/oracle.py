@@ -31,7 +31,8 @@ WSUM_NAMES = ["source", "leak", "absorb", "time_end", "gain", "loss", "path"]
 
 EV = dict(source=0, scatter=1, absorb=2, surface=3, leak=4, census=5, time_end=6, split=7,
           roulette_kill=8, roulette_survive=9, cutoff_kill=10, cutoff_survive=11, pc_kill=12,
-          pc_keep=13, ww_plane=14)
+          pc_keep=13, ww_plane=14, fission=15)
+E_EXTINCT = -9
 
 
 def build(force: bool = True) -> str:
@@ -73,8 +74,14 @@ class OrcProblem(C.Structure):
         ("col_tally", C.c_int32), ("surf_on", C.c_int32), ("surf_axis", C.c_int32),
         ("surf_pos", C.c_double), ("pc_on", C.c_int32), ("pc_target", C.c_double),
         ("n_batches", C.c_int32), ("max_events", C.c_int64), ("stack_cap", C.c_int32),
-        ("problem_id", C.c_uint32),
+        ("problem_id", C.c_uint32), ("nu_sigma_f", PD), ("chi", PD),
     ]
+
+
+class OrcKeff(C.Structure):
+    _fields_ = [("M", C.c_uint64), ("n_inactive", C.c_int32), ("n_active", C.c_int32),
+                ("k0", C.c_double), ("k_col", PD), ("k_site", PD),
+                ("n_sites", C.POINTER(C.c_uint64)), ("src_out", PD)]
 
 
 class OrcTraceRec(C.Structure):
@@ -114,6 +121,9 @@ def lib():
         L.orc_run.argtypes = [C.POINTER(OrcProblem), C.c_uint64, C.c_uint64, C.c_uint64,
                               C.POINTER(OrcResult)]
         L.orc_run.restype = C.c_int
+        L.orc_run_keff.argtypes = [C.POINTER(OrcProblem), C.c_uint64, C.POINTER(OrcKeff),
+                                   C.POINTER(OrcResult)]
+        L.orc_run_keff.restype = C.c_int
         L.orc_philox4x32_10.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32),
                                         C.POINTER(C.c_uint32)]
         L.orc_philox4x32_10.restype = None
@@ -224,6 +234,9 @@ class _Problem:
         s.max_events = int(prob["max_events"])
         s.stack_cap = int(prob["stack_cap"])
         s.problem_id = problem_id
+        if prob.get("nu_sigma_f") is not None:
+            s.nu_sigma_f = _pd(arr(np.asarray(prob["nu_sigma_f"], float).reshape(M, G), np.float64))
+            s.chi = _pd(arr(np.asarray(prob["chi"], float).reshape(M, G), np.float64))
         self.s = s
         mn = [int(v) for v in m["n"]]
         self.nbins = (G if m["per_group"] else 1) * mn[0] * mn[1] * mn[2] * mn[3]
@@ -305,6 +318,57 @@ class OracleRun:
         if trace is not None:
             trace = trace[: self.R.trace_n].copy()
         return trace, xh
+
+    def run_keff(self, M: int, n_inactive: int, n_active: int, seed: int, k0: float = 1.0,
+                 trace_cap: int = 0, per_history: bool = False, src_out: bool = False):
+        """k-eigenvalue power iteration (histories g M + j); tallies score in
+        the active generations, one batch each.  Returns a dict with per
+        generation k_col, k_site, n_sites, and optionally the trace, the
+        per-history (detector score, path) of every generation and the last
+        combed source [M][x, y, z, g]."""
+        n_gen = n_inactive + n_active
+        out = dict(k_col=np.zeros(n_gen), k_site=np.zeros(n_gen),
+                   n_sites=np.zeros(n_gen, np.uint64))
+        K = OrcKeff()
+        K.M, K.n_inactive, K.n_active, K.k0 = M, n_inactive, n_active, k0
+        K.k_col, K.k_site = _pd(out["k_col"]), _pd(out["k_site"])
+        K.n_sites = out["n_sites"].ctypes.data_as(C.POINTER(C.c_uint64))
+        src = np.zeros((M, 4)) if src_out else None
+        K.src_out = _pd(src) if src_out else PD()
+        trace = None
+        if trace_cap:
+            trace = np.zeros(trace_cap, TRACE_DTYPE)
+            self.R.trace = trace.ctypes.data_as(C.POINTER(OrcTraceRec))
+            self.R.trace_cap = trace_cap
+        else:
+            self.R.trace = C.POINTER(OrcTraceRec)()
+            self.R.trace_cap = 0
+        self.R.trace_n = 0
+        xh = np.zeros((n_gen * M, 2)) if per_history else None
+        self.R.hist_xh = _pd(xh) if per_history else PD()
+        t0 = time.perf_counter()
+        st = lib().orc_run_keff(C.byref(self.P.s), seed, C.byref(K), C.byref(self.R))
+        self.last_seconds = time.perf_counter() - t0
+        if st != 0:
+            raise OracleError(st)
+        self.n_hist += M * n_active
+        if trace is not None:
+            out["trace"] = trace[: self.R.trace_n].copy()
+        if per_history:
+            out["xh"] = xh
+        if src_out:
+            out["src"] = src
+        return out
+
+    @staticmethod
+    def keff_stats(k_gen, n_inactive):
+        """Mean of the active generations' estimates and its standard error
+        (sample variance over n_active - 1, divided by n_active)."""
+        k = np.asarray(k_gen, float)[n_inactive:]
+        n = k.size
+        m = float(np.mean(k))
+        se = float(np.sqrt(np.sum((k - m) ** 2) / (n * (n - 1)))) if n > 1 else float("nan")
+        return m, se
 
     # ---- results -------------------------------------------------------
     @property

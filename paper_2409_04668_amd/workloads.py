@@ -35,6 +35,10 @@ Problem dict schema (all lengths in cm, times in s):
 ``importance``               None or dict(n[4]) coarse space-time grid
 ``ww``                       None or dict(params float32[...], hidden, logk, ratio, n_max,
                              ymin, ymax, map (nx, ny, nz, nt) or None)
+``nu_sigma_f``, ``chi``      None, or float64[M,G] each: fission production nu*Sigma_f per
+                             material and group, and the fission spectrum (outgoing group
+                             of a fission neutron); problems with fission run in the
+                             k-eigenvalue mode
 
 The slab of the one-group problem is an outer box with infinite y/z extent; a
 plane source on x=0 is then a point source at the origin (translation
@@ -68,7 +72,7 @@ def _base(G: int = 1) -> dict:
         implicit_capture=False, w_cut=0.25, w_surv=1.0,
         detector=None, n_batches=20, max_events=1_000_000, stack_cap=64,
         importance=None, ww=None, collision_tally=False, surface_tally=None,
-        population_control=None,
+        population_control=None, nu_sigma_f=None, chi=None,
     )
 
 
@@ -267,6 +271,63 @@ def config5(n_problems: int = 256, seed: int = ROOT_SEED):
     n_hist = np.floor(10.0 ** rng.uniform(4.0, 6.0, size=n_problems)).astype(np.int64)
     probs = [batch_problem(seed + 1 + i) for i in range(n_problems)]
     return probs, n_hist
+
+
+# ---------------------------------------------------------------------------
+# k-eigenvalue problems (steady state: every generation starts at t = 0)
+# ---------------------------------------------------------------------------
+
+T_STEADY = 1.0e30          # one census edge far beyond any history
+
+
+def keff_infinite_medium(sigma_t, sigma_s, nu_sigma_f, chi, half=50.0) -> dict:
+    """Homogeneous all-reflective box with fission; the first generation
+    starts at the centre in the fastest group.  Its multiplication is the
+    infinite-medium k, a closed form of the data."""
+    sigma_t = np.atleast_1d(np.asarray(sigma_t, float))
+    G = sigma_t.size
+    p = infinite_medium(sigma_t, sigma_s, np.ones(G), half=half, t_end=T_STEADY, nt=1)
+    p["nu_sigma_f"] = np.asarray(nu_sigma_f, float).reshape(1, G)
+    p["chi"] = np.asarray(chi, float).reshape(1, G)
+    p["mesh"]["per_group"] = G > 1
+    return p
+
+
+CORE_HALF, REFLECTOR_HALF = 20.0, 30.0
+
+
+def keff_core(nx: int = 30) -> dict:
+    """Two-group reflected core (synthetic data, chosen for k near 1; not a
+    published benchmark): a 40 cm fissile cube centred in a 60 cm cube of
+    moderating reflector, vacuum outside.  Group 0 thermal, group 1 fast;
+    every fission neutron is born fast.  Mesh nx^3 x 2 groups, one time bin;
+    the first generation is a uniform source over the core."""
+    G = 2
+    p = _base(G)
+    p["outer_lo"] = np.full(3, -REFLECTOR_HALF)
+    p["outer_hi"] = np.full(3, REFLECTOR_HALF)
+    p["bc"] = np.zeros(6, np.int32)
+    p["box_lo"] = np.full((1, 3), -CORE_HALF)
+    p["box_hi"] = np.full((1, 3), CORE_HALF)
+    p["box_mat"] = np.array([0], np.int32)
+    p["background_mat"] = 1
+    #                 thermal  fast
+    p["sigma_t"] = np.array([[1.25, 0.25],          # core
+                             [1.50, 0.30]])         # reflector
+    p["sigma_s"] = np.zeros((2, G, G))              # rows: from-group
+    p["sigma_s"][0] = [[1.05, 0.0], [0.017, 0.205]]
+    p["sigma_s"][1] = [[1.48, 0.0], [0.035, 0.264]]
+    p["nu_sigma_f"] = np.array([[0.50, 0.008], [0.0, 0.0]])
+    p["chi"] = np.array([[0.0, 1.0], [0.0, 1.0]])
+    p["speed"] = np.array([2.2e5, 1.0e7])
+    p["source"] = dict(kind="box", lo=np.full(3, -CORE_HALF), hi=np.full(3, CORE_HALF), t0=0.0,
+                       t1=0.0, isotropic=True, dir=np.array([1.0, 0.0, 0.0]), group=1)
+    p["mesh"] = dict(lo=np.array([-REFLECTOR_HALF] * 3 + [0.0]),
+                     hi=np.array([REFLECTOR_HALF] * 3 + [T_STEADY]),
+                     n=np.array([nx, nx, nx, 1], np.int32), per_group=True)
+    p["census"] = np.array([T_STEADY])
+    p["detector"] = dict(lo=np.full(3, -5.0), hi=np.full(3, 5.0))
+    return p
 
 
 def with_(p: dict, **kw) -> dict:
