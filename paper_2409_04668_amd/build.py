@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmcdc.so")
 SOURCES = ["mcdc_api.hip", "mcdc_history.hip", "mcdc_event.hip", "mcdc_mlp.hip", "mcdc_batch.hip",
-           "mcdc_micro.hip", "mcdc_wwmap.hip"]
+           "mcdc_micro.hip", "mcdc_wwmap.hip", "mcdc_keff.hip"]
 ARCH = os.environ.get("MCDC_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", f"--offload-arch={ARCH}", "-fPIC", "-std=c++17", "-ffp-contract=off",
          "-munsafe-fp-atomics", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -26,6 +26,28 @@ int hip_fail(hipError_t e, const char *where) {
 
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
+int cancel_init(mcdc_problem *h) {
+    void *p = nullptr;
+    hipError_t e = hipHostMalloc(&p, sizeof(int), hipHostMallocCoherent);
+    if (e != hipSuccess) return hip_fail(e, "cancel word");
+    h->cancel_host = (int *)p;
+    __atomic_store_n(h->cancel_host, 0, __ATOMIC_RELEASE);
+    void *d = nullptr;
+    e = hipHostGetDevicePointer(&d, p, 0);
+    if (e != hipSuccess) {
+        cancel_free(h);
+        return hip_fail(e, "cancel word device address");
+    }
+    h->cancel_dev = (int *)d;
+    return MCDC_OK;
+}
+
+void cancel_free(mcdc_problem *h) {
+    if (h->cancel_host) (void)hipHostFree(h->cancel_host);
+    h->cancel_host = nullptr;
+    h->cancel_dev = nullptr;
+}
+
 int validate_desc(const mcdc_problem_desc *d) {
     if (!d) return fail(MCDC_E_INVALID, "null problem description");
     if (d->G < 1 || d->G > MCDC_MAX_G) return fail(MCDC_E_INVALID, "G out of range");
@@ -76,12 +98,35 @@ int validate_desc(const mcdc_problem_desc *d) {
         for (int a = 0; a < 3; ++a)
             if (isinf(d->outer_lo[a]) || isinf(d->outer_hi[a]))
                 return fail(MCDC_E_INVALID, "weight windows / importance need a finite outer box");
+    if (d->nu_sigma_f) {
+        if (!d->chi) return fail(MCDC_E_INVALID, "fission data needs the fission spectrum chi");
+        for (int m = 0; m < d->n_mat; ++m) {
+            double sf = 0.0, sc = 0.0;
+            for (int g = 0; g < d->G; ++g) {
+                const double f = d->nu_sigma_f[m * d->G + g], c = d->chi[m * d->G + g];
+                if (!(f >= 0.0) || !isfinite(f) || !(c >= 0.0) || !isfinite(c))
+                    return fail(MCDC_E_INVALID, "nu_sigma_f and chi must be finite and >= 0");
+                sf += f;
+                sc += c;
+            }
+            if (sf > 0.0 && !(sc > 0.0))
+                return fail(MCDC_E_INVALID, "a fissile material needs a spectrum with a positive sum");
+        }
+    }
     return MCDC_OK;
+}
+
+// any positive nu Sigma_f: the problem runs in the k-eigenvalue mode
+int desc_fissile(const mcdc_problem_desc *d) {
+    if (!d->nu_sigma_f) return 0;
+    for (int i = 0; i < d->n_mat * d->G; ++i)
+        if (d->nu_sigma_f[i] > 0.0) return 1;
+    return 0;
 }
 
 // surface-current bins: 2 sides x groups of the mesh x time bins x the mesh
 // bins of the two in-plane axes
-static size_t desc_nsurf(const mcdc_problem_desc *d) {
+size_t desc_nsurf(const mcdc_problem_desc *d) {
     if (!d->surf_on) return 0;
     const int a = d->surf_axis, b1 = a == 0 ? 1 : 0, b2 = a == 2 ? 1 : 2;
     return (size_t)2 * (d->mesh_per_group ? d->G : 1) * d->mesh_n[3] * d->mesh_n[b1] * d->mesh_n[b2];
@@ -150,7 +195,8 @@ int check_options(const Options &o) {
 Layout make_layout(const mcdc_problem_desc *d, const Options &o) {
     Layout L;
     size_t off = 0;
-    const size_t n_tab = (size_t)d->n_mat * d->G + (size_t)d->n_mat * d->G * d->G + d->G + d->n_census;
+    const size_t n_tab = (size_t)d->n_mat * d->G + (size_t)d->n_mat * d->G * d->G + d->G + d->n_census +
+                         (desc_fissile(d) ? 2 * (size_t)d->n_mat * d->G : 0);
     L.tables = off; off = align_up(off + n_tab * sizeof(double));
     const size_t nb = desc_nbins(d);
     // the event schedule keeps every batch of a run resident (one slice per
@@ -207,6 +253,11 @@ void build_dev_problem(const mcdc_problem_desc *d, char *ws, const Layout &L, De
     P.sigma_s = tab + nst;
     P.speed = tab + nst + nss;
     P.census = tab + nst + nss + d->G;
+    P.fis_on = desc_fissile(d);
+    if (P.fis_on) {
+        P.nu_sigma_f = P.census + d->n_census;
+        P.chi = P.nu_sigma_f + nst;
+    }
     P.src_box = d->src_kind == MCDC_SRC_BOX;
     P.src_isotropic = d->src_isotropic;
     P.src_group = d->src_group;
@@ -311,6 +362,10 @@ std::vector<double> pack_tables(const mcdc_problem_desc *d) {
     t.insert(t.end(), d->sigma_s, d->sigma_s + nss);
     t.insert(t.end(), d->speed, d->speed + d->G);
     t.insert(t.end(), d->census, d->census + d->n_census);
+    if (desc_fissile(d)) {
+        t.insert(t.end(), d->nu_sigma_f, d->nu_sigma_f + nst);
+        t.insert(t.end(), d->chi, d->chi + nst);
+    }
     return t;
 }
 
@@ -398,7 +453,12 @@ int mcdc_create_problem(const mcdc_problem_desc *d, const mcdc_options *opt, voi
             return fail(MCDC_E_HIP, "kernel argument layout differs from the problem description");
         }
     }
+    if ((st = cancel_init(h))) {
+        delete h;
+        return st;
+    }
     if (o.schedule == MCDC_SCHED_EVENT && (st = event_init(h))) {
+        cancel_free(h);
         delete h;
         return st;
     }
@@ -436,7 +496,14 @@ void mcdc_destroy_problem(mcdc_handle h) {
     timing_clear(h);
     event_destroy(h);
     batch_destroy(h);
+    cancel_free(h);
     delete h;
+}
+
+int mcdc_set_cancel(mcdc_handle h, int on) {
+    if (!h || !h->cancel_host) return fail(MCDC_E_INVALID, "null handle");
+    __atomic_store_n(h->cancel_host, on ? 1 : 0, __ATOMIC_RELEASE);
+    return MCDC_OK;
 }
 
 int mcdc_set_trace(mcdc_handle h, mcdc_trace_rec *buf, uint64_t cap, uint64_t *count) {
@@ -464,6 +531,7 @@ int mcdc_set_ww_mlp(mcdc_handle h, const float *params, size_t n, double logk, d
         return MCDC_OK;
     }
     if (h->desc.stack_cap < 1) return fail(MCDC_E_STATE, "problem was created with stack_cap = 0");
+    if (h->P.fis_on) return fail(MCDC_E_STATE, "weight windows are not combined with the k-eigenvalue mode");
     if (h->desc.imp_on) return fail(MCDC_E_STATE, "weight windows and the importance estimate exclude each other");
     if (n != mcdc_mlp_param_count(4 + h->desc.G)) return fail(MCDC_E_INVALID, "wrong parameter count");
     if (!(ratio >= 1.0) || n_max < 2) return fail(MCDC_E_INVALID, "ratio >= 1 and n_max >= 2 required");
@@ -522,8 +590,15 @@ static RunArgs base_args(mcdc_handle h, uint64_t seed) {
     A.imp_cnt = (double *)(h->ws + h->L.imp_list + align_up(kImpList * Ln * sizeof(int32_t)));
     A.imp_xsum = A.imp_cnt + kImpList * Ln;
     A.n_lanes = Ln;
+    A.cancel = h->cancel_dev;
     return A;
 }
+
+}  // extern "C"
+
+RunArgs mcdc::base_args_for(mcdc_problem *h, uint64_t seed) { return base_args(h, seed); }
+
+extern "C" {
 
 // Batch close-outs of an event- or hybrid-schedule run of n histories: every
 // per-batch slice in one launch per tally.
@@ -548,6 +623,7 @@ static int close_event_run(mcdc_handle h, uint64_t n, hipStream_t s) {
 int mcdc_run(mcdc_handle h, uint64_t n, uint64_t seed, void *stream) {
     if (!h) return fail(MCDC_E_INVALID, "null handle");
     if (h->is_batch) return fail(MCDC_E_STATE, "batched handle: use mcdc_run_batch");
+    if (h->P.fis_on) return fail(MCDC_E_STATE, "a problem with fission runs in the k-eigenvalue mode (mcdc_run_keff)");
     if (h->in_run) return fail(MCDC_E_STATE, "a census-stepped run is in progress");
     if (h->n_hist + n >= (1ull << 48)) return fail(MCDC_E_INVALID, "history ids exhausted (2^48)");
     hipStream_t s = (hipStream_t)stream;
@@ -610,6 +686,7 @@ int mcdc_run(mcdc_handle h, uint64_t n, uint64_t seed, void *stream) {
             e = launch_closeout(sbatch, ssum, ssumsq, h->P.surf_nbins, (double)(hi - lo), s);
         if (e != hipSuccess) return hip_fail(e, "run launch");
         h->batches += 1;
+        if (cancel_set(h)) return fail(MCDC_E_CANCELLED, "run cancelled");
     }
     h->n_hist += n;
     return MCDC_OK;
@@ -633,6 +710,7 @@ static RunArgs stepped_args(mcdc_handle h) {
 
 int mcdc_run_begin(mcdc_handle h, uint64_t n, uint64_t seed, void *stream) {
     if (!h) return fail(MCDC_E_INVALID, "null handle");
+    if (h->P.fis_on) return fail(MCDC_E_STATE, "a problem with fission runs in the k-eigenvalue mode (mcdc_run_keff)");
     if (h->is_batch || h->opt.schedule != MCDC_SCHED_EVENT)
         return fail(MCDC_E_STATE, "census-step control runs in the event schedule");
     if (h->in_run) return fail(MCDC_E_STATE, "a census-stepped run is in progress");
@@ -810,29 +888,87 @@ int mcdc_get_counters(mcdc_handle h, mcdc_counters *out, void *stream) {
     return MCDC_OK;
 }
 
-int mcdc_get_tallies(mcdc_handle h, int kind, double *mean, double *rel, size_t n, void *stream) {
-    if (!h || !mean) return fail(MCDC_E_INVALID, "null argument");
-    DevAcc acc;
-    int st = read_acc(h, acc, (hipStream_t)stream);
-    if (st) return st;
-    const double N = (double)h->n_hist;
+}  // extern "C"
+
+namespace mcdc {
+
+// What a run reports (the finalization step: tallies with their statistical
+// error).  One definition serves the host read-back and the device kernel, so
+// both give the same bits.
+//   mesh-type bin: mean = S / N / size, with S the sum of the batch sums, N
+//   the source histories and size the bin's volume (area on a surface) times
+//   its time width; rel = standard error / (S / N) from the batch means,
+//   sqrt((S2 - N m^2) / ((B - 1) N)) / m with S2 = sum of S_b^2 / N_b (the
+//   weighted form, exact for equal batches too); 0 for a zero mean; NaN with
+//   fewer than two batches.
+//   detector: mean = X / N; rel = sqrt((X2 / N - m^2) / (N - 1)) / m from the
+//   per-history scores (0 for a zero mean, NaN with fewer than two histories).
+__host__ __device__ inline void bin_result(double s, double s2, double N, double B, double size,
+                                           double &mean, double &rel) {
+    const double m = s / N;
+    mean = m / size;
+    if (B < 2.0) {
+        rel = NAN;
+    } else if (m <= 0.0) {
+        rel = 0.0;
+    } else {
+        const double var = (s2 - N * m * m) / ((B - 1.0) * N);
+        rel = sqrt(var > 0.0 ? var : 0.0) / m;
+    }
+}
+
+__host__ __device__ inline void detector_result(double x, double x2, double N, double &mean,
+                                                double &rel) {
+    const double m = x / N;
+    mean = m;
+    if (N < 2.0) {
+        rel = NAN;
+    } else if (m <= 0.0) {
+        rel = 0.0;
+    } else {
+        const double var = (x2 / N - m * m) / (N - 1.0);
+        rel = sqrt(var > 0.0 ? var : 0.0) / m;
+    }
+}
+
+__global__ void k_bin_results(const double *__restrict__ s, const double *__restrict__ s2,
+                              uint32_t n, double N, double B, double size, double *__restrict__ mean,
+                              double *__restrict__ rel) {
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        double m, r;
+        bin_result(s[i], s2[i], N, B, size, m, r);
+        mean[i] = m;
+        if (rel) rel[i] = r;
+    }
+}
+
+// kind: 1 detector (one value), 2 leakage (six values)
+__global__ void k_scalar_results(const DevAcc *__restrict__ acc, int kind, double N,
+                                 double *__restrict__ mean, double *__restrict__ rel) {
+    const int i = threadIdx.x;
+    if (kind == MCDC_TALLY_DETECTOR) {
+        if (i != 0) return;
+        double m, r;
+        detector_result(acc->det[0], acc->det[1], N, m, r);
+        mean[0] = m;
+        if (rel) rel[0] = r;
+    } else if (i < 6) {
+        mean[i] = acc->leak[i] / N;
+        if (rel) rel[i] = NAN;
+    }
+}
+
+// Checks shared by both read-backs; on success the sum / sum-of-squares
+// offsets and the bin size of a mesh-type kind.
+static int tally_kind(mcdc_handle h, int kind, size_t n, size_t &o1, size_t &o2, double &size) {
     if (h->n_hist == 0) return fail(MCDC_E_STATE, "no histories run yet");
     if (kind == MCDC_TALLY_DETECTOR) {
         if (n != 1) return fail(MCDC_E_INVALID, "detector tally has 1 value");
-        const double m = acc.det[0] / N;
-        mean[0] = m;
-        if (rel) {
-            const double var = N > 1 ? (acc.det[1] / N - m * m) / (N - 1.0) : NAN;
-            rel[0] = m > 0.0 ? sqrt(var > 0.0 ? var : 0.0) / m : 0.0;
-        }
         return MCDC_OK;
     }
     if (kind == MCDC_TALLY_LEAKAGE) {
         if (n != 6) return fail(MCDC_E_INVALID, "leakage tally has 6 values");
-        for (int f = 0; f < 6; ++f) {
-            mean[f] = acc.leak[f] / N;
-            if (rel) rel[f] = NAN;
-        }
         return MCDC_OK;
     }
     if (kind != MCDC_TALLY_MESH && kind != MCDC_TALLY_COLLISION && kind != MCDC_TALLY_SURFACE)
@@ -843,31 +979,82 @@ int mcdc_get_tallies(mcdc_handle h, int kind, double *mean, double *rel, size_t 
         return fail(MCDC_E_STATE, "problem created without the surface-current tally");
     const bool surf = kind == MCDC_TALLY_SURFACE;
     if (n != (surf ? desc_nsurf(&h->desc) : (size_t)h->nbins)) return fail(MCDC_E_INVALID, "wrong bin count");
-    const size_t o1 = surf ? h->L.surf_sum : (kind == MCDC_TALLY_MESH ? h->L.tally_sum : h->L.col_sum);
-    const size_t o2 = surf ? h->L.surf_sumsq : (kind == MCDC_TALLY_MESH ? h->L.tally_sumsq : h->L.col_sumsq);
+    o1 = surf ? h->L.surf_sum : (kind == MCDC_TALLY_MESH ? h->L.tally_sum : h->L.col_sum);
+    o2 = surf ? h->L.surf_sumsq : (kind == MCDC_TALLY_MESH ? h->L.tally_sumsq : h->L.col_sumsq);
+    // mesh bins: volume times time width; surface bins: area on the plane
+    // times time width; an unbounded axis is not cut
+    size = 1.0;
+    for (int a = 0; a < 4; ++a)
+        if ((a == 3 || h->P.mesh_bounded[a]) && !(surf && a == h->desc.surf_axis))
+            size *= h->P.mesh_delta[a];
+    return MCDC_OK;
+}
+
+}  // namespace mcdc
+
+extern "C" {
+
+int mcdc_get_tallies(mcdc_handle h, int kind, double *mean, double *rel, size_t n, void *stream) {
+    if (!h || !mean) return fail(MCDC_E_INVALID, "null argument");
+    if (h->is_batch) return fail(MCDC_E_STATE, "batched handle: use mcdc_get_batch_raw");
+    DevAcc acc;
+    int st = read_acc(h, acc, (hipStream_t)stream);
+    if (st) return st;
+    size_t o1 = 0, o2 = 0;
+    double size = 1.0;
+    if ((st = tally_kind(h, kind, n, o1, o2, size))) return st;
+    const double N = (double)h->n_hist;
+    if (kind == MCDC_TALLY_DETECTOR) {
+        double r;
+        detector_result(acc.det[0], acc.det[1], N, mean[0], r);
+        if (rel) rel[0] = r;
+        return MCDC_OK;
+    }
+    if (kind == MCDC_TALLY_LEAKAGE) {
+        for (int f = 0; f < 6; ++f) {
+            mean[f] = acc.leak[f] / N;
+            if (rel) rel[f] = NAN;
+        }
+        return MCDC_OK;
+    }
     std::vector<double> s(n), s2(n);
     hipError_t e = hipMemcpy(s.data(), h->ws + o1, n * sizeof(double), hipMemcpyDeviceToHost);
     if (e == hipSuccess) e = hipMemcpy(s2.data(), h->ws + o2, n * sizeof(double), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "get_tallies");
-    // mesh bins: divided by volume and time width; surface bins: by the bin's
-    // area on the plane and time width
-    double vol = 1.0;
-    for (int a = 0; a < 4; ++a)
-        if ((a == 3 || h->P.mesh_bounded[a]) && !(surf && a == h->desc.surf_axis))
-            vol *= h->P.mesh_delta[a];
     const double B = (double)h->batches;
     for (size_t i = 0; i < n; ++i) {
-        const double m = s[i] / N;
-        mean[i] = m / vol;
-        if (rel) {
-            if (B < 2 || m <= 0.0) {
-                rel[i] = B < 2 ? NAN : 0.0;
-            } else {
-                const double var = (s2[i] - N * m * m) / ((B - 1.0) * N);
-                rel[i] = sqrt(var > 0.0 ? var : 0.0) / m;
-            }
-        }
+        double r;
+        bin_result(s[i], s2[i], N, B, size, mean[i], r);
+        if (rel) rel[i] = r;
     }
+    return MCDC_OK;
+}
+
+int mcdc_get_tallies_device(mcdc_handle h, int kind, double *dev_mean, double *dev_rel, size_t n,
+                            void *stream) {
+    if (!h || !dev_mean) return fail(MCDC_E_INVALID, "null argument");
+    if (h->is_batch) return fail(MCDC_E_STATE, "batched handle: use mcdc_get_batch_raw");
+    if (h->in_run) return fail(MCDC_E_STATE, "a census-stepped run is in progress");
+    size_t o1 = 0, o2 = 0;
+    double size = 1.0;
+    int st = tally_kind(h, kind, n, o1, o2, size);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const double N = (double)h->n_hist;
+    if (kind == MCDC_TALLY_DETECTOR || kind == MCDC_TALLY_LEAKAGE) {
+        hipLaunchKernelGGL(k_scalar_results, dim3(1), dim3(64), 0, s,
+                           (const DevAcc *)(h->ws + h->L.acc), kind, N, dev_mean, dev_rel);
+    } else {
+        const int block = 256;
+        int grid = (int)((n + block - 1) / block);
+        if (grid > 65536) grid = 65536;
+        if (grid < 1) grid = 1;
+        hipLaunchKernelGGL(k_bin_results, dim3(grid), dim3(block), 0, s,
+                           (const double *)(h->ws + o1), (const double *)(h->ws + o2), (uint32_t)n,
+                           N, (double)h->batches, size, dev_mean, dev_rel);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "get_tallies_device");
     return MCDC_OK;
 }
 

@@ -54,6 +54,7 @@ struct BDev {
     uint32_t *chunk_off;                      // [n_prob + 1]
     uint64_t *hist_base;                      // [n_prob]
     BCtl *ctl;
+    const int *cancel;                        // host-coherent cancel word
     uint64_t cap;
     uint64_t total_bins;
 };
@@ -172,16 +173,21 @@ template <bool TILE>
 __global__ void __launch_bounds__(512) k_b_persistent(BDev D) {
     extern __shared__ double s_tile[];
     __shared__ Shared S;
-    __shared__ uint32_t s_chunk;
+    __shared__ uint32_t s_chunk, s_cancel;
     const BCtl *c = D.ctl;
     const uint32_t step = c->step, cur = step & 1u, total = c->total_chunks;
     RunArgs A{};
     A.seed = c->seed;
     int tile_p = -1;
     shared_zero(S);
+    if (threadIdx.x == 0) s_cancel = 0u;
     __syncthreads();
-    for (;;) {
-        if (threadIdx.x == 0) s_chunk = atomicAdd(&D.ctl->chunk_next, 1u);
+    for (uint32_t fetch = 0;; ++fetch) {
+        if (threadIdx.x == 0) {
+            // the host's cancel word, every eighth chunk of this workgroup
+            if (fetch % 8u == 0u && cancel_requested(D.cancel)) s_cancel = 1u;
+            s_chunk = s_cancel ? total : atomicAdd(&D.ctl->chunk_next, 1u);
+        }
         __syncthreads();
         const uint32_t ch = s_chunk;
         __syncthreads();
@@ -289,6 +295,9 @@ __global__ void __launch_bounds__(512) k_b_persistent(BDev D) {
         }
         shared_flush(S, &D.acc[tile_p]);
     }
+    if (s_cancel)
+        for (uint32_t i = threadIdx.x; i < D.n_prob; i += blockDim.x)
+            atomicMin(&D.acc[i].status, (int)MCDC_E_CANCELLED);
 }
 
 // close-out of one pass (one batch per problem): flattened over all bins
@@ -361,6 +370,7 @@ static int bvalidate(const mcdc_problem_desc *ds, size_t n, const uint64_t *nh) 
         if (ds[p].has_detector) return fail(MCDC_E_INVALID, "batched problems have no detector tally");
         if (ds[p].col_tally) return fail(MCDC_E_INVALID, "batched problems have no collision-estimator tally");
         if (ds[p].surf_on) return fail(MCDC_E_INVALID, "batched problems have no surface-current tally");
+        if (desc_fissile(&ds[p])) return fail(MCDC_E_INVALID, "batched problems have no fission (k-eigenvalue runs one problem)");
         if (ds[p].pc_on) return fail(MCDC_E_INVALID, "batched problems run without population control");
         if (nh[p] > 0xFFFFFFF0ull) return fail(MCDC_E_INVALID, "too many histories in one problem");
         cap += nh[p];
@@ -418,6 +428,11 @@ int mcdc_create_batch(const mcdc_problem_desc *ds, size_t n, const uint64_t *nh,
     D.chunk_off = (uint32_t *)(w + L.chunk_off);
     D.hist_base = (uint64_t *)(w + L.hist_base);
     D.ctl = (BCtl *)(w + L.ctl);
+    if ((st = cancel_init(h))) {
+        mcdc_destroy_problem(h);
+        return st;
+    }
+    D.cancel = h->cancel_dev;
     std::vector<double> tables;
     uint64_t tally_off = 0, bank_off = 0;
     Layout dummy{};
@@ -533,6 +548,7 @@ int mcdc_run_batch(mcdc_handle h, uint64_t seed, void *stream) {
     e = hipGraphLaunch(B->exec, s);
     if (e != hipSuccess) return hip_fail(e, "run_batch graph launch");
     B->passes += 1;
+    if (cancel_set(h)) return fail(MCDC_E_CANCELLED, "run cancelled");
     return MCDC_OK;
 }
 

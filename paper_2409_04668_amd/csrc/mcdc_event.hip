@@ -363,8 +363,13 @@ __global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_ev_lead(DevProblem, R
     Part q;
     q.alive = false;
     bool in_hist = false;
+    uint32_t turn = 0;
     for (;;) {
         CP &PL = problem_reload(P);
+        if (turn++ % kCancelPoll == 0 && cancel_requested(A.cancel)) {
+            set_status(A, MCDC_E_CANCELLED);
+            break;
+        }
         if (!q.alive) {
             if (WW != 0 && C.sp > 0) {
                 C.sp -= 1;
@@ -879,6 +884,7 @@ static int ev_iterate(mcdc_problem *h, const RunArgs &A, hipStream_t s, bool &do
                                       hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return hip_fail(e, "event loop");
+        if (cancel_set(h)) return fail(MCDC_E_CANCELLED, "run cancelled");
         if (E->host_done[0]) {
             done = true;
             return MCDC_OK;

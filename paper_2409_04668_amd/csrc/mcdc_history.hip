@@ -14,11 +14,14 @@
 namespace mcdc {
 
 // Per-work-item history context (registers).  WW: 0 no weight windows,
-// 1 network evaluated at each check, 2 baked window map.
-template <int WW, bool IMP>
+// 1 network evaluated at each check, 2 baked window map.  FIS: a generation
+// of the k-eigenvalue mode (fission sites recorded with their history slot
+// and ordinal).
+template <int WW, bool IMP, bool FIS = false>
 struct HistCtx {
     static constexpr bool kWW = WW != 0;
     static constexpr bool kWWMap = WW == 2;
+    static constexpr bool kFis = FIS;
     CP &P;
     const RunArgs &A;
     uint64_t lane;
@@ -26,6 +29,22 @@ struct HistCtx {
     double xh, path;
     int64_t events;
     int sp, n_imp;
+    uint32_t n_site;
+
+    // fission site `pos` of the generation's bank (in reservation order;
+    // past the capacity it is dropped and the host reports the overflow)
+    MCDC_DEV void put_site(const Part &q, int g, uint32_t pos) {
+        const uint32_t ord = n_site;
+        n_site += 1;
+        if (pos >= A.site_cap) return;
+        const uint64_t c = A.site_cap;
+        A.site_d[pos] = q.x[0];
+        A.site_d[c + pos] = q.x[1];
+        A.site_d[2 * c + pos] = q.x[2];
+        A.site_g[pos] = g;
+        A.site_key[pos] = (uint32_t)(id - A.gen_first);
+        A.site_key[c + pos] = ord;
+    }
 
     MCDC_DEV uint64_t hist() const { return id; }
     MCDC_DEV double *col_tally() const { return A.col; }
@@ -88,13 +107,18 @@ struct HistCtx {
     }
 };
 
-template <int WW, bool IMP>
-MCDC_DEV void finish_history(const RunArgs &A, Shared &S, const HistCtx<WW, IMP> &H) {
-    if (H.xh != 0.0) {
-        unsafeAtomicAdd(&A.acc->det[0], H.xh);
-        unsafeAtomicAdd(&A.acc->det[1], H.xh * H.xh);
+template <int WW, bool IMP, bool FIS>
+MCDC_DEV void finish_history(const RunArgs &A, Shared &S, const HistCtx<WW, IMP, FIS> &H) {
+    if (FIS) A.hist_sites[H.id - A.gen_first] = H.n_site;
+    if (FIS && A.det_off) {
+        // an inactive generation: its detector scores are discarded
+    } else {
+        if (H.xh != 0.0) {
+            unsafeAtomicAdd(&A.acc->det[0], H.xh);
+            unsafeAtomicAdd(&A.acc->det[1], H.xh * H.xh);
+        }
+        if (H.xh > 0.0) atomicAdd(&S.cnt[C_DET_HIT], 1ull);
     }
-    if (H.xh > 0.0) atomicAdd(&S.cnt[C_DET_HIT], 1ull);
     if (A.xh_out) {
         A.xh_out[2 * (H.id - A.h_run0)] = H.xh;
         A.xh_out[2 * (H.id - A.h_run0) + 1] = H.path;
@@ -133,7 +157,7 @@ MCDC_DEV HotTileTally make_tally(HotTileTally *, CP &P, const RunArgs &A, double
     return t;
 }
 
-template <int LDS, int WW, bool IMP>
+template <int LDS, int WW, bool IMP, bool FIS>
 __global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_history(DevProblem, RunArgs A) {
     CP &P = kernel_problem();
     extern __shared__ double s_tile[];
@@ -150,14 +174,19 @@ __global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_history(DevProblem, R
     double path = 0.0;
     Part q;
     q.alive = false;
-    HistCtx<WW, IMP> H{P, A, lane, 0, 0.0, 0.0, 0, 0, 0};
+    HistCtx<WW, IMP, FIS> H{P, A, lane, 0, 0.0, 0.0, 0, 0, 0, 0u};
     bool in_hist = false;
     using Tally = typename TallyFor<LDS>::type;
     const Tally tally = make_tally((Tally *)nullptr, P, A, s_tile);
 
     bool ww_due = false;                    // a weight-window check waits for this lane
+    uint32_t turn = 0;
     for (;;) {
         CP &PL = problem_reload(P);
+        if (turn++ % kCancelPoll == 0 && cancel_requested(A.cancel)) {
+            set_status(A, MCDC_E_CANCELLED);
+            break;
+        }
         if (WW == 1) {
             // Weight-window checks run batched: a lane that needs one waits
             // (its particle does not move) until at least half of the wave's
@@ -190,9 +219,11 @@ __global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_history(DevProblem, R
                 H.events = 0;
                 H.sp = 0;
                 H.n_imp = 0;
+                H.n_site = 0;
                 in_hist = true;
                 n_hist += 1;
-                stage_source(PL, A, S, H, q);
+                if (FIS && A.src_d != nullptr) stage_source_site(PL, A, S, H, q, H.id - A.gen_first);
+                else stage_source(PL, A, S, H, q);
                 if (!q.alive) continue;
             }
         }
@@ -316,14 +347,20 @@ hipError_t launch_history(const DevProblem &P, const RunArgs &A, int grid, int b
                                  : (mode == 1 ? (size_t)P.nbins * sizeof(double) : 0);
     const int ww = P.ww_on ? (P.ww_map ? 2 : 1) : 0;
     const bool imp = P.imp_on != 0;
-#define MCDC_LAUNCH(L, W, I)                                                                   \
+#define MCDC_LAUNCH_F(L, W, I, F)                                                              \
     do {                                                                                       \
         if (shm > 65536)                                                                       \
-            (void)hipFuncSetAttribute((const void *)k_history<L, W, I>,                        \
+            (void)hipFuncSetAttribute((const void *)k_history<L, W, I, F>,                     \
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);   \
-        hipLaunchKernelGGL((k_history<L, W, I>), dim3(grid), dim3(block), shm, s, P, A);       \
+        hipLaunchKernelGGL((k_history<L, W, I, F>), dim3(grid), dim3(block), shm, s, P, A);    \
     } while (0)
-    if (mode == 2) {
+#define MCDC_LAUNCH(L, W, I) MCDC_LAUNCH_F(L, W, I, false)
+    if (P.fis_on) {
+        // a k-eigenvalue generation (no weight windows, no importance estimate)
+        if (mode == 2) MCDC_LAUNCH_F(2, 0, false, true);
+        else if (mode == 1) MCDC_LAUNCH_F(1, 0, false, true);
+        else MCDC_LAUNCH_F(0, 0, false, true);
+    } else if (mode == 2) {
         if (ww == 2) MCDC_LAUNCH(2, 2, false);
         else if (ww == 1) MCDC_LAUNCH(2, 1, false);
         else if (imp) MCDC_LAUNCH(2, 0, true);
@@ -340,6 +377,7 @@ hipError_t launch_history(const DevProblem &P, const RunArgs &A, int grid, int b
         else MCDC_LAUNCH(0, 0, false);
     }
 #undef MCDC_LAUNCH
+#undef MCDC_LAUNCH_F
     return hipGetLastError();
 }
 

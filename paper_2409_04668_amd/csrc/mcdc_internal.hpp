@@ -30,7 +30,7 @@ enum { W_SOURCE = 0, W_LEAK, W_ABSORB, W_TIME_END, W_GAIN, W_LOSS, W_PATH, N_WSU
 enum {
     EV_SOURCE = 0, EV_SCATTER = 1, EV_ABSORB = 2, EV_SURFACE = 3, EV_LEAK = 4, EV_CENSUS = 5,
     EV_TIME_END = 6, EV_SPLIT = 7, EV_RR_KILL = 8, EV_RR_SURVIVE = 9, EV_CUT_KILL = 10,
-    EV_CUT_SURVIVE = 11, EV_PC_KILL = 12, EV_PC_KEEP = 13, EV_WW_PLANE = 14,
+    EV_CUT_SURVIVE = 11, EV_PC_KILL = 12, EV_PC_KEEP = 13, EV_WW_PLANE = 14, EV_FISSION = 15,
 };
 
 struct DevAcc {
@@ -40,6 +40,8 @@ struct DevAcc {
     double det[2];
     int status;
     int pad;
+    double kcol;                         // k-eigenvalue: sum of w nuSigma_f / Sigma_t
+                                         // over the generation's collisions
 };
 
 // Problem tables as seen by the kernels: every kernel takes them by value as
@@ -83,6 +85,8 @@ struct DevProblem {
     int32_t stack_cap;
     uint32_t problem_id;
     uint32_t nbins;
+    int32_t fis_on;                      // fission data present (k-eigenvalue mode)
+    const double *nu_sigma_f, *chi;      // device [n_mat][G] each
     uint32_t hot_lo[5], hot_n[5];        // LDS hot tile (x, y, z, t, g); hot_bins 0 = off
     uint32_t hot_bins;
 };
@@ -111,6 +115,24 @@ struct RunArgs {
     int32_t *imp_cell;                   // [kImpList][n_lanes]
     double *imp_cnt, *imp_xsum;          // [kImpList][n_lanes]
     uint64_t n_lanes;
+    const int *cancel;                   // host-coherent cancel word (may be null)
+    // k-eigenvalue generation (history schedule): histories [gen_first,
+    // gen_first + gen_m) start at the sites src_* (null: the problem's
+    // source); fission sites go to site_* in any order with their key
+    // (history slot, ordinal within the history) and hist_sites counts them
+    // per slot; the collision estimate accumulates in acc->kcol
+    double k_norm;                       // site production is divided by this
+    uint64_t gen_first, gen_m;
+    const double *src_d;                 // [3][gen_m] positions
+    const int32_t *src_g;                // [gen_m] groups
+    double *site_d;                      // [3][site_cap]
+    int32_t *site_g;                     // [site_cap]
+    uint32_t *site_key;                  // [2][site_cap]: slot, ordinal
+    uint32_t *site_n;                    // sites reserved (may pass site_cap: overflow)
+    uint32_t *hist_sites;                // [gen_m]
+    uint32_t site_cap;
+    int32_t det_off;                     // 1: detector scores not accumulated (inactive
+                                         // generation)
 };
 
 struct Layout {                          // workspace carving (byte offsets)

@@ -1,6 +1,7 @@
 // Micro-benchmarks that set the measured ceilings of the tally roofline:
-// FP64 atomic adds at random bins of an array the size of a tally, and a
-// streaming copy for the HBM ceiling.  Not part of the transport path.
+// FP64 atomic adds at random bins of an array the size of a tally (HBM), the
+// same adds into a workgroup's LDS array the size of a hot tile (ds_add_f64),
+// and a streaming copy for the HBM ceiling.  Not part of the transport path.
 #include "mcdc_runtime.hpp"
 
 namespace mcdc {
@@ -34,6 +35,34 @@ __global__ void __launch_bounds__(256) k_atomic_ceiling(double *__restrict__ buf
     }
 }
 
+// Each work-item performs `per_item` LDS adds at hashed bins of its
+// workgroup's array (bin = high word of hash * n_bins: one multiply, so the
+// loop is the ds_add_f64 and the hash); the array is zeroed first and added
+// into `out` at the end (one HBM atomic per touched bin).
+typedef __attribute__((address_space(3))) double lds_f64_t;
+__global__ void __launch_bounds__(1024) k_lds_atomic_ceiling(double *__restrict__ out,
+                                                             uint32_t n_bins, uint32_t n_items,
+                                                             uint32_t per_item) {
+    extern __shared__ double s_bins[];
+    for (uint32_t i = threadIdx.x; i < n_bins; i += blockDim.x) s_bins[i] = 0.0;
+    __syncthreads();
+    const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid < n_items) {
+        uint32_t h = mix32(tid * 2654435761u + 777u);
+        lds_f64_t *base = (lds_f64_t *)s_bins;
+        for (uint32_t k = 0; k < per_item; ++k) {
+            h = mix32(h + k);
+            const uint32_t i = (uint32_t)(((uint64_t)h * n_bins) >> 32);
+            __hip_atomic_fetch_add(base + i, 1.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < n_bins; i += blockDim.x) {
+        const double v = s_bins[i];
+        if (v != 0.0) unsafeAtomicAdd(out + i, v);
+    }
+}
+
 __global__ void __launch_bounds__(256) k_stream_copy(const double4 *__restrict__ src,
                                                      double4 *__restrict__ dst, size_t n) {
     const size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -57,6 +86,23 @@ int mcdc_micro_atomics(double *dev_buf, uint64_t n_bins, uint64_t n_items, uint3
                        dev_buf, (uint32_t)n_bins, (uint32_t)n_items, per_item, run);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? MCDC_OK : hip_fail(e, "micro_atomics");
+}
+
+int mcdc_micro_lds_atomics(double *dev_out, uint32_t n_bins, uint64_t n_items, uint32_t per_item,
+                           void *stream) {
+    if (!dev_out || n_bins == 0 || n_bins > MCDC_MAX_TILE_BINS || per_item == 0)
+        return fail(MCDC_E_INVALID, "micro_lds_atomics arguments");
+    if (n_items == 0 || n_items > (1ull << 31)) return fail(MCDC_E_INVALID, "micro_lds_atomics item count");
+    const int block = 1024;
+    const uint64_t grid = (n_items + block - 1) / block;
+    const size_t shm = (size_t)n_bins * sizeof(double);
+    if (shm > 65536)
+        (void)hipFuncSetAttribute((const void *)k_lds_atomic_ceiling,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    hipLaunchKernelGGL(k_lds_atomic_ceiling, dim3((uint32_t)grid), dim3(block), shm,
+                       (hipStream_t)stream, dev_out, n_bins, (uint32_t)n_items, per_item);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? MCDC_OK : hip_fail(e, "micro_lds_atomics");
 }
 
 int mcdc_micro_copy(const void *dev_src, void *dev_dst, size_t bytes, void *stream) {

@@ -53,11 +53,21 @@ struct mcdc_problem {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
     mcdc::EventState *ev = nullptr;
     mcdc::BatchState *batch = nullptr;
+    // cancel word: pinned, host-coherent memory that kernels read while the
+    // host may write it (cancel_dev is its device address)
+    int *cancel_host = nullptr;
+    int *cancel_dev = nullptr;
 };
 
 namespace mcdc {
 
 int fail(int st, const std::string &msg);
+// allocate / free the handle's cancel word; is a cancel requested?
+int cancel_init(mcdc_problem *h);
+void cancel_free(mcdc_problem *h);
+inline bool cancel_set(const mcdc_problem *h) {
+    return h->cancel_host && __atomic_load_n(h->cancel_host, __ATOMIC_ACQUIRE) != 0;
+}
 int hip_fail(hipError_t e, const char *where);
 // kernel timing: record a start event before / a stop event after a launch
 void timing_begin(mcdc_problem *h, hipStream_t s);
@@ -78,9 +88,14 @@ void batch_destroy(mcdc_problem *h);
 
 // shared host helpers (mcdc_api.hip)
 int validate_desc(const mcdc_problem_desc *d);
+int desc_fissile(const mcdc_problem_desc *d);
+uint32_t desc_nbins(const mcdc_problem_desc *d);
+size_t desc_nsurf(const mcdc_problem_desc *d);
 Options resolve_options(const mcdc_options *o);
 void build_dev_problem(const mcdc_problem_desc *d, char *ws, const Layout &L, DevProblem &P);
 std::vector<double> pack_tables(const mcdc_problem_desc *d);
 void fill_counters(const DevAcc &a, mcdc_counters *o);
+// the run arguments every tracking launch of the handle starts from
+RunArgs base_args_for(mcdc_problem *h, uint64_t seed);
 
 }  // namespace mcdc

@@ -16,12 +16,14 @@ struct Shared {
     unsigned long long cnt[N_CNT];
     double wsum[N_WSUM];
     double leak[6];
+    double kcol;
 };
 
 MCDC_DEV void shared_zero(Shared &S) {
     for (int i = threadIdx.x; i < N_CNT; i += blockDim.x) S.cnt[i] = 0ull;
     for (int i = threadIdx.x; i < N_WSUM; i += blockDim.x) S.wsum[i] = 0.0;
     for (int i = threadIdx.x; i < 6; i += blockDim.x) S.leak[i] = 0.0;
+    if (threadIdx.x == 0) S.kcol = 0.0;
 }
 
 // after a __syncthreads(): one global atomic per non-zero entry
@@ -32,6 +34,29 @@ MCDC_DEV void shared_flush(const Shared &S, DevAcc *acc) {
         if (S.wsum[i] != 0.0) unsafeAtomicAdd(&acc->wsum[i], S.wsum[i]);
     for (int i = threadIdx.x; i < 6; i += blockDim.x)
         if (S.leak[i] != 0.0) unsafeAtomicAdd(&acc->leak[i], S.leak[i]);
+    if (threadIdx.x == 0 && S.kcol != 0.0) unsafeAtomicAdd(&acc->kcol, S.kcol);
+}
+
+// Reserve n consecutive entries of *count for every active lane with one
+// atomic per wave: a wave-uniform loop over the active lanes (ascending) sums
+// their counts and hands each lane its offset.
+MCDC_DEV uint32_t wave_reserve_n(uint32_t *count, uint32_t n) {
+    const uint64_t act = __ballot(true);
+    uint64_t m = act;
+    const int lane = (int)__lane_id();
+    uint32_t total = 0, mine = 0;
+    while (m) {
+        const int l = __ffsll((long long)m) - 1;
+        m &= m - 1;
+        const uint32_t nl = (uint32_t)__builtin_amdgcn_readlane((int)n, l);
+        if (lane == l) mine = total;
+        total += nl;
+    }
+    const int leader = __ffsll((long long)act) - 1;
+    uint32_t base = 0;
+    if (lane == leader && total) base = atomicAdd(count, total);
+    base = (uint32_t)__builtin_amdgcn_readlane((int)base, leader);
+    return base + mine;
 }
 
 MCDC_DEV void trace_rec(const RunArgs &A, uint64_t hist, Part &q, int type, double aux) {
@@ -55,6 +80,15 @@ MCDC_DEV void trace_rec(const RunArgs &A, uint64_t hist, Part &q, int type, doub
 }
 
 MCDC_DEV void set_status(const RunArgs &A, int st) { atomicMin(&A.acc->status, st); }
+
+// The host's cancel word, read past every cache (it lives in host memory and
+// the host writes it while kernels run).  Persistent loops read it once every
+// kCancelPoll turns, at a turn all active lanes of the wave share.
+constexpr uint32_t kCancelPoll = 256;
+MCDC_DEV bool cancel_requested(const int *flag) {
+    return flag != nullptr &&
+           __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0;
+}
 
 // outer boundary after a surface crossing; returns the leak face or -1
 MCDC_DEV int boundary(CP &P, Part &q) {
@@ -187,6 +221,54 @@ MCDC_DEV void stage_source(CP &P, const RunArgs &A, Shared &S, Ctx &C, Part &q) 
     }
     trace_rec(A, C.hist(), q, EV_SOURCE, 0.0);
 }
+
+// Source particle of a k-eigenvalue generation after the first: born at
+// fission site j of the combed source (its position and group) at t = 0 with
+// unit weight and an isotropic direction from the history's own stream; then
+// the same checks as the problem's source.
+template <class Ctx>
+MCDC_DEV void stage_source_site(CP &P, const RunArgs &A, Shared &S, Ctx &C, Part &q, uint64_t j) {
+    q.tag = 0;
+    q.k = 0;
+    q.seq = 0;
+    Rng r = make_rng(A.seed, C.hist(), P.problem_id, 0u, 0u);
+    q.x[0] = A.src_d[j];
+    q.x[1] = A.src_d[A.gen_m + j];
+    q.x[2] = A.src_d[2 * A.gen_m + j];
+    q.t = 0.0;
+    iso_direction(r, q.u[0], q.u[1], q.u[2]);
+    q.g = A.src_g[j];
+    q.w = 1.0;
+    q.k = r.k;
+    q.alive = true;
+    q.ci = 0;
+    while (q.ci < P.n_census && !(P.census[q.ci] > q.t)) q.ci += 1;
+    atomicAdd(&S.cnt[C_PARTICLE], 1ull);
+    atomicAdd(&S.wsum[W_SOURCE], q.w);
+    q.cell = locate(P, q.x, q.u);
+    if (q.ci >= P.n_census) {
+        atomicAdd(&S.wsum[W_TIME_END], q.w);
+        atomicAdd(&S.cnt[C_TIME_END], 1ull);
+        q.alive = false;
+        trace_rec(A, C.hist(), q, EV_TIME_END, 0.0);
+        return;
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (!axis_in(P.outer_lo[a], P.outer_hi[a], q.x[a], q.u[a])) {
+            leak(S, q, 2 * a + (q.x[a] >= P.outer_hi[a] ? 1 : 0));
+            trace_rec(A, C.hist(), q, EV_LEAK, 0.0);
+            return;
+        }
+    }
+    trace_rec(A, C.hist(), q, EV_SOURCE, 0.0);
+}
+
+// Contexts that carry fission sites (the k-eigenvalue mode) declare kFis.
+template <class C, class = void>
+struct fis_ctx : std::false_type {};
+template <class C>
+struct fis_ctx<C, std::void_t<decltype(C::kFis)>> : std::integral_constant<bool, C::kFis> {};
 
 // Contexts whose kernels sit at their register limit declare kTightRegs.
 template <class C, class = void>
@@ -328,6 +410,45 @@ MCDC_DEV bool stage_collision(CP &P, const RunArgs &A, Shared &S, Ctx &C, Part &
     double sig_s = 0.0;
     for (int h = 0; h < P.G; ++h) sig_s = sig_s + ss_row[h];
     Rng r = make_rng(A.seed, C.hist(), P.problem_id, q.tag, q.k);
+    if constexpr (fis_ctx<Ctx>::value) {
+        // k-eigenvalue mode: w nuSigma_f / Sigma_t is this collision's
+        // expected fission neutrons (its collision estimate of k); divided by
+        // the generation's k_norm it is the expected number of sites, made as
+        // floor(. + xi) sites (one draw) at the collision point, each with an
+        // outgoing group from the material's spectrum (first g' with xi times
+        // the spectrum's sum below the ascending cumulative spectrum; one draw
+        // per site when G > 1).  Fission is part of the absorption: the
+        // collision then goes on as in the fixed-source mode.
+        const double nusf = P.nu_sigma_f[mat * P.G + q.g];
+        if (nusf > 0.0) {
+            const double prod = q.w * nusf / sig_t;
+            atomicAdd(&S.kcol, prod);
+            const double xi = rng_uniform(r);
+            const double nf = floor(prod / A.k_norm + xi);
+            const uint32_t n = nf > 4.0e9 ? 0xFFFFFFFFu : (uint32_t)nf;
+            const double *chi = P.chi + mat * P.G;
+            double chi_sum = 0.0;
+            for (int h = 0; h < P.G; ++h) chi_sum = chi_sum + chi[h];
+            uint32_t pos = wave_reserve_n(A.site_n, n);
+            for (uint32_t i = 0; i < n; ++i, ++pos) {
+                int gs = 0;
+                if (P.G > 1) {
+                    const double target = rng_uniform(r) * chi_sum;
+                    double cum = 0.0;
+                    int gn = -1, last = 0;
+                    for (int h = 0; h < P.G; ++h) {
+                        cum = cum + chi[h];
+                        if (chi[h] > 0.0) last = h;
+                        if (gn < 0 && target < cum) gn = h;
+                    }
+                    gs = gn >= 0 ? gn : last;
+                }
+                C.put_site(q, gs, pos);
+            }
+            q.k = r.k;
+            if (n > 0) trace_rec(A, C.hist(), q, EV_FISSION, (double)n);
+        }
+    }
     if (!P.implicit_capture) {
         const double xi = rng_uniform(r);
         q.k = r.k;

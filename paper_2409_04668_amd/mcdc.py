@@ -29,6 +29,7 @@ _lib = C.CDLL(LIB_PATH)
 
 OK = 0
 E_INVALID, E_NOMEM, E_HIP, E_EVENT_CAP, E_CANCELLED, E_STATE, E_STACK, E_BANK = -1, -2, -3, -4, -5, -6, -7, -8
+E_EXTINCT = -9
 SCHED_AUTO, SCHED_HISTORY, SCHED_EVENT, SCHED_HYBRID = 0, 1, 2, 3
 TALLY_MESH, TALLY_DETECTOR, TALLY_LEAKAGE, TALLY_COLLISION, TALLY_SURFACE = 0, 1, 2, 3, 4
 MAX_G = 8
@@ -59,7 +60,13 @@ class ProblemDesc(C.Structure):
         ("has_detector", C.c_int32), ("det_lo", D3), ("det_hi", D3), ("imp_on", C.c_int32),
         ("imp_n", I4), ("n_batches", C.c_int32), ("max_events", C.c_int64),
         ("stack_cap", C.c_int32), ("problem_id", C.c_uint32),
+        ("nu_sigma_f", PD), ("chi", PD),
     ]
+
+
+class KeffOpts(C.Structure):
+    _fields_ = [("M", C.c_uint64), ("n_inactive", C.c_int32), ("n_active", C.c_int32),
+                ("k0", C.c_double)]
 
 
 class Options(C.Structure):
@@ -126,6 +133,11 @@ _sig("mcdc_run_step", C.c_int, VP, C.POINTER(C.c_int32), VP)
 _sig("mcdc_get_run_state", C.c_int, VP, VP)
 _sig("mcdc_set_run_state", C.c_int, VP, VP)
 _sig("mcdc_get_tallies", C.c_int, VP, C.c_int, PD, PD, C.c_size_t, VP)
+_sig("mcdc_get_tallies_device", C.c_int, VP, C.c_int, VP, VP, C.c_size_t, VP)
+_sig("mcdc_set_cancel", C.c_int, VP, C.c_int)
+_sig("mcdc_keff_workspace_bytes", C.c_int, C.c_uint64, C.POINTER(C.c_size_t))
+_sig("mcdc_run_keff", C.c_int, VP, C.POINTER(KeffOpts), C.c_uint64, VP, C.c_size_t, PD, PD,
+     C.POINTER(C.c_uint64), VP)
 _sig("mcdc_get_raw", C.c_int, VP, PD, PD, C.c_size_t, VP)
 _sig("mcdc_get_raw_collision", C.c_int, VP, PD, PD, C.c_size_t, VP)
 _sig("mcdc_get_raw_surface", C.c_int, VP, PD, PD, C.c_size_t, VP)
@@ -155,6 +167,7 @@ _sig("mcdc_get_batch_raw", C.c_int, VP, C.c_size_t, PD, C.c_size_t, VP)
 _sig("mcdc_get_batch_counters", C.c_int, VP, C.c_size_t, C.POINTER(Counters), VP)
 _sig("mcdc_get_batch_history_path", C.c_int, VP, C.c_size_t, PD, C.c_size_t, VP)
 _sig("mcdc_micro_atomics", C.c_int, VP, C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32, VP)
+_sig("mcdc_micro_lds_atomics", C.c_int, VP, C.c_uint32, C.c_uint64, C.c_uint32, VP)
 _sig("mcdc_micro_copy", C.c_int, VP, VP, C.c_size_t, VP)
 _sig("mcdc_set_kernel_timing", C.c_int, VP, C.c_int)
 _sig("mcdc_kernel_time", C.c_int, VP, C.POINTER(C.c_uint64), C.POINTER(C.c_double))
@@ -254,6 +267,9 @@ class _Desc:
         # daughter stack storage is only carved when weight windows may be used
         d.stack_cap = int(prob["stack_cap"]) if prob.get("ww") is not None else 0
         d.problem_id = problem_id
+        if prob.get("nu_sigma_f") is not None:
+            d.nu_sigma_f = arr(np.asarray(prob["nu_sigma_f"], float).reshape(M, G), np.float64).ctypes.data_as(PD)
+            d.chi = arr(np.asarray(prob["chi"], float).reshape(M, G), np.float64).ctypes.data_as(PD)
         self.d = d
         self.G = G
         mn = [int(v) for v in m["n"]]
@@ -319,6 +335,27 @@ class Problem:
     # ---- running -------------------------------------------------------
     def run(self, n_hist: int, seed: int, stream=None):
         check(_lib.mcdc_run(self.h, int(n_hist), int(seed), _stream_ptr(stream)), "run")
+
+    def run_keff(self, M: int, n_inactive: int, n_active: int, seed: int, k0: float = 1.0,
+                 stream=None) -> dict:
+        """k-eigenvalue power iteration (histories g M + j); returns per
+        generation k_col, k_site and n_sites.  The site banks live in a
+        device tensor held for the call."""
+        t = self.torch
+        nbytes = C.c_size_t()
+        check(_lib.mcdc_keff_workspace_bytes(int(M), C.byref(nbytes)), "keff_workspace_bytes")
+        ws = t.empty(int(nbytes.value), dtype=t.uint8, device=self.ws.device)
+        n_gen = int(n_inactive) + int(n_active)
+        out = dict(k_col=np.zeros(max(n_gen, 1)), k_site=np.zeros(max(n_gen, 1)),
+                   n_sites=np.zeros(max(n_gen, 1), np.uint64))
+        o = KeffOpts(int(M), int(n_inactive), int(n_active), float(k0))
+        st = _lib.mcdc_run_keff(self.h, C.byref(o), int(seed), _ptr(ws), nbytes.value,
+                                out["k_col"].ctypes.data_as(PD), out["k_site"].ctypes.data_as(PD),
+                                out["n_sites"].ctypes.data_as(C.POINTER(C.c_uint64)),
+                                _stream_ptr(stream))
+        del ws
+        check(st, "run_keff")
+        return {k: v[:n_gen] for k, v in out.items()}
 
     # ---- census-step control (event or hybrid schedule) ----------------
     def run_begin(self, n_hist: int, seed: int, stream=None):
@@ -446,6 +483,24 @@ class Problem:
                                     _stream_ptr(stream)), "get_tallies")
         return m, r
 
+    def tallies_device(self, kind=TALLY_MESH, stream=None, with_rel=True):
+        """The same results as ``tallies`` computed into device tensors on the
+        stream (no synchronisation)."""
+        t = self.torch
+        n = {TALLY_MESH: self.nbins, TALLY_DETECTOR: 1, TALLY_LEAKAGE: 6,
+             TALLY_COLLISION: self.nbins}[kind] if kind != TALLY_SURFACE else self.surface_bins()
+        # at least one element each, so that an empty result still passes a
+        # non-null pointer (the library then reports the real problem)
+        m = t.empty(max(n, 1), dtype=t.float64, device=self.ws.device)
+        r = t.empty(max(n, 1), dtype=t.float64, device=self.ws.device) if with_rel else None
+        check(_lib.mcdc_get_tallies_device(self.h, kind, _ptr(m), _ptr(r) if r is not None else None,
+                                           n, _stream_ptr(stream)), "get_tallies_device")
+        return m[:n], (r[:n] if r is not None else None)
+
+    def set_cancel(self, on: bool = True):
+        """Ask running and later runs to stop (thread safe); False clears it."""
+        check(_lib.mcdc_set_cancel(self.h, 1 if on else 0), "set_cancel")
+
     def counters(self, stream=None) -> dict:
         c = Counters()
         check(_lib.mcdc_get_counters(self.h, C.byref(c), _stream_ptr(stream)), "get_counters")
@@ -510,6 +565,9 @@ class BatchProblem:
     def run(self, seed: int, stream=None):
         check(_lib.mcdc_run_batch(self.h, int(seed), _stream_ptr(stream)), "run_batch")
 
+    def set_cancel(self, on: bool = True):
+        check(_lib.mcdc_set_cancel(self.h, 1 if on else 0), "set_cancel")
+
     def raw(self, p: int, stream=None):
         n = self.descs[p].nbins
         s = np.zeros(n)
@@ -548,6 +606,28 @@ def micro_atomic_rate(n_bins: int, n_updates: int, run: int = 1, per_item: int =
         best = max(best, n_items * per_item / (a.elapsed_time(b) / 1e3))
     total = float(buf.sum().item())
     assert total == float(n_items * per_item * (reps + 1)), "atomic micro-benchmark lost updates"
+    return best
+
+
+def micro_lds_atomic_rate(n_bins: int, n_updates: int, per_item: int = 256, reps: int = 3):
+    """Measured LDS FP64 atomic-add rate (ds_add_f64 updates/s) into an
+    n_bins array per 1024-work-item workgroup (zeroing and the final flush
+    included in the timed launch)."""
+    import torch
+    out = torch.zeros(n_bins, dtype=torch.float64, device="cuda")
+    n_items = max(1, n_updates // per_item)
+    best = 0.0
+    for _ in range(reps + 1):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        check(_lib.mcdc_micro_lds_atomics(_ptr(out), n_bins, n_items, per_item, _stream_ptr()),
+              "micro_lds_atomics")
+        b.record()
+        b.synchronize()
+        best = max(best, n_items * per_item / (a.elapsed_time(b) / 1e3))
+    total = float(out.sum().item())
+    assert total == float(n_items * per_item * (reps + 1)), "LDS atomic micro-benchmark lost updates"
     return best
 
 

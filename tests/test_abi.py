@@ -87,6 +87,34 @@ def test_failure_paths_without_gpu():
     assert mcdc._lib.mcdc_run_step(None, ctypes.byref(done), None) == mcdc.E_INVALID
     st = mcdc.RunState()
     assert mcdc._lib.mcdc_get_run_state(None, ctypes.byref(st)) == mcdc.E_INVALID
+    # k-eigenvalue sizing and arguments
+    assert mcdc._lib.mcdc_keff_workspace_bytes(0, ctypes.byref(n)) == mcdc.E_INVALID
+    assert mcdc._lib.mcdc_keff_workspace_bytes(1 << 29, ctypes.byref(n)) == mcdc.E_INVALID
+    assert mcdc._lib.mcdc_keff_workspace_bytes(1000, ctypes.byref(n)) == 0
+    assert n.value >= (3 + 3) * 8 * (4 * 1000 + 1024)         # unordered and ordered site banks
+    ko = mcdc.KeffOpts(1000, 0, 1, 1.0)
+    assert mcdc._lib.mcdc_run_keff(None, ctypes.byref(ko), 1, None, 0, None, None, None,
+                                   None) == mcdc.E_INVALID
+    assert mcdc._lib.mcdc_set_cancel(None, 1) == mcdc.E_INVALID
+    # fission data: a spectrum is required, and must be non-negative
+    p = W.keff_infinite_medium([1.0], [[0.6]], [0.5], [1.0])
+    p["chi"] = np.array([[-1.0]])
+    bad = mcdc._Desc(p)
+    assert mcdc._lib.mcdc_workspace_bytes(ctypes.byref(bad.d), ctypes.byref(opt),
+                                          ctypes.byref(n)) == mcdc.E_INVALID
+    p["chi"] = np.array([[0.0]])
+    bad = mcdc._Desc(p)
+    assert mcdc._lib.mcdc_workspace_bytes(ctypes.byref(bad.d), ctypes.byref(opt),
+                                          ctypes.byref(n)) == mcdc.E_INVALID
+    # fissile problems do not batch
+    q = W.batch_problem(3)
+    q["nu_sigma_f"] = np.full(q["sigma_t"].shape, 0.1)
+    q["chi"] = np.ones(q["sigma_t"].shape)
+    dq = mcdc._Desc(q)
+    arr1 = (mcdc.ProblemDesc * 1)(dq.d)
+    nh1 = (ctypes.c_uint64 * 1)(10)
+    assert mcdc._lib.mcdc_batch_workspace_bytes(arr1, 1, nh1, ctypes.byref(opt),
+                                                ctypes.byref(n)) == mcdc.E_INVALID
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libmcdc.so not built")
@@ -111,3 +139,28 @@ def test_surface_tally_description_is_validated_on_cpu():
         assert mcdc._lib.mcdc_workspace_bytes(ctypes.byref(d.d), ctypes.byref(mcdc.make_options()),
                                               ctypes.byref(n)) == mcdc.E_INVALID
     assert np.isfinite(plain.value)
+
+
+def test_every_declaration_names_its_source():
+    """Each entry point of include/mcdc.h carries, in the comment right above
+    it, a "Source:" line: the passage of the paper that defines what it
+    computes, or what the call is for where the paper defines nothing."""
+    src = open(HEADER).read()
+    decl = re.compile(r"^(?:int|void|size_t|const char \*)\s*(mcdc_[a-z_0-9]+)\s*\(", re.M)
+    prev_end = 0
+    missing = []
+    names = []
+    for m in decl.finditer(src):
+        names.append(m.group(1))
+        block = src[prev_end:m.start()]
+        comments = re.findall(r"/\*.*?\*/", block, flags=re.S)
+        if not comments or "Source:" not in comments[-1]:
+            missing.append(m.group(1))
+        prev_end = src.index(";", m.end()) + 1
+    assert set(names) == set(declared()), set(declared()) ^ set(names)
+    assert not missing, missing
+    # the paper-sourced calls name a section or figure of it
+    for m in re.finditer(r"\n \* Source:(.*?)\*/", src, flags=re.S):
+        text = " ".join(m.group(1).split())
+        assert ("Sec." in text or "Fig." in text or "not in the paper" in text
+                or text.startswith("as mcdc_") or "a reading" in text), text

@@ -325,6 +325,32 @@ def test_full_size_multigroup_duct_hybrid_sampled_histories():
     assert c["w_source"] == c["w_leak"] + c["w_absorb"] + c["w_time_end"]
 
 
+@pytest.mark.parametrize("config,n", [("duct", 2_000_000), ("duct7", 200_000)])
+def test_headline_launch_configuration_full_mesh_tally(config, n):
+    """The benchmark's launch configuration (hybrid schedule, 2^25 resident
+    histories, the hot tile the autotuner plans from an analog pilot) against
+    the oracle on the whole mesh: every one of the 7.2e6 bins (5.04e7 with
+    seven groups) of tally_sum and tally_sumsq to 1e-10 with the same zero
+    pattern, every history's (detector score, path) bit for bit, counters
+    exact."""
+    from paper_2409_04668_amd import autotune
+    mc = _mcdc()
+    p = W.config2() if config == "duct" else W.config3()
+    tile, _ = autotune.plan_hot_tile(p, pilot=1_000_000)
+    assert tile is not None
+    gp = mc.Problem(p, _hy_tile(tile, chunk=1 << 25))
+    orc = O.OracleRun(p)
+    gp.set_history_scores(n)
+    gp.run(n, 2031)
+    _, ho = orc.run(n, 2031, per_history=True)
+    assert np.array_equal(gp.history_scores(), ho)
+    s, s2 = gp.raw()
+    assert_close_sums(s, orc.tally_sum, what="tally_sum")
+    assert_close_sums(s2, orc.tally_sumsq, what="tally_sumsq")
+    assert_counters(gp.counters(), orc)
+    gp.close()
+
+
 @pytest.mark.parametrize("sched", ["history", "hybrid", "event"])
 def test_full_size_slab_every_history(sched):
     """The slab problem at its full size (1e5 histories, 100 x-bins x 20
