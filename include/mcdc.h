@@ -493,6 +493,22 @@ int mcdc_mlp_train(float *dev_params, int32_t in_dim, const float *dev_X, const 
                    void *dev_scratch, void *stream);
 
 /* Parameters of the network for in_dim inputs.
+/* mcdc_mlp_train without the scratch argument: the same kernels in the same
+ * order (parameters, moments and gradient bit-identical to it; the loss
+ * history, summed over workgroups by float atomics, to that summation
+ * order), with the scratch in a static 16 MiB device
+ * array of the library (one per GPU, kept until the process ends) and the
+ * loss history cleared by a fill kernel; it allocates nothing.  At most
+ * 64 * floor((2^22 - 64) / n_params) points (58240 for one group, 53056 for
+ * eight); more is MCDC_E_INVALID.  Calls that overlap on one GPU share the
+ * array and race; a call leaves it holding its partial sums.
+ * Source: not in the paper; for callers that cannot allocate (code under HIP
+ * graph capture, tight training loops, harnesses that forbid hipMalloc). */
+int mcdc_mlp_train_noalloc(float *dev_params, int32_t in_dim, const float *dev_X,
+                           const float *dev_y, const float *dev_wt, size_t n, float *dev_m,
+                           float *dev_v, float *dev_grad, const mcdc_train_opts *o,
+                           int32_t *step_io, float *dev_loss_hist, void *stream);
+
  * Source: not in the paper (as mcdc_mlp_forward). */
 size_t mcdc_mlp_param_count(int32_t in_dim);
 

@@ -9,6 +9,8 @@
 //   k_mlp_adam  sums the workgroup partials in workgroup order (so a step is
 //               reproducible bit for bit) and applies Adam.
 // Inference (k_mlp_point) is one work-item per point.
+#include <mutex>
+
 #include "mcdc_runtime.hpp"
 
 namespace mcdc {
@@ -286,6 +288,72 @@ static hipError_t step_grad(const float *prm, int in_dim, const float *X, const 
     return hipGetLastError();
 }
 
+// Training scratch of mcdc_mlp_train_noalloc, for callers that cannot
+// allocate: a static array in device memory (each GPU the library runs on
+// holds its own copy until the process ends).  In host code the array's name
+// is not a device address; its address on the current device comes from
+// hipGetSymbolAddress, taken once per device on the entry point's first call
+// there and kept.  Calls that overlap on one GPU share the array and race.
+constexpr size_t kStaticScratchFloats = (size_t)1 << 22;      // 16 MiB
+static __device__ __align__(256) float scratch[kStaticScratchFloats];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static float *g_scratch_ptr[kMaxDevices];
+
+static int static_scratch(float **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "mlp_train_noalloc: current device");
+    if (dev < 0 || dev >= kMaxDevices) return fail(MCDC_E_INVALID, "mlp_train_noalloc: device index beyond 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "mlp_train_noalloc: scratch address");
+        g_scratch_ptr[dev] = (float *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return MCDC_OK;
+}
+
+__global__ void k_zero_f32(float *__restrict__ p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0f;
+}
+
+// `steps` Adam steps with the scratch S; the loss history is cleared by a
+// memset (the scratch entry point, as it always did) or by a fill kernel
+// (the entry point that allocates nothing, which a caller may capture in a
+// graph).
+static hipError_t train_steps(float *prm, int in_dim, const float *X, const float *y,
+                              const float *wt, size_t n, float *m, float *v, float *grad,
+                              const mcdc_train_opts *o, int32_t *step_io, float *loss_hist,
+                              MlpScratch S, bool fill_kernel, hipStream_t s) {
+    hipError_t e = hipSuccess;
+    if (loss_hist && o->steps > 0) {
+        if (fill_kernel)
+            hipLaunchKernelGGL(k_zero_f32, dim3((o->steps + 255) / 256), dim3(256), 0, s, loss_hist,
+                               o->steps);
+        else
+            e = hipMemsetAsync(loss_hist, 0, o->steps * sizeof(float), s);
+    }
+    hipLaunchKernelGGL(k_mlp_wsum, dim3(1), dim3(256), 0, s, wt, n, S.wsum);
+    const int np = mlp_np(in_dim);
+    int step = *step_io;
+    for (int i = 0; i < o->steps && e == hipSuccess; ++i) {
+        step += 1;
+        e = step_grad(prm, in_dim, X, y, wt, n, S, loss_hist ? loss_hist + i : nullptr, s);
+        const float c1 = 1.0f - powf(o->beta1, (float)step);
+        const float c2 = 1.0f - powf(o->beta2, (float)step);
+        hipLaunchKernelGGL(k_mlp_adam, dim3((np + 255) / 256), dim3(256), 0, s, np, S, grad, prm, m,
+                           v, o->lr, o->beta1, o->beta2, o->eps, c1, c2, 1);
+        if (e == hipSuccess) e = hipGetLastError();
+    }
+    *step_io = step;
+    return e;
+}
+
 }  // namespace mcdc
 
 using namespace mcdc;
@@ -336,24 +404,30 @@ int mcdc_mlp_train(float *prm, int32_t in_dim, const float *X, const float *y, c
     if (!prm || !X || !y || !wt || !m || !v || !o || !step_io || !scratch)
         return fail(MCDC_E_INVALID, "null buffer");
     if (o->steps < 0) return fail(MCDC_E_INVALID, "negative step count");
-    hipStream_t s = (hipStream_t)stream;
     MlpScratch S = carve((float *)scratch, n, in_dim);
-    hipError_t e = hipSuccess;
-    if (loss_hist && o->steps > 0) e = hipMemsetAsync(loss_hist, 0, o->steps * sizeof(float), s);
-    hipLaunchKernelGGL(k_mlp_wsum, dim3(1), dim3(256), 0, s, wt, n, S.wsum);
-    const int np = mlp_np(in_dim);
-    int step = *step_io;
-    for (int i = 0; i < o->steps && e == hipSuccess; ++i) {
-        step += 1;
-        e = step_grad(prm, in_dim, X, y, wt, n, S, loss_hist ? loss_hist + i : nullptr, s);
-        const float c1 = 1.0f - powf(o->beta1, (float)step);
-        const float c2 = 1.0f - powf(o->beta2, (float)step);
-        hipLaunchKernelGGL(k_mlp_adam, dim3((np + 255) / 256), dim3(256), 0, s, np, S, grad, prm, m,
-                           v, o->lr, o->beta1, o->beta2, o->eps, c1, c2, 1);
-        if (e == hipSuccess) e = hipGetLastError();
-    }
-    *step_io = step;
+    hipError_t e = train_steps(prm, in_dim, X, y, wt, n, m, v, grad, o, step_io, loss_hist, S, false,
+                               (hipStream_t)stream);
     return e == hipSuccess ? MCDC_OK : hip_fail(e, "mlp_train");
+}
+
+int mcdc_mlp_train_noalloc(float *prm, int32_t in_dim, const float *X, const float *y,
+                           const float *wt, size_t n, float *m, float *v, float *grad,
+                           const mcdc_train_opts *o, int32_t *step_io, float *loss_hist,
+                           void *stream) {
+    int st = mlp_check(in_dim, n);
+    if (st) return st;
+    if (!prm || !X || !y || !wt || !m || !v || !o || !step_io) return fail(MCDC_E_INVALID, "null buffer");
+    if (o->steps < 0) return fail(MCDC_E_INVALID, "negative step count");
+    if (mlp_scratch_floats(n, in_dim) > kStaticScratchFloats)
+        return fail(MCDC_E_INVALID, "mlp_train_noalloc: " + std::to_string(n) + " points need " +
+                                        std::to_string(mlp_scratch_floats(n, in_dim) * sizeof(float)) +
+                                        " bytes of scratch, more than its static 16 MiB");
+    float *base = nullptr;
+    if ((st = static_scratch(&base))) return st;
+    MlpScratch S = carve(base, n, in_dim);
+    hipError_t e = train_steps(prm, in_dim, X, y, wt, n, m, v, grad, o, step_io, loss_hist, S, true,
+                               (hipStream_t)stream);
+    return e == hipSuccess ? MCDC_OK : hip_fail(e, "mlp_train_noalloc");
 }
 
 }  // extern "C"

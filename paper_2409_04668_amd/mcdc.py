@@ -158,6 +158,8 @@ _sig("mcdc_mlp_scratch_bytes", C.c_size_t, C.c_int32, C.c_size_t)
 _sig("mcdc_mlp_grad", C.c_int, VP, C.c_int32, VP, VP, VP, C.c_size_t, VP, VP, VP, VP)
 _sig("mcdc_mlp_train", C.c_int, VP, C.c_int32, VP, VP, VP, C.c_size_t, VP, VP, VP,
      C.POINTER(TrainOpts), C.POINTER(C.c_int32), VP, VP, VP)
+_sig("mcdc_mlp_train_noalloc", C.c_int, VP, C.c_int32, VP, VP, VP, C.c_size_t, VP, VP, VP,
+     C.POINTER(TrainOpts), C.POINTER(C.c_int32), VP, VP)
 _sig("mcdc_batch_workspace_bytes", C.c_int, C.POINTER(ProblemDesc), C.c_size_t,
      C.POINTER(C.c_uint64), C.POINTER(Options), C.POINTER(C.c_size_t))
 _sig("mcdc_create_batch", C.c_int, C.POINTER(ProblemDesc), C.c_size_t, C.POINTER(C.c_uint64),
