@@ -2,14 +2,23 @@
 3D duct problem (60x100x60 cm box, bent 10x10 cm void duct, 1 cm mesh x 20
 time bins = 7.2e6 FP64 bins, 1e8 histories per step) on one MI355X.
 
-One step = one mcdc_run of 1e8 source histories: 20 batches, each one launch
-of the tracking kernel plus one batch close-out launch, with all inputs
-resident in HBM.  Prints one JSON line with the roofline of the tracking
-kernel (algorithmic bytes = 16 B per FP64 atomic tally update, i.e. per scored
-piece, against the 8 TB/s HBM peak), the figure of merit 1/(R^2 T) at 1%
-detector relative error of the analog run against the learned weight windows
-(block "fom", measured after the timed steps), and the CPU oracle timed on a
-bounded sample of the same workload on this host.
+One step = one mcdc_run of 1e8 source histories (20 batches) under the
+schedule the autotuner picks, with all inputs resident in HBM.  Prints one
+JSON line with:
+  * the roofline of the tracking kernel.  Its binding limit is VALU issue
+    under divergence, so the headline is the ALU roofline: useful VALU
+    lane-instructions per launch (SQ counters of the committed profile) over
+    the launch time measured here, against 256 CUs x 4 SIMDs x 16 lanes x
+    2.4 GHz.  Beside it the memory views: HBM bytes (16 B per FP64 atomic
+    update that reaches HBM, the HBM share of the updates taken from the
+    committed PMC write requests) against 8 TB/s and the measured copy rate,
+    HBM atomics against the measured random-atomic ceiling, LDS ds_add_f64
+    updates against the measured LDS ceiling;
+  * the figure of merit 1/(R^2 T) at 1% detector relative error of the
+    analog run against the learned weight windows (window map, and the
+    network evaluated at every check), measured after the timed steps;
+  * the 256-problem batched workload's rate;
+  * the CPU oracle timed on a bounded sample of the same workload.
 
     python bench.py [--gpus 1] [--steps 5] [--warmup 1]
 """
@@ -22,11 +31,17 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_PIECE = 16.0          # FP64 atomic read-modify-write: 8 B read + 8 B written
+# VALU issue peak: 256 CUs x 4 SIMDs, each retiring a wave64 instruction every
+# 4 cycles (16 lanes per cycle), at 2.4 GHz
+VALU_LANE_PEAK = 256 * 4 * 16 * 2.4e9
+ATOMIC_REQUEST_BYTES = 32.0     # one device-scope FP64 atomic = one 32-byte write request
 KERNEL_SOURCES = ["transport_device.hpp", "transport_stages.hpp", "lane_stack.hpp",
                   "mcdc_internal.hpp", "mcdc_history.hip", "mcdc_event.hip"]
 SCHED_NAMES = {1: "history", 2: "event", 3: "hybrid"}
@@ -91,9 +106,64 @@ def measured_valu(kernel: str):
         return {"simd_valu_busy_fraction": float(vals["simd_valu_busy_fraction"]),
                 "active_lanes_per_valu_instruction": float(vals["active_lanes_per_valu_instruction"].split()[0]),
                 "lane_throughput_fraction": float(vals["lane_throughput_fraction"]),
+                "lane_instructions_per_launch": float(vals["SQ_THREAD_CYCLES_VALU"]),
+                "histories_per_launch": float(vals.get("histories_per_launch", "nan")),
                 "source": os.path.relpath(path, ROOT)}
     except (KeyError, ValueError):
         return None
+
+
+def roofline(kernel, launches, avg_launch_s, hist_per_launch, pieces_per_launch, traffic,
+             ceil_rand, ceil_run8, ceil_lds, copy_bw):
+    """The tracking kernel's roofline object.  Every rate divides per-launch
+    work by the mean launch time measured in this run (HIP events on the
+    launch stream).  Work per launch: VALU lane-instructions from the
+    committed SQ summary (scaled to this run's histories per launch); scored
+    pieces from the run's own counters, split into HBM updates (PMC write
+    requests of the committed summary, 32 B each, which also count the tile
+    flushes: an upper bound) and LDS updates (the rest)."""
+    out = {"kernel": kernel, "launches": launches, "avg_launch_ms": 1e3 * avg_launch_s,
+           "histories_per_launch": hist_per_launch, "traffic": traffic}
+    # memory side
+    if traffic is not None:
+        hbm_updates = min(traffic / ATOMIC_REQUEST_BYTES, pieces_per_launch)
+        share = "measured (PMC WRITE_SIZE / 32 B)"
+    else:
+        hbm_updates = pieces_per_launch
+        share = "unknown (no current PMC summary): every piece counted as an HBM update"
+    lds_updates = pieces_per_launch - hbm_updates
+    hbm_bytes = BYTES_PER_PIECE * hbm_updates
+    hbm_gbps = hbm_bytes / avg_launch_s / 1e9
+    hbm_rate = hbm_updates / avg_launch_s
+    lds_rate = lds_updates / avg_launch_s
+    out["hbm"] = {"algorithmic_bytes_per_launch": hbm_bytes, "achieved_GBps": hbm_gbps,
+                  "peak_GBps": HBM_PEAK_GBS, "frac_of_peak": hbm_gbps / HBM_PEAK_GBS,
+                  "measured_copy_GBps": copy_bw / 1e9,
+                  "frac_of_measured": hbm_gbps / (copy_bw / 1e9) if copy_bw else None}
+    out["atomics"] = {"pieces_per_launch": pieces_per_launch,
+                      "hbm_updates_per_launch": hbm_updates, "lds_updates_per_launch": lds_updates,
+                      "hbm_share": share,
+                      "hbm_updates_per_s": hbm_rate,
+                      "hbm_frac_of_random_ceiling": hbm_rate / ceil_rand if ceil_rand else None,
+                      "hbm_frac_of_runs8_ceiling": hbm_rate / ceil_run8 if ceil_run8 else None,
+                      "lds_updates_per_s": lds_rate,
+                      "lds_frac_of_ceiling": lds_rate / ceil_lds if ceil_lds else None}
+    mem = [f for f in (out["hbm"]["frac_of_measured"], out["atomics"]["hbm_frac_of_random_ceiling"])
+           if f is not None]
+    out["memory_frac"] = max(mem) if mem else None     # max(HBM, atomic) against measured ceilings
+    # ALU side: the binding limit
+    valu = measured_valu(kernel)
+    out["valu_issue"] = valu
+    if valu is not None and valu["histories_per_launch"] > 0:
+        lanes = valu["lane_instructions_per_launch"] * hist_per_launch / valu["histories_per_launch"]
+        ach = lanes / avg_launch_s
+        out.update(bound="alu", achieved=ach / 1e12, peak=VALU_LANE_PEAK / 1e12,
+                   unit="T VALU lane-instructions/s", frac=ach / VALU_LANE_PEAK,
+                   lane_instructions_per_launch=lanes)
+    else:
+        out.update(bound="hbm", achieved=hbm_gbps, peak=HBM_PEAK_GBS, unit="GB/s",
+                   frac=hbm_gbps / HBM_PEAK_GBS)
+    return out
 
 
 def cpu_baseline(prob, n_sample, seed):
@@ -199,10 +269,22 @@ def main():
     n_done = args.steps * N
     pieces = c1["pieces"] - c0["pieces"]
     avg_launch_s = kms / 1e3 / max(launches, 1)
-    bytes_per_launch = BYTES_PER_PIECE * pieces / max(launches, 1)
-    achieved = bytes_per_launch / avg_launch_s / 1e9
-    traffic = measured_traffic(kernel, n_done / max(launches, 1))
+    hist_per_launch = n_done / max(launches, 1)
+    pieces_per_launch = pieces / max(launches, 1)
+    traffic = measured_traffic(kernel, hist_per_launch)
     det_mean, det_rel = gp.tallies(mcdc.TALLY_DETECTOR)
+    # measured ceilings: FP64 atomics scattered over an array of the tally's
+    # size (fully random, and in runs of 8 consecutive bins like the mesh
+    # walk), LDS ds_add_f64 into an array of the hot tile's size per
+    # workgroup, and a streaming copy
+    nb = W.n_bins(prob)
+    ceil_rand = mcdc.micro_atomic_rate(nb, int(pieces_per_launch), run=1)
+    ceil_run8 = mcdc.micro_atomic_rate(nb, int(pieces_per_launch), run=8)
+    tile_bins = int(np.prod(tile[1])) if tile is not None else 7680
+    ceil_lds = mcdc.micro_lds_atomic_rate(tile_bins, 2_000_000_000)
+    copy_bw = mcdc.micro_copy_rate()
+    roof = roofline(kernel, launches, avg_launch_s, hist_per_launch, pieces_per_launch, traffic,
+                    ceil_rand, ceil_run8, ceil_lds, copy_bw)
     out = {
         "metric": "histories/s (analog, FP64 tallies) on the 3D duct problem",
         "value": n_done / T,
@@ -225,31 +307,15 @@ def main():
                    "lds_hot_tile": None if tile is None else
                    {"lo_xyztg": [int(v) for v in tile[0]], "n_xyztg": [int(v) for v in tile[1]],
                     "pilot_track_length_fraction": tile_frac}},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": kernel, "launches": launches,
-                     "avg_launch_ms": 1e3 * avg_launch_s,
-                     "algorithmic_bytes_per_launch": bytes_per_launch,
-                     "atomic_updates_per_s": pieces / (kms / 1e3) if kms > 0 else None,
-                     "valu_issue": measured_valu(kernel)},
+        "roofline": roof,
         "pieces_per_history": pieces / n_done,
         "flights_per_history": (c1["flights"] - c0["flights"]) / n_done,
         "detector": {"mean": float(det_mean[0]), "rel_err": float(det_rel[0])},
     }
-    # measured ceilings: FP64 atomics scattered over an array of the tally's
-    # size (fully random, and in runs of 8 consecutive bins like the mesh
-    # walk), and a streaming copy
-    nb = W.n_bins(prob)
-    per_launch = int(pieces / max(launches, 1))
-    ceil_rand = mcdc.micro_atomic_rate(nb, per_launch, run=1)
-    ceil_run8 = mcdc.micro_atomic_rate(nb, per_launch, run=8)
-    copy_bw = mcdc.micro_copy_rate()
-    ach_atomics = pieces / (kms / 1e3) if kms > 0 else 0.0
     out["measured_ceilings"] = {
         "fp64_atomics_random_per_s": ceil_rand, "fp64_atomics_runs8_per_s": ceil_run8,
-        "copy_GBps": copy_bw / 1e9,
-        "atomic_frac_of_random_ceiling": ach_atomics / ceil_rand if ceil_rand else None,
-        "atomic_frac_of_runs8_ceiling": ach_atomics / ceil_run8 if ceil_run8 else None}
+        "lds_fp64_atomics_per_s": ceil_lds, "lds_ceiling_bins": tile_bins,
+        "copy_GBps": copy_bw / 1e9}
     # the paper's own rate, quoted as context only (other problem, other GPU):
     # 1e10 histories of its time-dependent duct benchmark in 1500 s on one V100
     out["paper_context"] = {"histories_per_s": 1e10 / 1500.0, "hardware": "1x NVIDIA V100 (Lassen)",
@@ -346,6 +412,8 @@ def main():
             "histories_per_s_with": rates["with_target_1"],
             "pc_kills_per_history": rates["pc_kills_per_history"],
             "pc_copies_per_history": rates["pc_copies_per_history"]}
+    if not args.no_other_schedule:
+        out["batched_256_problems"] = batch_rate(torch, mcdc, W, steps=3, warmup=1)
     if not args.no_fom:
         out["fom"] = fom_comparison(mcdc, W, oargs, tile)
     if not args.no_cpu_baseline:
@@ -353,33 +421,45 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def bench_batch(args, torch, mcdc, W):
+def batch_rate(torch, mcdc, W, steps, warmup):
     """256 batched problems (1e4-1e6 histories each, 10 census steps): one
-    pass = every problem's histories; histories/s over the whole batch."""
+    pass = every problem's histories, one persistent launch per census step,
+    graph-replayed; work-chunk size and occupancy from the autotuner (full
+    passes, setup).  Histories/s over the whole batch."""
     probs, n_hist = W.config5()
-    # work-chunk size and occupancy from the autotuner (full passes, setup)
     from paper_2409_04668_amd import autotune
     tuned = autotune.tune_batch(probs, n_hist, use_cache=False)
     bp = mcdc.BatchProblem(probs, n_hist, mcdc.make_options(**tuned["options"]))
     total = int(n_hist.sum())
-    for i in range(args.warmup):
+    for i in range(warmup):
         bp.run(7 + i)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(args.steps):
+    for i in range(steps):
         bp.run(1000 + i)
     torch.cuda.synchronize()
     T = time.perf_counter() - t0
     pieces = sum(bp.counters(p)["pieces"] for p in range(len(probs)))
+    bp.close()
+    return {"histories_per_s": total * steps / T, "ms_per_pass": 1e3 * T / steps,
+            "passes": steps, "histories_per_pass": total,
+            "workload": "256 box problems, 1-8 regions, 1-7 groups, 20^3 x 10 t-bins each",
+            "autotuned_options": tuned["options"], "autotune_trials": tuned["trials"],
+            "pieces_per_history": pieces / (total * (steps + warmup))}
+
+
+def bench_batch(args, torch, mcdc, W):
+    """The batched workload on its own (one JSON line)."""
+    r = batch_rate(torch, mcdc, W, args.steps, args.warmup)
     print(json.dumps({
         "metric": "histories/s, 256 batched problems (one persistent launch per census step, "
-                  "graph-replayed)", "value": total * args.steps / T, "unit": "histories/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * T / args.steps,
+                  "graph-replayed)", "value": r["histories_per_s"], "unit": "histories/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_pass"],
         "higher_is_better": True, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "256 box problems, 1-8 regions, 1-7 groups, 20^3 x 10 t-bins each",
-                   "histories_per_pass": total, "autotuned_options": tuned["options"],
-                   "autotune_trials": tuned["trials"]},
-        "pieces_per_history": pieces / (total * (args.steps + args.warmup))}), flush=True)
+        "config": {"workload": r["workload"], "histories_per_pass": r["histories_per_pass"],
+                   "autotuned_options": r["autotuned_options"],
+                   "autotune_trials": r["autotune_trials"]},
+        "pieces_per_history": r["pieces_per_history"]}), flush=True)
 
 
 WW_MAP_DIMS = (30, 50, 30, 20)      # 2 cm cells x 10 s: network baked per cell centre
@@ -406,24 +486,36 @@ def fom_comparison(mcdc, W, analog_options, tile, target=0.01):
     # short pilot; resident histories for the event schedule then follow the
     # run length (up to 2^23)
     from paper_2409_04668_amd import autotune
+    # the history schedule runs a history's whole split chain on one work-item
+    # (1e6-1e7 histories/s with windows): not a candidate
     choice = autotune.tune_single(pw, pilot=4_000_000, waves=(16,), event_chunks=(1 << 22,),
-                                  tile=tile, use_cache=False)
+                                  tile=tile, use_cache=False,
+                                  schedules=(mcdc.SCHED_EVENT, mcdc.SCHED_HYBRID))
     wopt = dict(choice["options"])
-    if wopt["schedule"] in (mcdc.SCHED_EVENT, mcdc.SCHED_HYBRID):
-        wopt["event_chunk"] = 1 << 25
+    wopt["event_chunk"] = 1 << 25
     analog = L.fom_at_target(p, seed=31, target=target, pilot=20_000_000,
                              options=mcdc.make_options(**analog_options))
     learned = L.fom_at_target(pw, seed=41, target=target, pilot=4_000_000,
                               options=mcdc.make_options(**wopt))
-    z = abs(analog["mean"] - learned["mean"]) / (
-        (analog["mean"] * analog["rel_err"]) ** 2 + (learned["mean"] * learned["rel_err"]) ** 2) ** 0.5
+    # the same network evaluated in the kernel at every window check (no map)
+    pn = W.config4(dict(ww, map=None))
+    net = L.fom_at_target(pn, seed=51, target=target, pilot=2_000_000,
+                          options=mcdc.make_options(**wopt))
+
+    def z(a, b):
+        return abs(a["mean"] - b["mean"]) / ((a["mean"] * a["rel_err"]) ** 2 +
+                                             (b["mean"] * b["rel_err"]) ** 2) ** 0.5
     return {"target_rel_err": target, "ratio": learned["fom"] / analog["fom"],
             "analog": dict(analog, schedule=SCHED_NAMES[analog_options["schedule"]],
                            options=analog_options),
             "learned_ww": dict(learned, window_map=list(WW_MAP_DIMS),
                                schedule=SCHED_NAMES[wopt["schedule"]], options=wopt,
                                autotune_trials=choice["trials"]),
-            "agreement_sigma": z, "training": dict(info, total_seconds=t_build),
+            "learned_ww_network_per_check": dict(net, schedule=SCHED_NAMES[wopt["schedule"]],
+                                                 ratio_to_analog=net["fom"] / analog["fom"]),
+            "agreement_sigma": z(analog, learned),
+            "agreement_sigma_network_per_check": z(analog, net),
+            "training": dict(info, total_seconds=t_build),
             "fom_with_training_amortised": 1.0 / (learned["rel_err"] ** 2 *
                                                   (learned["seconds"] + t_build))}
 

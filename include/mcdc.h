@@ -214,7 +214,8 @@ int mcdc_create_problem(const mcdc_problem_desc *d, const mcdc_options *opt, voi
  * calls; MCDC_E_CANCELLED is also returned here when the cancel word is set.
  * Source: Sec. "MC/DC on CPUs", transport-loop paragraph (loop over the
  * particles; transport each until a physical, simulation or variance-reduction
- * event ends its history); Fig. 2 (the move). */
+ * event ends its history); straight-line motion between events (the
+ * particle-state example of Fig. 2). */
 int mcdc_run(mcdc_handle h, uint64_t n_histories, uint64_t seed, void *stream);
 
 /* k-eigenvalue mode: power iteration on the fission source, n_inactive +
@@ -492,7 +493,6 @@ int mcdc_mlp_train(float *dev_params, int32_t in_dim, const float *dev_X, const 
                    const mcdc_train_opts *o, int32_t *step_io, float *dev_loss_hist,
                    void *dev_scratch, void *stream);
 
-/* Parameters of the network for in_dim inputs.
 /* mcdc_mlp_train without the scratch argument: the same kernels in the same
  * order (parameters, moments and gradient bit-identical to it; the loss
  * history, summed over workgroups by float atomics, to that summation
@@ -509,6 +509,7 @@ int mcdc_mlp_train_noalloc(float *dev_params, int32_t in_dim, const float *dev_X
                            float *dev_v, float *dev_grad, const mcdc_train_opts *o,
                            int32_t *step_io, float *dev_loss_hist, void *stream);
 
+/* Parameters of the network for in_dim inputs.
  * Source: not in the paper (as mcdc_mlp_forward). */
 size_t mcdc_mlp_param_count(int32_t in_dim);
 
@@ -571,10 +572,11 @@ int mcdc_micro_atomics(double *dev_buf, uint64_t n_bins, uint64_t n_items, uint3
                        uint32_t run, void *stream);
 
 /* Micro-benchmark: n_items work-items (1024 per workgroup) each add 1.0 to
- * per_item bins of their workgroup's LDS array of n_bins doubles (at most
- * MCDC_MAX_TILE_BINS, the hot tile's size), scattered by a hash
- * (ds_add_f64); each workgroup's array is then added once into
- * dev_out[n_bins] (device, caller-owned).  Asynchronous on `stream`.
+ * per_item bins of their workgroup's LDS array of n_bins doubles (2 ..
+ * MCDC_MAX_TILE_BINS, the hot tile's size) with ds_add_f64, starting at a
+ * hashed bin and walking with a per-lane odd stride modulo the largest power
+ * of two not above n_bins; each workgroup's total is then added to
+ * dev_out[0] (device, caller-owned).  Asynchronous on `stream`.
  * Source: Fig. 3 (atomic tally adds), here their on-chip ceiling. */
 int mcdc_micro_lds_atomics(double *dev_out, uint32_t n_bins, uint64_t n_items, uint32_t per_item,
                            void *stream);

@@ -14,8 +14,9 @@
  *    event (capture, time or space boundary), a simulation event (time census)
  *    or a variance-reduction event (implicit capture) ends it: Sec. "MC/DC on
  *    CPUs", transport-loop paragraph;
- *  - the move kernel (position += direction * distance, time += distance /
- *    speed): Fig. 2;
+ *  - straight-line motion between events: position advances by direction
+ *    times distance and time by distance over speed (the particle-state
+ *    example of Fig. 2);
  *  - tally accumulation by a plain add on the CPU, an atomic add on the GPU:
  *    Fig. 3;
  *  - hash-based (counter-based) random numbers for replicable testing: Sec.
@@ -869,7 +870,7 @@ static double o_dist_wwplane(const o_ctx *C, const double p[3], const double u[3
 /* One flight of particle q: the candidate distances (census, surface, the
  * next weight-window grid plane when windows and a grid are on, collision),
  * the event with the tie order census < surface < grid plane < collision,
- * track-length scoring of the flight, the move of Fig. 2, and the event. */
+ * track-length scoring of the flight, the straight-line motion, and the event. */
 static void o_flight(o_ctx *C, o_part *q)
 {
     const orc_problem *P = C->P;
@@ -926,10 +927,10 @@ static void o_flight(o_ctx *C, o_part *q)
                                                               q->u, iu, q->t, v, d, q->w, q->g,
                                                               R->surf_batch);
 
-    /* move (Fig. 2) */
-    q->p[0] = q->p[0] + q->u[0] * d;
-    q->p[1] = q->p[1] + q->u[1] * d;
-    q->p[2] = q->p[2] + q->u[2] * d;
+    /* straight-line motion over the flight: every coordinate advances by its
+     * direction cosine times the distance (the time advances below, by
+     * distance over speed, unless the flight ends at a census) */
+    for (int a = 0; a < 3; ++a) q->p[a] += q->u[a] * d;
 
     if (ev == ORC_EV_CENSUS) {
         q->t = tc;

@@ -79,16 +79,18 @@ def _time_single(prob, opt, n, seed) -> float:
 
 def tune_single(prob, pilot=2_000_000, waves=(8, 12, 16, 24, 32),
                 event_chunks=(1 << 20, 1 << 22, 1 << 23), tile=None, cache_path=DEFAULT_CACHE,
-                use_cache=True, seed=12345):
+                use_cache=True, seed=12345, schedules=None):
     """Returns {"options": dict for mcdc.make_options, "histories_per_s": ..., "trials": [...]}.
     Tries the history schedule at each occupancy and the event and hybrid
-    schedules at each chunk size.  `tile` = (lo[5], n[5]), e.g. from
-    plan_hot_tile: the LDS hot tile of the history schedule and of the hybrid
-    schedule's lead stage.  Population control runs only in the event and
-    hybrid schedules, with every batch of the pilot resident (chunks below the
-    batch size are skipped)."""
+    schedules at each chunk size (`schedules` restricts the set).  `tile` =
+    (lo[5], n[5]), e.g. from plan_hot_tile: the LDS hot tile of the history
+    schedule and of the hybrid schedule's lead stage.  Population control runs
+    only in the event and hybrid schedules, with every batch of the pilot
+    resident (chunks below the batch size are skipped)."""
     tj = None if tile is None else [[int(v) for v in tile[0]], [int(v) for v in tile[1]]]
-    key = "single:" + _device_name() + ":" + _hash_problem(prob) + f":{pilot}:{tj}"
+    allowed = set(schedules or (mcdc.SCHED_HISTORY, mcdc.SCHED_EVENT, mcdc.SCHED_HYBRID))
+    key = ("single:" + _device_name() + ":" + _hash_problem(prob) + f":{pilot}:{tj}:" +
+           ",".join(str(v) for v in sorted(allowed)))
     cache = _load(cache_path) if use_cache else {}
     if key in cache:
         return cache[key]
@@ -100,7 +102,7 @@ def tune_single(prob, pilot=2_000_000, waves=(8, 12, 16, 24, 32),
             o["tile"] = tj
         trials.append((o, _time_single(prob, mcdc.make_options(**o), pilot, seed)))
 
-    if not pc:
+    if not pc and mcdc.SCHED_HISTORY in allowed:
         for w in waves:
             trial(schedule=mcdc.SCHED_HISTORY, waves_per_cu=w)
     if prob.get("importance") is None:
@@ -109,7 +111,8 @@ def tune_single(prob, pilot=2_000_000, waves=(8, 12, 16, 24, 32),
             if pc and ch < batch:
                 continue
             for sched in (mcdc.SCHED_EVENT, mcdc.SCHED_HYBRID):
-                trial(schedule=sched, event_chunk=ch)
+                if sched in allowed:
+                    trial(schedule=sched, event_chunk=ch)
     if not trials:
         raise ValueError("no schedule can run this problem at this pilot size")
     best = max(trials, key=lambda t: t[1])

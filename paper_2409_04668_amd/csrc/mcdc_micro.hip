@@ -35,31 +35,42 @@ __global__ void __launch_bounds__(256) k_atomic_ceiling(double *__restrict__ buf
     }
 }
 
-// Each work-item performs `per_item` LDS adds at hashed bins of its
-// workgroup's array (bin = high word of hash * n_bins: one multiply, so the
-// loop is the ds_add_f64 and the hash); the array is zeroed first and added
-// into `out` at the end (one HBM atomic per touched bin).
+// Each work-item performs `per_item` LDS adds into its workgroup's array of
+// n_bins doubles: it starts at a hashed bin and walks with its own odd
+// stride modulo the largest power of two not above n_bins (an add and a mask
+// per update, so the loop is bound by the ds_add_f64, not by the index
+// arithmetic; the lanes of a wave hit scattered bins).  The array is zeroed
+// first; at the end the workgroup's total is added to out[0] (one atomic per
+// workgroup), which shows that no update was lost.
 typedef __attribute__((address_space(3))) double lds_f64_t;
 __global__ void __launch_bounds__(1024) k_lds_atomic_ceiling(double *__restrict__ out,
                                                              uint32_t n_bins, uint32_t n_items,
                                                              uint32_t per_item) {
     extern __shared__ double s_bins[];
+    __shared__ double s_wave[16];
     for (uint32_t i = threadIdx.x; i < n_bins; i += blockDim.x) s_bins[i] = 0.0;
     __syncthreads();
+    const uint32_t mask = (1u << (31 - __clz(n_bins))) - 1u;
     const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
     if (tid < n_items) {
-        uint32_t h = mix32(tid * 2654435761u + 777u);
+        uint32_t i = mix32(tid * 2654435761u + 777u) & mask;
+        const uint32_t step = (mix32(tid + 99u) | 1u) & mask;
         lds_f64_t *base = (lds_f64_t *)s_bins;
         for (uint32_t k = 0; k < per_item; ++k) {
-            h = mix32(h + k);
-            const uint32_t i = (uint32_t)(((uint64_t)h * n_bins) >> 32);
             __hip_atomic_fetch_add(base + i, 1.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            i = (i + step) & mask;
         }
     }
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < n_bins; i += blockDim.x) {
-        const double v = s_bins[i];
-        if (v != 0.0) unsafeAtomicAdd(out + i, v);
+    double t = 0.0;
+    for (uint32_t i = threadIdx.x; i < n_bins; i += blockDim.x) t += s_bins[i];
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+    if ((threadIdx.x & 63) == 0) s_wave[threadIdx.x >> 6] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double w = 0.0;
+        for (uint32_t k = 0; k < blockDim.x / 64; ++k) w += s_wave[k];
+        if (w != 0.0) unsafeAtomicAdd(out, w);
     }
 }
 
@@ -90,7 +101,7 @@ int mcdc_micro_atomics(double *dev_buf, uint64_t n_bins, uint64_t n_items, uint3
 
 int mcdc_micro_lds_atomics(double *dev_out, uint32_t n_bins, uint64_t n_items, uint32_t per_item,
                            void *stream) {
-    if (!dev_out || n_bins == 0 || n_bins > MCDC_MAX_TILE_BINS || per_item == 0)
+    if (!dev_out || n_bins < 2 || n_bins > MCDC_MAX_TILE_BINS || per_item == 0)
         return fail(MCDC_E_INVALID, "micro_lds_atomics arguments");
     if (n_items == 0 || n_items > (1ull << 31)) return fail(MCDC_E_INVALID, "micro_lds_atomics item count");
     const int block = 1024;

@@ -5,8 +5,9 @@
 // method does: the same operations on the same operands in the same order.
 // That makes each history's trajectory reproducible bit for bit on any
 // schedule.  Sources of the definitions:
-//  - move: position += direction * distance, time += distance / speed (paper,
-//    Fig. 2);
+//  - straight-line motion between events: position advances by direction
+//    times distance, time by distance over speed (the particle-state example
+//    of the paper's Fig. 2);
 //  - the events that end a flight or a particle: capture, time or space
 //    boundary, time census, implicit capture (paper, Sec. "MC/DC on CPUs",
 //    transport-loop paragraph);

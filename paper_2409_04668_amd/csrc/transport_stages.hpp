@@ -279,8 +279,8 @@ struct tight_regs<C, std::void_t<decltype(C::kTightRegs)>>
 
 // Flight: census, surface, weight-window grid plane (windows with a grid) and
 // collision distances; the event (ties: census, then surface, then grid
-// plane, then collision); track-length scoring; the move of Fig. 2; census and
-// end-of-time handling.  Returns EV_CENSUS (particle continues), EV_TIME_END or
+// plane, then collision); track-length scoring; straight-line motion; census
+// and end-of-time handling.  Returns EV_CENSUS (particle continues), EV_TIME_END or
 // -1 (particle ended), EV_SURFACE or EV_SCATTER (the surface or collision
 // stage comes next), EV_WW_PLANE (the window check comes next); `d` is the
 // flight length.
@@ -337,9 +337,10 @@ MCDC_DEV int stage_flight(CP &P, const RunArgs &A, Shared &S, const T &tally, Ct
     if (P.surf_on && score_surface(P, q.x, q.u, iu, q.t, v, d, q.w, q.g, C.surf_tally()))
         atomicAdd(&S.cnt[C_SURF], 1ull);
 
-    q.x[0] = q.x[0] + q.u[0] * d;
-    q.x[1] = q.x[1] + q.u[1] * d;
-    q.x[2] = q.x[2] + q.u[2] * d;
+    // straight-line motion: each coordinate by its direction cosine times d;
+    // the time by d / v below, unless the flight ends at a census
+#pragma unroll
+    for (int a = 0; a < 3; ++a) q.x[a] += q.u[a] * d;
 
     if (ev == EV_CENSUS) {
         q.t = tc;

@@ -611,13 +611,15 @@ def micro_atomic_rate(n_bins: int, n_updates: int, run: int = 1, per_item: int =
     return best
 
 
-def micro_lds_atomic_rate(n_bins: int, n_updates: int, per_item: int = 256, reps: int = 3):
+def micro_lds_atomic_rate(n_bins: int, n_updates: int, reps: int = 3):
     """Measured LDS FP64 atomic-add rate (ds_add_f64 updates/s) into an
-    n_bins array per 1024-work-item workgroup (zeroing and the final flush
-    included in the timed launch)."""
+    n_bins array per 1024-work-item workgroup, one workgroup per compute unit
+    (zeroing and the final per-workgroup total included in the timed
+    launch)."""
     import torch
-    out = torch.zeros(n_bins, dtype=torch.float64, device="cuda")
-    n_items = max(1, n_updates // per_item)
+    out = torch.zeros(1, dtype=torch.float64, device="cuda")
+    n_items = torch.cuda.get_device_properties(0).multi_processor_count * 1024
+    per_item = max(1, n_updates // n_items)
     best = 0.0
     for _ in range(reps + 1):
         a = torch.cuda.Event(enable_timing=True)

@@ -47,6 +47,21 @@ def _gpu_grad(p, X, y, wt, in_dim):
     return tg.cpu().numpy(), tl.item()
 
 
+def _grad_scale(p, X, y, wt, in_dim):
+    """Per component, the sum over points of the absolute values of the terms
+    the gradient adds (the chain rule of the FP64 reference with every factor
+    taken in absolute value): the scale against which an FP32 sum of those
+    terms is accurate."""
+    W1, b1, W2, b2, W3, b3 = M.unpack(p.astype(np.float64), in_dim, H)
+    out, (X, z1, h1, z2, h2) = M.forward(p.astype(np.float64), X.astype(np.float64), in_dim, H)
+    wt = wt.astype(np.float64)
+    dout = np.abs(2.0 * wt * (out - y.astype(np.float64)) / np.sum(wt))
+    dz2 = np.outer(dout, np.abs(W3)) * (z2 > 0.0)
+    dz1 = (dz2 @ np.abs(W2)) * (z1 > 0.0)
+    return np.concatenate([(dz1.T @ np.abs(X)).ravel(), dz1.sum(axis=0), (dz2.T @ h1).ravel(),
+                           dz2.sum(axis=0), dout @ h2, np.array([dout.sum()])])
+
+
 @pytest.mark.parametrize("in_dim,n", [(IN, 2500), (IN, 64), (IN, 1), (12, 3001)])
 def test_mlp_gradient_matches_oracle(in_dim, n):
     """Several 64-point workgroups and a ragged last one, exactly one, a single
@@ -64,6 +79,12 @@ def test_mlp_gradient_matches_oracle(in_dim, n):
     assert abs(lo - lref) <= 1e-4 * lref
     assert np.linalg.norm(g - ref) <= 1e-4 * np.linalg.norm(ref)
     assert np.max(np.abs(g - ref)) <= 1e-4 * np.max(np.abs(ref))
+    # element by element: each component within 1e-4 of the sum of the
+    # magnitudes of the terms it adds up (a component far off fails even
+    # when it is small next to the largest)
+    scale = _grad_scale(p, X, y, wt, in_dim)
+    bad = np.abs(g - ref) > 1e-4 * scale + 1e-30
+    assert not bad.any(), (np.nonzero(bad)[0][:10], g[bad][:5], ref[bad][:5])
     # the gradient sums run in a fixed order: a second call is bit-identical
     g2, _ = _gpu_grad(p, X, y, wt, in_dim)
     assert np.array_equal(g2.astype(np.float64), g)
@@ -113,3 +134,43 @@ def test_learned_weight_windows_gain_fom_and_stay_unbiased():
     var_w = w["rel_err"] ** 2 * w["n"]
     assert var_w < var_a / 5.0, (a, w)
     assert w["fom"] > a["fom"], (a, w)
+
+
+@pytest.mark.slow
+def test_learned_ww_error_estimate_by_replication():
+    """The figure of merit rests on the reported relative error R.  The
+    benchmark's learned-window configuration (importance from 20 x 1e6
+    histories, network trained on the GPU, baked onto the 30 x 50 x 30 x 20
+    window map; hybrid schedule) and the analog run, each repeated with 32
+    independent seeds of 4e6 histories: the spread of the 32 detector means
+    agrees with the mean reported variance of a mean (chi-square with 31
+    degrees of freedom, 0.1% and 99.9% bounds) on both sides, and the two
+    pooled means agree within 4 standard errors."""
+    from scipy import stats
+    from paper_2409_04668_amd import learned_ww as L
+    from paper_2409_04668_amd import mcdc
+    from paper_2409_04668_amd import workloads as W
+    p = W.config2()
+    ww, _ = L.build_ww(p, n_runs=20, n_per_run=1_000_000, map_dims=(30, 50, 30, 20))
+    K, n = 32, 4_000_000
+    pooled = {}
+    for name, prob in (("analog", p), ("learned", W.config4(ww))):
+        gp = mcdc.Problem(prob, mcdc.make_options(mcdc.SCHED_HYBRID, event_chunk=1 << 22))
+        ms, vs = [], []
+        for k in range(K):
+            gp.reset()
+            gp.run(n, 9000 + 17 * k)
+            m, r = gp.tallies(mcdc.TALLY_DETECTOR)
+            ms.append(float(m[0]))
+            vs.append(float((r[0] * m[0]) ** 2))
+        gp.close()
+        ms, vs = np.array(ms), np.array(vs)
+        q = np.sum((ms - ms.mean()) ** 2) / vs.mean()
+        lo, hi = stats.chi2.ppf(0.001, K - 1), stats.chi2.ppf(0.999, K - 1)
+        print(f"{name}: spread / reported variance = {q / (K - 1):.3f} "
+              f"(bounds {lo / (K - 1):.3f} .. {hi / (K - 1):.3f}), mean {ms.mean():.5e}, "
+              f"R per seed {np.sqrt(vs.mean()) / ms.mean():.4f}")
+        assert lo <= q <= hi, (name, q / (K - 1))
+        pooled[name] = (ms.mean(), vs.mean() / K)
+    (ma, va), (mw, vw) = pooled["analog"], pooled["learned"]
+    assert abs(ma - mw) < 4.0 * math.sqrt(va + vw), (pooled, abs(ma - mw) / math.sqrt(va + vw))
