@@ -414,6 +414,7 @@ def main():
             "pc_copies_per_history": rates["pc_copies_per_history"]}
     if not args.no_other_schedule:
         out["batched_256_problems"] = batch_rate(torch, mcdc, W, steps=3, warmup=1)
+        out["k_eigenvalue"] = keff_rate(torch, mcdc, W)
     if not args.no_fom:
         out["fom"] = fom_comparison(mcdc, W, oargs, tile)
     if not args.no_cpu_baseline:
@@ -446,6 +447,39 @@ def batch_rate(torch, mcdc, W, steps, warmup):
             "workload": "256 box problems, 1-8 regions, 1-7 groups, 20^3 x 10 t-bins each",
             "autotuned_options": tuned["options"], "autotune_trials": tuned["trials"],
             "pieces_per_history": pieces / (total * (steps + warmup))}
+
+
+def keff_rate(torch, mcdc, W, M=1_000_000, n_inactive=5, n_active=10):
+    """The k-eigenvalue mode on the two-group reflected core (30^3 x 2 mesh
+    bins): one warm-up iteration, then n_inactive + n_active generations of M
+    histories timed; the mean of each estimator over the active generations
+    with its standard error."""
+    import numpy as np
+    p = W.keff_core(nx=30)
+    gp = mcdc.Problem(p, mcdc.make_options(mcdc.SCHED_HISTORY))
+    gp.run_keff(100_000, 1, 2, seed=5)
+    gp.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = gp.run_keff(M, n_inactive, n_active, seed=6)
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    c = gp.counters()
+    gp.close()
+
+    def stats(k):
+        k = np.asarray(k, float)[n_inactive:]
+        return float(k.mean()), float(k.std(ddof=1) / np.sqrt(k.size))
+    kc, sc = stats(out["k_col"])
+    ks, ss = stats(out["k_site"])
+    n = M * (n_inactive + n_active)
+    return {"workload": "two-group reflected core (40 cm fissile cube in a 60 cm reflector), "
+                        "30^3 x 2 mesh bins, history schedule",
+            "histories_per_generation": M, "generations": [n_inactive, n_active],
+            "histories_per_s": n / T, "seconds": T,
+            "collisions_per_history": c["collisions"] / n,
+            "k_col": [kc, sc], "k_site": [ks, ss],
+            "sites_per_generation_last": int(out["n_sites"][-1])}
 
 
 def bench_batch(args, torch, mcdc, W):
@@ -515,9 +549,19 @@ def fom_comparison(mcdc, W, analog_options, tile, target=0.01):
                                                  ratio_to_analog=net["fom"] / analog["fom"]),
             "agreement_sigma": z(analog, learned),
             "agreement_sigma_network_per_check": z(analog, net),
-            "training": dict(info, total_seconds=t_build),
+            "training": dict(info, total_seconds=t_build,
+                             flops_per_s=mlp_train_flops(info["n_points"], 5, 3000) /
+                             info["train_seconds"]),
             "fom_with_training_amortised": 1.0 / (learned["rel_err"] ** 2 *
                                                   (learned["seconds"] + t_build))}
+
+
+def mlp_train_flops(n_points, in_dim, steps, hidden=64):
+    """Arithmetic of full-batch training: per point and step the forward pass
+    (multiply and add of every weight: 2 (H in + H H + H)) and the backward
+    pass (twice that: gradients with respect to weights and activations)."""
+    fwd = 2 * (hidden * in_dim + hidden * hidden + hidden)
+    return 3.0 * fwd * n_points * steps
 
 
 def bench_fom(args, torch, mcdc, W):

@@ -263,8 +263,12 @@ int mcdc_run_keff(mcdc_handle h, const mcdc_keff_opts *o, uint64_t seed, void *d
                   size_t bytes, double *k_col, double *k_site, uint64_t *n_sites, void *stream);
 
 /* Cancel word of the handle: on != 0 asks every later and every running
- * launch of the handle's runs to stop (persistent kernels read it every 256
- * loop turns, from host-coherent memory, and end early; the host side of
+ * launch of the handle's runs to stop (in the persistent kernels one
+ * work-item per workgroup reads it from host-coherent memory before the
+ * first history and at every 64th history it starts, and shares it in LDS;
+ * every work-item checks that copy when it starts a history, and a batched
+ * run's workgroups read it every 8th work chunk; they then end early,
+ * leaving histories in flight unfinished; the host side of
  * mcdc_run / mcdc_run_step / mcdc_run_batch stops launching and returns
  * MCDC_E_CANCELLED); the results of a cancelled run are incomplete and carry
  * the sticky status MCDC_E_CANCELLED until mcdc_reset_tallies.  on = 0
@@ -273,24 +277,30 @@ int mcdc_run_keff(mcdc_handle h, const mcdc_keff_opts *o, uint64_t seed, void *d
  * Source: not in the paper (failure handling for long runs). */
 int mcdc_set_cancel(mcdc_handle h, int on);
 
-/* A run taken census step by census step (event or hybrid schedule; all histories
- * resident: n_histories <= event_chunk; with population control, n_batches
- * must be 1).  mcdc_run_begin samples the sources and returns; each
- * mcdc_run_step transports until the next census step begins, or to the end
- * of the run (*done = 1, after which the results include the run, as after
- * mcdc_run with the same arguments).  Between steps the whole state of the
- * run lives in the caller-owned workspace and in the host record below, so a
- * run is checkpointed by copying both, and resumed by copying them into a
- * handle created from the same description and options (then
- * mcdc_set_run_state) and stepping on.  The per-history outputs of
- * mcdc_set_history_scores are written when the run ends.  Steps synchronise
- * `stream`.  MCDC_E_STATE for a step without a run in progress. */
+/* A run taken step by step, with the same results as mcdc_run with the same
+ * arguments.  It goes segment by segment in mcdc_run's order: under the
+ * event and hybrid schedules the resident chunks of event_chunk histories
+ * (with population control, the batches instead, each at most event_chunk
+ * histories, controlled on its own), and each of these census step by census
+ * step; under the history schedule the batches, one step each (a history
+ * runs through every census time within its launch).  mcdc_run_begin samples
+ * the first segment's sources and returns; each mcdc_run_step transports to
+ * the next census step or to the end of a segment (then the next segment's
+ * sources are sampled), or to the end of the run (*done = 1, after which the
+ * results include the run).  Between steps the whole state of the run lives
+ * in the caller-owned workspace and in the host record below, so a run is
+ * checkpointed by copying both, and resumed by copying them into a handle
+ * created from the same description and options (then mcdc_set_run_state)
+ * and stepping on.  The per-history outputs of mcdc_set_history_scores are
+ * written as each segment ends (a checkpoint of a run that asks for them
+ * copies that array too).  Steps synchronise `stream`.  MCDC_E_STATE
+ * for a step without a run in progress, and for other runs while one is. */
 typedef struct {
     uint64_t magic;                    /* identifies the record layout           */
     uint64_t workspace_bytes, bins;    /* of the handle that wrote it            */
     uint64_t n_hist, batches, event_iterations;
     uint64_t run_first, run_n, run_seed;
-    double pc_m;
+    uint64_t segment;                  /* segment of the run in progress         */
     int32_t in_run, steps;
 } mcdc_run_state;
 
@@ -301,7 +311,8 @@ typedef struct {
  * simulation event that ends a flight). */
 int mcdc_run_begin(mcdc_handle h, uint64_t n_histories, uint64_t seed, void *stream);
 
-/* Transport to the next census step or to the end of the run (*done).
+/* Transport to the next census step, the end of a segment, or the end of
+ * the run (*done).
  * Source: as mcdc_run_begin. */
 int mcdc_run_step(mcdc_handle h, int32_t *done, void *stream);
 
@@ -311,7 +322,7 @@ int mcdc_get_run_state(mcdc_handle h, mcdc_run_state *out);
 
 /* Restore a host record into a handle made from the same description and
  * options whose workspace holds the matching copy.  MCDC_E_INVALID for a
- * record of another layout.
+ * record of another layout or one that names no segment of its run.
  * Source: not in the paper (checkpoint/resume at a census step). */
 int mcdc_set_run_state(mcdc_handle h, const mcdc_run_state *in);
 

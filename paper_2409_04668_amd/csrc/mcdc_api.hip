@@ -620,6 +620,29 @@ static int close_event_run(mcdc_handle h, uint64_t n, hipStream_t s) {
     return MCDC_OK;
 }
 
+// One batch of the history schedule: histories [A.h_begin, A.h_end) in one
+// launch, then the batch close-out of every tally.
+static int history_batch(mcdc_handle h, const RunArgs &A, hipStream_t s) {
+    const double nb = (double)(A.h_end - A.h_begin);
+    const bool lds = h->opt.lds_tally && h->nbins <= (uint32_t)kLdsTallyMaxBins;
+    timing_begin(h, s);
+    hipError_t e = launch_history(h->P, A, h->opt.grid, h->opt.block, lds, s);
+    timing_end(h, s);
+    if (e == hipSuccess)
+        e = launch_closeout((double *)(h->ws + h->L.tally_batch), (double *)(h->ws + h->L.tally_sum),
+                            (double *)(h->ws + h->L.tally_sumsq), h->nbins, nb, s);
+    if (e == hipSuccess && h->desc.col_tally)
+        e = launch_closeout((double *)(h->ws + h->L.col_batch), (double *)(h->ws + h->L.col_sum),
+                            (double *)(h->ws + h->L.col_sumsq), h->nbins, nb, s);
+    if (e == hipSuccess && h->desc.surf_on)
+        e = launch_closeout((double *)(h->ws + h->L.surf_batch), (double *)(h->ws + h->L.surf_sum),
+                            (double *)(h->ws + h->L.surf_sumsq), h->P.surf_nbins, nb, s);
+    if (e != hipSuccess) return hip_fail(e, "run launch");
+    h->batches += 1;
+    if (cancel_set(h)) return fail(MCDC_E_CANCELLED, "run cancelled");
+    return MCDC_OK;
+}
+
 int mcdc_run(mcdc_handle h, uint64_t n, uint64_t seed, void *stream) {
     if (!h) return fail(MCDC_E_INVALID, "null handle");
     if (h->is_batch) return fail(MCDC_E_STATE, "batched handle: use mcdc_run_batch");
@@ -631,17 +654,6 @@ int mcdc_run(mcdc_handle h, uint64_t n, uint64_t seed, void *stream) {
     const uint64_t h0 = h->n_hist;
     RunArgs A = base_args(h, seed);
     A.h_run0 = h0;
-    double *batch = (double *)(h->ws + h->L.tally_batch);
-    double *sum = (double *)(h->ws + h->L.tally_sum);
-    double *sumsq = (double *)(h->ws + h->L.tally_sumsq);
-    double *cbatch = (double *)(h->ws + h->L.col_batch);
-    double *csum = (double *)(h->ws + h->L.col_sum);
-    double *csumsq = (double *)(h->ws + h->L.col_sumsq);
-    const bool col = h->desc.col_tally != 0;
-    double *sbatch = (double *)(h->ws + h->L.surf_batch);
-    double *ssum = (double *)(h->ws + h->L.surf_sum);
-    double *ssumsq = (double *)(h->ws + h->L.surf_sumsq);
-    const bool lds = h->opt.lds_tally && h->nbins <= (uint32_t)kLdsTallyMaxBins;
     if (h->opt.schedule == MCDC_SCHED_EVENT) {
         // one pass over all histories of the run; each particle scores into
         // the slice of its history's batch; then every batch is closed out
@@ -676,57 +688,94 @@ int mcdc_run(mcdc_handle h, uint64_t n, uint64_t seed, void *stream) {
         if (hi == lo) continue;
         A.h_begin = h0 + lo;
         A.h_end = h0 + hi;
-        timing_begin(h, s);
-        hipError_t e = launch_history(h->P, A, h->opt.grid, h->opt.block, lds, s);
-        timing_end(h, s);
-        if (e == hipSuccess) e = launch_closeout(batch, sum, sumsq, h->nbins, (double)(hi - lo), s);
-        if (e == hipSuccess && col)
-            e = launch_closeout(cbatch, csum, csumsq, h->nbins, (double)(hi - lo), s);
-        if (e == hipSuccess && h->desc.surf_on)
-            e = launch_closeout(sbatch, ssum, ssumsq, h->P.surf_nbins, (double)(hi - lo), s);
-        if (e != hipSuccess) return hip_fail(e, "run launch");
-        h->batches += 1;
-        if (cancel_set(h)) return fail(MCDC_E_CANCELLED, "run cancelled");
+        int st = history_batch(h, A, s);
+        if (st) return st;
     }
     h->n_hist += n;
     return MCDC_OK;
 }
 
 // ---- census-step control ----------------------------------------------------
+//
+// A stepped run is taken segment by segment, in the order mcdc_run takes the
+// same histories, so that it ends with the same results:
+//   event or hybrid schedule, no population control: the resident chunks;
+//   event or hybrid schedule with population control: the batches (each one
+//     resident chunk, controlled on its own);
+//   history schedule: the batches (one launch each).
+// An event-schedule segment takes one step per census step; a
+// history-schedule segment one step (a history runs through every census
+// time within its launch).
 
-static const uint64_t kRunStateMagic = 0x6D636463'72756E31ull;   // "mcdcrun1"
+static const uint64_t kRunStateMagic = 0x6D636463'72756E32ull;   // "mcdcrun2"
+
+static bool seg_by_batch(const mcdc_problem *h) {
+    return h->opt.schedule == MCDC_SCHED_HISTORY || h->desc.pc_on;
+}
+
+static uint64_t seg_count(const mcdc_problem *h) {
+    if (seg_by_batch(h)) return (uint64_t)h->desc.n_batches;
+    const uint64_t c = ev_resident_histories(h);
+    return c ? (h->run_n + c - 1) / c : 0;
+}
+
+static void seg_range(const mcdc_problem *h, uint64_t k, uint64_t &lo, uint64_t &hi) {
+    if (seg_by_batch(h)) {
+        const uint64_t B = (uint64_t)h->desc.n_batches;
+        lo = (k * h->run_n) / B;
+        hi = ((k + 1) * h->run_n) / B;
+    } else {
+        const uint64_t c = ev_resident_histories(h);
+        lo = k * c;
+        hi = lo + c < h->run_n ? lo + c : h->run_n;
+    }
+}
+
+// The first non-empty segment at or after k (seg_count when none is left).
+static uint64_t seg_next(const mcdc_problem *h, uint64_t k) {
+    const uint64_t K = seg_count(h);
+    for (; k < K; ++k) {
+        uint64_t lo, hi;
+        seg_range(h, k, lo, hi);
+        if (hi > lo) break;
+    }
+    return k;
+}
 
 static RunArgs stepped_args(mcdc_handle h) {
+    uint64_t lo, hi;
+    seg_range(h, h->run_seg, lo, hi);
     RunArgs A = base_args(h, h->run_seed);
     A.h_run0 = h->run_first;
-    A.h_begin = h->run_first;
-    A.h_end = h->run_first + h->run_n;
+    A.h_begin = h->run_first + lo;
+    A.h_end = h->run_first + hi;
     A.run_n = h->run_n;
     A.run_batches = (uint64_t)h->desc.n_batches;
-    A.pc_m = h->run_pc_m;
+    const double m = floor(h->desc.pc_target * (double)(hi - lo) + 0.5);
+    A.pc_m = m < 1.0 ? 1.0 : m;
     A.keep_path = 1;                     // outputs may be asked for before the last step
     return A;
 }
 
 int mcdc_run_begin(mcdc_handle h, uint64_t n, uint64_t seed, void *stream) {
     if (!h) return fail(MCDC_E_INVALID, "null handle");
+    if (h->is_batch) return fail(MCDC_E_STATE, "batched handle: use mcdc_run_batch");
     if (h->P.fis_on) return fail(MCDC_E_STATE, "a problem with fission runs in the k-eigenvalue mode (mcdc_run_keff)");
-    if (h->is_batch || h->opt.schedule != MCDC_SCHED_EVENT)
-        return fail(MCDC_E_STATE, "census-step control runs in the event schedule");
     if (h->in_run) return fail(MCDC_E_STATE, "a census-stepped run is in progress");
     if (n == 0) return fail(MCDC_E_INVALID, "empty run");
-    if (n > ev_resident_histories(h)) return fail(MCDC_E_INVALID, "census-step control needs n <= event_chunk");
-    if (h->desc.pc_on && h->desc.n_batches != 1)
-        return fail(MCDC_E_INVALID, "census-step control with population control needs n_batches = 1");
+    const uint64_t B = (uint64_t)h->desc.n_batches;
+    if (h->opt.schedule == MCDC_SCHED_EVENT && h->desc.pc_on && (n + B - 1) / B > ev_resident_histories(h))
+        return fail(MCDC_E_INVALID, "population control needs event_chunk >= histories per batch");
     if (h->n_hist + n >= (1ull << 48)) return fail(MCDC_E_INVALID, "history ids exhausted (2^48)");
     h->run_first = h->n_hist;
     h->run_n = n;
     h->run_seed = seed;
-    const double m = floor(h->desc.pc_target * (double)n + 0.5);
-    h->run_pc_m = m < 1.0 ? 1.0 : m;
     h->run_steps = 0;
-    int st = event_begin(h, stepped_args(h), (hipStream_t)stream);
-    if (st) return st;
+    h->run_seg = seg_next(h, 0);
+    if (h->opt.schedule == MCDC_SCHED_EVENT) {
+        int st = event_begin(h, stepped_args(h), (hipStream_t)stream);
+        if (st) return st;
+    }
     h->in_run = true;
     return MCDC_OK;
 }
@@ -734,16 +783,25 @@ int mcdc_run_begin(mcdc_handle h, uint64_t n, uint64_t seed, void *stream) {
 int mcdc_run_step(mcdc_handle h, int32_t *done, void *stream) {
     if (!h || !done) return fail(MCDC_E_INVALID, "null argument");
     if (!h->in_run) return fail(MCDC_E_STATE, "no census-stepped run in progress");
+    *done = 0;
     hipStream_t s = (hipStream_t)stream;
-    bool fin = false;
-    int st = event_step(h, stepped_args(h), s, fin);
+    const bool ev = h->opt.schedule == MCDC_SCHED_EVENT;
+    bool seg_done = true;
+    int st = ev ? event_step(h, stepped_args(h), s, seg_done) : history_batch(h, stepped_args(h), s);
     if (st) return st;
-    h->run_steps += 1;
-    *done = fin ? 1 : 0;
-    if (fin) {
-        h->in_run = false;
-        return close_event_run(h, h->run_n, s);
+    if (!ev) {
+        const hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "run step");
     }
+    h->run_steps += 1;
+    if (!seg_done) return MCDC_OK;
+    h->run_seg = seg_next(h, h->run_seg + 1);
+    if (h->run_seg < seg_count(h))
+        return ev ? event_begin(h, stepped_args(h), s) : MCDC_OK;
+    h->in_run = false;
+    *done = 1;
+    if (ev) return close_event_run(h, h->run_n, s);
+    h->n_hist += h->run_n;
     return MCDC_OK;
 }
 
@@ -759,7 +817,7 @@ int mcdc_get_run_state(mcdc_handle h, mcdc_run_state *o) {
     o->run_first = h->run_first;
     o->run_n = h->run_n;
     o->run_seed = h->run_seed;
-    o->pc_m = h->run_pc_m;
+    o->segment = h->run_seg;
     o->in_run = h->in_run ? 1 : 0;
     o->steps = h->run_steps;
     return MCDC_OK;
@@ -770,17 +828,20 @@ int mcdc_set_run_state(mcdc_handle h, const mcdc_run_state *in) {
     if (in->magic != kRunStateMagic) return fail(MCDC_E_INVALID, "not a run-state record");
     if (in->workspace_bytes != h->L.total || in->bins != h->nbins)
         return fail(MCDC_E_INVALID, "run state of a handle with another description or options");
-    if (in->in_run && (h->is_batch || h->opt.schedule != MCDC_SCHED_EVENT))
-        return fail(MCDC_E_STATE, "census-step control runs in the event schedule");
+    if (in->in_run && h->is_batch) return fail(MCDC_E_STATE, "batched handle: use mcdc_run_batch");
     h->n_hist = in->n_hist;
     h->batches = (int64_t)in->batches;
     h->event_iterations = in->event_iterations;
     h->run_first = in->run_first;
     h->run_n = in->run_n;
     h->run_seed = in->run_seed;
-    h->run_pc_m = in->pc_m;
+    h->run_seg = in->segment;
     h->in_run = in->in_run != 0;
     h->run_steps = in->steps;
+    if (h->in_run && (h->run_n == 0 || h->run_seg >= seg_count(h))) {
+        h->in_run = false;
+        return fail(MCDC_E_INVALID, "run-state record names no segment of its run");
+    }
     return MCDC_OK;
 }
 

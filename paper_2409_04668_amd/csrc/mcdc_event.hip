@@ -226,19 +226,26 @@ __global__ void __launch_bounds__(256) k_ev_source(DevProblem, RunArgs A, EvBank
 }
 
 // Lead-stage flights per history (its particles together) before the rest of
-// the history is handed to the event stages: short histories finish in the
-// lead, long split chains are spread over the grid instead of holding one
-// work-item.
+// the history is handed to the banks: short histories finish in the lead,
+// long split chains are spread over the grid instead of holding one
+// work-item.  The re-lead stage's budget counts the flights of one banked
+// particle and its daughters.
 #ifndef MCDC_LEAD_FLIGHTS
 #define MCDC_LEAD_FLIGHTS 64
+#endif
+#ifndef MCDC_RELEAD_FLIGHTS
+#define MCDC_RELEAD_FLIGHTS MCDC_LEAD_FLIGHTS
 #endif
 
 // Context of a history in the lead stage: one work-item owns the history (its
 // banked particles, if any, move only after the lead stage), so its sums stay
 // in registers and are stored to the per-history arrays when the lead ends.
-// Split daughters go onto the work-item's stack while it has room, else into
-// the active bank.
-template <int WW>
+// In the re-lead stage (BANK) a work-item follows one banked particle of a
+// history whose other particles may be in flight on other work-items, so the
+// sums are atomic adds to the per-history arrays.  Split daughters go onto the
+// work-item's stack while it has room, else into bank `cur` (the active bank
+// after the lead stage; the next active bank in the re-lead stage).
+template <int WW, bool BANK = false>
 struct LeadCtx {
     static constexpr bool kWW = WW != 0;
     static constexpr bool kWWMap = WW == 2;
@@ -260,15 +267,24 @@ struct LeadCtx {
     MCDC_DEV double *surf_tally() const { return A.surf + batch() * (uint64_t)P.surf_nbins; }
     MCDC_DEV const float *mlp_params(CP &Pp) const { return Pp.ww_params; }
     MCDC_DEV bool count_flight() {
+        if constexpr (BANK) {
+            const uint32_t e = atomicAdd(&B.events[slot], 1u) + 1u;
+            return (int64_t)e <= P.max_events;
+        }
         events += 1u;
         return (int64_t)events <= P.max_events;
     }
-    MCDC_DEV void add_score(double v) { xh += v; }
+    MCDC_DEV void add_score(double v) {
+        if constexpr (BANK) unsafeAtomicAdd(&B.xh[slot], v);
+        else xh += v;
+    }
     MCDC_DEV void add_path(double v) {
-        if (A.keep_path) path += v;
+        if (!A.keep_path) return;
+        if constexpr (BANK) unsafeAtomicAdd(&B.path[slot], v);
+        else path += v;
     }
     MCDC_DEV void imp_point(CP &, const Part &) {}
-    // copy a particle ready for its next flight into the active bank
+    // copy a particle ready for its next flight into bank `cur`
     MCDC_DEV void to_bank(const Part &q, uint32_t pos) const {
         bank_put(A, B, B.b[cur], pos, q, 0.0, slot);
     }
@@ -325,6 +341,48 @@ MCDC_DEV uint64_t batch_of(const RunArgs &A, uint32_t slot) {
     return ((r + 1) * A.run_batches - 1) / A.run_n;
 }
 
+// One loop turn of the lead and re-lead stages for the live particle q: once
+// `flights` reaches the budget, hand the particle and the stacked daughters
+// over to bank C.cur; else one flight and the event that ends it.
+template <int WW, uint32_t BUDGET, class Ctx, class Tally>
+MCDC_DEV void lead_turn(CP &PL, const RunArgs &A, const EvBank &B, Shared &S, const Tally &tally,
+                        Ctx &C, Part &q, uint32_t &flights, uint32_t &n_flight, uint32_t &n_piece,
+                        double &path, bool stop_at_census, uint32_t cen) {
+    if (WW != 0 && flights >= BUDGET) {
+        const uint32_t base = atomicAdd(&B.ctl->n_act[C.cur], (uint32_t)C.sp + 1u);
+        C.to_bank(q, base);
+        for (int i = 0; i < C.sp; ++i) {
+            Part r;
+            stack_pop(A, C.lane, PL.stack_cap, i, r);
+            C.to_bank(r, base + 1u + (uint32_t)i);
+        }
+        C.sp = 0;
+        q.alive = false;
+        return;
+    }
+    flights += 1;
+    double d = 0.0;
+    const int ev = stage_flight(PL, A, S, tally, C, q, d, n_piece, path);
+    if (ev >= 0) n_flight += 1;
+    if (!q.alive) {
+        if (ev < 0) C.sp = 0;               // event cap: the history is abandoned
+        return;
+    }
+    bool due = false;
+    if (ev == EV_SURFACE) {
+        due = stage_surface(PL, A, S, C, q, d);
+    } else if (ev == EV_SCATTER) {
+        due = stage_collision(PL, A, S, C, q, d);
+    } else if (ev == EV_WW_PLANE) {
+        due = true;
+    } else if (ev == EV_CENSUS && stop_at_census) {
+        bank_put(A, B, B.b[cen], atomicAdd(&B.ctl->n_act[cen], 1u), q, d, C.slot);
+        q.alive = false;
+        return;
+    }
+    if (WW != 0 && due) ww_check(PL, A, S, C, q);
+}
+
 // Lead stage (hybrid schedule).  Workgroup w takes the contiguous slots
 // [w n / G, (w+1) n / G) (so its LDS tile, if any, sees one batch apart from
 // at most one boundary); its work-items take the next slot from a counter in
@@ -340,8 +398,10 @@ __global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_ev_lead(DevProblem, R
     CP &P = kernel_problem();
     extern __shared__ double s_tile[];
     __shared__ Shared S;
-    __shared__ uint32_t s_next;
+    __shared__ uint32_t s_next, s_cancel;
+    const CancelSeen cancel{&s_cancel};
     shared_zero(S);
+    cancel.init(A.cancel);
     const uint32_t r0 = (uint32_t)((uint64_t)blockIdx.x * n / gridDim.x);
     const uint32_t r1 = (uint32_t)((uint64_t)(blockIdx.x + 1) * n / gridDim.x);
     if (threadIdx.x == 0) s_next = r0;
@@ -363,13 +423,9 @@ __global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_ev_lead(DevProblem, R
     Part q;
     q.alive = false;
     bool in_hist = false;
-    uint32_t turn = 0;
+    uint32_t n_started = 0;
     for (;;) {
         CP &PL = problem_reload(P);
-        if (turn++ % kCancelPoll == 0 && cancel_requested(A.cancel)) {
-            set_status(A, MCDC_E_CANCELLED);
-            break;
-        }
         if (!q.alive) {
             if (WW != 0 && C.sp > 0) {
                 C.sp -= 1;
@@ -396,6 +452,10 @@ __global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_ev_lead(DevProblem, R
                     }
                     in_hist = false;
                 }
+                if (cancel.check(A.cancel, n_started++)) {
+                    set_status(A, MCDC_E_CANCELLED);
+                    break;
+                }
                 const uint32_t s = atomicAdd(&s_next, 1u);
                 if (s >= r1) break;
                 C.slot = s;
@@ -410,40 +470,9 @@ __global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_ev_lead(DevProblem, R
                 if (!q.alive) continue;
             }
         }
-        if (WW != 0 && lead_flights >= MCDC_LEAD_FLIGHTS) {
-            // hand the rest of the history over: this particle and the stack
-            const uint32_t base = atomicAdd(&B.ctl->n_act[cur], (uint32_t)C.sp + 1u);
-            C.to_bank(q, base);
-            for (int i = 0; i < C.sp; ++i) {
-                Part r;
-                stack_pop(A, lane, PL.stack_cap, i, r);
-                C.to_bank(r, base + 1u + (uint32_t)i);
-            }
-            C.sp = 0;
-            q.alive = false;
-            continue;
-        }
-        lead_flights += 1;
-        double d = 0.0;
-        const int ev = stage_flight(PL, A, S, tally.t, C, q, d, n_piece, path);
-        if (ev >= 0) n_flight += 1;
-        if (!q.alive) {
-            if (ev < 0) C.sp = 0;           // event cap: the history is abandoned
-            continue;
-        }
-        bool due = false;
-        if (ev == EV_SURFACE) {
-            due = stage_surface(PL, A, S, C, q, d);
-        } else if (ev == EV_SCATTER) {
-            due = stage_collision(PL, A, S, C, q, d);
-        } else if (ev == EV_WW_PLANE) {
-            due = true;
-        } else if (ev == EV_CENSUS && stop_at_census) {
-            bank_put(A, B, B.b[cen], atomicAdd(&B.ctl->n_act[cen], 1u), q, d, C.slot);
-            q.alive = false;
-            continue;
-        }
-        if (WW != 0 && due) ww_check(PL, A, S, C, q);
+        // the rest of the history is handed over after MCDC_LEAD_FLIGHTS flights
+        lead_turn<WW, MCDC_LEAD_FLIGHTS>(PL, A, B, S, tally.t, C, q, lead_flights, n_flight,
+                                         n_piece, path, stop_at_census, cen);
     }
     atomicAdd(&S.cnt[C_FLIGHT], (unsigned long long)n_flight);
     atomicAdd(&S.cnt[C_PIECE], (unsigned long long)n_piece);
@@ -590,6 +619,80 @@ __global__ void __launch_bounds__(256) k_ev_interact(DevProblem, RunArgs A, EvBa
         if (WW != 0) wave_write_copies(A, B, out, &B.ctl->n_act[nxt], q, slot, nd, tag0);
     }
     __syncthreads();
+    shared_flush(S, A.acc);
+    if (last_block(B.ctl, s_last) && threadIdx.x == 0) ev_advance(B.ctl, P.pc_on != 0);
+}
+
+// Re-lead stage (hybrid schedule): the lead stage's loop run over the
+// particles of the active bank instead of new histories, in place of the
+// flight and interaction stages.  Workgroup w takes the bank entries
+// [w n / G, (w+1) n / G); a work-item follows each particle it takes, with its
+// split daughters on the work-item's stack, for MCDC_RELEAD_FLIGHTS flights and
+// hands what is left to the next active bank (a census stop, with population
+// control or census-step control, to the census bank).  The tally target is
+// the lead stage's, its LDS tile holding the batch of the workgroup's first
+// particle.  The last workgroup to finish advances the bank roles as the
+// interaction stage does.
+template <int LDS, int WW>
+__global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_ev_relead(DevProblem, RunArgs A, EvBank B) {
+    CP &P = kernel_problem();
+    extern __shared__ double s_tile[];
+    __shared__ Shared S;
+    __shared__ uint32_t s_next, s_cancel;
+    __shared__ bool s_last;
+    if (B.ctl->paused) return;
+    const CancelSeen cancel{&s_cancel};
+    shared_zero(S);
+    cancel.init(A.cancel);
+    const uint32_t cur = B.ctl->cur, nxt = B.ctl->nxt, cen = B.ctl->cen;
+    const uint32_t n = min(B.ctl->n_act[cur], B.cap);   // counts can pass cap on overflow
+    const uint32_t r0 = (uint32_t)((uint64_t)blockIdx.x * n / gridDim.x);
+    const uint32_t r1 = (uint32_t)((uint64_t)(blockIdx.x + 1) * n / gridDim.x);
+    if (threadIdx.x == 0) s_next = r0;
+    if (LDS == 2 && r0 < r1)
+        for (uint32_t i = threadIdx.x; i < P.hot_bins; i += blockDim.x) s_tile[i] = 0.0;
+    __syncthreads();
+    const Bank in = B.b[cur];
+    const uint64_t b_tile = r0 < r1 ? batch_of(A, in.i[6 * (size_t)B.cap + r0]) : 0;
+    const bool stop_at_census = P.pc_on || B.ctl->pause_at_census;
+    const uint64_t lane = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t n_flight = 0, n_piece = 0, flights = 0;
+    double path = 0.0;
+    LeadCtx<WW, true> C{P, A, B, lane, nxt, 0u, 0.0, 0.0, 0u, 0};
+    LeadTally<LDS> tally;
+    tally.init(P, s_tile);
+    Part q;
+    q.alive = false;
+    uint32_t n_started = 0;
+    for (;;) {
+        CP &PL = problem_reload(P);
+        if (!q.alive) {
+            if (WW != 0 && C.sp > 0) {
+                C.sp -= 1;
+                stack_pop(A, lane, PL.stack_cap, C.sp, q);
+            } else {
+                if (cancel.check(A.cancel, n_started++)) {
+                    set_status(A, MCDC_E_CANCELLED);
+                    break;
+                }
+                const uint32_t j = atomicAdd(&s_next, 1u);
+                if (j >= r1) break;
+                double d0;
+                uint32_t slot;
+                bank_load(in, B.cap, j, q, d0, slot);
+                C.slot = slot;
+                flights = 0;
+                tally.select(PL, A, batch_of(A, slot), b_tile);
+            }
+        }
+        lead_turn<WW, MCDC_RELEAD_FLIGHTS>(PL, A, B, S, tally.t, C, q, flights, n_flight, n_piece,
+                                           path, stop_at_census, cen);
+    }
+    atomicAdd(&S.cnt[C_FLIGHT], (unsigned long long)n_flight);
+    atomicAdd(&S.cnt[C_PIECE], (unsigned long long)n_piece);
+    atomicAdd(&S.wsum[W_PATH], path);
+    __syncthreads();
+    if (LDS == 2 && r0 < r1) hot_tile_flush(P, s_tile, A.tally + b_tile * (uint64_t)P.nbins);
     shared_flush(S, A.acc);
     if (last_block(B.ctl, s_last) && threadIdx.x == 0) ev_advance(B.ctl, P.pc_on != 0);
 }
@@ -853,8 +956,38 @@ static void ev_launch_source(mcdc_problem *h, const RunArgs &A, hipStream_t s, u
     else hipLaunchKernelGGL((k_ev_source<false>), dim3(sg), dim3(E->block), 0, s, h->P, A, B, n);
 }
 
+// The re-lead stage on the lead stage's grid and block (work-item i owns
+// stack lane i); every workgroup reads the bank count on the device.
+static void ev_launch_relead(mcdc_problem *h, const RunArgs &A, hipStream_t s) {
+    const DevProblem &P = h->P;
+    const EvBank &B = h->ev->B;
+    const dim3 grid(h->opt.grid), block(h->opt.block);
+    const int ww = P.ww_on ? (P.ww_map ? 2 : 1) : 0;
+    const size_t shm = P.hot_bins ? (size_t)P.hot_bins * sizeof(double) : 0;
+#define MCDC_RELEAD(L, W)                                                                      \
+    do {                                                                                       \
+        if (shm > 65536)                                                                       \
+            (void)hipFuncSetAttribute((const void *)k_ev_relead<L, W>,                         \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);   \
+        hipLaunchKernelGGL((k_ev_relead<L, W>), grid, block, shm, s, P, A, B);                 \
+    } while (0)
+    if (P.hot_bins) {
+        if (ww == 2) MCDC_RELEAD(2, 2);
+        else if (ww == 1) MCDC_RELEAD(2, 1);
+        else MCDC_RELEAD(2, 0);
+    } else {
+        if (ww == 2) MCDC_RELEAD(0, 2);
+        else if (ww == 1) MCDC_RELEAD(0, 1);
+        else MCDC_RELEAD(0, 0);
+    }
+#undef MCDC_RELEAD
+}
+
 // Iterate the stages of the resident chunk until it ends (or, under
 // census-step control, a census step begins): K iterations per host check.
+// An iteration is the flight and interaction stages, or in the hybrid
+// schedule the re-lead stage; then, with population control, the control
+// launches.
 static int ev_iterate(mcdc_problem *h, const RunArgs &A, hipStream_t s, bool &done) {
     EventState *E = h->ev;
     const DevProblem &P = h->P;
@@ -863,18 +996,23 @@ static int ev_iterate(mcdc_problem *h, const RunArgs &A, hipStream_t s, bool &do
     const bool ww = P.ww_on != 0, pc = P.pc_on != 0, lead = h->opt.lead;
     for (int iter = 0;; ++iter) {
         // after a lead stage the banks are often empty: check after one
-        // iteration first, then every eight
-        const int K = lead && iter == 0 ? 1 : 8;
+        // iteration first, then every four (a re-lead iteration finishes most
+        // of what it takes); every eight in the event schedule
+        const int K = lead ? (iter == 0 ? 1 : 4) : 8;
         h->event_iterations += K;
         for (int k = 0; k < K; ++k) {
-            // timed stage: the flight stage (the lead stage in the hybrid schedule)
-            if (!lead) timing_begin(h, s);
-            if (ww) hipLaunchKernelGGL((k_ev_flight<true>), dim3(grid), dim3(block), 0, s, P, A, B);
-            else hipLaunchKernelGGL((k_ev_flight<false>), dim3(grid), dim3(block), 0, s, P, A, B);
-            if (!lead) timing_end(h, s);
-            if (!ww) hipLaunchKernelGGL((k_ev_interact<0>), dim3(grid), dim3(block), 0, s, P, A, B);
-            else if (P.ww_map) hipLaunchKernelGGL((k_ev_interact<2>), dim3(grid), dim3(block), 0, s, P, A, B);
-            else hipLaunchKernelGGL((k_ev_interact<1>), dim3(grid), dim3(block), 0, s, P, A, B);
+            if (lead) {
+                ev_launch_relead(h, A, s);
+            } else {
+                // timed stage: the flight stage (the lead stage in the hybrid schedule)
+                timing_begin(h, s);
+                if (ww) hipLaunchKernelGGL((k_ev_flight<true>), dim3(grid), dim3(block), 0, s, P, A, B);
+                else hipLaunchKernelGGL((k_ev_flight<false>), dim3(grid), dim3(block), 0, s, P, A, B);
+                timing_end(h, s);
+                if (!ww) hipLaunchKernelGGL((k_ev_interact<0>), dim3(grid), dim3(block), 0, s, P, A, B);
+                else if (P.ww_map) hipLaunchKernelGGL((k_ev_interact<2>), dim3(grid), dim3(block), 0, s, P, A, B);
+                else hipLaunchKernelGGL((k_ev_interact<1>), dim3(grid), dim3(block), 0, s, P, A, B);
+            }
             if (pc) {
                 hipLaunchKernelGGL(k_ev_pc_sum, dim3(grid), dim3(block), 0, s, B);
                 hipLaunchKernelGGL(k_ev_pc_apply, dim3(grid), dim3(block), 0, s, P, A, B);

@@ -162,7 +162,10 @@ __global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_history(DevProblem, R
     CP &P = kernel_problem();
     extern __shared__ double s_tile[];
     __shared__ Shared S;
+    __shared__ uint32_t s_cancel;
+    const CancelSeen cancel{&s_cancel};
     shared_zero(S);
+    cancel.init(A.cancel);
     const uint32_t tile_bins = LDS == 1 ? P.nbins : (LDS == 2 ? P.hot_bins : 0u);
     for (uint32_t i = threadIdx.x; i < tile_bins; i += blockDim.x) s_tile[i] = 0.0;
     __syncthreads();
@@ -180,13 +183,8 @@ __global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_history(DevProblem, R
     const Tally tally = make_tally((Tally *)nullptr, P, A, s_tile);
 
     bool ww_due = false;                    // a weight-window check waits for this lane
-    uint32_t turn = 0;
     for (;;) {
         CP &PL = problem_reload(P);
-        if (turn++ % kCancelPoll == 0 && cancel_requested(A.cancel)) {
-            set_status(A, MCDC_E_CANCELLED);
-            break;
-        }
         if (WW == 1) {
             // Weight-window checks run batched: a lane that needs one waits
             // (its particle does not move) until at least half of the wave's
@@ -212,6 +210,10 @@ __global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_history(DevProblem, R
                     in_hist = false;
                 }
                 if (next >= A.h_end) break;
+                if (cancel.check(A.cancel, n_hist)) {
+                    set_status(A, MCDC_E_CANCELLED);
+                    break;
+                }
                 H.id = next;
                 next += stride;
                 H.xh = 0.0;

@@ -38,11 +38,12 @@ struct mcdc_problem {
     size_t nimp = 0;
     uint64_t n_hist = 0;
     uint64_t event_iterations = 0;
-    // a run taken census step by census step (event schedule)
+    // a run taken step by step: segment by segment (resident chunks, or
+    // batches), each event-schedule segment census step by census step
     bool in_run = false;
     int32_t run_steps = 0;
     uint64_t run_first = 0, run_n = 0, run_seed = 0;
-    double run_pc_m = 0.0;
+    uint64_t run_seg = 0;
     int64_t batches = 0;
     mcdc_trace_rec *trace = nullptr;
     uint64_t trace_cap = 0;

@@ -82,13 +82,34 @@ MCDC_DEV void trace_rec(const RunArgs &A, uint64_t hist, Part &q, int type, doub
 MCDC_DEV void set_status(const RunArgs &A, int st) { atomicMin(&A.acc->status, st); }
 
 // The host's cancel word, read past every cache (it lives in host memory and
-// the host writes it while kernels run).  Persistent loops read it once every
-// kCancelPoll turns, at a turn all active lanes of the wave share.
-constexpr uint32_t kCancelPoll = 256;
+// the host writes it while kernels run).  A read of host memory is slow and
+// many at once queue on the link (every lane reading it at its own history
+// starts made the lead stage 2.3x slower; one read per wave every 256 flights
+// still cost 4%), so the persistent tracking kernels read it from one
+// work-item per workgroup (before the first history, then at every
+// kCancelPoll-th history that work-item starts) and publish it in LDS, where
+// every work-item looks at each history start.
+constexpr uint32_t kCancelPoll = 64;
 MCDC_DEV bool cancel_requested(const int *flag) {
     return flag != nullptr &&
            __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0;
 }
+
+// The workgroup's copy of the cancel word (LDS).
+struct CancelSeen {
+    uint32_t *lds;
+    // before the workgroup's first history (a __syncthreads() must follow)
+    MCDC_DEV void init(const int *flag) const {
+        if (threadIdx.x == 0) *(volatile uint32_t *)lds = cancel_requested(flag) ? 1u : 0u;
+    }
+    // at a history start: work-item 0 reads the host word again every
+    // kCancelPoll-th of its histories; every work-item reads the copy
+    MCDC_DEV bool check(const int *flag, uint32_t started) const {
+        if (threadIdx.x == 0 && started % kCancelPoll == kCancelPoll - 1 && cancel_requested(flag))
+            *(volatile uint32_t *)lds = 1u;
+        return *(volatile uint32_t *)lds != 0u;
+    }
+};
 
 // outer boundary after a surface crossing; returns the leak face or -1
 MCDC_DEV int boundary(CP &P, Part &q) {

@@ -87,7 +87,7 @@ class RunState(C.Structure):
     _fields_ = [("magic", C.c_uint64), ("workspace_bytes", C.c_uint64), ("bins", C.c_uint64),
                 ("n_hist", C.c_uint64), ("batches", C.c_uint64), ("event_iterations", C.c_uint64),
                 ("run_first", C.c_uint64), ("run_n", C.c_uint64), ("run_seed", C.c_uint64),
-                ("pc_m", C.c_double), ("in_run", C.c_int32), ("steps", C.c_int32)]
+                ("segment", C.c_uint64), ("in_run", C.c_int32), ("steps", C.c_int32)]
 
 
 class Counters(C.Structure):
@@ -359,12 +359,12 @@ class Problem:
         check(st, "run_keff")
         return {k: v[:n_gen] for k, v in out.items()}
 
-    # ---- census-step control (event or hybrid schedule) ----------------
+    # ---- stepped runs: census step by census step, segment by segment --
     def run_begin(self, n_hist: int, seed: int, stream=None):
         check(_lib.mcdc_run_begin(self.h, int(n_hist), int(seed), _stream_ptr(stream)), "run_begin")
 
     def run_step(self, stream=None) -> bool:
-        """Transport to the next census step; True when the run has ended."""
+        """Transport to the next census step or segment; True when the run has ended."""
         done = C.c_int32(0)
         check(_lib.mcdc_run_step(self.h, C.byref(done), _stream_ptr(stream)), "run_step")
         return bool(done.value)

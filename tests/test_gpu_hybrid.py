@@ -103,7 +103,9 @@ def test_hybrid_long_histories_hand_over_to_the_banks(stack_cap):
     assert_counters(gp.counters(), orc)
     c = orc.counters
     assert c["split"] % 3 == 0 and c["split"] > 500 and c["flight"] > 200 * 64
-    assert gp.counters()["event_iterations"] > 8        # the banks were used
+    # the banks were used: what the lead stage handed over took more than one
+    # re-lead iteration (the first host check comes after one)
+    assert gp.counters()["event_iterations"] > 1
 
 
 def test_hybrid_weight_window_map_duct_small_chunks():
@@ -139,7 +141,7 @@ def test_hybrid_census_steps_checkpoint_resume():
     p = W.config2(n_census=5)
     p["mesh"]["n"] = np.array([12, 20, 12, 10], np.int32)
     n, seed = 4000, 181
-    gb, steps = _stepped_with_checkpoint(p, n, seed, _hy(1 << 13))
+    gb, steps, _ = _stepped_with_checkpoint(p, n, seed, _hy(1 << 13))
     assert 3 <= steps <= 6
     orc = O.OracleRun(p)
     _, ho = orc.run(n, seed, per_history=True)

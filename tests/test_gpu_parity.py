@@ -585,31 +585,53 @@ def test_largest_hot_tile_and_most_groups():
 
 
 # ---------------------------------------------------------------------------
-# census-step control with checkpoint/resume (event schedule)
+# stepped runs with checkpoint/resume
 # ---------------------------------------------------------------------------
 
 def _stepped_with_checkpoint(p, n, seed, opt, stop_after=2):
-    """Begin a run, take `stop_after` census steps, copy the workspace and the
-    run record into a fresh handle, and step that one to the end."""
+    """Begin a run, take `stop_after` steps, copy the workspace, the run
+    record and the per-history output array into a fresh handle, and step
+    that one to the end."""
     mc = _mcdc()
     ga = mc.Problem(p, opt)
+    ga.set_history_scores(n)
     ga.run_begin(n, seed)
     for _ in range(stop_after):
         assert not ga.run_step()
     st = ga.run_state()
     assert st.in_run == 1 and st.steps == stop_after
     ws = ga.ws.clone()
+    xh = ga._xh.clone()
     ga.close()
     gb = mc.Problem(p, opt)
     assert gb.ws.numel() == ws.numel()
     gb.ws.copy_(ws)
     gb.set_run_state(st)
     gb.set_history_scores(n)
+    gb._xh.copy_(xh)
     steps = stop_after
     while not gb.run_step():
         steps += 1
-        assert steps < 100
-    return gb, steps + 1
+        assert steps < 200
+    return gb, steps + 1, st
+
+
+def _check_stepped_against_oracle(gb, p, n, seed, exact_scores=True):
+    orc = O.OracleRun(p)
+    _, ho = orc.run(n, seed, per_history=True)
+    if exact_scores:
+        assert np.array_equal(gb.history_scores(), ho)
+    else:
+        np.testing.assert_allclose(gb.history_scores(), ho, rtol=1e-12, atol=1e-300)
+    s, s2 = gb.raw()
+    assert_close_sums(s, orc.tally_sum, what="tally_sum")
+    assert_close_sums(s2, orc.tally_sumsq, what="tally_sumsq")
+    if p.get("collision_tally"):
+        c, _ = gb.raw_collision()
+        assert_close_sums(c, orc.col_sum, what="col_sum")
+    from gpu_util import assert_counters
+    assert_counters(gb.counters(), orc)
+    return orc
 
 
 def test_census_steps_checkpoint_resume_matches_oracle():
@@ -617,18 +639,40 @@ def test_census_steps_checkpoint_resume_matches_oracle():
     p["mesh"]["n"] = np.array([12, 20, 12, 10], np.int32)
     p["collision_tally"] = True
     n, seed = 4000, 161
-    gb, steps = _stepped_with_checkpoint(p, n, seed, _ev(1 << 13))
+    gb, steps, _ = _stepped_with_checkpoint(p, n, seed, _ev(1 << 13))
     assert 3 <= steps <= 6
-    orc = O.OracleRun(p)
-    _, ho = orc.run(n, seed, per_history=True)
-    assert np.array_equal(gb.history_scores(), ho)
-    s, s2 = gb.raw()
-    assert_close_sums(s, orc.tally_sum, what="tally_sum")
-    assert_close_sums(s2, orc.tally_sumsq, what="tally_sumsq")
-    c, c2 = gb.raw_collision()
-    assert_close_sums(c, orc.col_sum, what="col_sum")
-    from gpu_util import assert_counters
-    assert_counters(gb.counters(), orc)
+    _check_stepped_against_oracle(gb, p, n, seed)
+    gb.close()
+
+
+@pytest.mark.parametrize("hybrid", [False, True])
+def test_stepped_run_over_several_resident_chunks(hybrid):
+    """4500 histories with 1000 resident: five chunks (the last one ragged),
+    each taken census step by census step, under three batches whose edges
+    fall inside chunks; checkpointed inside the second or third chunk and
+    resumed in a fresh handle."""
+    mc = _mcdc()
+    p = W.config2(n_census=3)
+    p["mesh"]["n"] = np.array([12, 20, 12, 10], np.int32)
+    p["n_batches"] = 3
+    p["collision_tally"] = True
+    n, seed = 4500, 163
+    opt = mc.make_options(mc.SCHED_HYBRID if hybrid else mc.SCHED_EVENT, event_chunk=1000)
+    ga = mc.Problem(p, opt)
+    ga.run_begin(n, seed)
+    per_chunk = 0
+    while ga.run_state().segment == 0:
+        assert not ga.run_step()
+        per_chunk += 1
+    ga.close()
+    # a chunk takes one step per census step that some particle of it reaches
+    assert 2 <= per_chunk <= 4
+    gb, steps, st = _stepped_with_checkpoint(p, n, seed, opt, stop_after=2 * per_chunk + 1)
+    assert 1 <= st.segment <= 2
+    assert 5 * 2 <= steps <= 5 * 4
+    _check_stepped_against_oracle(gb, p, n, seed)
+    c = gb.counters()
+    assert c["batches"] == 3 and c["histories"] == n
     gb.close()
 
 
@@ -638,38 +682,88 @@ def test_census_steps_checkpoint_resume_with_population_control():
     p["population_control"] = dict(target=1.5)
     p["n_batches"] = 1
     n, seed = 3000, 162
-    gb, steps = _stepped_with_checkpoint(p, n, seed, _ev(1 << 12), stop_after=3)
+    gb, steps, _ = _stepped_with_checkpoint(p, n, seed, _ev(1 << 12), stop_after=3)
     assert steps == 8
-    orc = O.OracleRun(p)
-    _, ho = orc.run(n, seed, per_history=True)
-    np.testing.assert_allclose(gb.history_scores(), ho, rtol=1e-12, atol=1e-300)
-    s, _ = gb.raw()
-    assert_close_sums(s, orc.tally_sum, what="tally_sum")
-    from gpu_util import assert_counters
-    assert_counters(gb.counters(), orc)
+    _check_stepped_against_oracle(gb, p, n, seed, exact_scores=False)
     gb.close()
 
 
-def test_census_step_control_rejections():
+def test_stepped_run_with_population_control_per_batch():
+    """Population control over three batches (1000, 1000, 1001 histories),
+    each one resident chunk controlled on its own, as a plain run takes
+    them; checkpointed inside the second batch."""
+    p = W.infinite_medium(1.0, [[0.9]], [1.0], half=5.0, t_end=8.0, nt=8)
+    p["census"] = np.linspace(1.0, 8.0, 8)
+    p["population_control"] = dict(target=1.5)
+    p["n_batches"] = 3
+    n, seed = 3001, 164
+    gb, steps, st = _stepped_with_checkpoint(p, n, seed, _ev(1 << 11), stop_after=10)
+    assert st.segment == 1
+    assert steps == 24
+    orc = _check_stepped_against_oracle(gb, p, n, seed, exact_scores=False)
+    assert orc.counters["pc_copy"] > 100
+    gb.close()
+
+
+def test_history_schedule_stepped_run_batch_by_batch():
+    """Under the history schedule a step is one batch; checkpointed after two
+    of four batches."""
     mc = _mcdc()
     p = W.config2(n_census=3)
-    gh = mc.Problem(p)                               # history schedule
-    with pytest.raises(mc.McdcError):
-        gh.run_begin(100, 1)
-    gh.close()
+    p["mesh"]["n"] = np.array([12, 20, 12, 10], np.int32)
+    p["n_batches"] = 4
+    p["collision_tally"] = True
+    n, seed = 4001, 165
+    gb, steps, st = _stepped_with_checkpoint(p, n, seed, mc.make_options(mc.SCHED_HISTORY))
+    assert st.segment == 2 and steps == 4
+    _check_stepped_against_oracle(gb, p, n, seed)
+    assert gb.counters()["batches"] == 4
+    gb.close()
+
+
+def test_stepped_run_rejections():
+    mc = _mcdc()
+    p = W.config2(n_census=3)
     ge = mc.Problem(p, _ev(1000))
-    with pytest.raises(mc.McdcError):
-        ge.run_begin(5000, 1)                        # more than the resident histories
-    with pytest.raises(mc.McdcError):
+    with pytest.raises(mc.McdcError) as e:
         ge.run_step()                                # no run in progress
-    ge.run_begin(500, 1)
-    with pytest.raises(mc.McdcError):
+    assert e.value.status == mc.E_STATE
+    with pytest.raises(mc.McdcError) as e:
+        ge.run_begin(0, 1)                           # empty run
+    assert e.value.status == mc.E_INVALID
+    ge.run_begin(2500, 1)                            # three resident chunks
+    with pytest.raises(mc.McdcError) as e:
         ge.run(10, 2)                                # a stepped run is in progress
+    assert e.value.status == mc.E_STATE
+    with pytest.raises(mc.McdcError) as e:
+        ge.run_begin(10, 2)
+    assert e.value.status == mc.E_STATE
     while not ge.run_step():
         pass
     ge.run(10, 2)                                    # and afterwards plain runs work again
-    assert ge.counters()["histories"] == 510
+    assert ge.counters()["histories"] == 2510
+    st = ge.run_state()
+    assert st.in_run == 0
+    st.in_run = 1
+    st.segment = 3                                   # the run had segments 0..2
+    with pytest.raises(mc.McdcError) as e:
+        ge.set_run_state(st)
+    assert e.value.status == mc.E_INVALID
+    with pytest.raises(mc.McdcError) as e:
+        ge.run_step()                                # the bad record left no run in progress
+    assert e.value.status == mc.E_STATE
     ge.close()
+    q = W.infinite_medium(1.0, [[0.9]], [1.0], half=5.0, t_end=8.0, nt=8)
+    q["population_control"] = dict(target=1.0)
+    q["n_batches"] = 2
+    gq = mc.Problem(q, _ev(1000))
+    with pytest.raises(mc.McdcError) as e:
+        gq.run_begin(2500, 1)                        # 1250 histories per controlled batch
+    assert e.value.status == mc.E_INVALID
+    gq.run_begin(2000, 1)
+    while not gq.run_step():
+        pass
+    gq.close()
 
 
 # ---------------------------------------------------------------------------

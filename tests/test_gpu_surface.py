@@ -99,7 +99,7 @@ def test_surface_tally_census_steps_checkpoint_resume():
     p["mesh"]["n"] = np.array([12, 20, 12, 10], np.int32)
     p["surface_tally"] = dict(axis=1, pos=20.0)
     n, seed = 4000, 197
-    gb, steps = _stepped_with_checkpoint(p, n, seed, _opt("hybrid", 1 << 13))
+    gb, steps, _ = _stepped_with_checkpoint(p, n, seed, _opt("hybrid", 1 << 13))
     orc = O.OracleRun(p)
     _, ho = orc.run(n, seed, per_history=True)
     assert np.array_equal(gb.history_scores(), ho)
