@@ -59,12 +59,14 @@ enum { MCDC_SRC_POINT = 0, MCDC_SRC_BOX = 1 };
  * EVENT: particles live in banks and move through the transport loop one
  * event class per launch.
  * HYBRID: a lead stage follows each history in one work-item, split daughters
- * on its stack (daughters past a full stack go to the event banks at once),
- * for at most 64 flights of that history (MCDC_LEAD_FLIGHTS in the library);
- * then the particle and its stacked daughters go to the event banks and the
- * event stages finish them.  With population control or census-step control
- * a particle that reaches an intermediate census goes to the census bank
- * instead.  Analog histories that end within the budget never touch the
+ * on its stack (daughters past a full stack go to the banks at once), for at
+ * most 32 flights of that history (MCDC_LEAD_FLIGHTS in the library); then
+ * the particle and its stacked daughters go to the banks.  A re-lead stage
+ * follows each banked particle the same way, for at most 8 flights of it and
+ * its daughters (MCDC_RELEAD_FLIGHTS), banking what is left for its next
+ * launch, until the banks are empty.  With population control or census-step
+ * control a particle that reaches an intermediate census goes to the census
+ * bank instead.  Analog histories that end within the budget never touch the
  * banks.  HYBRID uses the EVENT schedule's workspace and supports everything
  * it does. */
 enum { MCDC_SCHED_AUTO = 0, MCDC_SCHED_HISTORY = 1, MCDC_SCHED_EVENT = 2, MCDC_SCHED_HYBRID = 3 };

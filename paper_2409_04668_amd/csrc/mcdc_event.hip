@@ -229,12 +229,15 @@ __global__ void __launch_bounds__(256) k_ev_source(DevProblem, RunArgs A, EvBank
 // the history is handed to the banks: short histories finish in the lead,
 // long split chains are spread over the grid instead of holding one
 // work-item.  The re-lead stage's budget counts the flights of one banked
-// particle and its daughters.
+// particle and its daughters.  Measured on the learned-window duct (lead /
+// re-lead budget, histories/s with the window map and with the network at
+// every check): 64/64 4.95e8 and 3.23e8, 32/16 5.37e8 and 3.86e8, 32/8
+// 5.41e8 and 3.98e8, 16/8 5.33e8 and 3.97e8, 8/8 5.21e8 and 3.93e8.
 #ifndef MCDC_LEAD_FLIGHTS
-#define MCDC_LEAD_FLIGHTS 64
+#define MCDC_LEAD_FLIGHTS 32
 #endif
 #ifndef MCDC_RELEAD_FLIGHTS
-#define MCDC_RELEAD_FLIGHTS MCDC_LEAD_FLIGHTS
+#define MCDC_RELEAD_FLIGHTS 8
 #endif
 
 // Context of a history in the lead stage: one work-item owns the history (its
