@@ -267,8 +267,9 @@ int mcdc_run_keff(mcdc_handle h, const mcdc_keff_opts *o, uint64_t seed, void *d
 /* Cancel word of the handle: on != 0 asks every later and every running
  * launch of the handle's runs to stop (in the persistent kernels one
  * work-item per workgroup reads it from host-coherent memory before the
- * first history and at every 64th history it starts, and shares it in LDS;
- * every work-item checks that copy when it starts a history, and a batched
+ * first history and at every 64th history (or banked particle) it starts,
+ * and shares it in LDS; every work-item checks that copy when it starts a
+ * history or banked particle, and a batched
  * run's workgroups read it every 8th work chunk; they then end early,
  * leaving histories in flight unfinished; the host side of
  * mcdc_run / mcdc_run_step / mcdc_run_batch stops launching and returns

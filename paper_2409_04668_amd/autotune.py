@@ -185,7 +185,7 @@ def plan_hot_tile(prob, pilot=2_000_000, max_bins=None, seed=4242):
     return grow_tile(s.reshape(G, nt, nz, ny, nx), max_bins)
 
 
-def tune_batch(probs, n_hist, chunks=(512, 2048, 8192), waves=(8, 16), cache_path=DEFAULT_CACHE,
+def tune_batch(probs, n_hist, chunks=(2048, 8192, 16384), waves=(8, 16), cache_path=DEFAULT_CACHE,
                use_cache=True, seed=777):
     """Chunk size and occupancy of the batched persistent kernel."""
     import torch

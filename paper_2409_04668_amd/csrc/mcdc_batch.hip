@@ -9,7 +9,9 @@
 //   k_b_persistent grid sized to the chip; each workgroup pops chunks
 //                  (problem p, entry range) from the device work queue until it
 //                  is empty.  A chunk belongs to one problem, so the problem's
-//                  description is wave-uniform (scalar loads).  Particles fly
+//                  description is wave-uniform (scalar loads).  Within a chunk
+//                  each work-item takes the next entry when its particle ends
+//                  and runs one flight per loop turn.  Particles fly
 //                  until they end or reach the census time of step s; those
 //                  that reach it are appended (one atomic per wave) to the
 //                  problem's queue for step s+1.  Tally pieces in the step's
@@ -169,11 +171,13 @@ __global__ void __launch_bounds__(1024) k_b_plan(BDev D, uint32_t step) {
     }
 }
 
+// Four waves per SIMD (at most 128 VGPRs): with three, the 256-problem batch
+// runs at 2.07e9 histories/s instead of 2.70e9.
 template <bool TILE>
-__global__ void __launch_bounds__(512) k_b_persistent(BDev D) {
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k_b_persistent(BDev D) {
     extern __shared__ double s_tile[];
     __shared__ Shared S;
-    __shared__ uint32_t s_chunk, s_cancel;
+    __shared__ uint32_t s_chunk, s_cancel, s_entry;
     const BCtl *c = D.ctl;
     const uint32_t step = c->step, cur = step & 1u, total = c->total_chunks;
     RunArgs A{};
@@ -231,12 +235,20 @@ __global__ void __launch_bounds__(512) k_b_persistent(BDev D) {
                         TILE && BP.slice ? (step + 1) * BP.slice : 0u};
         uint32_t n_flight = 0, n_piece = 0, n_new = 0;
         double path = 0.0;
-        for (uint32_t e = e0 + threadIdx.x; e - threadIdx.x < e1; e += blockDim.x) {
-            const bool valid = e < e1;
-            bool to_census = false;
-            uint32_t local = 0;
-            if (valid) {
-                Part q;
+        // work-items take the chunk's entries one at a time from a counter in
+        // LDS and run one flight per loop turn: a lane whose particle ends (or
+        // reaches the census) takes the next entry while the others fly on,
+        // instead of the wave waiting for its longest history per entry
+        if (threadIdx.x == 0) s_entry = e0;
+        __syncthreads();
+        const uint32_t nxt = cur ^ 1u;
+        Part q;
+        q.alive = false;
+        uint32_t local = 0;
+        for (;;) {
+            if (!q.alive) {
+                const uint32_t e = atomicAdd(&s_entry, 1u);
+                if (e >= e1) break;
                 if (step == 0) {
                     local = e;
                     BatchCtx C{P, A, D, D.hist_base[p] + local, BP.bank_off + local};
@@ -244,40 +256,30 @@ __global__ void __launch_bounds__(512) k_b_persistent(BDev D) {
                     D.bi[6 * D.cap + C.slot] = 0u;
                     n_new += 1;
                     stage_source(P, A, S, C, q);
+                    if (!q.alive) continue;
                 } else {
                     local = D.q[(uint64_t)cur * D.cap + BP.bank_off + e];
                     bload(D, BP.bank_off + local, q);
                 }
-                BatchCtx C{P, A, D, D.hist_base[p] + local, BP.bank_off + local};
-                while (q.alive) {
-                    double d;
-                    const int ev = stage_flight(P, A, S, tally, C, q, d, n_piece, path);
-                    if (ev >= 0) n_flight += 1;
-                    if (ev == EV_SURFACE) stage_surface(P, A, S, C, q, d);
-                    else if (ev == EV_SCATTER) stage_collision(P, A, S, C, q, d);
-                    else if (ev == EV_CENSUS) {
-                        to_census = true;
-                        break;
-                    }
-                }
-                if (to_census) bstore(D, BP.bank_off + local, q);
             }
-            // census survivors: problem-local index into the next queue
-            const uint32_t nxt = cur ^ 1u;
-            const uint64_t m = __ballot(to_census);
-            if (m) {
-                const int lane = (int)__lane_id();
-                const int leader = __ffsll((long long)m) - 1;
-                uint32_t base = 0;
-                if (lane == leader) base = atomicAdd(&D.nq[nxt * D.n_prob + p], (uint32_t)__popcll(m));
-                base = __shfl(base, leader);
-                if (to_census) {
-                    const uint32_t off = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                    D.q[(uint64_t)nxt * D.cap + BP.bank_off + base + off] = local;
-                }
+            BatchCtx C{P, A, D, D.hist_base[p] + local, BP.bank_off + local};
+            double d;
+            const int ev = stage_flight(P, A, S, tally, C, q, d, n_piece, path);
+            if (ev >= 0) n_flight += 1;
+            if (!q.alive) continue;
+            if (ev == EV_SURFACE) {
+                stage_surface(P, A, S, C, q, d);
+            } else if (ev == EV_SCATTER) {
+                stage_collision(P, A, S, C, q, d);
+            } else if (ev == EV_CENSUS) {
+                // census survivor: its problem-local index into the next queue
+                bstore(D, BP.bank_off + local, q);
+                const uint32_t pos = wave_reserve_one(&D.nq[nxt * D.n_prob + p]);
+                D.q[(uint64_t)nxt * D.cap + BP.bank_off + pos] = local;
+                q.alive = false;
             }
         }
+        __syncthreads();                      // the chunk's entries are done before s_entry is reused
         if (n_new) atomicAdd(&S.cnt[C_HIST], (unsigned long long)n_new);
         atomicAdd(&S.cnt[C_FLIGHT], (unsigned long long)n_flight);
         atomicAdd(&S.cnt[C_PIECE], (unsigned long long)n_piece);

@@ -59,6 +59,18 @@ MCDC_DEV uint32_t wave_reserve_n(uint32_t *count, uint32_t n) {
     return base + mine;
 }
 
+// One entry of *count for every active lane with one atomic per wave; the
+// active lanes take consecutive entries in ascending lane order.
+MCDC_DEV uint32_t wave_reserve_one(uint32_t *count) {
+    const uint64_t act = __ballot(true);
+    const int leader = __ffsll((long long)act) - 1;
+    uint32_t base = 0;
+    if ((int)__lane_id() == leader) base = atomicAdd(count, (uint32_t)__popcll(act));
+    base = (uint32_t)__builtin_amdgcn_readlane((int)base, leader);
+    return base + __builtin_amdgcn_mbcnt_hi((uint32_t)(act >> 32),
+                                            __builtin_amdgcn_mbcnt_lo((uint32_t)act, 0u));
+}
+
 MCDC_DEV void trace_rec(const RunArgs &A, uint64_t hist, Part &q, int type, double aux) {
     const uint32_t seq = q.seq;
     q.seq += 1u;
