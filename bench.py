@@ -193,7 +193,7 @@ def duct_options(args, mcdc, prob):
         sched = {"history": mcdc.SCHED_HISTORY, "event": mcdc.SCHED_EVENT,
                  "hybrid": mcdc.SCHED_HYBRID}[args.schedule]
         oargs = dict(schedule=sched, event_chunk=1 << 25)
-        if tile is not None and sched != mcdc.SCHED_EVENT:
+        if tile is not None:
             oargs["tile"] = [[int(v) for v in tile[0]], [int(v) for v in tile[1]]]
     if args.waves_per_cu:
         oargs["waves_per_cu"] = args.waves_per_cu
@@ -322,7 +322,7 @@ def main():
                             "workload": "Kobayashi dog-leg void duct, time dependent, 1 group",
                             "source": "Sec. Performance (GPU profiling paragraph)"}
     gp.close()
-    # the same step under the other schedules (tile where they take one),
+    # the same step under the other schedules (with the tile),
     # one timed step after a warm-up, as a comparison
     if not args.no_other_schedule:
         out["other_schedules"] = {}
@@ -330,7 +330,7 @@ def main():
             if osched == sched:
                 continue
             o = dict(schedule=osched, event_chunk=1 << 25)
-            if tile is not None and osched != mcdc.SCHED_EVENT:
+            if tile is not None:
                 o["tile"] = tile
             go = mcdc.Problem(prob, mcdc.make_options(**o))
             go.run(N, seed)

@@ -84,7 +84,8 @@ def tune_single(prob, pilot=2_000_000, waves=(8, 12, 16, 24, 32),
     Tries the history schedule at each occupancy and the event and hybrid
     schedules at each chunk size (`schedules` restricts the set).  `tile` =
     (lo[5], n[5]), e.g. from plan_hot_tile: the LDS hot tile of the history
-    schedule and of the hybrid schedule's lead stage.  Population control runs
+    schedule, of the hybrid schedule's lead and re-lead stages and of the
+    event schedule's flight stage.  Population control runs
     only in the event and hybrid schedules, with every batch of the pilot
     resident (chunks below the batch size are skipped)."""
     tj = None if tile is None else [[int(v) for v in tile[0]], [int(v) for v in tile[1]]]
@@ -98,7 +99,7 @@ def tune_single(prob, pilot=2_000_000, waves=(8, 12, 16, 24, 32),
     pc = prob.get("population_control") is not None
 
     def trial(**o):
-        if tj is not None and o["schedule"] != mcdc.SCHED_EVENT:
+        if tj is not None:
             o["tile"] = tj
         trials.append((o, _time_single(prob, mcdc.make_options(**o), pilot, seed)))
 

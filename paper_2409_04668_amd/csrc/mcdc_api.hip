@@ -171,10 +171,10 @@ Options resolve_options(const mcdc_options *o) {
     // the hybrid schedule is the event schedule with a lead stage
     r.lead = r.schedule == MCDC_SCHED_HYBRID;
     if (r.lead) r.schedule = MCDC_SCHED_EVENT;
-    // the hot tile runs one 1024-work-item workgroup per CU-share of LDS
-    // (history schedule, and the lead stage of the hybrid schedule)
-    if (r.tile_bins && (r.schedule == MCDC_SCHED_HISTORY || r.lead)) r.block = 1024;
-    else r.tile_bins = 0;
+    // the hot tile runs one 1024-work-item workgroup per CU-share of LDS (the
+    // history schedule, the lead and re-lead stages of the hybrid schedule,
+    // the event schedule's flight stage)
+    if (r.tile_bins) r.block = 1024;
     r.grid = history_grid(r.block, r.waves_per_cu);
     r.n_lanes = (uint64_t)r.grid * r.block;
     return r;

@@ -486,22 +486,39 @@ __global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_ev_lead(DevProblem, R
     shared_flush(S, A.acc);
 }
 
-template <bool WW>
-__global__ void __launch_bounds__(256) k_ev_flight(DevProblem, RunArgs A, EvBank B) {
+// Flight stage.  LDS 0: tally updates to HBM atomics, the workgroups stride
+// over the active bank.  LDS 2: workgroup w takes the contiguous entries
+// [w n / G, (w+1) n / G) (particles stay near the order of their histories,
+// so a range holds few batches) and keeps the hot tile of its first
+// particle's batch in LDS, as the lead stage does.
+template <bool WW, int LDS>
+__global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_ev_flight(DevProblem, RunArgs A, EvBank B) {
     CP &P = kernel_problem();
+    extern __shared__ double s_tile[];
     __shared__ Shared S;
     if (B.ctl->paused) return;
     shared_zero(S);
-    __syncthreads();
     const uint32_t cur = B.ctl->cur, cen = B.ctl->cen;
     const uint32_t n = min(B.ctl->n_act[cur], B.cap);   // counts can pass cap on overflow
+    uint32_t r0 = blockIdx.x * blockDim.x, r1 = n, stride = gridDim.x * blockDim.x;
+    if (LDS == 2) {
+        r0 = (uint32_t)((uint64_t)blockIdx.x * n / gridDim.x);
+        r1 = (uint32_t)((uint64_t)(blockIdx.x + 1) * n / gridDim.x);
+        stride = blockDim.x;
+        if (r0 < r1)
+            for (uint32_t i = threadIdx.x; i < P.hot_bins; i += blockDim.x) s_tile[i] = 0.0;
+    }
+    __syncthreads();
     const Bank in = B.b[cur], X = B.b[R_X], CB = B.b[cen];
+    const uint64_t b_tile = LDS == 2 && r0 < r1 ? batch_of(A, in.i[6 * (size_t)B.cap + r0]) : 0;
+    LeadTally<LDS> tally;
+    tally.init(P, s_tile);
     uint32_t n_piece = 0, n_flight = 0;
     double path = 0.0;
-    for (uint32_t j0 = blockIdx.x * blockDim.x; j0 < n; j0 += gridDim.x * blockDim.x) {
+    for (uint32_t j0 = r0; j0 < r1; j0 += stride) {
         CP &PL = problem_reload(P);
         const uint32_t jj = j0 + threadIdx.x;
-        const bool valid = jj < n;
+        const bool valid = jj < r1;
         int ev = -1;
         Part q;
         double d = 0.0;
@@ -509,8 +526,8 @@ __global__ void __launch_bounds__(256) k_ev_flight(DevProblem, RunArgs A, EvBank
         if (valid) {
             bank_load(in, B.cap, jj, q, d, slot);
             EvCtx<WW> C{PL, A, B, slot};
-            GlobalTally tally{A.tally + C.batch() * (uint64_t)PL.nbins};
-            ev = stage_flight(PL, A, S, tally, C, q, d, n_piece, path);
+            tally.select(PL, A, C.batch(), b_tile);
+            ev = stage_flight(PL, A, S, tally.t, C, q, d, n_piece, path);
             if (ev >= 0) n_flight += 1;
             if (!q.alive) ev = -1;
         }
@@ -528,6 +545,7 @@ __global__ void __launch_bounds__(256) k_ev_flight(DevProblem, RunArgs A, EvBank
     atomicAdd(&S.cnt[C_PIECE], (unsigned long long)n_piece);
     atomicAdd(&S.wsum[W_PATH], path);
     __syncthreads();
+    if (LDS == 2 && r0 < r1) hot_tile_flush(P, s_tile, A.tally + b_tile * (uint64_t)P.nbins);
     shared_flush(S, A.acc);
 }
 
@@ -986,6 +1004,24 @@ static void ev_launch_relead(mcdc_problem *h, const RunArgs &A, hipStream_t s) {
 #undef MCDC_RELEAD
 }
 
+// The flight stage: with a hot tile on the options' grid of 1024-work-item
+// workgroups and the tile in dynamic LDS, else on the event grid.
+static void ev_launch_flight(mcdc_problem *h, const RunArgs &A, hipStream_t s) {
+    const DevProblem &P = h->P;
+    const EventState *E = h->ev;
+    const bool ww = P.ww_on != 0;
+    if (P.hot_bins) {
+        const size_t shm = (size_t)P.hot_bins * sizeof(double);
+        const void *k = ww ? (const void *)k_ev_flight<true, 2> : (const void *)k_ev_flight<false, 2>;
+        if (shm > 65536) (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+        if (ww) hipLaunchKernelGGL((k_ev_flight<true, 2>), dim3(h->opt.grid), dim3(h->opt.block), shm, s, P, A, E->B);
+        else hipLaunchKernelGGL((k_ev_flight<false, 2>), dim3(h->opt.grid), dim3(h->opt.block), shm, s, P, A, E->B);
+    } else {
+        if (ww) hipLaunchKernelGGL((k_ev_flight<true, 0>), dim3(E->grid), dim3(E->block), 0, s, P, A, E->B);
+        else hipLaunchKernelGGL((k_ev_flight<false, 0>), dim3(E->grid), dim3(E->block), 0, s, P, A, E->B);
+    }
+}
+
 // Iterate the stages of the resident chunk until it ends (or, under
 // census-step control, a census step begins): K iterations per host check.
 // An iteration is the flight and interaction stages, or in the hybrid
@@ -1009,8 +1045,7 @@ static int ev_iterate(mcdc_problem *h, const RunArgs &A, hipStream_t s, bool &do
             } else {
                 // timed stage: the flight stage (the lead stage in the hybrid schedule)
                 timing_begin(h, s);
-                if (ww) hipLaunchKernelGGL((k_ev_flight<true>), dim3(grid), dim3(block), 0, s, P, A, B);
-                else hipLaunchKernelGGL((k_ev_flight<false>), dim3(grid), dim3(block), 0, s, P, A, B);
+                ev_launch_flight(h, A, s);
                 timing_end(h, s);
                 if (!ww) hipLaunchKernelGGL((k_ev_interact<0>), dim3(grid), dim3(block), 0, s, P, A, B);
                 else if (P.ww_map) hipLaunchKernelGGL((k_ev_interact<2>), dim3(grid), dim3(block), 0, s, P, A, B);

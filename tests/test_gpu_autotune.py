@@ -68,7 +68,7 @@ def test_batch_tuner_returns_a_working_shape():
     bp.close()
 
 
-def test_tuner_gives_the_tile_to_the_history_and_hybrid_trials():
+def test_tuner_gives_the_tile_to_every_trial():
     from paper_2409_04668_amd import autotune, mcdc
     p = W.config2(n_census=3)
     tile = ([2, 3, 1, 0, 0], [10, 12, 9, 6, 1])
@@ -77,10 +77,7 @@ def test_tuner_gives_the_tile_to_the_history_and_hybrid_trials():
     scheds = [t["options"]["schedule"] for t in res["trials"]]
     assert scheds == [mcdc.SCHED_HISTORY, mcdc.SCHED_EVENT, mcdc.SCHED_HYBRID]
     for t in res["trials"]:
-        has = "tile" in t["options"]
-        assert has == (t["options"]["schedule"] != mcdc.SCHED_EVENT)
-        if has:
-            assert t["options"]["tile"] == [list(tile[0]), list(tile[1])]
+        assert t["options"]["tile"] == [list(tile[0]), list(tile[1])]
     gp = mcdc.Problem(p, mcdc.make_options(**res["options"]))
     gp.run(10_000, 3)
     assert gp.counters()["histories"] == 10_000

@@ -199,36 +199,41 @@ def test_hybrid_weight_window_map_matches_event_schedule_at_scale():
 
 
 # ---------------------------------------------------------------------------
-# LDS hot tile in the lead stage: one batch per workgroup tile
+# LDS hot tile in the lead and re-lead stages (hybrid) and in the flight stage
+# (event): one batch per workgroup tile
 # ---------------------------------------------------------------------------
 
-def _hy_tile(tile, chunk=0):
+def _hy_tile(tile, chunk=0, sched="hybrid"):
     mc = _mcdc()
-    return mc.make_options(mc.SCHED_HYBRID, event_chunk=chunk, tile=tile)
+    return mc.make_options(mc.SCHED_HYBRID if sched == "hybrid" else mc.SCHED_EVENT,
+                           event_chunk=chunk, tile=tile)
 
 
-def test_hybrid_hot_tile_duct_batches_straddle_workgroups():
+@pytest.mark.parametrize("sched", ["hybrid", "event"])
+def test_hot_tile_duct_batches_straddle_workgroups(sched):
     """3000 histories in 20 batches of 150 over workgroup ranges of other
     sizes: a workgroup's range crosses batch boundaries, and the batch slices
     (sums of squares per batch) still match the oracle."""
     p = W.config2(n_census=3)
     tile = ([2, 3, 1, 0, 0], [10, 12, 9, 6, 1])        # x, y, z, t, g
-    full_parity(p, 3000, seed=185, trace_cap=200000, options=_hy_tile(tile))
+    full_parity(p, 3000, seed=185, trace_cap=200000, options=_hy_tile(tile, sched=sched))
 
 
-def test_hybrid_hot_tile_multigroup_partial_groups_ragged_chunks():
+@pytest.mark.parametrize("sched", ["hybrid", "event"])
+def test_hot_tile_multigroup_partial_groups_ragged_chunks(sched):
     p = W.config3()
     tile = ([0, 0, 0, 0, 3], [12, 12, 10, 2, 4])       # groups 3..6 only
-    full_parity(p, 400, seed=186, trace_cap=300000, options=_hy_tile(tile, chunk=150))
+    full_parity(p, 400, seed=186, trace_cap=300000, options=_hy_tile(tile, chunk=150, sched=sched))
 
 
-def test_hybrid_hot_tile_weight_window_map():
+@pytest.mark.parametrize("sched", ["hybrid", "event"])
+def test_hot_tile_weight_window_map(sched):
     p = W.config2(n_census=3)
     p["ww"] = dict(params=ramp_mlp(-1.5, noise_seed=5), hidden=64, logk=0.3, ratio=5.0, n_max=10,
                    map=(12, 20, 12, 10))
     p["collision_tally"] = True
     tile = ([0, 0, 0, 0, 0], [16, 20, 10, 4, 1])
-    gp, orc, tg, to, hg, ho = run_pair(p, 900, 187, trace_cap=400000, options=_hy_tile(tile))
+    gp, orc, tg, to, hg, ho = run_pair(p, 900, 187, trace_cap=400000, options=_hy_tile(tile, sched=sched))
     assert_traces_equal(tg[0], to[0])
     np.testing.assert_allclose(hg[0], ho[0], rtol=1e-12, atol=1e-300)
     s, s2 = gp.raw()
@@ -238,10 +243,10 @@ def test_hybrid_hot_tile_weight_window_map():
     assert orc.counters["split"] > 10
 
 
-def test_hybrid_planned_tile_at_scale_matches_history_schedule():
+def test_planned_tile_at_scale_matches_history_schedule():
     """The autotuner's tile for the full duct problem, 5e6 histories: the
-    hybrid schedule with the tile gives the history schedule's per-history
-    results bit for bit and its tallies to reordering."""
+    hybrid and event schedules with the tile give the history schedule's
+    per-history results bit for bit and its tallies to reordering."""
     mc = _mcdc()
     from paper_2409_04668_amd import autotune
     p = W.config2()
@@ -249,16 +254,18 @@ def test_hybrid_planned_tile_at_scale_matches_history_schedule():
     assert tile is not None and frac > 0.5
     n = 5_000_000
     res = []
-    for opt in (mc.make_options(mc.SCHED_HISTORY, tile=tile), _hy_tile(tile, chunk=1 << 22)):
+    for opt in (mc.make_options(mc.SCHED_HISTORY, tile=tile), _hy_tile(tile, chunk=1 << 22),
+                _hy_tile(tile, chunk=1 << 22, sched="event")):
         gp = mc.Problem(p, opt)
         gp.set_history_scores(n)
         gp.run(n, 188)
         res.append((gp.history_scores(), gp.raw(), gp.counters()))
         gp.close()
-    assert np.array_equal(res[0][0], res[1][0])
-    assert_close_sums(res[0][1][0], res[1][1][0], what="tally")
-    assert_close_sums(res[0][1][1], res[1][1][1], what="tally_sumsq")
-    assert res[0][2]["pieces"] == res[1][2]["pieces"]
+    for other in res[1:]:
+        assert np.array_equal(res[0][0], other[0])
+        assert_close_sums(res[0][1][0], other[1][0], what="tally")
+        assert_close_sums(res[0][1][1], other[1][1], what="tally_sumsq")
+        assert res[0][2]["pieces"] == other[2]["pieces"]
 
 
 def test_full_size_duct_hybrid_tile_sampled_histories():
