@@ -23,9 +23,11 @@
 // split daughters on a per-work-item stack, until the history ends or has
 // taken MCDC_LEAD_FLIGHTS flights (or, with population control or
 // census-step control, a particle reaches a census); what is left then goes
-// to the banks.  Short histories never touch the banks; long split chains,
-// which would serialise on one work-item, are spread over the grid by the
-// event stages.
+// to the banks.  In place of the flight and interaction stages, a re-lead
+// stage then runs the same loop over the banked particles, MCDC_RELEAD_FLIGHTS
+// flights each before what is left is banked again, until the banks are
+// empty.  Short histories never touch the banks; long split chains, which
+// would serialise on one work-item, are spread over the grid.
 #include "lane_stack.hpp"
 #include "mcdc_runtime.hpp"
 #include "transport_stages.hpp"
@@ -259,8 +261,15 @@ struct LeadCtx {
     uint32_t cur;
     uint32_t slot;
     double xh, path;
+    // flights of the history: the lead stage's own count; in the re-lead
+    // stage the history's count when the particle was taken (ev0) plus this
+    // work-item's flights since, added to the per-history count when the
+    // work-item moves on (so a flight does not wait on a returning atomic;
+    // the event cap of a history split over several work-items can then
+    // trigger a few flights late)
     uint32_t events;
     int sp;
+    uint32_t ev0 = 0;
     MCDC_DEV uint64_t hist() const { return A.h_begin + slot; }
     MCDC_DEV uint64_t batch() const {
         const uint64_t r = A.h_begin + slot - A.h_run0;
@@ -270,12 +279,18 @@ struct LeadCtx {
     MCDC_DEV double *surf_tally() const { return A.surf + batch() * (uint64_t)P.surf_nbins; }
     MCDC_DEV const float *mlp_params(CP &Pp) const { return Pp.ww_params; }
     MCDC_DEV bool count_flight() {
-        if constexpr (BANK) {
-            const uint32_t e = atomicAdd(&B.events[slot], 1u) + 1u;
-            return (int64_t)e <= P.max_events;
-        }
         events += 1u;
         return (int64_t)events <= P.max_events;
+    }
+    // re-lead stage: take over the history of bank slot s / hand back the
+    // flights counted since
+    MCDC_DEV void take(uint32_t s) {
+        slot = s;
+        ev0 = events = B.events[s];
+    }
+    MCDC_DEV void flush_events() const {
+        if (events != ev0)
+            __hip_atomic_fetch_add(&B.events[slot], events - ev0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     MCDC_DEV void add_score(double v) {
         if constexpr (BANK) unsafeAtomicAdd(&B.xh[slot], v);
@@ -393,8 +408,8 @@ MCDC_DEV void lead_turn(CP &PL, const RunArgs &A, const EvBank &B, Shared &S, co
 // particle, then the daughters on the stack, then the next slot.  After
 // MCDC_LEAD_FLIGHTS flights of one history its particle and stacked daughters
 // go into the active bank; with population control or census-step control a
-// particle that reaches a census goes into the census bank.  The event stages
-// finish what was banked.  LDS: 0 tally in HBM, 2 hot tile in LDS.
+// particle that reaches a census goes into the census bank.  The re-lead
+// stage finishes what was banked.  LDS: 0 tally in HBM, 2 hot tile in LDS.
 template <int LDS, int WW>
 __global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_ev_lead(DevProblem, RunArgs A, EvBank B,
                                                                   uint32_t n) {
@@ -701,7 +716,8 @@ __global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_ev_relead(DevProblem,
                 double d0;
                 uint32_t slot;
                 bank_load(in, B.cap, j, q, d0, slot);
-                C.slot = slot;
+                C.flush_events();
+                C.take(slot);
                 flights = 0;
                 tally.select(PL, A, batch_of(A, slot), b_tile);
             }
@@ -709,6 +725,7 @@ __global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_ev_relead(DevProblem,
         lead_turn<WW, MCDC_RELEAD_FLIGHTS>(PL, A, B, S, tally.t, C, q, flights, n_flight, n_piece,
                                            path, stop_at_census, cen);
     }
+    C.flush_events();
     atomicAdd(&S.cnt[C_FLIGHT], (unsigned long long)n_flight);
     atomicAdd(&S.cnt[C_PIECE], (unsigned long long)n_piece);
     atomicAdd(&S.wsum[W_PATH], path);

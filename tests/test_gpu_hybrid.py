@@ -108,6 +108,27 @@ def test_hybrid_long_histories_hand_over_to_the_banks(stack_cap):
     assert gp.counters()["event_iterations"] > 1
 
 
+def test_hybrid_event_cap_reached_in_the_re_lead_stage():
+    """Histories of about 100 flights with a cap of 40: the lead stage hands
+    each over after 32 flights and the re-lead stage, counting on from the
+    history's stored count, reports the cap."""
+    mc = _mcdc()
+    p = W.infinite_medium(1.0, [[0.99]], [1.0], half=5.0, t_end=150.0, nt=5)
+    p["ww"] = dict(params=ramp_mlp(0.0), hidden=64, logk=float(np.log(0.25)), ratio=5.0, n_max=10)
+    p["max_events"] = 40
+    gp = mc.Problem(p, _hy())
+    gp.run(200, 184)
+    with pytest.raises(mc.McdcError) as e:
+        gp.tallies(mc.TALLY_MESH)
+    assert e.value.status == mc.E_EVENT_CAP
+    gp.close()
+    p["max_events"] = 100000                        # the same run without the cap is clean
+    gq = mc.Problem(p, _hy())
+    gq.run(200, 184)
+    gq.tallies(mc.TALLY_MESH)
+    gq.close()
+
+
 def test_hybrid_weight_window_map_duct_small_chunks():
     p = W.config2(n_census=3)
     p["mesh"]["n"] = np.array([6, 10, 6, 4], np.int32)
