@@ -332,10 +332,16 @@ static double o_dist_surface(const orc_problem *P, const double p[3], const doub
 /* Track-length estimator: a straight segment p + s u, s in [0,d], starting  */
 /* at time t0 with speed v, is cut at every mesh plane and time-bin edge it  */
 /* crosses; each piece adds w * length to tally[g][it][iz][iy][ix].  Edges   */
-/* are lo + k*delta with delta = (hi-lo)/n; crossing distances are computed  */
-/* fresh from the segment start; all axes that reach the minimum advance     */
-/* together; pieces of zero or negative length and pieces outside the mesh   */
-/* are not scored.  An axis with infinite bounds is not cut.                 */
+/* are lo + k*delta with delta = (hi-lo)/n.  The first crossing of an axis   */
+/* is (edge - p) / u from the segment start (time: (edge - t0) v); each      */
+/* later crossing of that axis is the previous one plus delta / |u| (time:   */
+/* delta v); all axes that reach the minimum advance together.  The walk     */
+/* ends at d or where the segment leaves the mesh: the far edge of a bounded */
+/* axis in the direction of travel, or the last time edge, each taken from   */
+/* the segment start, whichever comes first.  Pieces of zero or negative     */
+/* length and pieces whose bin lies outside the mesh are not scored.  An     */
+/* axis with infinite bounds is not cut.  (A reading: the paper names the    */
+/* estimator, not how the crossings are computed.)                           */
 /* ------------------------------------------------------------------------ */
 typedef struct {
     int n[4], bounded[3];
@@ -428,11 +434,19 @@ static int64_t o_score_mesh(const o_mesh *M, const double p[3], const double u[3
                             int g, double *tally)
 {
     int idx[4];
-    double s[4];
+    double s[4], ds[4];
     int64_t pieces = 0;
     if (!(d > 0.0)) return 0;
+    double end = d;
     for (int a = 0; a < 3; ++a) {
-        if (!M->bounded[a]) { idx[a] = 0; s[a] = O_INF; continue; }
+        if (!M->bounded[a]) { idx[a] = 0; s[a] = O_INF; ds[a] = O_INF; continue; }
+        if (u[a] > 0.0) {
+            double far = (M->lo[a] + (double)M->n[a] * M->delta[a] - p[a]) * iu[a];
+            if (far < end) end = far;
+        } else if (u[a] < 0.0) {
+            double far = (M->lo[a] - p[a]) * iu[a];
+            if (far < end) end = far;
+        }
         double q = (p[a] - M->lo[a]) * M->idelta[a];
         double fq = floor(q);
         if (fq < -1.0) fq = -1.0;
@@ -445,13 +459,16 @@ static int64_t o_score_mesh(const o_mesh *M, const double p[3], const double u[3
             if (i >= M->n[a]) return 0;                /* beyond and moving away */
             double e = M->lo[a] + (double)(i + 1) * M->delta[a];
             s[a] = (e - p[a]) * iu[a];
+            ds[a] = M->delta[a] * fabs(iu[a]);
         } else if (u[a] < 0.0) {
             if (i < 0) return 0;
             double e = M->lo[a] + (double)i * M->delta[a];
             s[a] = (e - p[a]) * iu[a];
+            ds[a] = M->delta[a] * fabs(iu[a]);
         } else {
             if (i < 0 || i >= M->n[a]) return 0;
             s[a] = O_INF;
+            ds[a] = O_INF;
         }
     }
     {
@@ -464,10 +481,13 @@ static int64_t o_score_mesh(const o_mesh *M, const double p[3], const double u[3
         idx[3] = i;
         double e = M->lo[3] + (double)(i + 1) * M->delta[3];
         s[3] = (e - t0) * v;
+        ds[3] = M->delta[3] * v;
+        double far = (M->lo[3] + (double)M->n[3] * M->delta[3] - t0) * v;
+        if (far < end) end = far;
     }
     double sp = 0.0;
     for (;;) {
-        double sn = d;
+        double sn = end;
         for (int a = 0; a < 4; ++a)
             if (s[a] < sn) sn = s[a];
         if (sn > sp) {
@@ -482,31 +502,12 @@ static int64_t o_score_mesh(const o_mesh *M, const double p[3], const double u[3
                 pieces += 1;
             }
         }
-        if (sn >= d) break;
-        int done = 0;
-        for (int a = 0; a < 3; ++a) {
+        if (sn >= end) break;
+        for (int a = 0; a < 4; ++a) {
             if (s[a] != sn) continue;
-            if (u[a] > 0.0) {
-                idx[a] += 1;
-                if (idx[a] >= M->n[a]) { done = 1; continue; }
-                double e = M->lo[a] + (double)(idx[a] + 1) * M->delta[a];
-                s[a] = (e - p[a]) * iu[a];
-            } else {
-                idx[a] -= 1;
-                if (idx[a] < 0) { done = 1; continue; }
-                double e = M->lo[a] + (double)idx[a] * M->delta[a];
-                s[a] = (e - p[a]) * iu[a];
-            }
+            idx[a] += (a == 3 || u[a] > 0.0) ? 1 : -1;
+            s[a] = s[a] + ds[a];
         }
-        if (s[3] == sn) {
-            idx[3] += 1;
-            if (idx[3] >= M->n[3]) done = 1;
-            else {
-                double e = M->lo[3] + (double)(idx[3] + 1) * M->delta[3];
-                s[3] = (e - t0) * v;
-            }
-        }
-        if (done) break;
         sp = sn;
     }
     return pieces;

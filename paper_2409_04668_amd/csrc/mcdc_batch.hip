@@ -79,8 +79,7 @@ struct BatchState {
 struct BatchCtx {
     static constexpr bool kWW = false;
     static constexpr bool kWWMap = false;
-    // the persistent batch kernel sits at its register limit: the mesh walk
-    // keeps the four index tests instead of carrying an entry distance
+    // the persistent batch kernel sits at its register limit
     static constexpr bool kTightRegs = true;
     MCDC_DEV double *col_tally() const { return nullptr; }
     MCDC_DEV double *surf_tally() const { return nullptr; }

@@ -22,6 +22,8 @@ struct HistCtx {
     static constexpr bool kWW = WW != 0;
     static constexpr bool kWWMap = WW == 2;
     static constexpr bool kFis = FIS;
+    // the fission variants sit at their register limit
+    static constexpr bool kTightRegs = FIS;
     CP &P;
     const RunArgs &A;
     uint64_t lane;

@@ -379,20 +379,27 @@ MCDC_DEV double min_f64(double a, double b) {
 
 // Track-length scoring of the segment p + s u, s in [0,d], from time t0 at
 // speed v: the segment is cut at every mesh plane and time edge it crosses
-// (edges lo + k*delta; crossing distances recomputed from the segment start;
-// all axes at the minimum advance together); each in-mesh piece of positive
-// length adds w * length to tally[g][it][iz][iy][ix].  Returns the pieces.
-template <bool kEntry, class T>
+// (edges lo + k*delta); each in-mesh piece of positive length adds
+// w * length to tally[g][it][iz][iy][ix].  Returns the pieces.
+//
+// Crossing distances: the first on each axis from the segment start,
+// (edge - p) * (1/u) (time: (edge - t0) * v); each later one adds the axis's
+// step delta * |1/u| (time: delta * v) to the one before; all axes at the
+// minimum advance together.  The walk ends at d or at the far mesh edge of a
+// bounded axis in the direction of travel or the last time edge, each
+// computed from the segment start, whichever comes first.  A piece is in the
+// mesh when all four indices are (the accumulated crossings and the end
+// distance come from different formulas, so the indices decide).
+// kKeepSteps: the four crossing steps are held in registers for the walk;
+// without it (kernels at their register limit) each step is recomputed from
+// the same operands where it is added, to the same value.
+template <bool kKeepSteps, class T>
 MCDC_DEV uint32_t score_mesh(CP &P, const double p[3], const double u[3],
-                             const double iu[3], double t0, double v, double d, double w, int g,
+                             double iu[3], double t0, double v, double d, double w, int g,
                              const T &tally) {
     if (!(d > 0.0)) return 0;
     int idx[4];
     double s[4];
-    // The walk ends at d or where it leaves the mesh, whichever comes first:
-    // the last edge of a bounded axis in the direction of travel (edge n
-    // moving up, edge 0 moving down) and the last time edge, each at the
-    // distance the walk itself would compute for that edge.
     double dd = d;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -437,47 +444,31 @@ MCDC_DEV uint32_t score_mesh(CP &P, const double p[3], const double u[3],
         if (se < dd) dd = se;
     }
     const uint32_t n0 = P.mesh_n[0], n1 = P.mesh_n[1], n2 = P.mesh_n[2], n3 = P.mesh_n[3];
-    // A segment that starts outside the mesh on some axes enters it where it
-    // crosses the entry edge of the last of them (that axis's first crossing,
-    // already in s); every piece that starts at or beyond that distance lies
-    // inside the mesh (the walk ends where it leaves), and none before it.
-    // With kEntry the in-mesh test is that one comparison; without it (for
-    // kernels already at their register limit) the four index tests.
-    double s_in = -kInf;
-    if constexpr (kEntry) {
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-            if (P.mesh_bounded[a] && (idx[a] < 0 || idx[a] >= P.mesh_n[a]) && s[a] > s_in)
-                s_in = s[a];
-        if (idx[3] < 0 && s[3] > s_in) s_in = s[3];
-    }
     const uint32_t gt = (uint32_t)(P.G_t > 1 ? g : 0);
     const uint32_t gbase = gt * n3;
-    // Per-axis step and edge offset: moving up, the next edge above cell i is
-    // edge i + 1; moving down, the edge below cell i is edge i.  The advance
-    // below computes every axis's candidate and keeps it by select, so lanes
-    // with different direction signs or tie patterns run the same
-    // instructions (the values are those of advancing axis by axis).
-    int step[3], off[3];
+    // Per-axis index step and crossing step.  The advance below computes every
+    // axis's candidate and keeps it by select, so lanes with different
+    // direction signs or tie patterns run the same instructions (the values
+    // are those of advancing axis by axis); an axis that is not cut keeps an
+    // infinite distance.
+    int step[3];
+    double ds[4];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         step[a] = u[a] > 0.0 ? 1 : -1;
-        off[a] = u[a] > 0.0 ? 1 : 0;
+        if constexpr (kKeepSteps) ds[a] = P.mesh_delta[a] * fabs(iu[a]);
     }
+    if constexpr (kKeepSteps) ds[3] = P.mesh_delta[3] * v;
     uint32_t pieces = 0;
     double sp = 0.0;
     for (;;) {
-        // the nearest of the walk's end and the four next-edge distances (no
-        // NaN occurs; +0 and -0, the only values min may order either way,
+        // the nearest of the walk's end and the four next crossings (no NaN
+        // occurs; +0 and -0, the only values min may order either way,
         // compare equal in every later test and give the same differences)
         const double sn = min_f64(min_f64(dd, s[0]), min_f64(min_f64(s[1], s[2]), s[3]));
         if (sn > sp) {
-            bool in;
-            if constexpr (kEntry)
-                in = sp >= s_in;
-            else
-                in = (uint32_t)idx[0] < n0 && (uint32_t)idx[1] < n1 && (uint32_t)idx[2] < n2 &&
-                     (uint32_t)idx[3] < n3;
+            const bool in = (uint32_t)idx[0] < n0 && (uint32_t)idx[1] < n1 &&
+                            (uint32_t)idx[2] < n2 && (uint32_t)idx[3] < n3;
             if (in) {
                 const uint32_t b =
                     (((gbase + (uint32_t)idx[3]) * n2 + (uint32_t)idx[2]) * n1 + (uint32_t)idx[1]) *
@@ -488,22 +479,24 @@ MCDC_DEV uint32_t score_mesh(CP &P, const double p[3], const double u[3],
             }
         }
         if (sn >= dd) break;
+        if constexpr (!kKeepSteps) {
+            // the operands look changed on every turn, so the products are
+            // formed here rather than hoisted out of the loop into registers
+            asm volatile("" : "+v"(iu[0]), "+v"(iu[1]), "+v"(iu[2]), "+v"(v));
+#pragma unroll
+            for (int a = 0; a < 3; ++a) ds[a] = P.mesh_delta[a] * fabs(iu[a]);
+            ds[3] = P.mesh_delta[3] * v;
+        }
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             const bool adv = s[a] == sn;
-            const int ni = idx[a] + step[a];
-            const double e = P.mesh_lo[a] + (double)(ni + off[a]) * P.mesh_delta[a];
-            const double sa = (e - p[a]) * iu[a];
-            idx[a] = adv ? ni : idx[a];
-            s[a] = adv ? sa : s[a];
+            idx[a] = adv ? idx[a] + step[a] : idx[a];
+            s[a] = adv ? s[a] + ds[a] : s[a];
         }
         {
             const bool adv = s[3] == sn;
-            const int ni = idx[3] + 1;
-            const double e = P.mesh_lo[3] + (double)(ni + 1) * P.mesh_delta[3];
-            const double sa = (e - t0) * v;
-            idx[3] = adv ? ni : idx[3];
-            s[3] = adv ? sa : s[3];
+            idx[3] = adv ? idx[3] + 1 : idx[3];
+            s[3] = adv ? s[3] + ds[3] : s[3];
         }
         sp = sn;
     }

@@ -358,6 +358,8 @@ MCDC_DEV int stage_flight(CP &P, const RunArgs &A, Shared &S, const T &tally, Ct
     else if (wax >= 0 && d_w <= d_c) { ev = EV_WW_PLANE; d = d_w; }
     else { ev = EV_SCATTER; d = d_c; }
 
+    // the weight-window kernels and those that declare tight registers
+    // recompute the walk's crossing steps
     n_piece += score_mesh<!Ctx::kWW && !tight_regs<Ctx>::value>(P, q.x, q.u, iu, q.t, v, d, q.w,
                                                                  q.g, tally);
     if (P.has_detector) {
