@@ -5,7 +5,7 @@ corner, so that the three spatial axes cross their edges at the same distance
 on every piece; a beam lying in a mesh plane; a beam that starts on a plane
 moving down.  Each case runs under the history, event and hybrid schedules
 (the analog kernels) and with a weight-window map (the window kernels, whose
-walk keeps per-axis index tests): one particle per history bit-identical,
+walk recomputes its crossing steps): one particle per history bit-identical,
 split particles to 1e-12, tally sums to 1e-10, counters exact."""
 import math
 
@@ -93,8 +93,8 @@ def test_walk_beams_with_ties(beam, sched):
 
 @pytest.mark.parametrize("sched", ["history", "event", "hybrid"])
 def test_walk_partial_mesh_with_window_map(sched):
-    """The weight-window kernels (split particles, per-axis index tests in the
-    walk)."""
+    """The weight-window kernels (split particles, crossing steps recomputed
+    in the walk)."""
     p = _partial_mesh_box()
     p["ww"] = dict(params=ramp_mlp(-1.5, noise_seed=7), hidden=64, logk=0.3, ratio=5.0, n_max=10,
                    map=(10, 10, 10, 6))
