@@ -242,9 +242,12 @@ int mcdc_run(mcdc_handle h, uint64_t n_histories, uint64_t seed, void *stream);
  * dev_workspace: caller-owned device memory of mcdc_keff_workspace_bytes(M)
  * bytes (site banks, the combed source; free after the call).  k_col, k_site,
  * n_sites: host arrays of n_inactive + n_active entries (each may be NULL).
- * Synchronises `stream` once per generation.  MCDC_E_BANK when a generation
- * makes more than 4 M + 1024 sites (start with k0 nearer k),
- * MCDC_E_EXTINCT when it makes none.
+ * The generations follow each other on `stream` without a host round trip;
+ * the call synchronises it once per 64 generations to collect their results.
+ * MCDC_E_BANK when a generation makes more than 4 M + 1024 sites, or when a
+ * single collision would make more than that (start with k0 nearer k),
+ * MCDC_E_EXTINCT when it makes none; the outputs then hold the generations
+ * up to the failed one.
  * Source: Sec. "Monte Carlo Neutron Transport and MC/DC" (the k-eigenvalue
  * mode beside the time-dependent one) and Sec. "MC/DC on CPUs" (fission as a
  * physical event that ends a history; daughter particles from fission in the

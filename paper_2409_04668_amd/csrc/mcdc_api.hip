@@ -713,10 +713,11 @@ static bool seg_by_batch(const mcdc_problem *h) {
     return h->opt.schedule == MCDC_SCHED_HISTORY || h->desc.pc_on;
 }
 
-static uint64_t seg_count(const mcdc_problem *h) {
+// Segments of a run of n histories.
+static uint64_t seg_count(const mcdc_problem *h, uint64_t n) {
     if (seg_by_batch(h)) return (uint64_t)h->desc.n_batches;
     const uint64_t c = ev_resident_histories(h);
-    return c ? (h->run_n + c - 1) / c : 0;
+    return c ? (n + c - 1) / c : 0;
 }
 
 static void seg_range(const mcdc_problem *h, uint64_t k, uint64_t &lo, uint64_t &hi) {
@@ -733,7 +734,7 @@ static void seg_range(const mcdc_problem *h, uint64_t k, uint64_t &lo, uint64_t 
 
 // The first non-empty segment at or after k (seg_count when none is left).
 static uint64_t seg_next(const mcdc_problem *h, uint64_t k) {
-    const uint64_t K = seg_count(h);
+    const uint64_t K = seg_count(h, h->run_n);
     for (; k < K; ++k) {
         uint64_t lo, hi;
         seg_range(h, k, lo, hi);
@@ -796,7 +797,7 @@ int mcdc_run_step(mcdc_handle h, int32_t *done, void *stream) {
     h->run_steps += 1;
     if (!seg_done) return MCDC_OK;
     h->run_seg = seg_next(h, h->run_seg + 1);
-    if (h->run_seg < seg_count(h))
+    if (h->run_seg < seg_count(h, h->run_n))
         return ev ? event_begin(h, stepped_args(h), s) : MCDC_OK;
     h->in_run = false;
     *done = 1;
@@ -829,6 +830,8 @@ int mcdc_set_run_state(mcdc_handle h, const mcdc_run_state *in) {
     if (in->workspace_bytes != h->L.total || in->bins != h->nbins)
         return fail(MCDC_E_INVALID, "run state of a handle with another description or options");
     if (in->in_run && h->is_batch) return fail(MCDC_E_STATE, "batched handle: use mcdc_run_batch");
+    if (in->in_run && (in->run_n == 0 || in->segment >= seg_count(h, in->run_n)))
+        return fail(MCDC_E_INVALID, "run-state record names no segment of its run");
     h->n_hist = in->n_hist;
     h->batches = (int64_t)in->batches;
     h->event_iterations = in->event_iterations;
@@ -838,10 +841,6 @@ int mcdc_set_run_state(mcdc_handle h, const mcdc_run_state *in) {
     h->run_seg = in->segment;
     h->in_run = in->in_run != 0;
     h->run_steps = in->steps;
-    if (h->in_run && (h->run_n == 0 || h->run_seg >= seg_count(h))) {
-        h->in_run = false;
-        return fail(MCDC_E_INVALID, "run-state record names no segment of its run");
-    }
     return MCDC_OK;
 }
 

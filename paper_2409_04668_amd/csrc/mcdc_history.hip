@@ -32,6 +32,7 @@ struct HistCtx {
     int64_t events;
     int sp, n_imp;
     uint32_t n_site;
+    double k_norm = 0.0;                 // the generation's normalisation (fission variants)
 
     // fission site `pos` of the generation's bank (in reservation order;
     // past the capacity it is dropped and the host reports the overflow)
@@ -162,6 +163,9 @@ MCDC_DEV HotTileTally make_tally(HotTileTally *, CP &P, const RunArgs &A, double
 template <int LDS, int WW, bool IMP, bool FIS>
 __global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_history(DevProblem, RunArgs A) {
     CP &P = kernel_problem();
+    // a k-eigenvalue generation after a failed one (its source would come from
+    // sites that were never made) transports nothing
+    if (FIS && A.acc->status != 0) return;
     extern __shared__ double s_tile[];
     __shared__ Shared S;
     __shared__ uint32_t s_cancel;
@@ -180,6 +184,8 @@ __global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_history(DevProblem, R
     Part q;
     q.alive = false;
     HistCtx<WW, IMP, FIS> H{P, A, lane, 0, 0.0, 0.0, 0, 0, 0, 0u};
+    // read once: the kernel's own writes could otherwise alias it at every use
+    if constexpr (FIS) H.k_norm = *A.k_norm;
     bool in_hist = false;
     using Tally = typename TallyFor<LDS>::type;
     const Tally tally = make_tally((Tally *)nullptr, P, A, s_tile);

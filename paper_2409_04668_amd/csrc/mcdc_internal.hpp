@@ -121,7 +121,7 @@ struct RunArgs {
     // source); fission sites go to site_* in any order with their key
     // (history slot, ordinal within the history) and hist_sites counts them
     // per slot; the collision estimate accumulates in acc->kcol
-    double k_norm;                       // site production is divided by this
+    const double *k_norm;                // site production is divided by *k_norm
     uint64_t gen_first, gen_m;
     const double *src_d;                 // [3][gen_m] positions
     const int32_t *src_g;                // [gen_m] groups

@@ -12,6 +12,13 @@
 // slot offset + ordinal.  The comb then picks M sites with one random offset;
 // its index arithmetic is the definition's, so the next generation starts
 // from exactly the sites a serial implementation picks.
+//
+// The normalisation k_norm, the site count and the per-generation estimates
+// stay on the device (k_keff_gen_end), so generations follow each other
+// without a host round trip; the host reads a block of kGenBlock generations'
+// results at a time.
+#include <string>
+
 #include "mcdc_runtime.hpp"
 #include "transport_device.hpp"
 
@@ -22,11 +29,23 @@ constexpr int kScanThreads = 256;
 constexpr int kScanPer = 16;                     // counts per work-item
 constexpr int kScanTile = kScanThreads * kScanPer;
 constexpr uint64_t kKeffMaxM = 1ull << 28;
+constexpr int kGenBlock = 64;                    // generations per host read-back
+
+// per generation, written by k_keff_gen_end
+struct KeffOut {
+    double k_col, k_site;
+    uint64_t n_sites;
+    int32_t status;                              // the run's status after the generation
+    int32_t pad;
+};
 
 struct KeffCtl {
     uint32_t site_n;                             // sites reserved by the generation
     uint32_t pad;
     uint64_t total;                              // sum of the per-slot counts
+    double k_norm;                               // normalisation of the running generation
+    uint64_t pad2;
+    KeffOut out[kGenBlock];                      // generation g at out[g % kGenBlock]
 };
 
 struct KeffLayout {
@@ -57,12 +76,42 @@ static KeffLayout keff_layout(uint64_t M) {
     return L;
 }
 
+// start of a run: the first generation's normalisation
+__global__ void k_keff_run_begin(KeffCtl *ctl, double k0) {
+    if (threadIdx.x == 0) ctl->k_norm = k0;
+}
+
 // start of a generation: no sites yet, collision estimate zero
 __global__ void k_keff_gen_begin(KeffCtl *ctl, DevAcc *acc) {
     if (threadIdx.x == 0) {
         ctl->site_n = 0u;
         acc->kcol = 0.0;
     }
+}
+
+// end of generation g (after the site-count scan): its estimates
+// k_col = (sum of w nuSigma_f / Sigma_t) / M and k_site = k_norm S / M, its
+// site count S and the run's status after it, and the next generation's
+// normalisation k_site.  A generation with more sites than the bank holds,
+// or with none, sets the status unless an earlier failure did; after any
+// failure the normalisation is infinite, so later generations make no sites
+// (the host reports the first failure at its next read-back).
+__global__ void k_keff_gen_end(KeffCtl *ctl, DevAcc *acc, uint64_t M, uint64_t cap, uint32_t g) {
+    if (threadIdx.x != 0) return;
+    const uint64_t S = ctl->total;
+    KeffOut &o = ctl->out[g % kGenBlock];
+    o.k_col = acc->kcol / (double)M;
+    o.k_site = ctl->k_norm * (double)S / (double)M;
+    o.n_sites = S;
+    int st = acc->status;
+    if (st == 0) {
+        if (ctl->site_n > cap || S > cap) st = MCDC_E_BANK;
+        else if (S != ctl->site_n) st = MCDC_E_HIP;
+        else if (S == 0) st = MCDC_E_EXTINCT;
+        if (st != 0) atomicMin(&acc->status, st);
+    }
+    o.status = st;
+    ctl->k_norm = st == 0 ? o.k_site : __builtin_inf();
 }
 
 __global__ void k_fill_zero(double *__restrict__ p, uint64_t n) {
@@ -149,14 +198,17 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(const uint32_t *__r
     }
 }
 
-// every site to its place in production order: slot offset + ordinal
+// every site to its place in production order: slot offset + ordinal (the
+// generation's S sites; nothing past the bank after an overflow)
 __global__ void k_site_order(const double *__restrict__ sd, const int32_t *__restrict__ sg,
                              const uint32_t *__restrict__ key, const uint32_t *__restrict__ off,
-                             uint64_t cap, uint64_t n, double *__restrict__ od,
+                             uint64_t cap, const KeffCtl *ctl, double *__restrict__ od,
                              int32_t *__restrict__ og) {
+    const uint64_t n = ctl->total < cap ? ctl->total : cap;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         const uint64_t dst = (uint64_t)off[key[i]] + key[cap + i];
+        if (dst >= cap) continue;
         od[dst] = sd[i];
         od[cap + dst] = sd[cap + i];
         od[2 * cap + dst] = sd[2 * cap + i];
@@ -169,8 +221,10 @@ __global__ void k_site_order(const double *__restrict__ sd, const int32_t *__res
 // (seed, history id of the next generation's first history, tag kCombTag)
 __global__ void k_site_comb(uint64_t seed, uint64_t comb_hist, uint32_t problem,
                             const double *__restrict__ od, const int32_t *__restrict__ og,
-                            uint64_t cap, uint64_t S, uint64_t M, double *__restrict__ src_d,
+                            uint64_t cap, const KeffCtl *ctl, uint64_t M, double *__restrict__ src_d,
                             int32_t *__restrict__ src_g) {
+    // the generation's site count (a failed generation's sources are never used)
+    const uint64_t S = ctl->total < cap ? (ctl->total > 0 ? ctl->total : 1) : cap;
     Rng r = make_rng(seed, comb_hist, problem, kCombTag, 0u);
     const double xi = rng_uniform(r);
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -254,10 +308,10 @@ int mcdc_run_keff(mcdc_handle h, const mcdc_keff_opts *o, uint64_t seed, void *w
     const bool col = h->desc.col_tally != 0, surf = h->desc.surf_on != 0;
     const bool lds = h->opt.lds_tally && h->nbins <= (uint32_t)kLdsTallyMaxBins;
     const int fg = history_grid(256, 8);
-    double k_norm = o->k0;
+    A.k_norm = &ctl->k_norm;
+    hipLaunchKernelGGL(k_keff_run_begin, dim3(1), dim3(64), 0, s, ctl, o->k0);
     for (int g = 0; g < n_gen; ++g) {
         const bool score = g >= o->n_inactive;
-        A.k_norm = k_norm;
         A.gen_first = (uint64_t)g * M;
         A.h_begin = A.gen_first;
         A.h_end = A.gen_first + M;
@@ -296,41 +350,42 @@ int mcdc_run_keff(mcdc_handle h, const mcdc_keff_opts *o, uint64_t seed, void *w
         hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, bsum, K.nblk, ctl);
         hipLaunchKernelGGL(k_scan_apply, dim3((uint32_t)K.nblk), dim3(kScanThreads), 0, s, hist_sites, M,
                            bsum, hist_off);
-        KeffCtl hc;
-        DevAcc ha;
-        e = hipGetLastError();
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e == hipSuccess) e = hipMemcpy(&hc, ctl, sizeof(hc), hipMemcpyDeviceToHost);
-        if (e == hipSuccess) e = hipMemcpy(&ha, acc, sizeof(ha), hipMemcpyDeviceToHost);
-        if (e != hipSuccess) return hip_fail(e, "keff generation read-back");
-        if (ha.status != 0) return fail(ha.status, "a generation failed on the device (status " +
-                                                       std::to_string(ha.status) + ")");
-        if (cancel_set(h)) return fail(MCDC_E_CANCELLED, "run cancelled");
-        if (hc.site_n > K.cap || hc.total > K.cap)
-            return fail(MCDC_E_BANK, "generation " + std::to_string(g) + " made more than " +
-                                         std::to_string(K.cap) + " fission sites (start with k0 nearer k)");
-        if (hc.total != hc.site_n) return fail(MCDC_E_HIP, "fission site count mismatch");
-        if (score) {
-            h->batches += 1;
-            h->n_hist += M;
-        }
-        const uint64_t S = hc.total;
-        const double kc = ha.kcol / (double)M;
-        const double ks = k_norm * (double)S / (double)M;
-        if (k_col) k_col[g] = kc;
-        if (k_site) k_site[g] = ks;
-        if (n_sites) n_sites[g] = S;
-        if (S == 0) return fail(MCDC_E_EXTINCT, "generation " + std::to_string(g) + " made no fission site");
+        hipLaunchKernelGGL(k_keff_gen_end, dim3(1), dim3(64), 0, s, ctl, acc, M, K.cap, (uint32_t)g);
         if (g + 1 < n_gen) {
-            hipLaunchKernelGGL(k_site_order, dim3(grid_for(S, 256, 16384)), dim3(256), 0, s, site_d, site_g,
-                               site_key, hist_off, K.cap, S, ord_d, ord_g);
+            hipLaunchKernelGGL(k_site_order, dim3(grid_for(K.cap, 256, 16384)), dim3(256), 0, s, site_d,
+                               site_g, site_key, hist_off, K.cap, ctl, ord_d, ord_g);
             hipLaunchKernelGGL(k_site_comb, dim3(grid_for(M, 256, fg)), dim3(256), 0, s, seed,
-                               (uint64_t)(g + 1) * M, h->P.problem_id, ord_d, ord_g, K.cap, S, M, src_d,
+                               (uint64_t)(g + 1) * M, h->P.problem_id, ord_d, ord_g, K.cap, ctl, M, src_d,
                                src_g);
-            e = hipGetLastError();
-            if (e != hipSuccess) return hip_fail(e, "keff comb");
         }
-        k_norm = ks;
+        e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "keff generation");
+        // a block of generations done (or the last one): read their results
+        if ((g + 1) % kGenBlock != 0 && g + 1 != n_gen && !cancel_set(h)) continue;
+        const int g0 = g - g % kGenBlock;
+        KeffOut res[kGenBlock];
+        e = hipStreamSynchronize(s);
+        if (e == hipSuccess) e = hipMemcpy(res, ctl->out, sizeof(res), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "keff generation read-back");
+        for (int j = g0; j <= g; ++j) {
+            const KeffOut &r = res[j % kGenBlock];
+            if (k_col) k_col[j] = r.k_col;
+            if (k_site) k_site[j] = r.k_site;
+            if (n_sites) n_sites[j] = r.n_sites;
+            // the first generation that failed names the error
+            const std::string gen = "generation " + std::to_string(j);
+            if (r.status == MCDC_E_BANK)
+                return fail(MCDC_E_BANK, gen + " made more than " + std::to_string(K.cap) +
+                                             " fission sites (start with k0 nearer k)");
+            if (r.status == MCDC_E_EXTINCT) return fail(MCDC_E_EXTINCT, gen + " made no fission site");
+            if (r.status != 0)
+                return fail(r.status, gen + " failed on the device (status " + std::to_string(r.status) + ")");
+            if (j >= o->n_inactive) {
+                h->batches += 1;
+                h->n_hist += M;
+            }
+        }
+        if (cancel_set(h)) return fail(MCDC_E_CANCELLED, "run cancelled");
     }
     return MCDC_OK;
 }

@@ -460,8 +460,13 @@ MCDC_DEV bool stage_collision(CP &P, const RunArgs &A, Shared &S, Ctx &C, Part &
             const double prod = q.w * nusf / sig_t;
             atomicAdd(&S.kcol, prod);
             const double xi = rng_uniform(r);
-            const double nf = floor(prod / A.k_norm + xi);
-            const uint32_t n = nf > 4.0e9 ? 0xFFFFFFFFu : (uint32_t)nf;
+            const double nf = floor(prod / C.k_norm + xi);
+            // more sites than the whole bank holds (a normalisation far below
+            // k, or none after a failed generation) fail the generation at
+            // once rather than looping over sites that cannot be kept
+            uint32_t n = 0;
+            if (nf <= (double)A.site_cap) n = (uint32_t)nf;
+            else set_status(A, MCDC_E_BANK);
             const double *chi = P.chi + mat * P.G;
             double chi_sum = 0.0;
             for (int h = 0; h < P.G; ++h) chi_sum = chi_sum + chi[h];

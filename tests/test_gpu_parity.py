@@ -752,6 +752,7 @@ def test_stepped_run_rejections():
     with pytest.raises(mc.McdcError) as e:
         ge.run_step()                                # the bad record left no run in progress
     assert e.value.status == mc.E_STATE
+    assert ge.counters()["histories"] == 2510       # and the handle as it was
     ge.close()
     q = W.infinite_medium(1.0, [[0.9]], [1.0], half=5.0, t_end=8.0, nt=8)
     q["population_control"] = dict(target=1.0)
