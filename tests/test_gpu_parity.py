@@ -688,16 +688,20 @@ def test_census_steps_checkpoint_resume_with_population_control():
     gb.close()
 
 
-def test_stepped_run_with_population_control_per_batch():
+@pytest.mark.parametrize("hybrid", [False, True])
+def test_stepped_run_with_population_control_per_batch(hybrid):
     """Population control over three batches (1000, 1000, 1001 histories),
     each one resident chunk controlled on its own, as a plain run takes
-    them; checkpointed inside the second batch."""
+    them; checkpointed inside the second batch (event schedule, or the
+    hybrid schedule's lead and re-lead stages)."""
+    mc = _mcdc()
     p = W.infinite_medium(1.0, [[0.9]], [1.0], half=5.0, t_end=8.0, nt=8)
     p["census"] = np.linspace(1.0, 8.0, 8)
     p["population_control"] = dict(target=1.5)
     p["n_batches"] = 3
     n, seed = 3001, 164
-    gb, steps, st = _stepped_with_checkpoint(p, n, seed, _ev(1 << 11), stop_after=10)
+    opt = mc.make_options(mc.SCHED_HYBRID, event_chunk=1 << 11) if hybrid else _ev(1 << 11)
+    gb, steps, st = _stepped_with_checkpoint(p, n, seed, opt, stop_after=10)
     assert st.segment == 1
     assert steps == 24
     orc = _check_stepped_against_oracle(gb, p, n, seed, exact_scores=False)

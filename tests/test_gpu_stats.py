@@ -219,3 +219,29 @@ def test_cancel_batched_run():
         c = bp.counters(i)
         assert c["status"] == mc.E_CANCELLED
     bp.close()
+
+
+def test_cancel_keff_run():
+    """The word set before a k-eigenvalue run: the first generation's launch
+    leaves at once, the later ones transport nothing, the run returns
+    MCDC_E_CANCELLED; after a reset the same handle runs the generations as
+    before (the estimates of an uncancelled handle)."""
+    mc = _mc()
+    p = W.keff_infinite_medium([1.0], [[0.6]], [0.5], [1.0])
+    ref = mc.Problem(p)
+    want = ref.run_keff(2000, 1, 3, seed=91)
+    ref.close()
+    gp = mc.Problem(p)
+    gp.set_cancel(True)
+    with pytest.raises(mc.McdcError) as e:
+        gp.run_keff(2000, 1, 3, seed=91)
+    assert e.value.status == mc.E_CANCELLED
+    c = gp.counters()
+    assert c["flights"] == 0 and c["n_hist"] == 0
+    gp.set_cancel(False)
+    gp.reset()
+    got = gp.run_keff(2000, 1, 3, seed=91)
+    for k in ("k_col", "k_site", "n_sites"):
+        assert np.array_equal(got[k], want[k]), k
+    gp.close()
+
