@@ -264,6 +264,28 @@ def test_hot_tile_weight_window_map(sched):
     assert orc.counters["split"] > 10
 
 
+@pytest.mark.parametrize("sched", ["hybrid", "event"])
+def test_hot_tile_with_population_control(sched):
+    """Population control at four census steps of the duct with the LDS hot
+    tile: census stops from the tiled flight stage (event) or the lead and
+    re-lead stages (hybrid), the control between steps; trajectories as the
+    oracle's, tallies and their batch slices to 1e-10."""
+    p = W.config2(n_census=4)
+    p["mesh"]["n"] = np.array([12, 20, 12, 8], np.int32)
+    p["population_control"] = dict(target=1.3)
+    p["n_batches"] = 2
+    tile = ([2, 3, 1, 0, 0], [8, 10, 8, 4, 1])
+    gp, orc, tg, to, hg, ho = run_pair(p, 2000, 189, trace_cap=600000,
+                                       options=_hy_tile(tile, chunk=1 << 11, sched=sched))
+    assert_traces_equal(tg[0], to[0])
+    np.testing.assert_allclose(hg[0], ho[0], rtol=1e-12, atol=1e-300)
+    s, s2 = gp.raw()
+    assert_close_sums(s, orc.tally_sum, what="tally_sum")
+    assert_close_sums(s2, orc.tally_sumsq, what="tally_sumsq")
+    assert_counters(gp.counters(), orc)
+    assert orc.counters["pc_copy"] + orc.counters["pc_kill"] > 100
+
+
 def test_planned_tile_at_scale_matches_history_schedule():
     """The autotuner's tile for the full duct problem, 5e6 histories: the
     hybrid and event schedules with the tile give the history schedule's
