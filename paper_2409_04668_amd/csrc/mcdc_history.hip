@@ -1,9 +1,11 @@
 // History-based tracking kernel: one work-item carries one history (its source
 // particle and, with weight windows, its split daughters on a LIFO stack) from
 // birth to the end, flight by flight.  The grid is persistent (a fixed number
-// of workgroups sized to the chip) and work-items stride over history ids, so
-// a work-item whose history ends starts its next history in the same loop
-// iteration instead of idling until the wave drains.
+// of workgroups sized to the chip); each workgroup takes a contiguous range of
+// the launch's history ids and its work-items take the next one from a
+// counter in LDS, so a work-item whose history ends starts its next history
+// in the same loop iteration instead of idling until the wave drains, and a
+// long history holds up no other history.
 //
 // Tallies: track-length pieces go to FP64 atomics, either straight into the
 // batch accumulator in HBM or, when the whole mesh fits, into an LDS tile per
@@ -169,16 +171,25 @@ __global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_history(DevProblem, R
     extern __shared__ double s_tile[];
     __shared__ Shared S;
     __shared__ uint32_t s_cancel;
+    __shared__ unsigned long long s_next;
     const CancelSeen cancel{&s_cancel};
     shared_zero(S);
     cancel.init(A.cancel);
     const uint32_t tile_bins = LDS == 1 ? P.nbins : (LDS == 2 ? P.hot_bins : 0u);
     for (uint32_t i = threadIdx.x; i < tile_bins; i += blockDim.x) s_tile[i] = 0.0;
+    // workgroup w takes the contiguous histories [w n / G, (w+1) n / G) of
+    // the launch; its work-items take the next one from a counter in LDS as
+    // their histories end, so a long history delays no other work-item's next
+    // (floor(b n / G) = b q + floor(b r / G) with n = q G + r, without overflow)
+    const uint64_t n_all = A.h_end - A.h_begin;
+    const uint64_t q_all = n_all / gridDim.x, r_all = n_all % gridDim.x;
+    const uint64_t b1 = blockIdx.x + 1u;
+    const uint64_t h1 = A.h_begin + b1 * q_all + (b1 * r_all) / gridDim.x;
+    if (threadIdx.x == 0)
+        s_next = A.h_begin + blockIdx.x * q_all + ((uint64_t)blockIdx.x * r_all) / gridDim.x;
     __syncthreads();
 
     const uint64_t lane = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint64_t stride = A.n_lanes;
-    uint64_t next = A.h_begin + lane;
     uint32_t n_flight = 0, n_piece = 0, n_hist = 0;
     double path = 0.0;
     Part q;
@@ -217,13 +228,13 @@ __global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_history(DevProblem, R
                     finish_history(A, S, H);
                     in_hist = false;
                 }
-                if (next >= A.h_end) break;
                 if (cancel.check(A.cancel, n_hist)) {
                     set_status(A, MCDC_E_CANCELLED);
                     break;
                 }
+                const uint64_t next = atomicAdd(&s_next, 1ull);
+                if (next >= h1) break;
                 H.id = next;
-                next += stride;
                 H.xh = 0.0;
                 H.path = 0.0;
                 H.events = 0;

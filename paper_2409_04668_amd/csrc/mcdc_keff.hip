@@ -41,7 +41,7 @@ struct KeffOut {
 
 struct KeffCtl {
     uint32_t site_n;                             // sites reserved by the generation
-    uint32_t pad;
+    uint32_t stop;                               // a generation failed: order and comb do nothing
     uint64_t total;                              // sum of the per-slot counts
     double k_norm;                               // normalisation of the running generation
     uint64_t pad2;
@@ -78,7 +78,10 @@ static KeffLayout keff_layout(uint64_t M) {
 
 // start of a run: the first generation's normalisation
 __global__ void k_keff_run_begin(KeffCtl *ctl, double k0) {
-    if (threadIdx.x == 0) ctl->k_norm = k0;
+    if (threadIdx.x == 0) {
+        ctl->k_norm = k0;
+        ctl->stop = 0u;
+    }
 }
 
 // start of a generation: no sites yet, collision estimate zero
@@ -112,6 +115,9 @@ __global__ void k_keff_gen_end(KeffCtl *ctl, DevAcc *acc, uint64_t M, uint64_t c
     }
     o.status = st;
     ctl->k_norm = st == 0 ? o.k_site : __builtin_inf();
+    // a generation whose history launch stopped early (or never ran) left
+    // site keys and counts that are not its own
+    if (st != 0) ctl->stop = 1u;
 }
 
 __global__ void k_fill_zero(double *__restrict__ p, uint64_t n) {
@@ -199,15 +205,19 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(const uint32_t *__r
 }
 
 // every site to its place in production order: slot offset + ordinal (the
-// generation's S sites; nothing past the bank after an overflow)
+// generation's S sites; nothing after a failed generation, and no key or
+// place outside the arrays)
 __global__ void k_site_order(const double *__restrict__ sd, const int32_t *__restrict__ sg,
                              const uint32_t *__restrict__ key, const uint32_t *__restrict__ off,
-                             uint64_t cap, const KeffCtl *ctl, double *__restrict__ od,
+                             uint64_t cap, uint64_t M, const KeffCtl *ctl, double *__restrict__ od,
                              int32_t *__restrict__ og) {
+    if (ctl->stop) return;
     const uint64_t n = ctl->total < cap ? ctl->total : cap;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const uint64_t dst = (uint64_t)off[key[i]] + key[cap + i];
+        const uint32_t slot = key[i];
+        if (slot >= M) continue;
+        const uint64_t dst = (uint64_t)off[slot] + key[cap + i];
         if (dst >= cap) continue;
         od[dst] = sd[i];
         od[cap + dst] = sd[cap + i];
@@ -223,7 +233,7 @@ __global__ void k_site_comb(uint64_t seed, uint64_t comb_hist, uint32_t problem,
                             const double *__restrict__ od, const int32_t *__restrict__ og,
                             uint64_t cap, const KeffCtl *ctl, uint64_t M, double *__restrict__ src_d,
                             int32_t *__restrict__ src_g) {
-    // the generation's site count (a failed generation's sources are never used)
+    if (ctl->stop) return;                       // a failed generation: no next source
     const uint64_t S = ctl->total < cap ? (ctl->total > 0 ? ctl->total : 1) : cap;
     Rng r = make_rng(seed, comb_hist, problem, kCombTag, 0u);
     const double xi = rng_uniform(r);
@@ -353,7 +363,7 @@ int mcdc_run_keff(mcdc_handle h, const mcdc_keff_opts *o, uint64_t seed, void *w
         hipLaunchKernelGGL(k_keff_gen_end, dim3(1), dim3(64), 0, s, ctl, acc, M, K.cap, (uint32_t)g);
         if (g + 1 < n_gen) {
             hipLaunchKernelGGL(k_site_order, dim3(grid_for(K.cap, 256, 16384)), dim3(256), 0, s, site_d,
-                               site_g, site_key, hist_off, K.cap, ctl, ord_d, ord_g);
+                               site_g, site_key, hist_off, K.cap, M, ctl, ord_d, ord_g);
             hipLaunchKernelGGL(k_site_comb, dim3(grid_for(M, 256, fg)), dim3(256), 0, s, seed,
                                (uint64_t)(g + 1) * M, h->P.problem_id, ord_d, ord_g, K.cap, ctl, M, src_d,
                                src_g);
