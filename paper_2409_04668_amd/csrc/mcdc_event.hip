@@ -310,7 +310,9 @@ struct LeadCtx {
     MCDC_DEV bool push_daughters(const Part &q, uint32_t tag0, int n) {
         const int room = P.stack_cap - sp;
         const int spill = n - 1 > room ? n - 1 - room : 0;
-        const uint32_t base = spill ? atomicAdd(&B.ctl->n_act[cur], (uint32_t)spill) : 0u;
+        // the lanes splitting together reserve their spills with one atomic
+        uint32_t base = 0u;
+        if (__ballot(spill != 0)) base = wave_reserve_n(&B.ctl->n_act[cur], (uint32_t)spill);
         for (int i = 1; i < n; ++i) {
             Part d = q;
             d.tag = tag0 + (uint32_t)i * 0x9E3779B9u;
@@ -367,7 +369,8 @@ MCDC_DEV void lead_turn(CP &PL, const RunArgs &A, const EvBank &B, Shared &S, co
                         Ctx &C, Part &q, uint32_t &flights, uint32_t &n_flight, uint32_t &n_piece,
                         double &path, bool stop_at_census, uint32_t cen) {
     if (WW != 0 && flights >= BUDGET) {
-        const uint32_t base = atomicAdd(&B.ctl->n_act[C.cur], (uint32_t)C.sp + 1u);
+        // one atomic for the lanes of the wave that hand over together
+        const uint32_t base = wave_reserve_n(&B.ctl->n_act[C.cur], (uint32_t)C.sp + 1u);
         C.to_bank(q, base);
         for (int i = 0; i < C.sp; ++i) {
             Part r;
@@ -394,7 +397,7 @@ MCDC_DEV void lead_turn(CP &PL, const RunArgs &A, const EvBank &B, Shared &S, co
     } else if (ev == EV_WW_PLANE) {
         due = true;
     } else if (ev == EV_CENSUS && stop_at_census) {
-        bank_put(A, B, B.b[cen], atomicAdd(&B.ctl->n_act[cen], 1u), q, d, C.slot);
+        bank_put(A, B, B.b[cen], wave_reserve_one(&B.ctl->n_act[cen]), q, d, C.slot);
         q.alive = false;
         return;
     }
