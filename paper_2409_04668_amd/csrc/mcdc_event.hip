@@ -363,9 +363,11 @@ MCDC_DEV uint64_t batch_of(const RunArgs &A, uint32_t slot) {
 
 // One loop turn of the lead and re-lead stages for the live particle q: once
 // `flights` reaches the budget, hand the particle and the stacked daughters
-// over to bank C.cur; else one flight and the event that ends it.
+// over to bank C.cur; else one flight and the event that ends it.  A
+// window-map check (WW 2) is made at once; a network check (WW 1) is
+// returned as due, for the caller to run in a wave-level batch.
 template <int WW, uint32_t BUDGET, class Ctx, class Tally>
-MCDC_DEV void lead_turn(CP &PL, const RunArgs &A, const EvBank &B, Shared &S, const Tally &tally,
+MCDC_DEV bool lead_turn(CP &PL, const RunArgs &A, const EvBank &B, Shared &S, const Tally &tally,
                         Ctx &C, Part &q, uint32_t &flights, uint32_t &n_flight, uint32_t &n_piece,
                         double &path, bool stop_at_census, uint32_t cen) {
     if (WW != 0 && flights >= BUDGET) {
@@ -379,7 +381,7 @@ MCDC_DEV void lead_turn(CP &PL, const RunArgs &A, const EvBank &B, Shared &S, co
         }
         C.sp = 0;
         q.alive = false;
-        return;
+        return false;
     }
     flights += 1;
     double d = 0.0;
@@ -387,7 +389,7 @@ MCDC_DEV void lead_turn(CP &PL, const RunArgs &A, const EvBank &B, Shared &S, co
     if (ev >= 0) n_flight += 1;
     if (!q.alive) {
         if (ev < 0) C.sp = 0;               // event cap: the history is abandoned
-        return;
+        return false;
     }
     bool due = false;
     if (ev == EV_SURFACE) {
@@ -399,9 +401,29 @@ MCDC_DEV void lead_turn(CP &PL, const RunArgs &A, const EvBank &B, Shared &S, co
     } else if (ev == EV_CENSUS && stop_at_census) {
         bank_put(A, B, B.b[cen], wave_reserve_one(&B.ctl->n_act[cen]), q, d, C.slot);
         q.alive = false;
-        return;
+        return false;
     }
-    if (WW != 0 && due) ww_check(PL, A, S, C, q);
+    if (WW == 2 && due) ww_check(PL, A, S, C, q);
+    return WW == 1 && due;
+}
+
+// Network checks (WW 1) run in wave-level batches, as in the history kernel:
+// a lane whose check is due waits (its particle does not move) until at
+// least half of the wave's active lanes wait, then they evaluate the network
+// together; the check sees exactly the state it would have seen at once.
+// Returns true when this loop turn was spent on (or waiting for) checks.
+template <int WW, class Ctx>
+MCDC_DEV bool batched_check(CP &PL, const RunArgs &A, Shared &S, Ctx &C, Part &q, bool &due) {
+    if constexpr (WW != 1) return false;
+    const uint64_t waiting = __ballot(due);
+    if (waiting && 2 * __popcll(waiting) >= __popcll(__ballot(true))) {
+        if (due) {
+            ww_check(PL, A, S, C, q);
+            due = false;
+        }
+        return true;
+    }
+    return due;
 }
 
 // Lead stage (hybrid schedule).  Workgroup w takes the contiguous slots
@@ -444,9 +466,11 @@ __global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_ev_lead(DevProblem, R
     Part q;
     q.alive = false;
     bool in_hist = false;
+    bool ww_due = false;
     uint32_t n_started = 0;
     for (;;) {
         CP &PL = problem_reload(P);
+        if (batched_check<WW>(PL, A, S, C, q, ww_due)) continue;
         if (!q.alive) {
             if (WW != 0 && C.sp > 0) {
                 C.sp -= 1;
@@ -492,8 +516,8 @@ __global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_ev_lead(DevProblem, R
             }
         }
         // the rest of the history is handed over after MCDC_LEAD_FLIGHTS flights
-        lead_turn<WW, MCDC_LEAD_FLIGHTS>(PL, A, B, S, tally.t, C, q, lead_flights, n_flight,
-                                         n_piece, path, stop_at_census, cen);
+        ww_due = lead_turn<WW, MCDC_LEAD_FLIGHTS>(PL, A, B, S, tally.t, C, q, lead_flights,
+                                                  n_flight, n_piece, path, stop_at_census, cen);
     }
     atomicAdd(&S.cnt[C_FLIGHT], (unsigned long long)n_flight);
     atomicAdd(&S.cnt[C_PIECE], (unsigned long long)n_piece);
@@ -702,9 +726,11 @@ __global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_ev_relead(DevProblem,
     tally.init(P, s_tile);
     Part q;
     q.alive = false;
+    bool ww_due = false;
     uint32_t n_started = 0;
     for (;;) {
         CP &PL = problem_reload(P);
+        if (batched_check<WW>(PL, A, S, C, q, ww_due)) continue;
         if (!q.alive) {
             if (WW != 0 && C.sp > 0) {
                 C.sp -= 1;
@@ -725,8 +751,8 @@ __global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_ev_relead(DevProblem,
                 tally.select(PL, A, batch_of(A, slot), b_tile);
             }
         }
-        lead_turn<WW, MCDC_RELEAD_FLIGHTS>(PL, A, B, S, tally.t, C, q, flights, n_flight, n_piece,
-                                           path, stop_at_census, cen);
+        ww_due = lead_turn<WW, MCDC_RELEAD_FLIGHTS>(PL, A, B, S, tally.t, C, q, flights, n_flight,
+                                                    n_piece, path, stop_at_census, cen);
     }
     C.flush_events();
     atomicAdd(&S.cnt[C_FLIGHT], (unsigned long long)n_flight);
