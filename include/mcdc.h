@@ -310,7 +310,7 @@ typedef struct {
     int32_t in_run, steps;
 } mcdc_run_state;
 
-/* Start a census-stepped run (see above).
+/* Start a stepped run (see above).
  * Source: Sec. "Monte Carlo Neutron Transport and MC/DC" (time census and
  * time-dependent population control among the features) and the
  * transport-loop paragraph of Sec. "MC/DC on CPUs" (time census as a
@@ -362,7 +362,7 @@ int mcdc_get_tallies(mcdc_handle h, int kind, double *mean, double *rel_err, siz
  * NULL), computed by a kernel enqueued on `stream` with the same arithmetic
  * (bit-identical to mcdc_get_tallies).  Does not synchronise and does not
  * report device errors: read them with mcdc_get_counters.  MCDC_E_STATE while
- * a census-stepped run is in progress.
+ * a stepped run is in progress.
  * Source: as mcdc_get_tallies; kept on the device because the paper's GPU
  * profile counts host-device copies as a cost (Sec. "Performance"). */
 int mcdc_get_tallies_device(mcdc_handle h, int kind, double *dev_mean, double *dev_rel_err,

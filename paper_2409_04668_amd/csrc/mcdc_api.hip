@@ -647,7 +647,7 @@ int mcdc_run(mcdc_handle h, uint64_t n, uint64_t seed, void *stream) {
     if (!h) return fail(MCDC_E_INVALID, "null handle");
     if (h->is_batch) return fail(MCDC_E_STATE, "batched handle: use mcdc_run_batch");
     if (h->P.fis_on) return fail(MCDC_E_STATE, "a problem with fission runs in the k-eigenvalue mode (mcdc_run_keff)");
-    if (h->in_run) return fail(MCDC_E_STATE, "a census-stepped run is in progress");
+    if (h->in_run) return fail(MCDC_E_STATE, "a stepped run is in progress");
     if (h->n_hist + n >= (1ull << 48)) return fail(MCDC_E_INVALID, "history ids exhausted (2^48)");
     hipStream_t s = (hipStream_t)stream;
     const uint64_t B = (uint64_t)h->desc.n_batches;
@@ -762,7 +762,7 @@ int mcdc_run_begin(mcdc_handle h, uint64_t n, uint64_t seed, void *stream) {
     if (!h) return fail(MCDC_E_INVALID, "null handle");
     if (h->is_batch) return fail(MCDC_E_STATE, "batched handle: use mcdc_run_batch");
     if (h->P.fis_on) return fail(MCDC_E_STATE, "a problem with fission runs in the k-eigenvalue mode (mcdc_run_keff)");
-    if (h->in_run) return fail(MCDC_E_STATE, "a census-stepped run is in progress");
+    if (h->in_run) return fail(MCDC_E_STATE, "a stepped run is in progress");
     if (n == 0) return fail(MCDC_E_INVALID, "empty run");
     const uint64_t B = (uint64_t)h->desc.n_batches;
     if (h->opt.schedule == MCDC_SCHED_EVENT && h->desc.pc_on && (n + B - 1) / B > ev_resident_histories(h))
@@ -783,7 +783,7 @@ int mcdc_run_begin(mcdc_handle h, uint64_t n, uint64_t seed, void *stream) {
 
 int mcdc_run_step(mcdc_handle h, int32_t *done, void *stream) {
     if (!h || !done) return fail(MCDC_E_INVALID, "null argument");
-    if (!h->in_run) return fail(MCDC_E_STATE, "no census-stepped run in progress");
+    if (!h->in_run) return fail(MCDC_E_STATE, "no stepped run in progress");
     *done = 0;
     hipStream_t s = (hipStream_t)stream;
     const bool ev = h->opt.schedule == MCDC_SCHED_EVENT;
@@ -1094,7 +1094,7 @@ int mcdc_get_tallies_device(mcdc_handle h, int kind, double *dev_mean, double *d
                             void *stream) {
     if (!h || !dev_mean) return fail(MCDC_E_INVALID, "null argument");
     if (h->is_batch) return fail(MCDC_E_STATE, "batched handle: use mcdc_get_batch_raw");
-    if (h->in_run) return fail(MCDC_E_STATE, "a census-stepped run is in progress");
+    if (h->in_run) return fail(MCDC_E_STATE, "a stepped run is in progress");
     size_t o1 = 0, o2 = 0;
     double size = 1.0;
     int st = tally_kind(h, kind, n, o1, o2, size);
@@ -1120,7 +1120,7 @@ int mcdc_get_tallies_device(mcdc_handle h, int kind, double *dev_mean, double *d
 
 int mcdc_reset_tallies(mcdc_handle h, void *stream) {
     if (!h) return fail(MCDC_E_INVALID, "null handle");
-    if (h->in_run) return fail(MCDC_E_STATE, "a census-stepped run is in progress");
+    if (h->in_run) return fail(MCDC_E_STATE, "a stepped run is in progress");
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipStreamSynchronize(s);
     if (e == hipSuccess) e = hipMemset(h->ws + h->L.tally_batch, 0, h->L.ww_params - h->L.tally_batch);

@@ -277,7 +277,7 @@ int mcdc_run_keff(mcdc_handle h, const mcdc_keff_opts *o, uint64_t seed, void *w
     if (h->P.ww_on || h->desc.imp_on || h->desc.pc_on)
         return fail(MCDC_E_STATE, "the k-eigenvalue mode runs without weight windows, importance "
                                   "estimate or population control");
-    if (h->in_run) return fail(MCDC_E_STATE, "a census-stepped run is in progress");
+    if (h->in_run) return fail(MCDC_E_STATE, "a stepped run is in progress");
     if (h->n_hist != 0 || h->batches != 0)
         return fail(MCDC_E_STATE, "the k-eigenvalue mode needs a fresh or reset handle");
     const uint64_t M = o->M;
