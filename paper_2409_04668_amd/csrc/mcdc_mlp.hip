@@ -4,8 +4,10 @@
 //
 // One training step is two launches:
 //   k_mlp_step  one workgroup per 64 consecutive points: forward pass, loss,
-//               backward pass and the gradient summed over its points (in
-//               point order) into partial[workgroup][param];
+//               backward pass and the gradient summed over its points into
+//               partial[workgroup][param]; the three 64 x 64 x 64
+//               contractions (hidden layer forward, its backward, the W2
+//               gradient) run on the FP32 matrix cores;
 //   k_mlp_adam  sums the workgroup partials in workgroup order (so a step is
 //               reproducible bit for bit) and applies Adam.
 // Inference (k_mlp_point) is one work-item per point.
@@ -79,125 +81,161 @@ __global__ void __launch_bounds__(256) k_mlp_point(const float *__restrict__ prm
     out[p] = o;
 }
 
-// One training step's gradient for points [64 b, 64 b + 64): 512 work-items,
-// lane l of every wave is point 64 b + l, and wave w owns hidden units
-// [8 w, 8 w + 8) of both layers.  Per-point activations and backward
-// quantities live in LDS; parameters come through scalar loads.  Points past
-// n contribute nothing (their dL/dout is zero).
+// One block's gradient: points [64 b, 64 b + 64), 512 work-items.  The
+// parameters are staged in LDS (W2 rows padded to kLd floats), with the
+// points' inputs and four per-point rows (h1, h2, dL/dz2, dL/dz1).  Lane l of
+// every wave is point 64 b + l for the per-point work, and wave w owns hidden
+// units [8 w, 8 w + 8) there.  The contractions over 64 run as 16 x 16 tiles
+// of v_mfma_f32_16x16x4f32 (lane l holds A[l % 16][l / 16] and
+// B[l / 16][l % 16] of each 16 x 4 by 4 x 16 slice; result element r of lane
+// l is D[4 (l / 16) + r][l % 16]): wave w takes row tile w % 4 and column
+// tiles 2 (w / 4) and 2 (w / 4) + 1 of each 64 x 64 product.  Points past n
+// contribute nothing (their dL/dout is zero).  Every sum runs in a fixed
+// order.
 constexpr int kStepThreads = 512;
-constexpr int kUnits = kH / (kStepThreads / 64);   // hidden units per wave
-constexpr size_t mlp_step_lds_floats(int in_dim) {
-    return (size_t)kPts * in_dim + 4 * kPts * kLd + (kStepThreads / 64) * kPts + kPts;
+constexpr int kWaves = kStepThreads / 64;
+constexpr int kUnits = kH / kWaves;                 // hidden units per wave
+static_assert(kH == 64 && kPts == 64 && kWaves == 8, "tiling assumes 64 x 64 blocks, 8 waves");
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr size_t mlp_prm_lds_floats(int in_dim) {
+    return (size_t)kH * in_dim + kH + (size_t)kH * kLd + kH + kH + 1;
+}
+constexpr size_t mlp_step_lds_floats(int in_dim) {   // up to 92 KiB (in_dim 12)
+    return mlp_prm_lds_floats(in_dim) + (size_t)kPts * in_dim + 4 * kPts * kLd + kWaves * kPts + kPts;
 }
 
-__global__ void __launch_bounds__(kStepThreads) k_mlp_step(const float *__restrict__ prm, int in_dim,
-                                                           const float *__restrict__ X,
-                                                           const float *__restrict__ y,
-                                                           const float *__restrict__ wt, size_t n,
-                                                           MlpScratch S, float *__restrict__ loss) {
-    constexpr int kWaves = kStepThreads / 64;
-    extern __shared__ float sm[];
-    float *s_x = sm;                                 // [64][in_dim]
+__device__ __forceinline__ void block_grad(const float *prm, int in_dim, const float *__restrict__ X,
+                                           const float *__restrict__ y,
+                                           const float *__restrict__ wt, size_t n, float wsum,
+                                           size_t blk, float *__restrict__ part, float *loss,
+                                           float *sm) {
+    const int np = mlp_np(in_dim);
+    const int oW1 = 0, ob1 = kH * in_dim, oW2 = ob1 + kH, ob2 = oW2 + kH * kH, oW3 = ob2 + kH,
+              ob3 = oW3 + kH;
+    float *s_b1 = sm + ob1;                          // W1 [64][in_dim] at sm
+    float *s_W2 = sm + oW2;                          // [64][kLd]
+    float *s_b2 = s_W2 + kH * kLd;
+    float *s_W3 = s_b2 + kH;                         // W3[64], then b3
+    float *s_x = s_W3 + kH + 1;                      // [64][in_dim]
     float *s_h1 = s_x + kPts * in_dim;               // [64][kLd]
     float *s_h2 = s_h1 + kPts * kLd;
-    float *s_dz1 = s_h2 + kPts * kLd;
-    float *s_dz2 = s_dz1 + kPts * kLd;
-    float *s_op = s_dz2 + kPts * kLd;                // [waves][64] output partials
+    float *s_dz2 = s_h2 + kPts * kLd;
+    float *s_dz1 = s_dz2 + kPts * kLd;
+    float *s_op = s_dz1 + kPts * kLd;                // [waves][64] output partials
     float *s_dout = s_op + kWaves * kPts;            // [64]
-    cparam_t *W1 = (cparam_t *)(uintptr_t)prm;
-    cparam_t *b1 = W1 + kH * in_dim;
-    cparam_t *W2 = b1 + kH;
-    cparam_t *b2 = W2 + kH * kH;
-    cparam_t *W3 = b2 + kH;
-    const float b3 = W3[kH];
-    const int np = mlp_np(in_dim);
     const int tid = threadIdx.x, l = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int u0 = kUnits * w;
-    const size_t p0 = (size_t)blockIdx.x * kPts;
+    const size_t p0 = blk * kPts;
+    const size_t p = p0 + l;
+    // this point's target and weight, loaded early (first wave only)
+    float yp = 0.0f, wp = 0.0f;
+    if (w == 0 && p < n) {
+        yp = y[p];
+        wp = wt[p];
+    }
+    for (int q = tid; q < np; q += kStepThreads) {
+        const int r = q - oW2;
+        const int d = q < oW2 ? q : r < kH * kH ? oW2 + (r >> 6) * kLd + (r & 63) : q + kH * (kLd - kH);
+        sm[d] = prm[q];
+    }
     for (int i = tid; i < kPts * in_dim; i += kStepThreads) {
         const size_t pi = p0 + (size_t)(i / in_dim);
         s_x[i] = pi < n ? X[p0 * in_dim + i] : 0.0f;
     }
     __syncthreads();
-    const size_t p = p0 + l;
     // layer 1: this wave's units of point l
     for (int u = 0; u < kUnits; ++u) {
         const int i = u0 + u;
-        float acc = b1[i];
-        for (int k = 0; k < in_dim; ++k) acc = acc + W1[i * in_dim + k] * s_x[l * in_dim + k];
+        float acc = s_b1[i];
+        for (int k = 0; k < in_dim; ++k) acc = acc + sm[oW1 + i * in_dim + k] * s_x[l * in_dim + k];
         s_h1[l * kLd + i] = acc > 0.0f ? acc : 0.0f;
     }
     __syncthreads();
-    // layer 2 (this wave's units) and its share of the output
-    float a2[kUnits];
+    const int m16 = l & 15, k4 = l >> 4;
+    const int rt = w & 3, ct = (w >> 2) * 2;         // row tile, first column tile
+    // layer 2: z2[p][j] = sum_i h1[p][i] W2[j][i] (+ b2[j])
+    {
+        f32x4 acc[2] = {{0.0f, 0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f, 0.0f}};
+        for (int kk = 0; kk < kH / 4; ++kk) {
+            const float a = s_h1[(16 * rt + m16) * kLd + 4 * kk + k4];
 #pragma unroll
-    for (int u = 0; u < kUnits; ++u) a2[u] = b2[u0 + u];
-    for (int i = 0; i < kH; ++i) {
-        const float h = s_h1[l * kLd + i];
+            for (int t = 0; t < 2; ++t) {
+                const float b = s_W2[(16 * (ct + t) + m16) * kLd + 4 * kk + k4];
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
+            }
+        }
 #pragma unroll
-        for (int u = 0; u < kUnits; ++u) a2[u] = a2[u] + W2[(u0 + u) * kH + i] * h;
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int p = 16 * rt + 4 * k4 + r, j = 16 * (ct + t) + m16;
+                const float z = acc[t][r] + s_b2[j];
+                s_h2[p * kLd + j] = z > 0.0f ? z : 0.0f;
+            }
     }
+    __syncthreads();
+    // this wave's units' share of the output of point l
     float op = 0.0f;
 #pragma unroll
-    for (int u = 0; u < kUnits; ++u) {
-        const float h2 = a2[u] > 0.0f ? a2[u] : 0.0f;
-        s_h2[l * kLd + u0 + u] = h2;
-        op = op + W3[u0 + u] * h2;
-    }
+    for (int u = 0; u < kUnits; ++u) op = op + s_W3[u0 + u] * s_h2[l * kLd + u0 + u];
     s_op[w * kPts + l] = op;
     __syncthreads();
-    // output (wave partials added in wave order), loss term and dL/dout
-    float o = b3;
-    for (int v = 0; v < kWaves; ++v) o = o + s_op[v * kPts + l];
-    float lterm = 0.0f, dout = 0.0f;
-    if (p < n) {
-        const float inv = 1.0f / S.wsum[0];
-        const float r = o - y[p];
-        lterm = wt[p] * r * r * inv;
-        dout = 2.0f * wt[p] * r * inv;
+    // output (wave partials added in wave order), loss term and dL/dout:
+    // wave 0 for every point
+    float o = s_W3[kH];
+    if (w == 0)
+        for (int v = 0; v < kWaves; ++v) o = o + s_op[v * kPts + l];
+    float lterm = 0.0f;
+    if (w == 0) {
+        float dout = 0.0f;
+        if (p < n) {
+            const float inv = 1.0f / wsum;
+            const float r = o - yp;
+            lterm = wp * r * r * inv;
+            dout = 2.0f * wp * r * inv;
+        }
+        s_dout[l] = dout;
     }
-    if (w == 0) s_dout[l] = dout;
+    __syncthreads();
+    const float dout = s_dout[l];
 #pragma unroll
     for (int u = 0; u < kUnits; ++u) {
         const int j = u0 + u;
-        s_dz2[l * kLd + j] = s_h2[l * kLd + j] > 0.0f ? dout * W3[j] : 0.0f;
+        s_dz2[l * kLd + j] = s_h2[l * kLd + j] > 0.0f ? dout * s_W3[j] : 0.0f;
     }
     __syncthreads();
-    // dL/dz1 for this wave's units
-    float a1[kUnits];
-#pragma unroll
-    for (int u = 0; u < kUnits; ++u) a1[u] = 0.0f;
-    for (int j = 0; j < kH; ++j) {
-        const float dz = s_dz2[l * kLd + j];
-#pragma unroll
-        for (int u = 0; u < kUnits; ++u) a1[u] = a1[u] + dz * W2[j * kH + u0 + u];
-    }
-#pragma unroll
-    for (int u = 0; u < kUnits; ++u) {
-        const int i = u0 + u;
-        s_dz1[l * kLd + i] = s_h1[l * kLd + i] > 0.0f ? a1[u] : 0.0f;
-    }
-    __syncthreads();
-    // the workgroup's gradient, each parameter summed over its 64 points in
-    // point order.  W2[j][i]: work-item (i = lane, wave w) takes rows
-    // j = w, w + 8, ..., sharing each h1 read among them.
-    float *part = S.partial + (size_t)blockIdx.x * np;
-    const int ob1 = kH * in_dim, oW2 = ob1 + kH, ob2 = oW2 + kH * kH, oW3 = ob2 + kH, ob3 = oW3 + kH;
+    // dL/dz1[p][i] = [h1 > 0] sum_j dz2[p][j] W2[j][i], and the W2 gradient
+    // g[j][i] = sum_p dz2[p][j] h1[p][i] (row tile over j, the sum over points)
     {
-        constexpr int kRows = kH / kWaves;
-        float g2[kRows];
+        f32x4 d1[2] = {{0.0f, 0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f, 0.0f}};
+        f32x4 g2[2] = {{0.0f, 0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f, 0.0f}};
+        for (int kk = 0; kk < kH / 4; ++kk) {
+            const float a1 = s_dz2[(16 * rt + m16) * kLd + 4 * kk + k4];
+            const float a2 = s_dz2[(4 * kk + k4) * kLd + 16 * rt + m16];
 #pragma unroll
-        for (int k = 0; k < kRows; ++k) g2[k] = 0.0f;
-        for (int r = 0; r < kPts; ++r) {
-            const float h = s_h1[r * kLd + l];
-#pragma unroll
-            for (int k = 0; k < kRows; ++k) g2[k] = g2[k] + s_dz2[r * kLd + w + kWaves * k] * h;
+            for (int t = 0; t < 2; ++t) {
+                const int c = 16 * (ct + t) + m16;
+                d1[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, s_W2[(4 * kk + k4) * kLd + c], d1[t],
+                                                             0, 0, 0);
+                g2[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2, s_h1[(4 * kk + k4) * kLd + c], g2[t],
+                                                             0, 0, 0);
+            }
         }
 #pragma unroll
-        for (int k = 0; k < kRows; ++k) part[oW2 + (w + kWaves * k) * kH + l] = g2[k];
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = 16 * rt + 4 * k4 + r, c = 16 * (ct + t) + m16;
+                s_dz1[row * kLd + c] = s_h1[row * kLd + c] > 0.0f ? d1[t][r] : 0.0f;
+                part[oW2 + row * kH + c] = g2[t][r];
+            }
     }
-    // every other parameter: W1, b1 (indices below oW2) and b2, W3, b3 (from ob2)
+    __syncthreads();
+    // every other parameter: W1, b1 (indices below oW2) and b2, W3, b3 (from
+    // ob2), each summed over the 64 points in point order
     const int n_small = oW2 + (np - ob2);
     for (int t = tid; t < n_small; t += kStepThreads) {
         const int q = t < oW2 ? t : ob2 + (t - oW2);
@@ -226,6 +264,16 @@ __global__ void __launch_bounds__(kStepThreads) k_mlp_step(const float *__restri
     }
 }
 
+__global__ void __launch_bounds__(kStepThreads) k_mlp_step(const float *__restrict__ prm, int in_dim,
+                                                           const float *__restrict__ X,
+                                                           const float *__restrict__ y,
+                                                           const float *__restrict__ wt, size_t n,
+                                                           MlpScratch S, float *__restrict__ loss) {
+    extern __shared__ float sm[];
+    block_grad(prm, in_dim, X, y, wt, n, S.wsum[0], blockIdx.x,
+               S.partial + (size_t)blockIdx.x * mlp_np(in_dim), loss, sm);
+}
+
 __global__ void k_mlp_wsum(const float *__restrict__ wt, size_t n, float *__restrict__ wsum) {
     __shared__ float red[256];
     float acc = 0.0f;
@@ -239,19 +287,28 @@ __global__ void k_mlp_wsum(const float *__restrict__ wt, size_t n, float *__rest
     if (threadIdx.x == 0) wsum[0] = red[0];
 }
 
-// gradient = sum of the workgroup partials (workgroup order); optional Adam
-// update
-__global__ void k_mlp_adam(int np, MlpScratch S, float *__restrict__ grad, float *__restrict__ prm,
-                           float *__restrict__ m, float *__restrict__ v, float lr, float b1,
-                           float b2, float eps, float c1, float c2, int do_adam) {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= np) return;
-    // eight interleaved running sums (independent loads in flight), added
-    // in a fixed order at the end
+struct AdamArgs {
+    float lr, b1, b2, eps;
+};
+
+// Parameter q: the gradient as the sum of the workgroup partials (workgroup
+// order); with `adam`, Adam step number `step` on it (bias corrections
+// 1 - beta^step, taken on the device).
+__device__ __forceinline__ void adam_param(int q, int np, const MlpScratch &S, float *grad, float *prm,
+                                           float *m, float *v, const AdamArgs &A, int step, bool adam) {
+    // eight interleaved running sums, a[k] over the partials c = k mod 8 in
+    // increasing c, added in a fixed order at the end; 32 loads in flight
     float a[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) a[k] = 0.0f;
     int c = 0;
+    for (; c + 32 <= S.groups; c += 32) {
+        float t[32];
+#pragma unroll
+        for (int k = 0; k < 32; ++k) t[k] = S.partial[(size_t)(c + k) * np + q];
+#pragma unroll
+        for (int k = 0; k < 32; ++k) a[k & 7] += t[k];
+    }
     for (; c + 8 <= S.groups; c += 8) {
 #pragma unroll
         for (int k = 0; k < 8; ++k) a[k] += S.partial[(size_t)(c + k) * np + q];
@@ -259,15 +316,25 @@ __global__ void k_mlp_adam(int np, MlpScratch S, float *__restrict__ grad, float
     for (int k = 0; c < S.groups; ++c, ++k) a[k] += S.partial[(size_t)c * np + q];
     const float g = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
     if (grad) grad[q] = g;
-    if (do_adam) {
-        const float mq = b1 * m[q] + (1.0f - b1) * g;
-        const float vq = b2 * v[q] + (1.0f - b2) * g * g;
+    if (adam) {
+        const float c1 = 1.0f - powf(A.b1, (float)step);
+        const float c2 = 1.0f - powf(A.b2, (float)step);
+        const float mq = A.b1 * m[q] + (1.0f - A.b1) * g;
+        const float vq = A.b2 * v[q] + (1.0f - A.b2) * g * g;
         m[q] = mq;
         v[q] = vq;
         const float mh = mq / c1;
         const float vh = vq / c2;
-        prm[q] = prm[q] - lr * mh / (sqrtf(vh) + eps);
+        prm[q] = prm[q] - A.lr * mh / (sqrtf(vh) + A.eps);
     }
+}
+
+// gradient = sum of the workgroup partials; optional Adam update
+__global__ void k_mlp_adam(int np, MlpScratch S, float *__restrict__ grad, float *__restrict__ prm,
+                           float *__restrict__ m, float *__restrict__ v, AdamArgs A, int step,
+                           int do_adam) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < np) adam_param(q, np, S, grad, prm, m, v, A, step, do_adam != 0);
 }
 
 static int mlp_check(int in_dim, size_t n) {
@@ -279,7 +346,7 @@ static int mlp_check(int in_dim, size_t n) {
 
 static hipError_t step_grad(const float *prm, int in_dim, const float *X, const float *y,
                             const float *wt, size_t n, MlpScratch S, float *loss, hipStream_t s) {
-    const size_t shm = mlp_step_lds_floats(in_dim) * sizeof(float);   // up to 71 KiB
+    const size_t shm = mlp_step_lds_floats(in_dim) * sizeof(float);
     if (shm > 65536)
         (void)hipFuncSetAttribute((const void *)k_mlp_step, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)shm);
@@ -340,17 +407,16 @@ static hipError_t train_steps(float *prm, int in_dim, const float *X, const floa
     }
     hipLaunchKernelGGL(k_mlp_wsum, dim3(1), dim3(256), 0, s, wt, n, S.wsum);
     const int np = mlp_np(in_dim);
-    int step = *step_io;
-    for (int i = 0; i < o->steps && e == hipSuccess; ++i) {
-        step += 1;
-        e = step_grad(prm, in_dim, X, y, wt, n, S, loss_hist ? loss_hist + i : nullptr, s);
-        const float c1 = 1.0f - powf(o->beta1, (float)step);
-        const float c2 = 1.0f - powf(o->beta2, (float)step);
+    const AdamArgs A{o->lr, o->beta1, o->beta2, o->eps};
+    const int step0 = *step_io;
+    int done = 0;
+    for (; done < o->steps && e == hipSuccess; ++done) {
+        e = step_grad(prm, in_dim, X, y, wt, n, S, loss_hist ? loss_hist + done : nullptr, s);
         hipLaunchKernelGGL(k_mlp_adam, dim3((np + 255) / 256), dim3(256), 0, s, np, S, grad, prm, m,
-                           v, o->lr, o->beta1, o->beta2, o->eps, c1, c2, 1);
+                           v, A, step0 + done + 1, 1);
         if (e == hipSuccess) e = hipGetLastError();
     }
-    *step_io = step;
+    *step_io = step0 + done;
     return e;
 }
 
@@ -390,8 +456,8 @@ int mcdc_mlp_grad(const float *prm, int32_t in_dim, const float *X, const float 
     if (e == hipSuccess) e = step_grad(prm, in_dim, X, y, wt, n, S, loss, s);
     const int np = mlp_np(in_dim);
     hipLaunchKernelGGL(k_mlp_adam, dim3((np + 255) / 256), dim3(256), 0, s, np, S, grad,
-                       (float *)nullptr, (float *)nullptr, (float *)nullptr, 0.f, 0.f, 0.f, 0.f,
-                       1.f, 1.f, 0);
+                       (float *)nullptr, (float *)nullptr, (float *)nullptr, AdamArgs{0.f, 0.f, 0.f, 0.f},
+                       0, 0);
     if (e == hipSuccess) e = hipGetLastError();
     return e == hipSuccess ? MCDC_OK : hip_fail(e, "mlp_grad");
 }

@@ -90,9 +90,12 @@ def test_mlp_gradient_matches_oracle(in_dim, n):
     assert np.array_equal(g2.astype(np.float64), g)
 
 
-def test_mlp_adam_training_matches_oracle_and_decreases_loss():
+@pytest.mark.parametrize("n", [2000, 20000])
+def test_mlp_adam_training_matches_oracle_and_decreases_loss(n):
+    """2000 points (32 workgroups, a ragged last one) and 20000 (313
+    workgroups, more than the GPU's compute units)."""
     from paper_2409_04668_amd import learned_ww as L
-    X, y, wt = _data(2000, 5)
+    X, y, wt = _data(n, 5)
     p0 = L._init_params(IN, 7)
     params, losses, _ = L.gpu_train(X, y, wt, steps=50, lr=1e-3, params=p0)
     ref = p0.astype(np.float64)
