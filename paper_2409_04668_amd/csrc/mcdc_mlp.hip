@@ -82,28 +82,34 @@ __global__ void __launch_bounds__(256) k_mlp_point(const float *__restrict__ prm
 }
 
 // One block's gradient: points [64 b, 64 b + 64), 512 work-items.  The
-// parameters are staged in LDS (W2 rows padded to kLd floats), with the
-// points' inputs and four per-point rows (h1, h2, dL/dz2, dL/dz1).  Lane l of
-// every wave is point 64 b + l for the per-point work, and wave w owns hidden
-// units [8 w, 8 w + 8) there.  The contractions over 64 run as 16 x 16 tiles
-// of v_mfma_f32_16x16x4f32 (lane l holds A[l % 16][l / 16] and
-// B[l / 16][l % 16] of each 16 x 4 by 4 x 16 slice; result element r of lane
-// l is D[4 (l / 16) + r][l % 16]): wave w takes row tile w % 4 and column
-// tiles 2 (w / 4) and 2 (w / 4) + 1 of each 64 x 64 product.  Points past n
+// parameters are staged in LDS with the points' inputs and four per-point
+// rows (h1, h2, dL/dz2, dL/dz1).  Inputs and W1 are padded to 16 columns: the
+// input row gets a 1 in column in_dim and W1's row the bias b1 there, so one
+// product gives layer 1 with its bias and one product the W1 and b1
+// gradient.  The contractions run as 16 x 16 tiles of v_mfma_f32_16x16x4f32
+// (lane l holds A[l % 16][l / 16] and B[l / 16][l % 16] of each 16 x 4 by
+// 4 x 16 slice; result element r of lane l is D[4 (l / 16) + r][l % 16]):
+// in the 64 x 64 products wave w takes row tile w % 4 and column tiles
+// 2 (w / 4) and 2 (w / 4) + 1.  For the per-point work lane l of every wave is
+// point 64 b + l and wave w owns hidden units [8 w, 8 w + 8).  Points past n
 // contribute nothing (their dL/dout is zero).  Every sum runs in a fixed
 // order.
 constexpr int kStepThreads = 512;
 constexpr int kWaves = kStepThreads / 64;
 constexpr int kUnits = kH / kWaves;                 // hidden units per wave
+constexpr int kXc = 16;                             // padded input columns
+constexpr int kXs = kXc + 1;                        // their LDS row stride
 static_assert(kH == 64 && kPts == 64 && kWaves == 8, "tiling assumes 64 x 64 blocks, 8 waves");
+static_assert(4 + kMaxG < kXc, "the bias column follows the inputs");
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr size_t mlp_prm_lds_floats(int in_dim) {
-    return (size_t)kH * in_dim + kH + (size_t)kH * kLd + kH + kH + 1;
+constexpr size_t mlp_step_lds_floats() {             // 94.7 KiB
+    return (size_t)2 * kH * kXs + (size_t)kH * kLd + kH + kH + 1 + 4 * kPts * kLd + kWaves * kPts + kPts;
 }
-constexpr size_t mlp_step_lds_floats(int in_dim) {   // up to 92 KiB (in_dim 12)
-    return mlp_prm_lds_floats(in_dim) + (size_t)kPts * in_dim + 4 * kPts * kLd + kWaves * kPts + kPts;
+
+__device__ __forceinline__ f32x4 mfma4(float a, float b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
 __device__ __forceinline__ void block_grad(const float *prm, int in_dim, const float *__restrict__ X,
@@ -112,14 +118,13 @@ __device__ __forceinline__ void block_grad(const float *prm, int in_dim, const f
                                            size_t blk, float *__restrict__ part, float *loss,
                                            float *sm) {
     const int np = mlp_np(in_dim);
-    const int oW1 = 0, ob1 = kH * in_dim, oW2 = ob1 + kH, ob2 = oW2 + kH * kH, oW3 = ob2 + kH,
-              ob3 = oW3 + kH;
-    float *s_b1 = sm + ob1;                          // W1 [64][in_dim] at sm
-    float *s_W2 = sm + oW2;                          // [64][kLd]
+    const int ob1 = kH * in_dim, oW2 = ob1 + kH, ob2 = oW2 + kH * kH, oW3 = ob2 + kH, ob3 = oW3 + kH;
+    float *s_W1 = sm;                                // [64][kXs]: W1 | b1 | 0
+    float *s_W2 = s_W1 + kH * kXs;                   // [64][kLd]
     float *s_b2 = s_W2 + kH * kLd;
     float *s_W3 = s_b2 + kH;                         // W3[64], then b3
-    float *s_x = s_W3 + kH + 1;                      // [64][in_dim]
-    float *s_h1 = s_x + kPts * in_dim;               // [64][kLd]
+    float *s_x = s_W3 + kH + 1;                      // [64][kXs]: x | 1 | 0
+    float *s_h1 = s_x + kPts * kXs;                  // [64][kLd]
     float *s_h2 = s_h1 + kPts * kLd;
     float *s_dz2 = s_h2 + kPts * kLd;
     float *s_dz1 = s_dz2 + kPts * kLd;
@@ -128,6 +133,8 @@ __device__ __forceinline__ void block_grad(const float *prm, int in_dim, const f
     const int tid = threadIdx.x, l = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int u0 = kUnits * w;
+    const int m16 = l & 15, k4 = l >> 4;
+    const int rt = w & 3, ct = (w >> 2) * 2;         // row tile, first column tile
     const size_t p0 = blk * kPts;
     const size_t p = p0 + l;
     // this point's target and weight, loaded early (first wave only)
@@ -136,44 +143,71 @@ __device__ __forceinline__ void block_grad(const float *prm, int in_dim, const f
         yp = y[p];
         wp = wt[p];
     }
-    for (int q = tid; q < np; q += kStepThreads) {
-        const int r = q - oW2;
-        const int d = q < oW2 ? q : r < kH * kH ? oW2 + (r >> 6) * kLd + (r & 63) : q + kH * (kLd - kH);
-        sm[d] = prm[q];
+    // staging, every load issued before the first store: the padded W1 and
+    // input rows (64 x 16 each), then W2 (rows padded to kLd), b2, W3, b3
+    constexpr int kPad = kH * kXc / kStepThreads;
+    constexpr int kRest = (kH * kH + kH + kH + 1 + kStepThreads - 1) / kStepThreads;
+    const int n_rest = np - oW2;
+    float vw[kPad], vx[kPad], vr[kRest];
+#pragma unroll
+    for (int k = 0; k < kPad; ++k) {
+        const int e = tid + k * kStepThreads, i = e / kXc, c = e % kXc;
+        vw[k] = c < in_dim ? prm[i * in_dim + c] : c == in_dim ? prm[ob1 + i] : 0.0f;
+        vx[k] = c < in_dim ? (p0 + i < n ? X[(p0 + i) * in_dim + c] : 0.0f) : c == in_dim ? 1.0f : 0.0f;
     }
-    for (int i = tid; i < kPts * in_dim; i += kStepThreads) {
-        const size_t pi = p0 + (size_t)(i / in_dim);
-        s_x[i] = pi < n ? X[p0 * in_dim + i] : 0.0f;
+#pragma unroll
+    for (int k = 0; k < kRest; ++k) {
+        const int j = tid + k * kStepThreads;
+        vr[k] = j < n_rest ? prm[oW2 + j] : 0.0f;
+    }
+#pragma unroll
+    for (int k = 0; k < kPad; ++k) {
+        const int e = tid + k * kStepThreads, i = e / kXc, c = e % kXc;
+        s_W1[i * kXs + c] = vw[k];
+        s_x[i * kXs + c] = vx[k];
+    }
+#pragma unroll
+    for (int k = 0; k < kRest; ++k) {
+        const int j = tid + k * kStepThreads;
+        if (j < n_rest) s_W2[j < kH * kH ? (j >> 6) * kLd + (j & 63) : j + kH * (kLd - kH)] = vr[k];
     }
     __syncthreads();
-    // layer 1: this wave's units of point l
-    for (int u = 0; u < kUnits; ++u) {
-        const int i = u0 + u;
-        float acc = s_b1[i];
-        for (int k = 0; k < in_dim; ++k) acc = acc + sm[oW1 + i * in_dim + k] * s_x[l * in_dim + k];
-        s_h1[l * kLd + i] = acc > 0.0f ? acc : 0.0f;
-    }
-    __syncthreads();
-    const int m16 = l & 15, k4 = l >> 4;
-    const int rt = w & 3, ct = (w >> 2) * 2;         // row tile, first column tile
-    // layer 2: z2[p][j] = sum_i h1[p][i] W2[j][i] (+ b2[j])
+    // layer 1: z1[p][i] = sum_c x[p][c] W1[i][c] (the bias through the 1 column)
     {
         f32x4 acc[2] = {{0.0f, 0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f, 0.0f}};
-        for (int kk = 0; kk < kH / 4; ++kk) {
-            const float a = s_h1[(16 * rt + m16) * kLd + 4 * kk + k4];
 #pragma unroll
-            for (int t = 0; t < 2; ++t) {
-                const float b = s_W2[(16 * (ct + t) + m16) * kLd + 4 * kk + k4];
-                acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
-            }
+        for (int kk = 0; kk < kXc / 4; ++kk) {
+            const float a = s_x[(16 * rt + m16) * kXs + 4 * kk + k4];
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+                acc[t] = mfma4(a, s_W1[(16 * (ct + t) + m16) * kXs + 4 * kk + k4], acc[t]);
         }
 #pragma unroll
         for (int t = 0; t < 2; ++t)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int p = 16 * rt + 4 * k4 + r, j = 16 * (ct + t) + m16;
+                const float z = acc[t][r];
+                s_h1[(16 * rt + 4 * k4 + r) * kLd + 16 * (ct + t) + m16] = z > 0.0f ? z : 0.0f;
+            }
+    }
+    __syncthreads();
+    // layer 2: z2[p][j] = sum_i h1[p][i] W2[j][i] (+ b2[j])
+    {
+        f32x4 acc[2] = {{0.0f, 0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f, 0.0f}};
+#pragma unroll
+        for (int kk = 0; kk < kH / 4; ++kk) {
+            const float a = s_h1[(16 * rt + m16) * kLd + 4 * kk + k4];
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+                acc[t] = mfma4(a, s_W2[(16 * (ct + t) + m16) * kLd + 4 * kk + k4], acc[t]);
+        }
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int pp = 16 * rt + 4 * k4 + r, j = 16 * (ct + t) + m16;
                 const float z = acc[t][r] + s_b2[j];
-                s_h2[p * kLd + j] = z > 0.0f ? z : 0.0f;
+                s_h2[pp * kLd + j] = z > 0.0f ? z : 0.0f;
             }
     }
     __syncthreads();
@@ -185,11 +219,10 @@ __device__ __forceinline__ void block_grad(const float *prm, int in_dim, const f
     __syncthreads();
     // output (wave partials added in wave order), loss term and dL/dout:
     // wave 0 for every point
-    float o = s_W3[kH];
-    if (w == 0)
-        for (int v = 0; v < kWaves; ++v) o = o + s_op[v * kPts + l];
     float lterm = 0.0f;
     if (w == 0) {
+        float o = s_W3[kH];
+        for (int v = 0; v < kWaves; ++v) o = o + s_op[v * kPts + l];
         float dout = 0.0f;
         if (p < n) {
             const float inv = 1.0f / wsum;
@@ -212,16 +245,15 @@ __device__ __forceinline__ void block_grad(const float *prm, int in_dim, const f
     {
         f32x4 d1[2] = {{0.0f, 0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f, 0.0f}};
         f32x4 g2[2] = {{0.0f, 0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f, 0.0f}};
+#pragma unroll 8
         for (int kk = 0; kk < kH / 4; ++kk) {
             const float a1 = s_dz2[(16 * rt + m16) * kLd + 4 * kk + k4];
             const float a2 = s_dz2[(4 * kk + k4) * kLd + 16 * rt + m16];
 #pragma unroll
             for (int t = 0; t < 2; ++t) {
                 const int c = 16 * (ct + t) + m16;
-                d1[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, s_W2[(4 * kk + k4) * kLd + c], d1[t],
-                                                             0, 0, 0);
-                g2[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2, s_h1[(4 * kk + k4) * kLd + c], g2[t],
-                                                             0, 0, 0);
+                d1[t] = mfma4(a1, s_W2[(4 * kk + k4) * kLd + c], d1[t]);
+                g2[t] = mfma4(a2, s_h1[(4 * kk + k4) * kLd + c], g2[t]);
             }
         }
 #pragma unroll
@@ -234,28 +266,37 @@ __device__ __forceinline__ void block_grad(const float *prm, int in_dim, const f
             }
     }
     __syncthreads();
-    // every other parameter: W1, b1 (indices below oW2) and b2, W3, b3 (from
-    // ob2), each summed over the 64 points in point order
-    const int n_small = oW2 + (np - ob2);
-    for (int t = tid; t < n_small; t += kStepThreads) {
-        const int q = t < oW2 ? t : ob2 + (t - oW2);
-        float acc = 0.0f;
-        if (q < ob1) {
-            const int i = q / in_dim, k = q % in_dim;
-            for (int r = 0; r < kPts; ++r) acc = acc + s_dz1[r * kLd + i] * s_x[r * in_dim + k];
-        } else if (q < oW2) {
-            const int i = q - ob1;
-            for (int r = 0; r < kPts; ++r) acc = acc + s_dz1[r * kLd + i];
-        } else if (q < oW3) {
-            const int j = q - ob2;
-            for (int r = 0; r < kPts; ++r) acc = acc + s_dz2[r * kLd + j];
-        } else if (q < ob3) {
-            const int j = q - oW3;
-            for (int r = 0; r < kPts; ++r) acc = acc + s_dout[r] * s_h2[r * kLd + j];
-        } else {
-            for (int r = 0; r < kPts; ++r) acc = acc + s_dout[r];
+    if (w < 4) {
+        // W1 and b1: g[i][c] = sum_p dz1[p][i] x[p][c] (row tile w over i;
+        // column in_dim, the 1 column, is the b1 gradient)
+        f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 8
+        for (int kk = 0; kk < kPts / 4; ++kk)
+            acc = mfma4(s_dz1[(4 * kk + k4) * kLd + 16 * w + m16], s_x[(4 * kk + k4) * kXs + m16], acc);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = 16 * w + 4 * k4 + r;
+            if (m16 < in_dim) part[i * in_dim + m16] = acc[r];
+            else if (m16 == in_dim) part[ob1 + i] = acc[r];
         }
-        part[q] = acc;
+    } else {
+        // b2, W3 and b3, each summed over the 64 points in point order
+        for (int t = tid - kStepThreads / 2; t < np - ob2; t += kStepThreads / 2) {
+            const int q = ob2 + t;
+            float acc = 0.0f;
+            if (q < oW3) {
+#pragma unroll 16
+                for (int r = 0; r < kPts; ++r) acc = acc + s_dz2[r * kLd + t];
+            } else if (q < ob3) {
+                const int j = q - oW3;
+#pragma unroll 16
+                for (int r = 0; r < kPts; ++r) acc = acc + s_dout[r] * s_h2[r * kLd + j];
+            } else {
+#pragma unroll 16
+                for (int r = 0; r < kPts; ++r) acc = acc + s_dout[r];
+            }
+            part[q] = acc;
+        }
     }
     if (loss && w == 0) {
         // wave reduction, then one atomic per workgroup
@@ -296,36 +337,38 @@ struct AdamArgs {
 // 1 - beta^step, taken on the device).
 __device__ __forceinline__ void adam_param(int q, int np, const MlpScratch &S, float *grad, float *prm,
                                            float *m, float *v, const AdamArgs &A, int step, bool adam) {
+    // the moments and the parameter first, then up to 96 partials in flight;
     // eight interleaved running sums, a[k] over the partials c = k mod 8 in
-    // increasing c, added in a fixed order at the end; 32 loads in flight
+    // increasing c (zeros past the last one), added in a fixed order at the end
+    float mq = 0.0f, vq = 0.0f, pq = 0.0f;
+    if (adam) {
+        mq = m[q];
+        vq = v[q];
+        pq = prm[q];
+    }
+    constexpr int kBatch = 96;
     float a[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) a[k] = 0.0f;
-    int c = 0;
-    for (; c + 32 <= S.groups; c += 32) {
-        float t[32];
+    for (int c = 0; c < S.groups; c += kBatch) {
+        float t[kBatch];
 #pragma unroll
-        for (int k = 0; k < 32; ++k) t[k] = S.partial[(size_t)(c + k) * np + q];
+        for (int k = 0; k < kBatch; ++k) t[k] = c + k < S.groups ? S.partial[(size_t)(c + k) * np + q] : 0.0f;
 #pragma unroll
-        for (int k = 0; k < 32; ++k) a[k & 7] += t[k];
+        for (int k = 0; k < kBatch; ++k) a[k & 7] += t[k];
     }
-    for (; c + 8 <= S.groups; c += 8) {
-#pragma unroll
-        for (int k = 0; k < 8; ++k) a[k] += S.partial[(size_t)(c + k) * np + q];
-    }
-    for (int k = 0; c < S.groups; ++c, ++k) a[k] += S.partial[(size_t)c * np + q];
     const float g = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
     if (grad) grad[q] = g;
     if (adam) {
         const float c1 = 1.0f - powf(A.b1, (float)step);
         const float c2 = 1.0f - powf(A.b2, (float)step);
-        const float mq = A.b1 * m[q] + (1.0f - A.b1) * g;
-        const float vq = A.b2 * v[q] + (1.0f - A.b2) * g * g;
+        mq = A.b1 * mq + (1.0f - A.b1) * g;
+        vq = A.b2 * vq + (1.0f - A.b2) * g * g;
         m[q] = mq;
         v[q] = vq;
         const float mh = mq / c1;
         const float vh = vq / c2;
-        prm[q] = prm[q] - A.lr * mh / (sqrtf(vh) + A.eps);
+        prm[q] = pq - A.lr * mh / (sqrtf(vh) + A.eps);
     }
 }
 
@@ -346,7 +389,7 @@ static int mlp_check(int in_dim, size_t n) {
 
 static hipError_t step_grad(const float *prm, int in_dim, const float *X, const float *y,
                             const float *wt, size_t n, MlpScratch S, float *loss, hipStream_t s) {
-    const size_t shm = mlp_step_lds_floats(in_dim) * sizeof(float);
+    const size_t shm = mlp_step_lds_floats() * sizeof(float);
     if (shm > 65536)
         (void)hipFuncSetAttribute((const void *)k_mlp_step, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)shm);
