@@ -5,9 +5,9 @@
 // One training step is two launches:
 //   k_mlp_step  one workgroup per 64 consecutive points: forward pass, loss,
 //               backward pass and the gradient summed over its points into
-//               partial[workgroup][param]; the three 64 x 64 x 64
-//               contractions (hidden layer forward, its backward, the W2
-//               gradient) run on the FP32 matrix cores;
+//               partial[workgroup][param]; every contraction (layer 1, the
+//               hidden layer forward and backward, the W1 and W2 gradients)
+//               runs on the FP32 matrix cores;
 //   k_mlp_adam  sums the workgroup partials in workgroup order (so a step is
 //               reproducible bit for bit) and applies Adam.
 // Inference (k_mlp_point) is one work-item per point.
@@ -18,7 +18,7 @@
 namespace mcdc {
 
 constexpr int kPts = 64;                  // points per workgroup of a training step
-constexpr int kLd = kH + 1;               // padded per-point row in LDS (no bank conflicts)
+constexpr int kLd = kH + 1;               // padded 64-wide row in LDS (fewer bank conflicts)
 
 __host__ __device__ inline int mlp_np(int in_dim) { return kH * in_dim + kH + kH * kH + kH + kH + 1; }
 
