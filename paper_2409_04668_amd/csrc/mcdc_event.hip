@@ -361,6 +361,16 @@ MCDC_DEV uint64_t batch_of(const RunArgs &A, uint32_t slot) {
     return ((r + 1) * A.run_batches - 1) / A.run_n;
 }
 
+// Work-items per workgroup of the lead and re-lead stages.  With the hot
+// tile, one workgroup per compute unit: 1024 work-items (16 waves, up to 128
+// VGPRs), or 768 (12 waves, up to 168 VGPRs) when every window check
+// evaluates the network: its values on top of the particle's spill at 128
+// VGPRs, and the extra registers gain more than the four waves of latency
+// hiding (7% on the duct's network-per-check run; the analog and window-map
+// stages lose 14% and 3% at 768).
+constexpr int kNetTileThreads = 768;
+constexpr int tile_threads(int LDS, int WW) { return LDS != 2 ? 256 : WW == 1 ? kNetTileThreads : 1024; }
+
 // One loop turn of the lead and re-lead stages for the live particle q: once
 // `flights` reaches the budget, hand the particle and the stacked daughters
 // over to bank C.cur; else one flight and the event that ends it.  A
@@ -436,7 +446,7 @@ MCDC_DEV bool batched_check(CP &PL, const RunArgs &A, Shared &S, Ctx &C, Part &q
 // particle that reaches a census goes into the census bank.  The re-lead
 // stage finishes what was banked.  LDS: 0 tally in HBM, 2 hot tile in LDS.
 template <int LDS, int WW>
-__global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_ev_lead(DevProblem, RunArgs A, EvBank B,
+__global__ void __launch_bounds__(tile_threads(LDS, WW)) k_ev_lead(DevProblem, RunArgs A, EvBank B,
                                                                   uint32_t n) {
     CP &P = kernel_problem();
     extern __shared__ double s_tile[];
@@ -697,7 +707,7 @@ __global__ void __launch_bounds__(256) k_ev_interact(DevProblem, RunArgs A, EvBa
 // particle.  The last workgroup to finish advances the bank roles as the
 // interaction stage does.
 template <int LDS, int WW>
-__global__ void __launch_bounds__(LDS == 2 ? 1024 : 256) k_ev_relead(DevProblem, RunArgs A, EvBank B) {
+__global__ void __launch_bounds__(tile_threads(LDS, WW)) k_ev_relead(DevProblem, RunArgs A, EvBank B) {
     CP &P = kernel_problem();
     extern __shared__ double s_tile[];
     __shared__ Shared S;
@@ -989,14 +999,15 @@ static void ev_launch_source(mcdc_problem *h, const RunArgs &A, hipStream_t s, u
     if (sg > E->grid) sg = E->grid;
     hipLaunchKernelGGL(k_ev_count_hist, dim3(1), dim3(1), 0, s, A.acc, (uint64_t)n);
     if (h->opt.lead) {
-        // the lead grid is the history schedule's (block, grid): work-item i
-        // owns stack lane i, and A.n_lanes = grid * block lanes exist
+        // the lead grid is the history schedule's (block, grid), with 768
+        // work-items per workgroup for tiled network checks: work-item i owns
+        // stack lane i, and A.n_lanes = grid * block lanes exist
         const DevProblem &P = h->P;
-        const int lb = h->opt.block;
+        const int ww = P.ww_on ? (P.ww_map ? 2 : 1) : 0;
+        const int lb = P.hot_bins && ww == 1 ? kNetTileThreads : h->opt.block;
         int lg = (int)((n + lb - 1) / lb);
         if (lg > h->opt.grid) lg = h->opt.grid;
         if (lg < 1) lg = 1;
-        const int ww = P.ww_on ? (P.ww_map ? 2 : 1) : 0;
         const size_t shm = P.hot_bins ? (size_t)P.hot_bins * sizeof(double) : 0;
 #define MCDC_LEAD(L, W)                                                                        \
     do {                                                                                       \
@@ -1028,8 +1039,8 @@ static void ev_launch_source(mcdc_problem *h, const RunArgs &A, hipStream_t s, u
 static void ev_launch_relead(mcdc_problem *h, const RunArgs &A, hipStream_t s) {
     const DevProblem &P = h->P;
     const EvBank &B = h->ev->B;
-    const dim3 grid(h->opt.grid), block(h->opt.block);
     const int ww = P.ww_on ? (P.ww_map ? 2 : 1) : 0;
+    const dim3 grid(h->opt.grid), block(P.hot_bins && ww == 1 ? kNetTileThreads : h->opt.block);
     const size_t shm = P.hot_bins ? (size_t)P.hot_bins * sizeof(double) : 0;
 #define MCDC_RELEAD(L, W)                                                                      \
     do {                                                                                       \

@@ -62,10 +62,11 @@ def _grad_scale(p, X, y, wt, in_dim):
                            dz2.sum(axis=0), dout @ h2, np.array([dout.sum()])])
 
 
-@pytest.mark.parametrize("in_dim,n", [(IN, 2500), (IN, 64), (IN, 1), (12, 3001)])
+@pytest.mark.parametrize("in_dim,n", [(IN, 2500), (IN, 64), (IN, 1), (9, 777), (12, 3001)])
 def test_mlp_gradient_matches_oracle(in_dim, n):
     """Several 64-point workgroups and a ragged last one, exactly one, a single
-    point, and the widest input (4 + 8 groups)."""
+    point, a middle width (4 + 5 groups) and the widest input (4 + 8 groups):
+    the inputs padded to 16 columns with the bias column right after them."""
     p = M.init_params(in_dim, H, seed=3)
     X, y, wt = _data(n, 4)
     if in_dim > IN:
