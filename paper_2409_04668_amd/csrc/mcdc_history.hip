@@ -361,6 +361,23 @@ int history_grid(int block, int waves_per_cu) {
     return g < 1 ? 1 : g;
 }
 
+// Each workgroup of the history kernel takes a fixed contiguous range of
+// histories, so workgroups beyond those the GPU holds at once would run
+// their whole ranges in a second, partly filled round: the grid is capped at
+// the workgroups of this kernel that are resident together (its occupancy,
+// which its registers and LDS set, times the compute units).
+static int resident_grid(const void *k, int grid, int block, size_t shm) {
+    int dev = 0, per_cu = 0, n_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, block, shm) != hipSuccess ||
+        hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return grid;
+    }
+    const int cap = per_cu * n_cu;
+    return cap > 0 && cap < grid ? cap : grid;
+}
+
 hipError_t launch_history(const DevProblem &P, const RunArgs &A, int grid, int block,
                           bool lds_tally, hipStream_t s) {
     const int mode = P.hot_bins ? 2 : (lds_tally ? 1 : 0);
@@ -370,10 +387,11 @@ hipError_t launch_history(const DevProblem &P, const RunArgs &A, int grid, int b
     const bool imp = P.imp_on != 0;
 #define MCDC_LAUNCH_F(L, W, I, F)                                                              \
     do {                                                                                       \
+        const void *kf = (const void *)k_history<L, W, I, F>;                                  \
         if (shm > 65536)                                                                       \
-            (void)hipFuncSetAttribute((const void *)k_history<L, W, I, F>,                     \
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);   \
-        hipLaunchKernelGGL((k_history<L, W, I, F>), dim3(grid), dim3(block), shm, s, P, A);    \
+            (void)hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm); \
+        const int g = resident_grid(kf, grid, block, shm);                                     \
+        hipLaunchKernelGGL((k_history<L, W, I, F>), dim3(g), dim3(block), shm, s, P, A);       \
     } while (0)
 #define MCDC_LAUNCH(L, W, I) MCDC_LAUNCH_F(L, W, I, false)
     if (P.fis_on) {
