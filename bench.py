@@ -451,12 +451,18 @@ def batch_rate(torch, mcdc, W, steps, warmup):
 
 def keff_rate(torch, mcdc, W, M=1_000_000, n_inactive=5, n_active=10):
     """The k-eigenvalue mode on the two-group reflected core (30^3 x 2 mesh
-    bins): one warm-up iteration, then n_inactive + n_active generations of M
-    histories timed; the mean of each estimator over the active generations
-    with its standard error."""
+    bins), under the occupancy (and hot tile) the autotuner picks for
+    generations of M histories: one warm-up iteration, then n_inactive +
+    n_active generations of M histories timed; the mean of each estimator
+    over the active generations with its standard error."""
     import numpy as np
+    from paper_2409_04668_amd import autotune
     p = W.keff_core(nx=30)
-    gp = mcdc.Problem(p, mcdc.make_options(mcdc.SCHED_HISTORY))
+    # the history kernel's occupancy for this generation size, and whether a
+    # hot tile pays, from short runs (setup, not timed)
+    tile, frac = autotune.plan_keff_tile(p)
+    choice = autotune.tune_keff(p, M, tile=tile, use_cache=False)
+    gp = mcdc.Problem(p, mcdc.make_options(**choice["options"]))
     gp.run_keff(100_000, 1, 2, seed=5)
     gp.reset()
     torch.cuda.synchronize()
@@ -475,6 +481,8 @@ def keff_rate(torch, mcdc, W, M=1_000_000, n_inactive=5, n_active=10):
     n = M * (n_inactive + n_active)
     return {"workload": "two-group reflected core (40 cm fissile cube in a 60 cm reflector), "
                         "30^3 x 2 mesh bins, history schedule",
+            "autotuned_options": choice["options"], "autotune_trials": choice["trials"],
+            "tile_track_length_fraction": frac,
             "histories_per_generation": M, "generations": [n_inactive, n_active],
             "histories_per_s": n / T, "seconds": T,
             "collisions_per_history": c["collisions"] / n,

@@ -2,7 +2,9 @@
 
 Single problems: history-based, event-based or hybrid schedule,
 persistent-grid occupancy target (waves per CU) and, for the event and hybrid
-schedules, the chunk of resident histories.  Batched problems: work-queue chunk size and occupancy.  Results are
+schedules, the chunk of resident histories.  The k-eigenvalue mode: the
+history kernel's occupancy for the generation size, with or without a hot
+tile.  Batched problems: work-queue chunk size and occupancy.  Results are
 cached in a JSON file keyed by a hash of the problem data and the device name,
 so a later run of the same workload skips the search.
 
@@ -184,6 +186,66 @@ def plan_hot_tile(prob, pilot=2_000_000, max_bins=None, seed=4242):
     nx, ny, nz, nt = [int(v) for v in m["n"]]
     G = prob["sigma_t"].shape[1] if m["per_group"] else 1
     return grow_tile(s.reshape(G, nt, nz, ny, nx), max_bins)
+
+
+def plan_keff_tile(prob, m=200_000, generations=5, max_bins=None, seed=4243):
+    """plan_hot_tile for a problem with fission, whose pilot is a few
+    k-eigenvalue generations of m histories (a fixed-source run refuses a
+    fissile problem).  Returns (tile, captured fraction) or (None, 0)."""
+    max_bins = max_bins or mcdc.MAX_TILE_BINS
+    from . import workloads as W
+    if W.n_bins(prob) <= 7680:
+        return None, 0.0
+    gp = mcdc.Problem(W.with_(prob, n_batches=1), mcdc.make_options(mcdc.SCHED_HISTORY))
+    gp.run_keff(m, generations - 1, 1, seed=seed)
+    s, _ = gp.raw()
+    gp.close()
+    mm = prob["mesh"]
+    nx, ny, nz, nt = [int(v) for v in mm["n"]]
+    G = prob["sigma_t"].shape[1] if mm["per_group"] else 1
+    return grow_tile(np.asarray(s).reshape(G, nt, nz, ny, nx), max_bins)
+
+
+def tune_keff(prob, m, waves=(4, 8, 16), tile=None, generations=(1, 2), cache_path=DEFAULT_CACHE,
+              use_cache=True, seed=2468):
+    """Occupancy (waves per CU) of the k-eigenvalue mode's history kernel
+    for generations of m histories, and whether the LDS hot tile `tile`
+    (e.g. from plan_keff_tile) pays: a generation is one launch, so with few
+    histories per work-item the grid size matters.  Each candidate runs a
+    warm-up, then `generations` = (inactive, active) generations of m
+    histories, timed.  Every candidate gives the same trajectories."""
+    import torch
+    tj = None if tile is None else [[int(v) for v in tile[0]], [int(v) for v in tile[1]]]
+    key = "keff:" + _device_name() + ":" + _hash_problem(prob) + f":{m}:{tj}:{tuple(waves)}"
+    cache = _load(cache_path) if use_cache else {}
+    if key in cache:
+        return cache[key]
+    n_in, n_act = generations
+    trials = []
+
+    def trial(**o):
+        gp = mcdc.Problem(prob, mcdc.make_options(mcdc.SCHED_HISTORY, **o))
+        gp.run_keff(min(m, 100_000), 1, 1, seed=seed)        # warm-up
+        gp.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gp.run_keff(m, n_in, n_act, seed=seed + 1)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        gp.close()
+        trials.append((dict(schedule=mcdc.SCHED_HISTORY, **o), m * (n_in + n_act) / dt))
+
+    for w in waves:
+        trial(waves_per_cu=w)
+    if tj is not None:
+        trial(tile=tj)
+    best = max(trials, key=lambda t: t[1])
+    res = {"options": best[0], "histories_per_s": best[1],
+           "trials": [{"options": o, "histories_per_s": r} for o, r in trials]}
+    if use_cache:
+        cache[key] = res
+        _save(cache_path, cache)
+    return res
 
 
 def tune_batch(probs, n_hist, chunks=(2048, 8192, 16384), waves=(8, 16), cache_path=DEFAULT_CACHE,

@@ -1,6 +1,7 @@
 """GPU tests of the autotuner: the schedule it picks runs the problem to the
 same per-history results as any other schedule, population control is only
-tried in the event and hybrid schedules, and the batched tuner returns a working shape."""
+tried in the event and hybrid schedules, the batched tuner returns a working
+shape, and the k-eigenvalue tuner's pick runs the same generations."""
 import numpy as np
 import pytest
 
@@ -82,3 +83,25 @@ def test_tuner_gives_the_tile_to_every_trial():
     gp.run(10_000, 3)
     assert gp.counters()["histories"] == 10_000
     gp.close()
+
+
+def test_keff_tuner_pick_runs_the_same_generations():
+    """The k-eigenvalue tuner (occupancy for the generation size, a hot tile
+    planned from a k-eigenvalue pilot) picks options that run the same
+    generations as the defaults: the same site counts and site estimates bit
+    for bit (trajectories do not depend on the grid or the tile), the
+    collision estimate to float-atomic summation order."""
+    from paper_2409_04668_amd import autotune, mcdc
+    p = W.keff_core(nx=30)
+    tile, frac = autotune.plan_keff_tile(p, m=20_000, generations=3)
+    assert tile is not None and 0.0 < frac <= 1.0
+    res = autotune.tune_keff(p, 20_000, waves=(4, 16), tile=tile, use_cache=False)
+    assert len(res["trials"]) == 3 and res["histories_per_s"] > 0
+    outs = []
+    for opt in (mcdc.make_options(**res["options"]), mcdc.make_options(mcdc.SCHED_HISTORY)):
+        gp = mcdc.Problem(p, opt)
+        outs.append(gp.run_keff(20_000, 2, 3, seed=8))
+        gp.close()
+    np.testing.assert_array_equal(outs[0]["n_sites"], outs[1]["n_sites"])
+    np.testing.assert_array_equal(outs[0]["k_site"], outs[1]["k_site"])
+    np.testing.assert_allclose(outs[0]["k_col"], outs[1]["k_col"], rtol=1e-12)
