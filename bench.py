@@ -387,15 +387,16 @@ def main():
         g7.close()
     if not args.no_other_schedule:
         # population control at census: the duct problem with 20 census steps
-        # under the hybrid schedule, without and with splitting-roulette to one
-        # particle per source history at every census
+        # under the hybrid schedule with the duct's hot tile, without and with
+        # splitting-roulette to one particle per source history at every census
         rates = {}
         for name, target in (("without", None), ("with_target_1", 1.0)):
             pp = W.config2(n_census=20)
             if target is not None:
                 pp["population_control"] = dict(target=target)
             # population control holds one batch of histories resident
-            gq = mcdc.Problem(pp, mcdc.make_options(mcdc.SCHED_HYBRID, event_chunk=N // 20))
+            gq = mcdc.Problem(pp, mcdc.make_options(mcdc.SCHED_HYBRID, event_chunk=N // 20,
+                                                    tile=tile))
             gq.run(N, seed)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -408,6 +409,7 @@ def main():
                 rates["pc_copies_per_history"] = c["pc_copies"] / (2 * N)
             gq.close()
         out["population_control_hybrid_20_census"] = {
+            "hot_tile": tile is not None,
             "histories_per_s_without": rates["without"],
             "histories_per_s_with": rates["with_target_1"],
             "pc_kills_per_history": rates["pc_kills_per_history"],
