@@ -206,6 +206,21 @@ def plan_keff_tile(prob, m=200_000, generations=5, max_bins=None, seed=4243):
     return grow_tile(np.asarray(s).reshape(G, nt, nz, ny, nx), max_bins)
 
 
+def _time_keff(prob, opt, m, generations, seed) -> float:
+    import torch
+    n_in, n_act = generations
+    gp = mcdc.Problem(prob, opt)
+    gp.run_keff(min(m, 100_000), 1, 1, seed=seed)        # warm-up
+    gp.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gp.run_keff(m, n_in, n_act, seed=seed + 1)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    gp.close()
+    return m * (n_in + n_act) / dt
+
+
 def tune_keff(prob, m, waves=(4, 8, 16), tile=None, generations=(1, 2), cache_path=DEFAULT_CACHE,
               use_cache=True, seed=2468):
     """Occupancy (waves per CU) of the k-eigenvalue mode's history kernel
@@ -214,26 +229,16 @@ def tune_keff(prob, m, waves=(4, 8, 16), tile=None, generations=(1, 2), cache_pa
     histories per work-item the grid size matters.  Each candidate runs a
     warm-up, then `generations` = (inactive, active) generations of m
     histories, timed.  Every candidate gives the same trajectories."""
-    import torch
     tj = None if tile is None else [[int(v) for v in tile[0]], [int(v) for v in tile[1]]]
     key = "keff:" + _device_name() + ":" + _hash_problem(prob) + f":{m}:{tj}:{tuple(waves)}"
     cache = _load(cache_path) if use_cache else {}
     if key in cache:
         return cache[key]
-    n_in, n_act = generations
     trials = []
 
     def trial(**o):
-        gp = mcdc.Problem(prob, mcdc.make_options(mcdc.SCHED_HISTORY, **o))
-        gp.run_keff(min(m, 100_000), 1, 1, seed=seed)        # warm-up
-        gp.reset()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        gp.run_keff(m, n_in, n_act, seed=seed + 1)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        gp.close()
-        trials.append((dict(schedule=mcdc.SCHED_HISTORY, **o), m * (n_in + n_act) / dt))
+        o = dict(schedule=mcdc.SCHED_HISTORY, **o)
+        trials.append((o, _time_keff(prob, mcdc.make_options(**o), m, generations, seed)))
 
     for w in waves:
         trial(waves_per_cu=w)

@@ -79,3 +79,24 @@ def test_tuner_trial_options_carry_the_tile(monkeypatch):
     p["population_control"] = dict(target=1.0)
     res = autotune.tune_single(p, pilot=100_000, event_chunks=(1 << 10, 1 << 16), use_cache=False)
     assert [t["options"]["event_chunk"] for t in res["trials"]] == [1 << 16, 1 << 16]
+
+
+def test_keff_tuner_trial_options(monkeypatch):
+    """tune_keff's trial list on the host (timings stubbed): the history
+    schedule at each occupancy, then the hot tile; the pick is the fastest.
+    No tile is planned when the mesh fits the whole-mesh LDS tally (and then
+    no GPU run is made)."""
+    from paper_2409_04668_amd import autotune, mcdc
+    monkeypatch.setattr(autotune, "_time_keff",
+                        lambda prob, opt, m, gens, seed: 100.0 if opt.tile_n[0] else float(opt.waves_per_cu))
+    monkeypatch.setattr(autotune, "_device_name", lambda: "test")
+    tile = ([1, 2, 2, 0, 1], [28, 26, 26, 1, 1])
+    res = autotune.tune_keff(W.keff_core(nx=30), 1000, waves=(4, 8, 16), tile=tile, use_cache=False)
+    opts = [t["options"] for t in res["trials"]]
+    assert [o.get("waves_per_cu") for o in opts] == [4, 8, 16, None]
+    assert all(o["schedule"] == mcdc.SCHED_HISTORY for o in opts)
+    assert opts[-1]["tile"] == [list(tile[0]), list(tile[1])]
+    assert res["options"] == opts[-1] and res["histories_per_s"] == 100.0
+    res = autotune.tune_keff(W.keff_core(nx=30), 1000, waves=(4, 8), use_cache=False)
+    assert res["options"]["waves_per_cu"] == 8 and len(res["trials"]) == 2
+    assert autotune.plan_keff_tile(W.keff_core(nx=12)) == (None, 0.0)
