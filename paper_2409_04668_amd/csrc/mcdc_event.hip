@@ -1132,7 +1132,7 @@ static int ev_iterate(mcdc_problem *h, const RunArgs &A, hipStream_t s, bool &do
 
 // Does the lead stage close the statistics of every history itself?  (The
 // same condition as `finalize` in k_ev_lead, for a run without census-step
-// control.)
+// control: then it banks nothing either.)
 static bool lead_finalizes(const mcdc_problem *h) {
     return h->opt.lead && !h->P.ww_on && !h->P.pc_on;
 }
@@ -1160,10 +1160,19 @@ int event_run_range(mcdc_problem *h, const RunArgs &A0, hipStream_t s) {
         A.h_end = c1;
         hipLaunchKernelGGL(k_ev_reset, dim3(1), dim3(1), 0, s, B);
         ev_launch_source(h, A, s, n);
+        if (lead_finalizes(h)) {
+            // the lead stage banked nothing and closed every history itself:
+            // no re-lead launch and no host check of the banks (the host
+            // stays ahead of the GPU, as in the history schedule)
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return hip_fail(e, "event launch");
+            if (cancel_set(h)) return fail(MCDC_E_CANCELLED, "run cancelled");
+            continue;
+        }
         bool done = false;
         int st = ev_iterate(h, A, s, done);
         if (st) return st;
-        if (!lead_finalizes(h) && (st = ev_finish_chunk(h, A, s, n))) return st;
+        if ((st = ev_finish_chunk(h, A, s, n))) return st;
     }
     return MCDC_OK;
 }
